@@ -1,0 +1,386 @@
+"""Oracle: plain CPU reference of the separable SOAP descriptor and GAP energy/forces.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  It shares no code, header,
+table or constant generator with the HIP library in ``paper_1905_02142_amd``
+and imports nothing from it; the HIP path never calls back into it.
+
+Layout:
+  * ``soap_oracle.c``  per-pair / per-atom arithmetic in x87 extended precision,
+                       brute-force neighbour search, GAP dot-product kernel.
+  * this module       the orthonormalisation table W = S^{-1/2} in 50-digit
+                       arithmetic (mpmath), parameter checking, ctypes marshalling,
+                       and the force assembly F_i = sum g - sum g.
+
+Paper: M. A. Caro, "Optimizing many-body atomic descriptors for enhanced
+computational performance of machine learning based interatomic potentials",
+arXiv:1905.02142.  Section / equation references are to that paper.
+
+Readings of points the paper leaves open (each is also listed in the design doc):
+  * W = S^{-1/2} is formed in 50-digit arithmetic from S by direct quadrature of
+    the basis definitions; S over [0, r_cut] for every pair of basis functions,
+    the Gaussian basis overlap with a neighbour integrated to infinity as printed.
+  * Eq. (08) is followed as printed (w_l = 2l+1); ``l_weight=1`` gives w_l = 1.
+  * The central atom is included with weight 1 and amplitude 1/(sigma_0r sigma_0perp^2).
+  * Y_lm uses the Condon-Shortley phase; the pole rule of the Legendre
+    recursions is not needed because Y_lm is evaluated from its definition.
+  * q = p / |p| with |p| over the full (n, n', l) set; q = 0 when p = 0.
+  * zeta is a positive integer.
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "soap_oracle.c")
+_LIB_LD = os.path.join(_HERE, "_soap_oracle.so")
+_LIB_F64 = os.path.join(_HERE, "_soap_oracle_f64.so")
+
+
+def build(force: bool = True) -> None:
+    """Compile the oracle's C (extended-precision and double variants) with gcc."""
+    for out, extra in ((_LIB_LD, []), (_LIB_F64, ["-DORACLE_REAL=double"])):
+        if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+            continue
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", out + ".tmp", _SRC, "-lm"] + extra
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("n_max", ctypes.c_int), ("l_max", ctypes.c_int), ("n_species", ctypes.c_int),
+        ("r_cut", ctypes.c_double), ("r_soft", ctypes.c_double), ("n_f", ctypes.c_double),
+        ("sigma0_r", ctypes.c_double), ("sigma0_perp", ctypes.c_double),
+        ("alpha_r", ctypes.c_double), ("alpha_perp", ctypes.c_double), ("a", ctypes.c_double),
+        ("central_weight", ctypes.c_double), ("l_weight", ctypes.c_int),
+    ]
+
+
+@dataclass(frozen=True)
+class Params:
+    """Descriptor hyper-parameters (Eq. (15) and Sec. "Density smoothing at the cutoff")."""
+
+    n_max: int
+    l_max: int
+    r_cut: float
+    sigma0_r: float
+    sigma0_perp: float
+    n_species: int = 1
+    r_soft: float | None = None      # None: no buffer zone (r_soft = r_cut)
+    n_f: float = 4.0
+    alpha_r: float = 0.0
+    alpha_perp: float = 0.0
+    a: float = 0.0
+    central_weight: float = 1.0
+    l_weight: int = 0               # 0: w_l = 2l+1 (Eq. (08)); 1: w_l = 1
+
+    @property
+    def n_channels(self) -> int:
+        return self.n_max * self.n_species
+
+    @property
+    def dim(self) -> int:
+        nch = self.n_channels
+        return nch * (nch + 1) // 2 * (self.l_max + 1)
+
+    def c_struct(self) -> _Params:
+        return _Params(self.n_max, self.l_max, self.n_species, self.r_cut,
+                       self.r_cut if self.r_soft is None else self.r_soft, self.n_f,
+                       self.sigma0_r, self.sigma0_perp, self.alpha_r, self.alpha_perp, self.a,
+                       self.central_weight, self.l_weight)
+
+
+@functools.lru_cache(maxsize=None)
+def _lib(precision: str = "ld"):
+    path = _LIB_LD if precision == "ld" else _LIB_F64
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_long
+    vp = ctypes.c_void_p
+    lib.or_descriptor.argtypes = [P(_Params), vp, vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.or_descriptor_vjp.argtypes = [P(_Params), vp, vp, i, vp, vp, vp, vp, vp, vp]
+    lib.or_gap.argtypes = [i, i, vp, i, vp, vp, i, vp, vp, vp]
+    lib.or_gap.restype = None
+    lib.or_neighbors.argtypes = [i, vp, vp, vp, d, i, vp, l, vp, vp, vp, vp]
+    lib.or_neighbors.restype = l
+    lib.or_overlap_integrals.argtypes = [d, d, d, d, d, i, vp]
+    lib.or_overlap_integrals.restype = None
+    lib.or_radial.argtypes = [P(_Params), vp, vp, d, vp, vp]
+    lib.or_radial.restype = None
+    lib.or_ilexp.argtypes = [d, i, vp, vp]
+    lib.or_ilexp.restype = None
+    lib.or_ylm_conj.argtypes = [i, i, vp, vp, vp, vp, vp]
+    lib.or_ylm_conj.restype = None
+    lib.or_gauss_basis_overlap.argtypes = [d, d, d, vp]
+    lib.or_gauss_basis_overlap.restype = None
+    lib.or_amplitude.argtypes = [P(_Params), d, vp]
+    lib.or_amplitude.restype = d
+    lib.or_descriptor_dim.argtypes = [P(_Params)]
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ------------------------------------------------------------------ basis table
+
+@functools.lru_cache(maxsize=None)
+def basis_tables(n_max: int, r_cut: float, sigma0_r: float, dps: int = 50):
+    """Overlap matrix S and W = S^{-1/2} of the radial basis (Sec. "Radial expansion coefficients").
+
+    phi_alpha(r) = (1 - r/r_cut)^(alpha+2) / N_alpha, N_alpha = sqrt(r_cut/(2 alpha + 5)),
+    alpha = 1..n_max-1, and phi_{n_max} = sqrt(2)/(sqrt(sigma0_r) pi^(1/4)) exp(-r^2/(2 sigma0_r^2))
+    (Eq. (06)).  S_ab = int_0^r_cut phi_a phi_b dr by direct quadrature of the definitions
+    in ``dps``-digit arithmetic; W from the symmetric eigendecomposition of S.
+
+    Returns (S, W, W_hi, W_lo, eigenvalues) with S, W as mpmath matrices and
+    W = W_hi + W_lo as a pair of float64 arrays.
+    """
+    import mpmath as mp
+
+    with mp.workdps(dps):
+        rc = mp.mpf(r_cut)
+        s0 = mp.mpf(sigma0_r)
+        n = n_max
+
+        def phi(a):
+            if a < n:
+                Na = mp.sqrt(rc / (2 * a + 5))
+                return lambda t: (1 - t / rc) ** (a + 2) / Na
+            cg = mp.sqrt(2) / (mp.sqrt(s0) * mp.pi ** mp.mpf("0.25"))
+            return lambda t: cg * mp.exp(-t ** 2 / (2 * s0 ** 2))
+
+        fs = [phi(a) for a in range(1, n + 1)]
+        # break points help the quadrature resolve the Gaussian near the origin
+        pts = [mp.mpf(0)] + [x for x in (s0, 4 * s0, 10 * s0) if x < rc] + [rc]
+        S = mp.matrix(n, n)
+        for a in range(n):
+            for b in range(a, n):
+                v = mp.quad(lambda t: fs[a](t) * fs[b](t), pts)
+                S[a, b] = v
+                S[b, a] = v
+        E, Q = mp.eigsy(S)
+        W = Q * mp.diag([1 / mp.sqrt(e) for e in E]) * Q.T
+        Whi = np.array([[float(W[i, j]) for j in range(n)] for i in range(n)])
+        Wlo = np.array([[float(W[i, j] - mp.mpf(Whi[i, j])) for j in range(n)] for i in range(n)])
+        eig = [E[i] for i in range(n)]
+    return S, W, Whi, Wlo, eig
+
+
+def _w(p: Params):
+    _, _, whi, wlo, _ = basis_tables(p.n_max, float(p.r_cut), float(p.sigma0_r))
+    return np.ascontiguousarray(whi), np.ascontiguousarray(wlo)
+
+
+def check_params(p: Params) -> None:
+    if not (2 <= p.n_max <= 12 and 0 <= p.l_max <= 12 and p.n_species >= 1):
+        raise ValueError("n_max must be in 2..12, l_max in 0..12")
+    if not (p.r_cut > 0 and p.sigma0_r > 0 and p.sigma0_perp > 0):
+        raise ValueError("r_cut and the widths must be positive")
+    if p.r_soft is not None and not (0 < p.r_soft <= p.r_cut):
+        raise ValueError("r_soft must be in (0, r_cut]")
+
+
+# ------------------------------------------------------------------ neighbours
+
+@dataclass
+class NeighbourList:
+    """Pairs grouped by centre: centre c owns pairs offsets[c]..offsets[c+1]-1."""
+
+    centres: np.ndarray   # (C,) atom index of each centre
+    offsets: np.ndarray   # (C+1,) int64
+    j: np.ndarray         # (P,) neighbour atom index
+    shift: np.ndarray     # (P, 3) lattice translation (integers)
+    d: np.ndarray         # (P, 3) r_j + T - r_i
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.offsets[-1])
+
+    def centre_of_pair(self) -> np.ndarray:
+        return np.repeat(self.centres, np.diff(self.offsets))
+
+
+def neighbors(positions, cell, pbc, r_cut, centres=None) -> NeighbourList:
+    """All (i, j, T) with 0 < |r_j + T - r_i| < r_cut, by brute force over atoms and images."""
+    pos = np.ascontiguousarray(positions, dtype=np.float64)
+    cel = np.ascontiguousarray(cell, dtype=np.float64)
+    pb = np.ascontiguousarray(pbc, dtype=np.int32)
+    n = pos.shape[0]
+    cen = np.arange(n, dtype=np.int32) if centres is None else np.ascontiguousarray(centres, dtype=np.int32)
+    off = np.zeros(len(cen) + 1, dtype=np.int64)
+    lib = _lib()
+    cnt = lib.or_neighbors(n, _ptr(pos), _ptr(cel), _ptr(pb), float(r_cut), len(cen), _ptr(cen), 0,
+                           _ptr(off), None, None, None)
+    j = np.zeros(cnt, dtype=np.int32)
+    sh = np.zeros((cnt, 3), dtype=np.int32)
+    d = np.zeros((cnt, 3), dtype=np.float64)
+    lib.or_neighbors(n, _ptr(pos), _ptr(cel), _ptr(pb), float(r_cut), len(cen), _ptr(cen), cnt,
+                     _ptr(off), _ptr(j), _ptr(sh), _ptr(d))
+    return NeighbourList(cen.astype(np.int64), off, j, sh, d)
+
+
+# ------------------------------------------------------------------ descriptor
+
+def descriptor(p: Params, nl: NeighbourList, species, want_c: bool = False, precision: str = "ld"):
+    """q (C, K) and |p| (C,) for the centres of ``nl``; with ``want_c`` also c_nlm.
+
+    c is returned complex with shape (C, n_channels, (l_max+1)(l_max+2)/2), the
+    last index running over (l, m) with 0 <= m <= l.
+    """
+    check_params(p)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    whi, wlo = _w(p)
+    C = len(nl.centres)
+    K = p.dim
+    q = np.zeros((C, K))
+    pn = np.zeros(C)
+    cs = np.ascontiguousarray(species[nl.centres])
+    ps = np.ascontiguousarray(species[nl.j])
+    d = np.ascontiguousarray(nl.d)
+    off = np.ascontiguousarray(nl.offsets, dtype=np.int64)
+    LM = (p.l_max + 1) * (p.l_max + 2) // 2
+    cre = cim = None
+    if want_c:
+        cre = np.zeros((C, p.n_channels, LM))
+        cim = np.zeros((C, p.n_channels, LM))
+    cp = p.c_struct()
+    rc = _lib(precision).or_descriptor(ctypes.byref(cp), _ptr(whi), _ptr(wlo), C, _ptr(cs), _ptr(off),
+                                       _ptr(ps), _ptr(d), _ptr(q), _ptr(pn), _ptr(cre), _ptr(cim))
+    if rc != 0:
+        raise ValueError("oracle rejected the parameters")
+    if want_c:
+        return q, pn, cre + 1j * cim
+    return q, pn
+
+
+def descriptor_vjp(p: Params, nl: NeighbourList, species, qbar, precision: str = "ld"):
+    """g (P, 3) = dE/dd_p for every pair, given qbar = dE/dq for the centres of ``nl``."""
+    check_params(p)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    whi, wlo = _w(p)
+    C = len(nl.centres)
+    qb = np.ascontiguousarray(qbar, dtype=np.float64)
+    assert qb.shape == (C, p.dim)
+    g = np.zeros((nl.n_pairs, 3))
+    cs = np.ascontiguousarray(species[nl.centres])
+    ps = np.ascontiguousarray(species[nl.j])
+    d = np.ascontiguousarray(nl.d)
+    off = np.ascontiguousarray(nl.offsets, dtype=np.int64)
+    cp = p.c_struct()
+    rc = _lib(precision).or_descriptor_vjp(ctypes.byref(cp), _ptr(whi), _ptr(wlo), C, _ptr(cs), _ptr(off),
+                                           _ptr(ps), _ptr(d), _ptr(qb), _ptr(g))
+    if rc != 0:
+        raise ValueError("oracle rejected the parameters")
+    return g
+
+
+def gap(q, q_sparse, alpha, zeta: int, want_grad: bool = True):
+    """GAP local energies e_i = sum_s alpha_s (q_i . q_s)^zeta, with dE/dq and dE/dalpha."""
+    if int(zeta) != zeta or zeta < 1:
+        raise ValueError("zeta must be a positive integer")
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    qs = np.ascontiguousarray(q_sparse, dtype=np.float64)
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    N, K = q.shape
+    M = qs.shape[0]
+    e = np.zeros(N)
+    qbar = np.zeros((N, K)) if want_grad else None
+    abar = np.zeros(M) if want_grad else None
+    _lib().or_gap(N, K, _ptr(q), M, _ptr(qs), _ptr(al), int(zeta), _ptr(e), _ptr(qbar), _ptr(abar))
+    return e, qbar, abar
+
+
+def assemble_forces(nl: NeighbourList, g, n_atoms: int):
+    """F = -dE/dr from pair gradients g_p = dE/dd_p, d_p = r_j + T - r_i:
+    F_i += g_p and F_j -= g_p."""
+    F = np.zeros((n_atoms, 3))
+    np.add.at(F, nl.centre_of_pair(), g)
+    np.add.at(F, nl.j, -g)
+    return F
+
+
+def energy_forces(p: Params, positions, cell, pbc, species, q_sparse, alpha, zeta: int,
+                  precision: str = "ld"):
+    """Per-atom energies, forces and dE/dalpha of a whole structure."""
+    nl = neighbors(positions, cell, pbc, p.r_cut)
+    q, _ = descriptor(p, nl, species, precision=precision)
+    e, qbar, abar = gap(q, q_sparse, alpha, zeta)
+    g = descriptor_vjp(p, nl, species, qbar, precision=precision)
+    F = assemble_forces(nl, g, len(positions))
+    return e, F, abar
+
+
+def energy_forces_subset(p: Params, positions, cell, pbc, species, q_sparse, alpha, zeta: int,
+                         atoms, precision: str = "ld"):
+    """Forces on ``atoms`` only, exact: every centre within r_cut of them is included."""
+    atoms = np.asarray(atoms, dtype=np.int64)
+    nl0 = neighbors(positions, cell, pbc, p.r_cut, centres=atoms)
+    involved = np.unique(np.concatenate([atoms, nl0.j.astype(np.int64)]))
+    nl = neighbors(positions, cell, pbc, p.r_cut, centres=involved)
+    q, _ = descriptor(p, nl, species, precision=precision)
+    e, qbar, abar = gap(q, q_sparse, alpha, zeta)
+    g = descriptor_vjp(p, nl, species, qbar, precision=precision)
+    F = assemble_forces(nl, g, len(positions))
+    pos_of = {int(a): k for k, a in enumerate(involved)}
+    e_atoms = np.array([e[pos_of[int(a)]] for a in atoms])
+    return e_atoms, F[atoms]
+
+
+# ------------------------------------------------------- pieces for pinning
+
+def overlap_integrals(lo, hi, mu, s, r_cut, kmax):
+    out = np.zeros(kmax + 1)
+    _lib().or_overlap_integrals(lo, hi, mu, s, r_cut, kmax, _ptr(out))
+    return out
+
+
+def radial(p: Params, r, precision: str = "ld"):
+    """(b_n(r), db_n/dr), n = 1..n_max, of one neighbour at distance r."""
+    whi, wlo = _w(p)
+    b = np.zeros(p.n_max)
+    db = np.zeros(p.n_max)
+    cp = p.c_struct()
+    _lib(precision).or_radial(ctypes.byref(cp), _ptr(whi), _ptr(wlo), float(r), _ptr(b), _ptr(db))
+    return b, db
+
+
+def ilexp(z, l_max):
+    """e_l(z) = exp(-z) i_l(z) and de_l/dz, l = 0..l_max."""
+    e = np.zeros(l_max + 1)
+    de = np.zeros(l_max + 1)
+    _lib().or_ilexp(float(z), l_max, _ptr(e), _ptr(de))
+    return e, de
+
+
+def ylm_conj(l, m, u):
+    """Y*_lm(u) (complex) and its gradient (3,) w.r.t. the components of u."""
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    re, im = ctypes.c_double(), ctypes.c_double()
+    gre = np.zeros(3)
+    gim = np.zeros(3)
+    _lib().or_ylm_conj(l, m, _ptr(uu), ctypes.byref(re), ctypes.byref(im), _ptr(gre), _ptr(gim))
+    return re.value + 1j * im.value, gre + 1j * gim
+
+
+def gauss_basis_overlap(mu, s, sigma0):
+    out = np.zeros(3)
+    _lib().or_gauss_basis_overlap(mu, s, sigma0, _ptr(out))
+    return out
+
+
+def amplitude(p: Params, r):
+    dA = ctypes.c_double()
+    cp = p.c_struct()
+    A = _lib().or_amplitude(ctypes.byref(cp), float(r), ctypes.byref(dA))
+    return A, dA.value
