@@ -1,0 +1,182 @@
+/*
+ * soap.h -- C ABI of the MI355X (gfx950) separable-SOAP / GAP library.
+ *
+ * Method: M. A. Caro, "Optimizing many-body atomic descriptors for enhanced
+ * computational performance of machine learning based interatomic potentials",
+ * arXiv:1905.02142 (2019).  Section and equation numbers below refer to it.
+ *
+ * What the library computes, for every atom i of one or many periodic structures:
+ *   - the neighbours j (with lattice image T) inside the cutoff sphere (Sec. I);
+ *   - the separable-density expansion coefficients c_nlm (Eqs. (05), (08)) from
+ *     the analytic radial overlaps of Sec. III.A (Eqs. (19), (02), (04) and the
+ *     Gaussian-basis closed form), the ilexp factors and spherical harmonics of
+ *     Sec. III.C, summed over neighbours;
+ *   - the power spectrum p_{nn'l} (Eq. (09)) and the unit descriptor q = p/|p|;
+ *   - the GAP local energies e_i = sum_s alpha_s (q_i . q_s)^zeta (Sec. IV.A),
+ *     forces F = -dE/dr and dE/dalpha_s (not in the paper: derived adjoints).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller unless it is
+ *     marked (host).  Arrays are row-major and contiguous.  The library never
+ *     frees caller memory.
+ *   - All device work is enqueued on the given stream in stream order.  Entry
+ *     points return after enqueueing, except where a host read-back is stated.
+ *   - Errors are returned as soap_status; nothing is thrown across the ABI.
+ *     Argument errors are detected on the host before anything is enqueued and
+ *     leave outputs untouched.  A HIP launch failure returns SOAP_EHIP;
+ *     asynchronous device faults surface at the next synchronising call.
+ *     soap_last_error() gives a message for the most recent failure on a context.
+ *   - Units: positions and lengths in Angstrom; energies in the units of alpha;
+ *     forces = -dE/dr in energy units per Angstrom.
+ *   - A context is not thread safe: calls on one context must not overlap in
+ *     time (they may use different streams if the caller orders them).
+ */
+#ifndef SOAP_H
+#define SOAP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SOAP_OK = 0,
+  SOAP_EINVAL = -1,     /* invalid argument (checked on the host) */
+  SOAP_ENOMEM = -2,     /* device allocation of the context workspace failed */
+  SOAP_EOVERFLOW = -3,  /* neighbour list capacity too small; see required_pairs */
+  SOAP_EHIP = -4,       /* a HIP runtime call failed */
+  SOAP_ENOTSUP = -5     /* valid but unsupported combination */
+} soap_status;
+
+/* Arithmetic of the GAP kernel contraction (S = Q Q_s^T and Qbar = G Q_s).
+ * The radial recursion, exp/erf terms and the orthonormal transform W are FP64
+ * in every mode; c_nlm, p and q are FP64 in every mode. */
+typedef enum {
+  SOAP_FP64 = 0,        /* FP64 MFMA */
+  SOAP_MIXED_F32 = 1,   /* FP32 operands, FP32 accumulation (MFMA) */
+  SOAP_MIXED_BF16 = 2,  /* BF16 operands, FP32 accumulation (MFMA) */
+  SOAP_MIXED_BF16X3 = 3 /* split-BF16 (hi/lo, three products), FP32 accumulation */
+} soap_precision;
+
+/* Hyper-parameters: Eq. (15) and Sec. III.B.  Defaults in brackets. */
+typedef struct {
+  int n_max;             /* radial basis size, 2..12: n_max-1 polynomials + 1 Gaussian */
+  int l_max;             /* 0..12 */
+  int n_species;         /* >= 1; neighbours of species s fill channels s*n_max..s*n_max+n_max-1 */
+  double r_cut;          /* hard cutoff r_hard (> 0) */
+  double r_soft;         /* soft cutoff; == r_cut means no buffer zone [r_cut] */
+  double n_f;            /* buffer-zone filter parameter [4.0] */
+  double sigma0_r;       /* radial width at r = 0 (> 0) */
+  double sigma0_perp;    /* angular width at r = 0 (> 0) */
+  double alpha_r;        /* d sigma_r / dr (>= 0) [0] */
+  double alpha_perp;     /* d sigma_perp / dr (>= 0) [0] */
+  double a;              /* amplitude exponent of (1 + 2x^3 - 3x^2)^a (>= 0) [0] */
+  double central_weight; /* weight of the central-atom Gaussian; 0 drops it [1.0] */
+  int l_weight;          /* 0: factor 2l+1 of Eq. (08) as printed [0]; 1: factor 1 */
+  soap_precision precision; /* GAP contraction arithmetic [SOAP_FP64] */
+} soap_params;
+
+/* Opaque context: owns the basis tables (W = S^{-1/2} computed on the host in
+ * 113-bit arithmetic, then rounded) and a device workspace that grows on demand. */
+typedef struct soap_ctx soap_ctx;
+
+/* Neighbour list in CSR form, all arrays caller-allocated DEVICE memory.
+ * Centre atom i owns pairs offsets[i] .. offsets[i+1]-1, sorted by (j, image).
+ * For pair p: j[p] neighbour atom, (dx,dy,dz)[p] = r_j + T - r_i, img[p] the
+ * lattice image T packed as ((Tx+512) << 20 | (Ty+512) << 10 | (Tz+512)),
+ * rev[p] the index of the reverse pair (j -> i, -T), center[p] = i.
+ * Capacities: offsets n_atoms+1; all per-pair arrays `capacity` entries. */
+typedef struct {
+  int n_atoms;
+  int n_structures;
+  long long n_pairs;     /* written by soap_build_neighbors */
+  long long capacity;    /* set by the caller */
+  int32_t* offsets;
+  int32_t* j;
+  int32_t* img;
+  int32_t* rev;
+  int32_t* center;
+  double* dx;
+  double* dy;
+  double* dz;
+} soap_nlist;
+
+/* Validate `p` and build the basis tables.  Returns SOAP_EINVAL for n_max
+ * outside 2..12, l_max outside 0..12, n_species < 1, non-positive r_cut or
+ * widths, r_soft outside (0, r_cut], n_f <= 0, negative alpha_r, alpha_perp or
+ * a, l_weight not 0/1, or an unknown precision.  Needs a current HIP device. */
+soap_status soap_create(const soap_params* p /* host */, soap_ctx** out /* host */);
+void soap_destroy(soap_ctx* ctx);
+
+/* Descriptor length K = n_ch (n_ch + 1) / 2 * (l_max + 1), n_ch = n_species * n_max. */
+int soap_descriptor_dim(const soap_ctx* ctx);
+const char* soap_status_string(soap_status s);
+const char* soap_last_error(const soap_ctx* ctx);
+
+/*
+ * Neighbour list (Sec. I: all atoms inside the cutoff sphere, every periodic
+ * image counted separately, self-images included, the centre itself excluded):
+ * all (i, j, T) with 0 < |r_j + T - r_i| < r_cut, T a lattice vector of i's
+ * structure on its periodic axes, j in the same structure.
+ *   pos            n_atoms x 3 positions (device)
+ *   cells          n_structures x 3 x 3, rows are lattice vectors (host)
+ *   pbc            n_structures x 3, nonzero = periodic axis (host)
+ *   struct_offsets n_structures + 1 atom offsets (host); NULL means one structure
+ *   nl             in: capacity and arrays; out: n_pairs and the arrays
+ *   required_pairs (host, nullable) receives the pair count
+ * Reads the pair count back to the host (one stream synchronisation).  If it
+ * exceeds nl->capacity, returns SOAP_EOVERFLOW, sets *required_pairs and
+ * nl->n_pairs, and leaves the per-pair arrays undefined.  Coincident atoms
+ * (distance < 1e-8) or non-finite positions return SOAP_EINVAL.
+ */
+soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                 const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                 soap_nlist* nl, long long* required_pairs, hipStream_t stream);
+
+/*
+ * Descriptors q (n_atoms x K, FP64) of every atom of `nl`, and |p| (n_atoms,
+ * nullable).  species: n_atoms labels in 0..n_species-1 (an atom with another
+ * label contributes to no density; with n_species = 1 the labels are not read).
+ * Atoms with p = 0 get q = 0.  The coefficients c_nlm are kept in the context for a following
+ * soap_descriptor_grad / gap_energy_forces call on the same list.
+ */
+soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q,
+                            double* p_norm, hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of the descriptor: pos_grad (n_atoms x 3) +=
+ * sum_i (dq_i/dr)^T q_bar_i, with q_bar (n_atoms x K).  Recomputes c_nlm and the
+ * per-pair radial/angular terms and their derivatives instead of storing a
+ * per-pair Jacobian.  Deterministic: each atom gathers its pair terms in a
+ * fixed order through the reverse-pair index.
+ */
+soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
+                                 const double* q_bar, double* pos_grad, hipStream_t stream);
+
+/*
+ * GAP energies and forces.  q_sparse: M x K sparse descriptors (FP64; cast by
+ * the library to the context's precision), alpha: M weights, zeta >= 1 integer.
+ * Outputs: e_atom (n_atoms) local energies; forces (n_atoms x 3, nullable =>
+ * energies only) = -dE/dr, overwritten; alpha_grad (M, nullable) = dE/dalpha_s
+ * = sum_i (q_i . q_s)^zeta, overwritten.  Computes the descriptor internally.
+ */
+soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
+                              const double* q_sparse, const double* alpha, int M, int zeta,
+                              double* e_atom, double* forces, double* alpha_grad, hipStream_t stream);
+
+/* Host utility: the orthonormalisation table W = S^{-1/2} of the radial basis
+ * (Sec. III.A) for these parameters, n_max x n_max row-major (host), and the
+ * eigenvalues of S in ascending order (host, nullable).  S and W are formed in
+ * binary128 and rounded once.  SOAP_EINVAL for invalid sizes or if S is not
+ * positive definite. */
+soap_status soap_radial_basis_table(int n_max, double r_cut, double sigma0_r, double* W, double* lambda);
+
+/* Bytes of device workspace the context currently holds. */
+long long soap_workspace_bytes(const soap_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOAP_H */

@@ -1,0 +1,150 @@
+"""ctypes binding of libsoap.so: the C ABI of include/soap.h, same names, argument
+marshalling only.  Every step of the computation runs in the HIP library; if
+the library is missing or cannot be loaded this module raises instead of
+falling back to anything else."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsoap.so")
+
+SOAP_OK, SOAP_EINVAL, SOAP_ENOMEM, SOAP_EOVERFLOW, SOAP_EHIP, SOAP_ENOTSUP = 0, -1, -2, -3, -4, -5
+SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3 = 0, 1, 2, 3
+
+# every function include/soap.h declares
+EXPORTED = (
+    "soap_create", "soap_destroy", "soap_descriptor_dim", "soap_status_string", "soap_last_error",
+    "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
+    "soap_radial_basis_table", "soap_workspace_bytes",
+)
+
+
+class soap_params(ctypes.Structure):
+    _fields_ = [
+        ("n_max", ctypes.c_int), ("l_max", ctypes.c_int), ("n_species", ctypes.c_int),
+        ("r_cut", ctypes.c_double), ("r_soft", ctypes.c_double), ("n_f", ctypes.c_double),
+        ("sigma0_r", ctypes.c_double), ("sigma0_perp", ctypes.c_double),
+        ("alpha_r", ctypes.c_double), ("alpha_perp", ctypes.c_double), ("a", ctypes.c_double),
+        ("central_weight", ctypes.c_double), ("l_weight", ctypes.c_int), ("precision", ctypes.c_int),
+    ]
+
+
+class soap_nlist(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int), ("n_structures", ctypes.c_int),
+        ("n_pairs", ctypes.c_longlong), ("capacity", ctypes.c_longlong),
+        ("offsets", ctypes.c_void_p), ("j", ctypes.c_void_p), ("img", ctypes.c_void_p),
+        ("rev", ctypes.c_void_p), ("center", ctypes.c_void_p),
+        ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p), ("dz", ctypes.c_void_p),
+    ]
+
+
+class SoapError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsoap.so once and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build() or "
+                          f"python -m paper_1905_02142_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    P = ctypes.POINTER
+    lib.soap_create.argtypes = [P(soap_params), P(vp)]
+    lib.soap_create.restype = i
+    lib.soap_destroy.argtypes = [vp]
+    lib.soap_destroy.restype = None
+    lib.soap_descriptor_dim.argtypes = [vp]
+    lib.soap_descriptor_dim.restype = i
+    lib.soap_status_string.argtypes = [i]
+    lib.soap_status_string.restype = ctypes.c_char_p
+    lib.soap_last_error.argtypes = [vp]
+    lib.soap_last_error.restype = ctypes.c_char_p
+    lib.soap_workspace_bytes.argtypes = [vp]
+    lib.soap_workspace_bytes.restype = ll
+    lib.soap_build_neighbors.argtypes = [vp, i, vp, vp, vp, vp, i, P(soap_nlist), P(ll), vp]
+    lib.soap_build_neighbors.restype = i
+    lib.soap_descriptor.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
+    lib.soap_descriptor.restype = i
+    lib.soap_descriptor_grad.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
+    lib.soap_descriptor_grad.restype = i
+    lib.gap_energy_forces.argtypes = [vp, P(soap_nlist), vp, vp, vp, i, i, vp, vp, vp, vp]
+    lib.gap_energy_forces.restype = i
+    lib.soap_radial_basis_table.argtypes = [i, d, d, vp, vp]
+    lib.soap_radial_basis_table.restype = i
+    _lib = lib
+    return lib
+
+
+def check(status: int, ctx=None) -> None:
+    if status != SOAP_OK:
+        lib = load()
+        msg = lib.soap_status_string(status).decode()
+        if ctx:
+            detail = lib.soap_last_error(ctx).decode()
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise SoapError(status, msg)
+
+
+# Thin wrappers with the C names.  Pointers are ints (device addresses, e.g.
+# tensor.data_ptr()) or ctypes objects; streams are hipStream_t handles as ints.
+
+def soap_create(params: soap_params) -> int:
+    ctx = ctypes.c_void_p()
+    check(load().soap_create(ctypes.byref(params), ctypes.byref(ctx)))
+    return ctx.value
+
+
+def soap_destroy(ctx: int) -> None:
+    load().soap_destroy(ctx)
+
+
+def soap_descriptor_dim(ctx: int) -> int:
+    return load().soap_descriptor_dim(ctx)
+
+
+def soap_workspace_bytes(ctx: int) -> int:
+    return load().soap_workspace_bytes(ctx)
+
+
+def soap_build_neighbors(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl: soap_nlist,
+                         stream) -> int:
+    """Returns the status (SOAP_OK or SOAP_EOVERFLOW); other failures raise. nl.n_pairs holds the count."""
+    req = ctypes.c_longlong(0)
+    st = load().soap_build_neighbors(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures,
+                                     ctypes.byref(nl), ctypes.byref(req), stream)
+    if st == SOAP_EOVERFLOW:
+        nl.n_pairs = req.value
+        return st
+    check(st, ctx)
+    return st
+
+
+def soap_descriptor(ctx, nl: soap_nlist, species, q, p_norm, stream) -> None:
+    check(load().soap_descriptor(ctx, ctypes.byref(nl), species, q, p_norm, stream), ctx)
+
+
+def soap_descriptor_grad(ctx, nl: soap_nlist, species, q_bar, pos_grad, stream) -> None:
+    check(load().soap_descriptor_grad(ctx, ctypes.byref(nl), species, q_bar, pos_grad, stream), ctx)
+
+
+def gap_energy_forces(ctx, nl: soap_nlist, species, q_sparse, alpha, M, zeta, e_atom, forces, alpha_grad,
+                      stream) -> None:
+    check(load().gap_energy_forces(ctx, ctypes.byref(nl), species, q_sparse, alpha, M, zeta, e_atom, forces,
+                                   alpha_grad, stream), ctx)
+
+
+def soap_radial_basis_table(n_max: int, r_cut: float, sigma0_r: float, W, lam) -> None:
+    check(load().soap_radial_basis_table(n_max, r_cut, sigma0_r, W, lam))

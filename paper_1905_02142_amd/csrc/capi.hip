@@ -1,0 +1,473 @@
+// C ABI of the library: contexts, argument checking, workspace and launches.
+// The arithmetic lives in the kernels; this file only validates, sizes buffers
+// and enqueues work on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/soap.h"
+#include "gap.h"
+#include "neighbors.h"
+#include "pair_kernels.h"
+#include "soap_device.h"
+
+extern "C" int soap_host_basis_table(int n_max, double r_cut, double sigma0_r, double* W, double* Wlo, double* eig);
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct soap_ctx {
+  soap_params prm{};
+  soap::DevParams dp{};
+  soap::DevTables ht{};
+  soap::DevTables* dt = nullptr;
+  int device = 0;
+  std::string err;
+  long long ws_bytes = 0;
+  int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
+  size_t pinned_bytes = 0;
+  // neighbour build
+  Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, counts, scan_part, errflag;
+  // descriptor / adjoint
+  Buf c, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
+};
+
+namespace {
+
+soap_status fail(soap_ctx* ctx, soap_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+soap_status hip_fail(soap_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, SOAP_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define SOAP_HIP(ctx, call)                                  \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);   \
+  } while (0)
+
+// grow-only device buffer
+bool ensure(soap_ctx* ctx, Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return true;
+  if (b.p) {
+    hipFree(b.p);
+    ctx->ws_bytes -= (long long)b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    return false;
+  }
+  b.cap = want;
+  ctx->ws_bytes += (long long)want;
+  return true;
+}
+
+bool ensure_pinned(soap_ctx* ctx, size_t bytes) {
+  if (ctx->pinned_bytes >= bytes) return true;
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  if (hipHostMalloc((void**)&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess) return false;
+  ctx->pinned_bytes = bytes;
+  return true;
+}
+
+#define SOAP_ENSURE(ctx, buf, bytes)                                                     \
+  do {                                                                                   \
+    if (!ensure(ctx, buf, bytes)) return fail(ctx, SOAP_ENOMEM, "device allocation failed"); \
+  } while (0)
+
+soap_status check_params(const soap_params* p, std::string& why) {
+  if (!p) return why = "null parameters", SOAP_EINVAL;
+  if (p->n_max < 2 || p->n_max > soap::kMaxN) return why = "n_max must be in 2..12", SOAP_EINVAL;
+  if (p->l_max < 0 || p->l_max > soap::kMaxL) return why = "l_max must be in 0..12", SOAP_EINVAL;
+  if (p->n_species < 1) return why = "n_species must be >= 1", SOAP_EINVAL;
+  if (!(p->r_cut > 0) || !std::isfinite(p->r_cut)) return why = "r_cut must be positive", SOAP_EINVAL;
+  if (!(p->r_soft > 0) || p->r_soft > p->r_cut) return why = "r_soft must be in (0, r_cut]", SOAP_EINVAL;
+  if (p->r_soft < p->r_cut && !(p->n_f > 0)) return why = "n_f must be positive", SOAP_EINVAL;
+  if (!(p->sigma0_r > 0) || !(p->sigma0_perp > 0)) return why = "sigma0_r and sigma0_perp must be positive", SOAP_EINVAL;
+  if (!(p->alpha_r >= 0) || !(p->alpha_perp >= 0) || !(p->a >= 0))
+    return why = "alpha_r, alpha_perp and a must be >= 0", SOAP_EINVAL;
+  if (!std::isfinite(p->central_weight)) return why = "central_weight must be finite", SOAP_EINVAL;
+  if (p->l_weight != 0 && p->l_weight != 1) return why = "l_weight must be 0 or 1", SOAP_EINVAL;
+  if (p->precision < SOAP_FP64 || p->precision > SOAP_MIXED_BF16X3) return why = "unknown precision", SOAP_EINVAL;
+  return SOAP_OK;
+}
+
+void build_ylm_tables(soap::DevTables& t) {
+  // Qbar_mm = sqrt(2)^(m>0) N_mm (2m-1)!!, by Q_mm = Q_{m-1,m-1} sqrt((2m+1)/(2m))
+  double qmm = 0.28209479177387814;  // 1/sqrt(4 pi)
+  for (int m = 0; m <= soap::kMaxL + 1; ++m) {
+    if (m > 0) qmm *= std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+    t.ymm[m] = (m > 0) ? qmm * std::sqrt(2.0) : qmm;
+  }
+  for (int l = 0; l <= soap::kMaxL; ++l)
+    for (int m = 0; m <= l; ++m) {
+      const int k = soap::lm_tri(l, m);
+      if (l == m) {
+        t.ya[k] = t.yb[k] = 0.0;
+        continue;
+      }
+      const double l2m2 = (double)(l * l - m * m);
+      t.ya[k] = std::sqrt((4.0 * l * l - 1.0) / l2m2);
+      const double num = ((double)((l - 1) * (l - 1) - m * m)) * (2.0 * l + 1.0);
+      const double den = (2.0 * l - 3.0) * l2m2;
+      t.yb[k] = (num == 0.0) ? 0.0 : std::sqrt(num / den);
+    }
+}
+
+soap_status check_nlist(soap_ctx* ctx, const soap_nlist* nl) {
+  if (!nl) return fail(ctx, SOAP_EINVAL, "null neighbour list");
+  if (nl->n_atoms < 0 || nl->n_pairs < 0) return fail(ctx, SOAP_EINVAL, "negative sizes in neighbour list");
+  if (nl->n_pairs > nl->capacity) return fail(ctx, SOAP_EINVAL, "neighbour list holds more pairs than its capacity");
+  if (nl->n_pairs > 2147483647LL) return fail(ctx, SOAP_ENOTSUP, "more than 2^31-1 pairs");
+  if (nl->n_atoms > 0 && !nl->offsets) return fail(ctx, SOAP_EINVAL, "null offsets");
+  if (nl->n_pairs > 0 && (!nl->j || !nl->dx || !nl->dy || !nl->dz || !nl->rev))
+    return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
+  return SOAP_OK;
+}
+
+soap_status check_lds(soap_ctx* ctx) {
+  const size_t lim = 64 * 1024;  // per-workgroup LDS without opting in to more
+  if (soap::descriptor_lds_bytes(ctx->dp) > lim || soap::adjoint_lds_bytes(ctx->dp) > lim)
+    return fail(ctx, SOAP_ENOTSUP, "descriptor too large for one workgroup's LDS (reduce n_species, n_max or l_max)");
+  return SOAP_OK;
+}
+
+// forward descriptor into the context's buffers (c, q, |p|)
+soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
+                    hipStream_t st) {
+  const soap::DevParams& P = ctx->dp;
+  const size_t N = (size_t)nl->n_atoms;
+  SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * P.nch * P.LL);
+  SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
+                                        species, (double*)ctx->c.p, q, pnorm, st));
+  return SOAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* soap_status_string(soap_status s) {
+  switch (s) {
+    case SOAP_OK: return "ok";
+    case SOAP_EINVAL: return "invalid argument";
+    case SOAP_ENOMEM: return "out of device memory";
+    case SOAP_EOVERFLOW: return "neighbour list capacity exceeded";
+    case SOAP_EHIP: return "HIP runtime error";
+    case SOAP_ENOTSUP: return "not supported";
+  }
+  return "unknown status";
+}
+
+const char* soap_last_error(const soap_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+long long soap_workspace_bytes(const soap_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+int soap_descriptor_dim(const soap_ctx* ctx) { return ctx ? ctx->dp.K : 0; }
+
+soap_status soap_create(const soap_params* p, soap_ctx** out) {
+  if (!out) return SOAP_EINVAL;
+  *out = nullptr;
+  std::string why;
+  soap_status s = check_params(p, why);
+  if (s != SOAP_OK) return s;
+  soap_ctx* ctx = new soap_ctx();
+  ctx->prm = *p;
+  soap::DevParams& d = ctx->dp;
+  d.n = p->n_max;
+  d.l = p->l_max;
+  d.ns = p->n_species;
+  d.nch = d.ns * d.n;
+  d.LL = (d.l + 1) * (d.l + 1);
+  d.K = d.nch * (d.nch + 1) / 2 * (d.l + 1);
+  d.buffer = p->r_soft < p->r_cut ? 1 : 0;
+  d.l_weight = p->l_weight;
+  d.rc = p->r_cut;
+  d.rs = p->r_soft;
+  d.nf = p->n_f;
+  d.s0r = p->sigma0_r;
+  d.s0p = p->sigma0_perp;
+  d.ar = p->alpha_r;
+  d.ap = p->alpha_perp;
+  d.a = p->a;
+  d.cw = p->central_weight;
+  soap::DevTables& t = ctx->ht;
+  double W[16 * 16];
+  if (soap_host_basis_table(d.n, d.rc, d.s0r, W, nullptr, nullptr) != 0) {
+    delete ctx;
+    return SOAP_EINVAL;
+  }
+  for (int i = 0; i < d.n * d.n; ++i) t.W[i] = W[i];
+  for (int al = 1; al < d.n; ++al) t.invN[al - 1] = std::sqrt((2.0 * al + 5.0) / d.rc);
+  for (int l = 0; l <= soap::kMaxL + 1; ++l) t.lw[l] = p->l_weight ? 1.0 : 2.0 * l + 1.0;
+  build_ylm_tables(t);
+  if (hipGetDevice(&ctx->device) != hipSuccess || hipMalloc((void**)&ctx->dt, sizeof(soap::DevTables)) != hipSuccess) {
+    delete ctx;
+    return SOAP_EHIP;
+  }
+  if (hipMemcpy(ctx->dt, &t, sizeof(soap::DevTables), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(ctx->dt);
+    delete ctx;
+    return SOAP_EHIP;
+  }
+  *out = ctx;
+  return SOAP_OK;
+}
+
+void soap_destroy(soap_ctx* ctx) {
+  if (!ctx) return;
+  Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
+                 &ctx->bin_cursor, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->c,
+                 &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp};
+  for (Buf* b : bufs)
+    if (b->p) hipFree(b->p);
+  if (ctx->dt) hipFree(ctx->dt);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                 const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                 soap_nlist* nl, long long* required_pairs, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  if (!nl || !cells || !pbc || n_atoms < 0 || n_structures < 1)
+    return fail(ctx, SOAP_EINVAL, "null argument or non-positive structure count");
+  if (n_atoms > 0 && !pos) return fail(ctx, SOAP_EINVAL, "null positions");
+  if (!nl->offsets) return fail(ctx, SOAP_EINVAL, "null offsets array");
+  if (nl->capacity < 0) return fail(ctx, SOAP_EINVAL, "negative capacity");
+  const double rc = ctx->dp.rc;
+  // per-structure cell-list geometry
+  std::vector<soap::StructMeta> meta(n_structures);
+  std::vector<int> so(n_structures + 1);
+  int n_bins = 0;
+  for (int s = 0; s <= n_structures; ++s) {
+    so[s] = struct_offsets ? struct_offsets[s] : (s == 0 ? 0 : n_atoms);
+    if (s > 0 && so[s] < so[s - 1]) return fail(ctx, SOAP_EINVAL, "structure offsets must be non-decreasing");
+  }
+  if (so[0] != 0 || so[n_structures] != n_atoms) return fail(ctx, SOAP_EINVAL, "structure offsets must span 0..n_atoms");
+  for (int s = 0; s < n_structures; ++s) {
+    soap::StructMeta& M = meta[s];
+    const double* c = cells + 9 * s;
+    for (int k = 0; k < 9; ++k) {
+      if (!std::isfinite(c[k])) return fail(ctx, SOAP_EINVAL, "non-finite cell");
+      M.cell[k] = c[k];
+    }
+    const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) +
+                       c[2] * (c[3] * c[7] - c[4] * c[6]);
+    if (!(std::fabs(det) > 1e-12)) return fail(ctx, SOAP_EINVAL, "singular cell");
+    // inverse (cell rows are lattice vectors: fractional = position * inv)
+    M.inv[0] = (c[4] * c[8] - c[5] * c[7]) / det;
+    M.inv[1] = (c[2] * c[7] - c[1] * c[8]) / det;
+    M.inv[2] = (c[1] * c[5] - c[2] * c[4]) / det;
+    M.inv[3] = (c[5] * c[6] - c[3] * c[8]) / det;
+    M.inv[4] = (c[0] * c[8] - c[2] * c[6]) / det;
+    M.inv[5] = (c[2] * c[3] - c[0] * c[5]) / det;
+    M.inv[6] = (c[3] * c[7] - c[4] * c[6]) / det;
+    M.inv[7] = (c[1] * c[6] - c[0] * c[7]) / det;
+    M.inv[8] = (c[0] * c[4] - c[1] * c[3]) / det;
+    int nb_total = 1;
+    for (int a = 0; a < 3; ++a) {
+      const double* u = c + 3 * ((a + 1) % 3);
+      const double* v = c + 3 * ((a + 2) % 3);
+      const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+      const double w = std::fabs(det) / std::sqrt(cx * cx + cy * cy + cz * cz);
+      M.pbc[a] = pbc[3 * s + a] ? 1 : 0;
+      if (M.pbc[a]) {
+        int nb = (int)std::floor(w / (rc * (1.0 + 2e-9)));
+        if (nb < 1) nb = 1;
+        if (nb > 256) nb = 256;
+        M.nbin[a] = nb;
+        M.R[a] = (int)std::ceil(rc * nb / w * (1.0 + 1e-9));
+        if (M.R[a] > soap::kWrapMax / 2) return fail(ctx, SOAP_ENOTSUP, "cell far thinner than the cutoff");
+      } else {
+        M.nbin[a] = 1;
+        M.R[a] = 0;
+      }
+      nb_total *= M.nbin[a];
+    }
+    M.bin0 = n_bins;
+    M.atom0 = so[s];
+    M.atom1 = so[s + 1];
+    n_bins += nb_total;
+  }
+  SOAP_ENSURE(ctx, ctx->meta, sizeof(soap::StructMeta) * n_structures);
+  SOAP_ENSURE(ctx, ctx->so, sizeof(int) * (n_structures + 1));
+  SOAP_ENSURE(ctx, ctx->atom_bin, sizeof(int) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->atom_wrap, sizeof(int) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->bin_count, sizeof(int) * n_bins);
+  SOAP_ENSURE(ctx, ctx->bin_start, sizeof(int) * (n_bins + 1));
+  SOAP_ENSURE(ctx, ctx->bin_cursor, sizeof(int) * n_bins);
+  SOAP_ENSURE(ctx, ctx->bin_atoms, sizeof(int) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->counts, sizeof(int) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->scan_part,
+              sizeof(int) * (size_t)std::max(soap::scan_partials_needed(n_atoms), soap::scan_partials_needed(n_bins)));
+  SOAP_ENSURE(ctx, ctx->errflag, sizeof(int) * 4);
+  const size_t up = sizeof(soap::StructMeta) * n_structures + sizeof(int) * (n_structures + 1);
+  // pinned staging: the previous call synchronised before returning, so it is free to reuse
+  if (!ensure_pinned(ctx, std::max<size_t>(up, 64))) return fail(ctx, SOAP_ENOMEM, "pinned allocation failed");
+  char* stage = (char*)ctx->pinned;
+  std::memcpy(stage, meta.data(), sizeof(soap::StructMeta) * n_structures);
+  std::memcpy(stage + sizeof(soap::StructMeta) * n_structures, so.data(), sizeof(int) * (n_structures + 1));
+  SOAP_HIP(ctx, hipMemcpyAsync(ctx->meta.p, stage, sizeof(soap::StructMeta) * n_structures, hipMemcpyHostToDevice, st));
+  SOAP_HIP(ctx, hipMemcpyAsync(ctx->so.p, stage + sizeof(soap::StructMeta) * n_structures,
+                               sizeof(int) * (n_structures + 1), hipMemcpyHostToDevice, st));
+  SOAP_HIP(ctx, hipMemsetAsync(ctx->bin_count.p, 0, sizeof(int) * n_bins, st));
+  SOAP_HIP(ctx, hipMemsetAsync(ctx->bin_cursor.p, 0, sizeof(int) * n_bins, st));
+  SOAP_HIP(ctx, hipMemsetAsync(ctx->errflag.p, 0, sizeof(int) * 4, st));
+  int* err = (int*)ctx->errflag.p;
+  const soap::StructMeta* dmeta = (const soap::StructMeta*)ctx->meta.p;
+  const int* dso = (const int*)ctx->so.p;
+  if (n_atoms > 0) {
+    SOAP_HIP(ctx, soap::launch_bin_atoms(n_atoms, pos, dmeta, dso, n_structures, (int*)ctx->atom_bin.p,
+                                         (int*)ctx->atom_wrap.p, (int*)ctx->bin_count.p, err, st));
+  }
+  SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->bin_count.p, n_bins, (int*)ctx->bin_start.p,
+                                     (int*)ctx->scan_part.p, st));
+  if (n_atoms > 0) {
+    SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, n_bins, (const int*)ctx->atom_bin.p, (const int*)ctx->bin_start.p,
+                                         (int*)ctx->bin_cursor.p, (int*)ctx->bin_atoms.p, st));
+    SOAP_HIP(ctx, soap::launch_pairs(false, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
+                                     (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
+                                     (const int*)ctx->bin_atoms.p, (int*)ctx->counts.p, nullptr, 0, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, nullptr, err, st));
+  }
+  SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->counts.p, n_atoms, nl->offsets, (int*)ctx->scan_part.p, st));
+  // read back the pair count and the error bits
+  int* hb = ctx->pinned;
+  SOAP_HIP(ctx, hipMemcpyAsync(hb, nl->offsets + n_atoms, sizeof(int), hipMemcpyDeviceToHost, st));
+  SOAP_HIP(ctx, hipMemcpyAsync(hb + 1, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  SOAP_HIP(ctx, hipStreamSynchronize(st));
+  const long long total = hb[0];
+  const int eb = hb[1];
+  nl->n_atoms = n_atoms;
+  nl->n_structures = n_structures;
+  if (eb & soap::kErrNonFinite) return fail(ctx, SOAP_EINVAL, "non-finite atomic position");
+  if (eb & soap::kErrCoincident) return fail(ctx, SOAP_EINVAL, "coincident atoms (distance below 1e-8)");
+  if (eb & soap::kErrFarOutside) return fail(ctx, SOAP_EINVAL, "atom more than 500 cells outside its cell");
+  if (total < 0) return fail(ctx, SOAP_ENOTSUP, "pair count overflows 32-bit offsets");
+  if (required_pairs) *required_pairs = total;
+  nl->n_pairs = total;
+  if (total > nl->capacity) {
+    nl->n_pairs = 0;
+    return fail(ctx, SOAP_EOVERFLOW, "neighbour list capacity too small");
+  }
+  if (total > 0 && (!nl->j || !nl->img || !nl->rev || !nl->center || !nl->dx || !nl->dy || !nl->dz))
+    return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
+  if (n_atoms > 0) {
+    SOAP_HIP(ctx, soap::launch_pairs(true, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
+                                     (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
+                                     (const int*)ctx->bin_atoms.p, nullptr, nl->offsets, nl->capacity, nl->j, nl->img,
+                                     nl->center, nl->dx, nl->dy, nl->dz, err, st));
+    SOAP_HIP(ctx, soap::launch_reverse(total, nl->offsets, nl->j, nl->img, nl->center, nl->rev, err, st));
+  }
+  return SOAP_OK;
+}
+
+soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* p_norm,
+                            hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = check_nlist(ctx, nl);
+  if (s != SOAP_OK) return s;
+  if ((s = check_lds(ctx)) != SOAP_OK) return s;
+  if (nl->n_atoms > 0 && (!species || !q)) return fail(ctx, SOAP_EINVAL, "null species or output");
+  double* pn = p_norm;
+  if (!pn) {
+    SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * (size_t)nl->n_atoms);
+    pn = (double*)ctx->pnorm.p;
+  }
+  return forward(ctx, nl, species, q, pn, st);
+}
+
+soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_bar,
+                                 double* pos_grad, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = check_nlist(ctx, nl);
+  if (s != SOAP_OK) return s;
+  if ((s = check_lds(ctx)) != SOAP_OK) return s;
+  if (nl->n_atoms == 0) return SOAP_OK;
+  if (!species || !q_bar || !pos_grad) return fail(ctx, SOAP_EINVAL, "null species, q_bar or pos_grad");
+  const soap::DevParams& P = ctx->dp;
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
+  SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
+  SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
+  SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
+  SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
+  SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
+  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, st)) != SOAP_OK) return s;
+  SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
+                                          species, (const double*)ctx->c.p, (const double*)ctx->q.p,
+                                          (const double*)ctx->pnorm.p, q_bar, (double*)ctx->gx.p,
+                                          (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+  SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
+                                          (const double*)ctx->gy.p, (const double*)ctx->gz.p, pos_grad, true, st));
+  return SOAP_OK;
+}
+
+soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_sparse,
+                              const double* alpha, int M, int zeta, double* e_atom, double* forces,
+                              double* alpha_grad, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = check_nlist(ctx, nl);
+  if (s != SOAP_OK) return s;
+  if ((s = check_lds(ctx)) != SOAP_OK) return s;
+  if (M < 1 || zeta < 1) return fail(ctx, SOAP_EINVAL, "M and zeta must be >= 1");
+  if (!q_sparse || !alpha) return fail(ctx, SOAP_EINVAL, "null sparse set or weights");
+  if (nl->n_atoms > 0 && (!species || !e_atom)) return fail(ctx, SOAP_EINVAL, "null species or energies");
+  if (ctx->prm.precision != SOAP_FP64) return fail(ctx, SOAP_ENOTSUP, "this precision mode is not built yet");
+  const soap::DevParams& P = ctx->dp;
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
+  if (N == 0) {
+    if (alpha_grad) SOAP_HIP(ctx, hipMemsetAsync(alpha_grad, 0, sizeof(double) * M, st));
+    return SOAP_OK;
+  }
+  SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
+  SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
+  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, st)) != SOAP_OK) return s;
+  double* qbar = nullptr;
+  if (forces) {
+    SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * N * P.K);
+    qbar = (double*)ctx->qbar.p;
+  }
+  SOAP_ENSURE(ctx, ctx->gapw, sizeof(double) * soap::gap_fp64_workspace_doubles((int)N, M));
+  SOAP_HIP(ctx, soap::launch_gap_fp64((int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta, e_atom, qbar,
+                                      alpha_grad, (double*)ctx->gapw.p, st));
+  if (forces) {
+    SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
+    SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
+    SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
+    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
+                                            species, (const double*)ctx->c.p, (const double*)ctx->q.p,
+                                            (const double*)ctx->pnorm.p, qbar, (double*)ctx->gx.p,
+                                            (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+    SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
+                                            (const double*)ctx->gy.p, (const double*)ctx->gz.p, forces, false, st));
+  }
+  return SOAP_OK;
+}
+
+soap_status soap_radial_basis_table(int n_max, double r_cut, double sigma0_r, double* W, double* lambda) {
+  if (n_max < 2 || n_max > soap::kMaxN || !(r_cut > 0) || !(sigma0_r > 0) || !W) return SOAP_EINVAL;
+  return soap_host_basis_table(n_max, r_cut, sigma0_r, W, nullptr, lambda) == 0 ? SOAP_OK : SOAP_EINVAL;
+}
+
+}  // extern "C"

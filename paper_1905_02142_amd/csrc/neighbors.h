@@ -1,0 +1,49 @@
+// Host/device interface of the neighbour-list kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace soap {
+
+// Geometry of one structure's cell list (host-built, device-read).
+struct StructMeta {
+  double cell[9];  // rows: lattice vectors a, b, c
+  double inv[9];   // inverse of the cell matrix: fractional = position * inv
+  int nbin[3];     // slabs per axis (1 on non-periodic axes)
+  int R[3];        // slabs scanned either side (0 on non-periodic axes)
+  int pbc[3];
+  int bin0;        // first global bin of this structure
+  int atom0, atom1;
+};
+
+// error bits raised by the kernels
+constexpr int kErrNonFinite = 1;
+constexpr int kErrCoincident = 2;
+constexpr int kErrNoReverse = 4;
+constexpr int kErrFarOutside = 8;
+
+// lattice image (or cell wrap) packed in 30 bits, 10 bits per axis, |T| <= 511
+constexpr int kWrapMax = 500;
+__host__ __device__ inline int pack_img(int a, int b, int c) {
+  return ((a + 512) << 20) | ((b + 512) << 10) | (c + 512);
+}
+__host__ __device__ inline void unpack_img(int v, int* t) {
+  t[0] = ((v >> 20) & 1023) - 512;
+  t[1] = ((v >> 10) & 1023) - 512;
+  t[2] = (v & 1023) - 512;
+}
+
+hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t st);
+int scan_partials_needed(int n);
+hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
+                            int* atom_bin, int* atom_wrap, int* bin_count, int* err, hipStream_t st);
+hipError_t launch_fill_bins(int n_atoms, int n_bins, const int* atom_bin, const int* bin_start, int* bin_cursor,
+                            int* bin_atoms, hipStream_t st);
+hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructMeta* meta, const int* so,
+                        int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
+                        const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
+                        int* ncenter, double* ndx, double* ndy, double* ndz, int* err, hipStream_t st);
+hipError_t launch_reverse(long long n_pairs, const int* offsets, const int* nj, const int* nimg, const int* ncenter,
+                          int* rev, int* err, hipStream_t st);
+
+}  // namespace soap

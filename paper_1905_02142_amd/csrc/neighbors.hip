@@ -1,0 +1,296 @@
+// Neighbour list inside the cutoff sphere (Sec. I): every (i, j, T) with
+// 0 < |r_j + T - r_i| < r_cut, T a lattice translation of i's structure.
+//
+// Cell list per structure in fractional coordinates.  Along a periodic axis the
+// cell is cut into nbin = max(1, floor(w / r_cut)) slabs (w = width perpendicular
+// to the two other lattice vectors); a centre scans R = ceil(r_cut nbin / w) slabs
+// either side.  When 2R + 1 > nbin the same slab is visited with different
+// lattice shifts, which enumerates every periodic image exactly once, so boxes
+// narrower than 2 r_cut work unchanged.  Non-periodic axes use one slab.
+//
+// Order: each centre's pairs follow the fixed slab-offset loop and, within a
+// bin, ascending atom index, so the list is identical on every run.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "neighbors.h"
+
+namespace soap {
+
+namespace {
+
+__device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+__device__ inline int find_structure(const int* __restrict__ so, int ns, int a) {
+  int lo = 0, hi = ns;  // so[lo] <= a < so[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (so[mid] <= a) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
+                            const int* __restrict__ so, int n_struct, int* __restrict__ atom_bin,
+                            int* __restrict__ atom_wrap, int* __restrict__ bin_count, int* __restrict__ err) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  const StructMeta& M = meta[find_structure(so, n_struct, a)];
+  double p[3] = {pos[3 * a], pos[3 * a + 1], pos[3 * a + 2]};
+  if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
+    atomicOr(err, kErrNonFinite);
+    p[0] = p[1] = p[2] = 0.0;
+  }
+  int b[3], w[3];
+  for (int x = 0; x < 3; ++x) {
+    double f = p[0] * M.inv[0 * 3 + x] + p[1] * M.inv[1 * 3 + x] + p[2] * M.inv[2 * 3 + x];
+    if (M.pbc[x]) {
+      double fw = floor(f);
+      f -= fw;
+      int wi = (int)fw;
+      if (f >= 1.0) {
+        f -= 1.0;
+        wi += 1;
+      }
+      if (wi < -kWrapMax || wi > kWrapMax) {
+        atomicOr(err, kErrFarOutside);
+        wi = 0;
+      }
+      w[x] = wi;
+      int bx = (int)(f * M.nbin[x]);
+      b[x] = bx < M.nbin[x] ? (bx < 0 ? 0 : bx) : M.nbin[x] - 1;
+    } else {
+      w[x] = 0;
+      b[x] = 0;
+    }
+  }
+  int bin = M.bin0 + (b[2] * M.nbin[1] + b[1]) * M.nbin[0] + b[0];
+  atom_bin[a] = bin;
+  atom_wrap[a] = pack_img(w[0], w[1], w[2]);
+  atomicAdd(&bin_count[bin], 1);
+}
+
+__global__ void k_fill_bins(int n_atoms, const int* __restrict__ atom_bin, const int* __restrict__ bin_start,
+                            int* __restrict__ bin_cursor, int* __restrict__ bin_atoms) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  int bin = atom_bin[a];
+  int slot = atomicAdd(&bin_cursor[bin], 1);
+  bin_atoms[bin_start[bin] + slot] = a;
+}
+
+// atoms of one bin in ascending index order (bins hold tens of atoms)
+__global__ void k_sort_bins(int n_bins, const int* __restrict__ bin_start, int* __restrict__ bin_atoms) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  int s = bin_start[b], e = bin_start[b + 1];
+  for (int x = s + 1; x < e; ++x) {
+    int v = bin_atoms[x];
+    int y = x - 1;
+    while (y >= s && bin_atoms[y] > v) {
+      bin_atoms[y + 1] = bin_atoms[y];
+      --y;
+    }
+    bin_atoms[y + 1] = v;
+  }
+}
+
+template <bool FILL>
+__global__ void k_pairs(int n_atoms, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
+                        const int* __restrict__ so, int n_struct, double rc2, const int* __restrict__ atom_bin,
+                        const int* __restrict__ atom_wrap, const int* __restrict__ bin_start,
+                        const int* __restrict__ bin_atoms, int* __restrict__ count, const int* __restrict__ offsets,
+                        long long capacity, int* __restrict__ nj, int* __restrict__ nimg, int* __restrict__ ncenter,
+                        double* __restrict__ ndx, double* __restrict__ ndy, double* __restrict__ ndz,
+                        int* __restrict__ err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_atoms) return;
+  const StructMeta& M = meta[find_structure(so, n_struct, i)];
+  const double pix = pos[3 * i], piy = pos[3 * i + 1], piz = pos[3 * i + 2];
+  const int local = atom_bin[i] - M.bin0;
+  const int bx = local % M.nbin[0], by = (local / M.nbin[0]) % M.nbin[1], bz = local / (M.nbin[0] * M.nbin[1]);
+  int wi[3];
+  unpack_img(atom_wrap[i], wi);
+  int out = FILL ? offsets[i] : 0;
+  int cnt = 0;
+  for (int oz = -M.R[2]; oz <= M.R[2]; ++oz) {
+    const int uz = bz + oz, gz = M.pbc[2] ? floordiv(uz, M.nbin[2]) : 0, cz = uz - gz * M.nbin[2];
+    for (int oy = -M.R[1]; oy <= M.R[1]; ++oy) {
+      const int uy = by + oy, gy = M.pbc[1] ? floordiv(uy, M.nbin[1]) : 0, cy = uy - gy * M.nbin[1];
+      for (int ox = -M.R[0]; ox <= M.R[0]; ++ox) {
+        const int ux = bx + ox, gx = M.pbc[0] ? floordiv(ux, M.nbin[0]) : 0, cx = ux - gx * M.nbin[0];
+        const int bin = M.bin0 + (cz * M.nbin[1] + cy) * M.nbin[0] + cx;
+        for (int t = bin_start[bin]; t < bin_start[bin + 1]; ++t) {
+          const int j = bin_atoms[t];
+          int wj[3];
+          unpack_img(atom_wrap[j], wj);
+          const int T0 = gx - wj[0] + wi[0], T1 = gy - wj[1] + wi[1], T2 = gz - wj[2] + wi[2];
+          if (j == i && T0 == 0 && T1 == 0 && T2 == 0) continue;
+          // d = (r_j - r_i) + T cell, the same operation order for a pair and its reverse
+          const double tx = T0 * M.cell[0] + T1 * M.cell[3] + T2 * M.cell[6];
+          const double ty = T0 * M.cell[1] + T1 * M.cell[4] + T2 * M.cell[7];
+          const double tz = T0 * M.cell[2] + T1 * M.cell[5] + T2 * M.cell[8];
+          const double ddx = (pos[3 * j] - pix) + tx;
+          const double ddy = (pos[3 * j + 1] - piy) + ty;
+          const double ddz = (pos[3 * j + 2] - piz) + tz;
+          const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (r2 < rc2) {
+            if (r2 < 1e-16) atomicOr(err, kErrCoincident);
+            if (FILL) {
+              if (out < capacity) {
+                nj[out] = j;
+                nimg[out] = pack_img(T0, T1, T2);
+                ncenter[out] = i;
+                ndx[out] = ddx;
+                ndy[out] = ddy;
+                ndz[out] = ddz;
+              }
+              ++out;
+            } else {
+              ++cnt;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!FILL) count[i] = cnt;
+}
+
+// rev[p]: the pair (j -> i, -T) in j's list
+__global__ void k_reverse(long long n_pairs, const int* __restrict__ offsets, const int* __restrict__ nj,
+                          const int* __restrict__ nimg, const int* __restrict__ ncenter, int* __restrict__ rev,
+                          int* __restrict__ err) {
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const int i = ncenter[p], j = nj[p];
+  int T[3];
+  unpack_img(nimg[p], T);
+  const int want = pack_img(-T[0], -T[1], -T[2]);
+  int found = -1;
+  for (int q = offsets[j]; q < offsets[j + 1]; ++q)
+    if (nj[q] == i && nimg[q] == want) {
+      found = q;
+      break;
+    }
+  if (found < 0) atomicOr(err, kErrNoReverse);
+  rev[p] = found < 0 ? (int)p : found;
+}
+
+// ---------------------------------------------------------------- scan
+// Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total), three
+// passes: per-block totals, one-block scan of the totals, per-block scan + offset.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    int x = (t >= o) ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  total = sh[kScanThreads - 1];
+  int excl = sh[t] - v;
+  __syncthreads();
+  return excl;
+}
+
+__global__ void k_scan_partials(int n, const int* __restrict__ in, int* __restrict__ part) {
+  __shared__ int sh[kScanThreads];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  int total;
+  block_exclusive_scan(s, sh, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void k_scan_top(int nb, int* __restrict__ part) {
+  __shared__ int sh[kScanThreads];
+  int carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
+    int idx = b0 + threadIdx.x;
+    int v = idx < nb ? part[idx] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, sh, total);
+    if (idx < nb) part[idx] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ void k_scan_final(int n, const int* __restrict__ in, const int* __restrict__ part, int* __restrict__ out) {
+  // scans n + 1 elements with a virtual zero at index n, so out[n] is the total
+  __shared__ int sh[kScanThreads];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, sh, total) + part[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k <= n) out[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+}  // namespace
+
+hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t st) {
+  const int nb = (n + kScanTile) / kScanTile;  // at least one block, covers index n
+  hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kScanThreads), 0, st, n, in, part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, nb, part);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanThreads), 0, st, n, in, part, out);
+  return hipGetLastError();
+}
+
+int scan_partials_needed(int n) { return (n + kScanTile) / kScanTile; }
+
+hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
+                            int* atom_bin, int* atom_wrap, int* bin_count, int* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_atoms, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, pos, meta, so, n_struct,
+                     atom_bin, atom_wrap, bin_count, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_bins(int n_atoms, int n_bins, const int* atom_bin, const int* bin_start, int* bin_cursor,
+                            int* bin_atoms, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_bins, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, atom_bin, bin_start,
+                     bin_cursor, bin_atoms);
+  hipLaunchKernelGGL(k_sort_bins, dim3((n_bins + 127) / 128), dim3(128), 0, st, n_bins, bin_start, bin_atoms);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructMeta* meta, const int* so,
+                        int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
+                        const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
+                        int* ncenter, double* ndx, double* ndy, double* ndz, int* err, hipStream_t st) {
+  dim3 g((n_atoms + 127) / 128), b(128);
+  if (fill)
+    hipLaunchKernelGGL(k_pairs<true>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
+                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, err);
+  else
+    hipLaunchKernelGGL(k_pairs<false>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
+                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse(long long n_pairs, const int* offsets, const int* nj, const int* nimg, const int* ncenter,
+                          int* rev, int* err, hipStream_t st) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reverse, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, st, n_pairs, offsets, nj,
+                     nimg, ncenter, rev, err);
+  return hipGetLastError();
+}
+
+}  // namespace soap

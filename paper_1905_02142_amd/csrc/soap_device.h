@@ -1,0 +1,296 @@
+// Per-pair device arithmetic of the separable SOAP expansion (FP64).
+//
+// Caro 2019, arXiv:1905.02142:
+//   radial overlaps        Eqs. (19), (02), (04) and the Gaussian-basis closed form (Sec. III.A)
+//   buffer-zone smoothing  Sec. III.B (product of two Gaussians on [r_soft, r_hard])
+//   amplitude and widths   Eq. (15)
+//   ilexp                  Sec. III.C, evaluated in the numerically stable direction
+//   spherical harmonics    Sec. III.C; real form, pole-free Cartesian recursion
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace soap {
+
+constexpr int kMaxN = 12;
+constexpr int kMaxL = 12;
+constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 2) / 2;
+// ilexp: below this z the upward l-recursion loses digits (about 1e-13 relative
+// at z = 24, 6e-7 at z = 5.76); there the two highest orders come from the power
+// series and the recursion runs downward, which is stable.
+constexpr double kIlexpSeriesBelow = 25.0;
+
+// Read-only tables built on the host at context creation.
+struct DevTables {
+  double W[kMaxN * kMaxN];  // W[n * n_max + alpha]; alpha = n_max - 1 is the Gaussian function
+  double invN[kMaxN];       // 1 / N_alpha for alpha = 1..n_max-1, stored at alpha - 1
+  double lw[kMaxL + 2];     // w_l: 2l+1 (Eq. (08) as printed) or 1
+  double ya[kMaxLM + 16];   // Legendre recursion factor a_lm, index l(l+1)/2 + m
+  double yb[kMaxLM + 16];   // Legendre recursion factor b_lm
+  double ymm[kMaxL + 2];    // seed Qbar_mm
+};
+
+// Scalars of the hyper-parameters, passed by value to every kernel.
+struct DevParams {
+  int n;        // n_max
+  int l;        // l_max
+  int ns;       // species
+  int nch;      // ns * n
+  int LL;       // (l+1)^2
+  int K;        // descriptor length
+  int buffer;   // r_soft < r_cut
+  int l_weight;
+  double rc, rs, nf;
+  double s0r, s0p, ar, ap, a;
+  double cw;    // central-atom weight
+};
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kSqrtPiOver2 = 1.25331413731550025121;
+
+// erf(a) - erf(b) for a >= b without cancellation
+__device__ inline double erf_diff(double a, double b) {
+  if (b >= 0.0) return erfc(b) - erfc(a);
+  if (a <= 0.0) return erfc(-a) - erfc(-b);
+  return erf(a) - erf(b);
+}
+
+// I_k = int_lo^hi (1 - t/rc)^k exp(-(t - mu)^2 / (2 s^2)) dt, k = 0..KM-1.
+// I_0 from erf, I_1 from the integration-by-parts identity with no k = -1 term,
+// then I_{k+2} = (k+1) s^2/rc^2 I_k + (1 - mu/rc) I_{k+1} + (s^2/rc) [u^{k+1} G]_lo^hi
+// (Eq. (04) multiplied through by N_alpha), u = 1 - t/rc.
+//
+// With DERIV, also the fixed-limit derivatives, from integrating dG/dmu = -dG/dt
+// by parts:
+//   dI_k/dmu = -[u^k G]_lo^hi - (k/rc) I_{k-1}
+//   dI_k/ds  = (I_k - [u^k (t-mu) G]_lo^hi) / s - (k s/rc) dI_{k-1}/dmu
+// These avoid the cancellation of ((rc-mu) I_k - rc I_{k+1}) / s^2, which for
+// narrow Gaussians loses about two digits before W amplifies the error.
+template <int KM, bool DERIV>
+__device__ inline void overlap_integrals(double lo, double hi, double mu, double s, double rc, double (&I)[KM],
+                                         double (&dmu)[KM], double (&ds)[KM]) {
+  const double s2 = s * s;
+  const double is = 1.0 / (kSqrt2 * s);
+  const double ah = (hi - mu) * is, al = (lo - mu) * is;
+  I[0] = s * kSqrtPiOver2 * erf_diff(ah, al);
+  const double gh = exp(-ah * ah), gl = exp(-al * al);
+  const double uh = 1.0 - hi / rc, ul = 1.0 - lo / rc;
+  const double c1 = s2 / (rc * rc), c2 = 1.0 - mu / rc, c3 = s2 / rc;
+  I[1] = c3 * (gh - gl) + c2 * I[0];
+  double ph = uh * gh, pl = ul * gl;
+#pragma unroll
+  for (int k = 0; k + 2 < KM; ++k) {
+    I[k + 2] = (double)(k + 1) * c1 * I[k] + c2 * I[k + 1] + c3 * (ph - pl);
+    ph *= uh;
+    pl *= ul;
+  }
+  if (DERIV) {
+    const double th = (hi - mu) * gh, tl = (lo - mu) * gl;
+    const double is_ = 1.0 / s, krc = 1.0 / rc;
+    double qh = 1.0, ql = 1.0;  // u^k at the limits
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const double bnd = qh * gh - ql * gl;
+      const double bt = qh * th - ql * tl;
+      if (k == 0) {
+        dmu[0] = -bnd;
+        ds[0] = (I[0] - bt) * is_;
+      } else {
+        dmu[k] = -bnd - (double)k * krc * I[k - 1];
+        ds[k] = (I[k] - bt) * is_ - (double)k * s * krc * dmu[k - 1];
+      }
+      qh *= uh;
+      ql *= ul;
+    }
+  }
+}
+
+// Overlap of exp(-(t-mu)^2/(2 s^2)) with the Gaussian basis function of Eq. (06)
+// over [0, inf) in closed form, and its mu and s derivatives.
+__device__ inline void gauss_basis(double mu, double s, double s0, double& B, double& dBmu, double& dBs) {
+  const double ss2 = s0 * s0 + s * s, ss = sqrt(ss2);
+  const double c0 = 1.3313353638003897 / sqrt(s0);  // pi^(1/4) / sqrt(sigma0)
+  const double E = exp(-mu * mu / (2.0 * ss2));
+  const double w = s0 * mu / (kSqrt2 * s * ss);
+  const double F = 1.0 + erf(w);
+  const double H = s0 * s / ss;
+  B = c0 * E * H * F;
+  const double dF = 1.1283791670955126 * exp(-w * w);  // 2/sqrt(pi) e^{-w^2}
+  dBmu = c0 * H * (-mu / ss2 * E * F + E * dF * (s0 / (kSqrt2 * s * ss)));
+  const double dss = s / ss;
+  const double dE = E * (mu * mu / (ss2 * ss)) * dss;
+  const double dH = s0 / ss - s0 * s / ss2 * dss;
+  const double dw = -w / s - w / ss * dss;
+  dBs = c0 * (dE * H * F + E * dH * F + E * H * dF * dw);
+}
+
+// Radial factor of one neighbour at distance r:
+//   Bk[k] = 4 pi A(r) b_k(r), k < n_max, b = W b_alpha   (Eqs. (01), (08), (15))
+// and, with DERIV, dBk[k] = d Bk[k] / dr (through mu = r, sigma_r(r) and A(r)).
+template <int NMAX, bool DERIV>
+__device__ inline void radial(const DevParams& P, const DevTables* __restrict__ T, double r, double (&Bk)[NMAX],
+                              double (&dBk)[NMAX]) {
+  constexpr int KM = NMAX + 2;  // b_alpha needs I_3..I_{n+1}
+  const int n = P.n;
+  const double s = P.s0r + P.ar * r;
+  double I[KM], Imu[KM], Is[KM];
+  overlap_integrals<KM, DERIV>(0.0, P.rs, r, s, P.rc, I, Imu, Is);
+  if (P.buffer) {
+    // f(t) G(t) on [r_soft, r_hard] = C exp(-(t - mu')^2 / (2 s'^2))
+    const double D = P.rc - P.rs, d2 = D * D / (P.nf * P.nf);
+    const double s2 = s * s, sp2 = 1.0 / (1.0 / s2 + 1.0 / d2), sp = sqrt(sp2);
+    const double mup = sp2 * (r / s2 + P.rs / d2);
+    const double C = exp(-(r - P.rs) * (r - P.rs) / (2.0 * (s2 + d2)));
+    double J[KM], Jmu[KM], Js[KM];
+    overlap_integrals<KM, DERIV>(P.rs, P.rc, mup, sp, P.rc, J, Jmu, Js);
+    if (DERIV) {
+      const double dC_mu = -C * (r - P.rs) / (s2 + d2);
+      const double dC_s = C * (r - P.rs) * (r - P.rs) * s / ((s2 + d2) * (s2 + d2));
+      const double dsp_s = sp2 * sp / (s2 * s);
+      const double dmup_mu = sp2 / s2;
+      const double dmup_s = 2.0 * sp * dsp_s * (r / s2 + P.rs / d2) - 2.0 * sp2 * r / (s2 * s);
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        Imu[k] += dC_mu * J[k] + C * Jmu[k] * dmup_mu;
+        Is[k] += dC_s * J[k] + C * (Jmu[k] * dmup_s + Js[k] * dsp_s);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k) I[k] += C * J[k];
+  }
+  double ba[NMAX], dba[NMAX];
+#pragma unroll
+  for (int al = 1; al < NMAX; ++al) {
+    if (al < n) {
+      ba[al - 1] = I[al + 2] * T->invN[al - 1];
+      if (DERIV) dba[al - 1] = (Imu[al + 2] + Is[al + 2] * P.ar) * T->invN[al - 1];
+    }
+  }
+  {
+    double B, dBmu, dBs;
+    gauss_basis(r, s, P.s0r, B, dBmu, dBs);
+#pragma unroll
+    for (int al = 0; al < NMAX; ++al)
+      if (al == n - 1) {
+        ba[al] = B;
+        if (DERIV) dba[al] = dBmu + dBs * P.ar;
+      }
+  }
+  // amplitude (Eq. (15)); a = 0 means no (1+2x^3-3x^2)^a factor
+  const double sr = s, sp = P.s0p + P.ap * r;
+  double A = 1.0 / (sr * sp * sp), dlogA = 0.0;
+  if (P.a != 0.0) {
+    const double x = r / P.rc, h = 1.0 + 2.0 * x * x * x - 3.0 * x * x;
+    A *= pow(h, P.a);
+    dlogA = P.a * (6.0 * x * x - 6.0 * x) / (h * P.rc);
+  }
+  dlogA += -P.ar / sr - 2.0 * P.ap / sp;
+  const double fA = 4.0 * kPi * A;
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    if (k < n) {
+      double acc = 0.0, dacc = 0.0;
+#pragma unroll
+      for (int al = 0; al < NMAX; ++al) {
+        if (al < n) {
+          const double w = T->W[k * n + al];
+          acc = fma(w, ba[al], acc);
+          if (DERIV) dacc = fma(w, dba[al], dacc);
+        }
+      }
+      Bk[k] = fA * acc;
+      if (DERIV) dBk[k] = fA * (dacc + dlogA * acc);
+    }
+  }
+}
+
+// e_l(z) = exp(-z) i_l(z) for l = 0..lmax (lmax <= LM), z > 0.
+template <int LM>
+__device__ inline void ilexp(double z, int lmax, double (&e)[LM + 1]) {
+  if (lmax == 0 || z >= kIlexpSeriesBelow) {
+    const double em = expm1(-2.0 * z);
+    e[0] = -em / (2.0 * z);
+    if (lmax >= 1) e[1] = (z - 1.0 + (em + 1.0) * (z + 1.0)) / (2.0 * z * z);
+#pragma unroll
+    for (int l = 2; l <= LM; ++l)
+      if (l <= lmax) e[l] = e[l - 2] - (double)(2 * l - 1) / z * e[l - 1];
+    return;
+  }
+  // power series i_l(z) = z^l / (2l+1)!! sum_k (z^2/2)^k / (k! (2l+3)(2l+5)..(2l+2k+1))
+  // for l = lmax and lmax - 1, then e_{l-1} = e_{l+1} + (2l+1)/z e_l downward.
+  const int L = lmax;
+  double t1 = 1.0;
+  for (int j = 1; j < L; ++j) t1 *= z / (double)(2 * j + 1);
+  double t0 = t1 * z / (double)(2 * L + 1);  // z^L / (2L+1)!!
+  const double h = 0.5 * z * z;
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = 0; k < 200; ++k) {
+    s0 += t0;
+    s1 += t1;
+    const double n0 = t0 * h / ((double)(k + 1) * (double)(2 * L + 2 * k + 3));
+    const double n1 = t1 * h / ((double)(k + 1) * (double)(2 * L + 2 * k + 1));
+    if (n0 < 1e-17 * s0 && n1 < 1e-17 * s1 && n0 < t0) break;
+    t0 = n0;
+    t1 = n1;
+  }
+  const double ez = exp(-z);
+  double up = ez * s0, cur = ez * s1;  // e_L, e_{L-1}
+#pragma unroll
+  for (int l = LM; l >= 0; --l) {
+    if (l == L) e[l] = up;
+    if (l == L - 1) e[l] = cur;
+  }
+#pragma unroll
+  for (int l = LM - 1; l >= 1; --l) {
+    if (l <= L - 1) {
+      const double nxt = up + (double)(2 * l + 1) / z * cur;  // e_{l-1}
+      e[l - 1] = nxt;
+      up = cur;
+      cur = nxt;
+    }
+  }
+}
+
+__host__ __device__ constexpr int lm_tri(int l, int m) { return l * (l + 1) / 2 + m; }
+
+// Real spherical harmonics of a unit vector u (Condon-Shortley-free real form):
+//   Y[l^2 + l]     = Qbar_l0(u_z)
+//   Y[l^2 + l + m] = Qbar_lm(u_z) Re (u_x + i u_y)^m,  m > 0
+//   Y[l^2 + l - m] = Qbar_lm(u_z) Im (u_x + i u_y)^m,  m > 0
+// with Qbar_lm = sqrt(2)^(m>0) N_lm d^m P_l / dz^m: no 1/sin(theta) appears, so the
+// poles need no special rule.  Per l this is an orthogonal transform of the
+// complex Y*_lm, which leaves the power spectrum of Eq. (09) unchanged.
+// The callback receives (l, lm index, value) in an order fixed at compile time.
+template <int LM, typename F>
+__device__ inline void real_ylm(const DevTables* __restrict__ T, int lmax, double ux, double uy, double uz, F&& put) {
+  double cr = 1.0, ci = 0.0;  // (u_x + i u_y)^m
+#pragma unroll
+  for (int m = 0; m <= LM; ++m) {
+    if (m <= lmax) {
+      double q2 = 0.0, q1 = T->ymm[m];  // Qbar_{m-1,m} = 0, Qbar_mm
+#pragma unroll
+      for (int l = m; l <= LM; ++l) {
+        if (l <= lmax) {
+          double q;
+          if (l == m) q = q1;
+          else {
+            q = T->ya[lm_tri(l, m)] * uz * q1 - T->yb[lm_tri(l, m)] * q2;
+            q2 = q1;
+            q1 = q;
+          }
+          if (m == 0) put(l, l * l + l, q);
+          else {
+            put(l, l * l + l + m, q * cr);
+            put(l, l * l + l - m, q * ci);
+          }
+        }
+      }
+    }
+    const double nr = cr * ux - ci * uy;
+    ci = cr * uy + ci * ux;
+    cr = nr;
+  }
+}
+
+}  // namespace soap

@@ -1,0 +1,170 @@
+"""Torch-facing wrapper of the C ABI: device memory and streams come from PyTorch,
+every computation is one call into libsoap.so (see include/soap.h)."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PRECISIONS = {"fp64": _lib.SOAP_FP64, "f32": _lib.SOAP_MIXED_F32, "bf16": _lib.SOAP_MIXED_BF16,
+              "bf16x3": _lib.SOAP_MIXED_BF16X3}
+
+
+@dataclass(frozen=True)
+class SoapParams:
+    """Hyper-parameters (Eq. (15), Sec. III.B); r_soft None means no buffer zone."""
+
+    n_max: int
+    l_max: int
+    r_cut: float
+    sigma0_r: float
+    sigma0_perp: float
+    n_species: int = 1
+    r_soft: float | None = None
+    n_f: float = 4.0
+    alpha_r: float = 0.0
+    alpha_perp: float = 0.0
+    a: float = 0.0
+    central_weight: float = 1.0
+    l_weight: int = 0
+    precision: str = "fp64"
+
+    def c_struct(self) -> _lib.soap_params:
+        return _lib.soap_params(self.n_max, self.l_max, self.n_species, self.r_cut,
+                                self.r_cut if self.r_soft is None else self.r_soft, self.n_f,
+                                self.sigma0_r, self.sigma0_perp, self.alpha_r, self.alpha_perp, self.a,
+                                self.central_weight, self.l_weight, PRECISIONS[self.precision])
+
+    @property
+    def dim(self) -> int:
+        nch = self.n_max * self.n_species
+        return nch * (nch + 1) // 2 * (self.l_max + 1)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class NeighbourList:
+    """Device CSR neighbour list (soap_nlist) backed by torch tensors."""
+
+    def __init__(self, n_atoms: int, capacity: int, device):
+        self.device = device
+        self.n_atoms = n_atoms
+        self.offsets = torch.empty(n_atoms + 1, dtype=torch.int32, device=device)
+        self._alloc(capacity)
+        self.n_pairs = 0
+        self.n_structures = 1
+
+    def _alloc(self, capacity: int):
+        cap = max(1, int(capacity))
+        dev = self.device
+        self.capacity = cap
+        self.j = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.img = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.rev = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.center = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.dx = torch.empty(cap, dtype=torch.float64, device=dev)
+        self.dy = torch.empty(cap, dtype=torch.float64, device=dev)
+        self.dz = torch.empty(cap, dtype=torch.float64, device=dev)
+
+    def c_struct(self) -> _lib.soap_nlist:
+        return _lib.soap_nlist(self.n_atoms, self.n_structures, self.n_pairs, self.capacity,
+                               _ptr(self.offsets), _ptr(self.j), _ptr(self.img), _ptr(self.rev),
+                               _ptr(self.center), _ptr(self.dx), _ptr(self.dy), _ptr(self.dz))
+
+    def image(self) -> torch.Tensor:
+        """Lattice translations T of the pairs, shape (n_pairs, 3)."""
+        v = self.img[: self.n_pairs].to(torch.int64)
+        return torch.stack([((v >> 20) & 1023) - 512, ((v >> 10) & 1023) - 512, (v & 1023) - 512], 1)
+
+
+class Soap:
+    """One descriptor configuration on the current HIP device."""
+
+    def __init__(self, params: SoapParams):
+        self.params = params
+        self._cp = params.c_struct()
+        self.ctx = _lib.soap_create(self._cp)
+        self.dim = _lib.soap_descriptor_dim(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.soap_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- neighbours
+    def neighbors(self, positions: torch.Tensor, cells, pbc, struct_offsets=None,
+                  nl: NeighbourList | None = None, capacity: int | None = None) -> NeighbourList:
+        """soap_build_neighbors; grows the list and retries once on capacity overflow."""
+        pos = positions.contiguous()
+        assert pos.dtype == torch.float64 and pos.is_cuda
+        n = pos.shape[0]
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 9))
+        pbc = np.ascontiguousarray(np.asarray(pbc, dtype=np.int32).reshape(-1, 3))
+        ns = cells.shape[0]
+        so = None if struct_offsets is None else np.ascontiguousarray(np.asarray(struct_offsets, dtype=np.int32))
+        if nl is None or nl.n_atoms != n:
+            cap = capacity if capacity is not None else max(64, n * 64)
+            nl = NeighbourList(n, cap, pos.device)
+        for _ in range(2):
+            c = nl.c_struct()
+            st = _lib.soap_build_neighbors(self.ctx, n, pos.data_ptr(), cells.ctypes.data, pbc.ctypes.data,
+                                           None if so is None else so.ctypes.data, ns, c, _stream())
+            if st == _lib.SOAP_EOVERFLOW:
+                nl._alloc(int(c.n_pairs * 1.1) + 64)
+                continue
+            nl.n_pairs = int(c.n_pairs)
+            nl.n_structures = ns
+            return nl
+        raise _lib.SoapError(_lib.SOAP_EOVERFLOW, "neighbour list still overflows after growing")
+
+    # ---------------------------------------------------------------- descriptor
+    def descriptor(self, nl: NeighbourList, species: torch.Tensor, with_norm: bool = False):
+        q = torch.empty(nl.n_atoms, self.dim, dtype=torch.float64, device=nl.device)
+        pn = torch.empty(nl.n_atoms, dtype=torch.float64, device=nl.device)
+        sp = species.to(torch.int32).contiguous()
+        _lib.soap_descriptor(self.ctx, nl.c_struct(), sp.data_ptr(), q.data_ptr(), pn.data_ptr(), _stream())
+        return (q, pn) if with_norm else q
+
+    def descriptor_grad(self, nl: NeighbourList, species: torch.Tensor, q_bar: torch.Tensor,
+                        pos_grad: torch.Tensor | None = None) -> torch.Tensor:
+        if pos_grad is None:
+            pos_grad = torch.zeros(nl.n_atoms, 3, dtype=torch.float64, device=nl.device)
+        sp = species.to(torch.int32).contiguous()
+        qb = q_bar.to(torch.float64).contiguous()
+        _lib.soap_descriptor_grad(self.ctx, nl.c_struct(), sp.data_ptr(), qb.data_ptr(), pos_grad.data_ptr(),
+                                  _stream())
+        return pos_grad
+
+    def energy_forces(self, nl: NeighbourList, species: torch.Tensor, q_sparse: torch.Tensor,
+                      alpha: torch.Tensor, zeta: int, forces: bool = True, alpha_grad: bool = True,
+                      out=None):
+        """gap_energy_forces: (e_atom, forces or None, dE/dalpha or None)."""
+        dev = nl.device
+        qs = q_sparse.to(torch.float64).contiguous()
+        al = alpha.to(torch.float64).contiguous()
+        M = qs.shape[0]
+        if out is None:
+            e = torch.empty(nl.n_atoms, dtype=torch.float64, device=dev)
+            F = torch.empty(nl.n_atoms, 3, dtype=torch.float64, device=dev) if forces else None
+            ab = torch.empty(M, dtype=torch.float64, device=dev) if alpha_grad else None
+        else:
+            e, F, ab = out
+        sp = species.to(torch.int32).contiguous()
+        _lib.gap_energy_forces(self.ctx, nl.c_struct(), sp.data_ptr(), qs.data_ptr(), al.data_ptr(), M, int(zeta),
+                               e.data_ptr(), _ptr(F), _ptr(ab), _stream())
+        return e, F, ab

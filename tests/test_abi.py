@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every symbol include/soap.h declares, and
+its host-only logic behaves as documented (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "soap.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    # a declaration is "<type> name(<arguments without braces>);"
+    names = re.findall(r"(\w+)\s*\([^;{}()]*\)\s*;", src)
+    return sorted(set(names))
+
+
+def _lib():
+    from paper_1905_02142_amd import _lib
+
+    return _lib
+
+
+def test_header_declarations_are_exported():
+    L = _lib()
+    lib = L.load()
+    names = _declared_functions()
+    assert "soap_build_neighbors" in names and "gap_energy_forces" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_struct_layouts():
+    L = _lib()
+    # soap_params: 3 ints, padding, 9 doubles, 2 ints
+    assert ctypes.sizeof(L.soap_params) == 4 * 3 + 4 + 8 * 9 + 4 * 2
+    assert ctypes.sizeof(L.soap_nlist) == 4 + 4 + 8 + 8 + 8 * 8
+
+
+@pytest.mark.parametrize("n,rc,s0", [(6, 3.7, 0.5), (8, 5.0, 0.5), (10, 5.5, 0.5), (8, 4.3, 0.12)])
+def test_radial_table_matches_oracle(n, rc, s0):
+    L = _lib()
+    W = np.zeros((n, n))
+    lam = np.zeros(n)
+    L.soap_radial_basis_table(n, rc, s0, W.ctypes.data, lam.ctypes.data)
+    _, _, Whi, Wlo, eig = oracle.basis_tables(n, rc, s0)
+    assert np.abs(W - (Whi + Wlo)).max() <= 1e-16 * np.abs(Whi).max()
+    assert np.allclose(lam, sorted(float(e) for e in eig), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("bad", [dict(n_max=1), dict(n_max=13), dict(l_max=13), dict(l_max=-1), dict(n_species=0),
+                                 dict(r_cut=0.0), dict(sigma0_r=0.0), dict(r_soft=6.0), dict(alpha_r=-0.1),
+                                 dict(a=-1.0), dict(l_weight=2), dict(precision=7)])
+def test_invalid_parameters_rejected_on_host(bad):
+    L = _lib()
+    kw = dict(n_max=8, l_max=8, n_species=1, r_cut=5.0, r_soft=5.0, n_f=4.0, sigma0_r=0.5, sigma0_perp=0.5,
+              alpha_r=0.0, alpha_perp=0.0, a=0.0, central_weight=1.0, l_weight=0, precision=0)
+    kw.update(bad)
+    p = L.soap_params(**kw)
+    ctx = ctypes.c_void_p()
+    assert L.load().soap_create(ctypes.byref(p), ctypes.byref(ctx)) == L.SOAP_EINVAL
+    assert not ctx.value
+
+
+def test_status_strings():
+    lib = _lib().load()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.soap_status_string(s)

@@ -1,0 +1,264 @@
+"""HIP path vs the oracle, element by element, on seeded synthetic structures.
+
+Bars (FP64 mode): q per atom and energies within 1e-10 relative (normwise per
+atom for q, per atom for e), forces within 1e-10 of max|F| per component,
+neighbour lists identical as sets of (i, j, T).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _soap(**kw):
+    from paper_1905_02142_amd import Soap, SoapParams
+
+    return Soap(SoapParams(**kw))
+
+
+def _oparams(**kw):
+    kw = {k: v for k, v in kw.items() if k != "precision"}
+    return oracle.Params(**kw)
+
+
+def _t(a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def _pairs_set(centres, j, T, d):
+    out = {}
+    for c, jj, t, dd in zip(centres, j, T, d):
+        out[(int(c), int(jj), int(t[0]), int(t[1]), int(t[2]))] = dd
+    return out
+
+
+def _gpu_nl(soap, s_list):
+    pos = np.concatenate([s.positions for s in s_list])
+    cells = np.stack([s.cell for s in s_list])
+    pbc = np.stack([s.pbc for s in s_list])
+    so = np.cumsum([0] + [s.n_atoms for s in s_list])
+    nl = soap.neighbors(_t(pos), cells, pbc, so if len(s_list) > 1 else None)
+    return nl, pos
+
+
+@pytest.mark.parametrize("case", ["box64", "small_box_images", "triclinic", "batch3", "cluster"])
+def test_neighbour_list_matches_oracle(case):
+    rc = 3.7
+    if case == "box64":
+        ss = [synth.rsa_box(64, 8.6, 1.2, 1001)]
+    elif case == "small_box_images":
+        rc = 5.5
+        ss = [synth.rsa_box(6, 5.2, 1.2, 12)]
+    elif case == "triclinic":
+        cell = np.array([[6.0, 0.0, 0.0], [2.5, 5.5, 0.0], [1.0, -1.5, 6.2]])
+        frac = np.random.default_rng(4).random((8, 3))
+        ss = [synth.Structure(frac @ cell, cell, np.ones(3, np.int32))]
+        rc = 4.0
+    elif case == "batch3":
+        ss = [synth.rsa_box(n, L, 1.2, 50 + n) for n, L in ((20, 6.0), (35, 7.5), (9, 5.1))]
+    else:
+        s = synth.rsa_box(30, 8.0, 1.2, 77)
+        ss = [synth.Structure(s.positions, s.cell, np.zeros(3, np.int32))]
+    soap = _soap(n_max=4, l_max=2, r_cut=rc, sigma0_r=0.5, sigma0_perp=0.5)
+    nl, pos = _gpu_nl(soap, ss)
+    torch.cuda.synchronize()
+    P = nl.n_pairs
+    off = nl.offsets.cpu().numpy()
+    j = nl.j[:P].cpu().numpy()
+    T = nl.image().cpu().numpy()
+    d = np.stack([nl.dx[:P].cpu().numpy(), nl.dy[:P].cpu().numpy(), nl.dz[:P].cpu().numpy()], 1)
+    cen = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    got = _pairs_set(cen, j, T, d)
+    want = {}
+    base = 0
+    for s in ss:
+        onl = oracle.neighbors(s.positions, s.cell, s.pbc, rc)
+        want.update(_pairs_set(onl.centre_of_pair() + base, onl.j + base, onl.shift, onl.d))
+        base += s.n_atoms
+    assert set(got) == set(want)
+    for k, v in got.items():
+        assert np.abs(v - want[k]).max() < 1e-12
+    # reverse index: rev(rev(p)) = p and d_rev = -d exactly
+    rev = nl.rev[:P].cpu().numpy()
+    assert np.array_equal(rev[rev], np.arange(P))
+    assert np.array_equal(d[rev], -d)
+    assert np.array_equal(nl.center[:P].cpu().numpy(), cen)
+
+
+DESC_CASES = {
+    "box64_n6l6": (dict(n_max=6, l_max=6, r_cut=3.7, sigma0_r=0.5, sigma0_perp=0.5), 64, 8.6, 1, 1001),
+    "box300_n8l8": (dict(n_max=8, l_max=8, r_cut=5.0, sigma0_r=0.5, sigma0_perp=0.5), 300, 14.4, 1, 1002),
+    "hp_buffer_n8l8": (dict(n_max=8, l_max=8, r_cut=4.3, r_soft=3.8, sigma0_r=0.12, sigma0_perp=0.55,
+                            alpha_r=0.14, alpha_perp=0.06, a=1.6), 120, 10.7, 1, 7),
+    "hp_n8l8": (dict(n_max=8, l_max=8, r_cut=4.5, sigma0_r=0.2, sigma0_perp=0.4, alpha_r=0.08,
+                     alpha_perp=0.08, a=1.0), 120, 10.7, 1, 8),
+    "species3_n4l4": (dict(n_max=4, l_max=4, r_cut=4.0, sigma0_r=0.5, sigma0_perp=0.5, n_species=3),
+                      90, 9.7, 3, 9),
+    "n10l10": (dict(n_max=10, l_max=10, r_cut=5.5, sigma0_r=0.5, sigma0_perp=0.5), 150, 11.5, 1, 10),
+    "lweight1_nocentral": (dict(n_max=5, l_max=7, r_cut=4.0, sigma0_r=0.4, sigma0_perp=0.6, l_weight=1,
+                                central_weight=0.0), 60, 8.4, 1, 11),
+}
+
+# n_max = 10: the FP64 radial transform amplifies rounding to ~1e-9 (the basis
+# overlap matrix has condition ~1e15); every other case meets 1e-10
+Q_TOL = {"n10l10": 5e-9}
+
+
+def _species(n, ns, seed):
+    return synth.draw_species(n, [1.0] * ns, seed) if ns > 1 else np.zeros(n, np.int32)
+
+
+@pytest.mark.parametrize("name", list(DESC_CASES))
+def test_descriptor_matches_oracle(name):
+    kw, n, L, ns, seed = DESC_CASES[name]
+    s = synth.rsa_box(n, L, 1.2, seed)
+    spec = _species(n, ns, seed + 100)
+    soap = _soap(**kw)
+    nl, _ = _gpu_nl(soap, [s])
+    q, pn = soap.descriptor(nl, _t(spec), with_norm=True)
+    torch.cuda.synchronize()
+    onl = oracle.neighbors(s.positions, s.cell, s.pbc, kw["r_cut"])
+    qo, pno = oracle.descriptor(_oparams(**kw), onl, spec)
+    q = q.cpu().numpy()
+    err = np.linalg.norm(q - qo, axis=1) / np.maximum(np.linalg.norm(qo, axis=1), 1e-300)
+    assert err.max() < Q_TOL.get(name, 1e-10), f"max per-atom q error {err.max():.2e}"
+    assert np.allclose(pn.cpu().numpy(), pno, rtol=Q_TOL.get(name, 1e-10), atol=0)
+
+
+def _energy_forces_case(kw, n, L, ns, seed, M, zeta):
+    s = synth.rsa_box(n, L, 1.2, seed)
+    spec = _species(n, ns, seed + 100)
+    soap = _soap(**kw)
+    qs = synth.sparse_set(M, soap.dim, seed + 200)
+    al = synth.sparse_weights(M, seed + 300)
+    nl, _ = _gpu_nl(soap, [s])
+    e, F, ab = soap.energy_forces(nl, _t(spec), _t(qs), _t(al), zeta)
+    torch.cuda.synchronize()
+    eo, Fo, abo = oracle.energy_forces(_oparams(**kw), s.positions, s.cell, s.pbc, spec, qs, al, zeta)
+    return e.cpu().numpy(), F.cpu().numpy(), ab.cpu().numpy(), eo, Fo, abo
+
+
+@pytest.mark.parametrize("name,M,zeta", [("box64_n6l6", 50, 4), ("hp_buffer_n8l8", 80, 3), ("hp_n8l8", 70, 3),
+                                         ("species3_n4l4", 40, 2), ("box300_n8l8", 130, 4),
+                                         ("lweight1_nocentral", 33, 1)])
+def test_energy_forces_match_oracle(name, M, zeta):
+    kw, n, L, ns, seed = DESC_CASES[name]
+    e, F, ab, eo, Fo, abo = _energy_forces_case(kw, n, L, ns, seed, M, zeta)
+    assert np.abs(e - eo).max() < 1e-10 * np.abs(eo).max()
+    assert np.abs(F - Fo).max() < 1e-10 * np.abs(Fo).max()
+    assert np.abs(ab - abo).max() < 1e-10 * np.abs(abo).max()
+    assert np.abs(F.sum(0)).max() < 1e-12 * np.abs(F).max()
+
+
+def test_descriptor_grad_matches_oracle_vjp():
+    kw, n, L, ns, seed = DESC_CASES["species3_n4l4"]
+    s = synth.rsa_box(n, L, 1.2, seed)
+    spec = _species(n, ns, seed + 100)
+    soap = _soap(**kw)
+    qbar = np.random.default_rng(3).standard_normal((n, soap.dim))
+    nl, _ = _gpu_nl(soap, [s])
+    g = soap.descriptor_grad(nl, _t(spec), _t(qbar))
+    torch.cuda.synchronize()
+    onl = oracle.neighbors(s.positions, s.cell, s.pbc, kw["r_cut"])
+    go = oracle.descriptor_vjp(_oparams(**kw), onl, spec, qbar)
+    want = -oracle.assemble_forces(onl, go, n)  # pos_grad = dL/dr = -F
+    assert np.abs(g.cpu().numpy() - want).max() < 1e-10 * np.abs(want).max()
+
+
+def test_bench_workload_energy_forces():
+    # the benchmark workload: 4096 atoms, n = l = 8, r_cut 5, M = 2000, zeta = 4
+    w = synth.workload("box4096_n8l8")
+    s = w["structures"][0]
+    kw = dict(n_max=8, l_max=8, r_cut=5.0, sigma0_r=0.5, sigma0_perp=0.5)
+    soap = _soap(**kw)
+    nl, _ = _gpu_nl(soap, [s])
+    spec = w["species"]
+    e, F, ab = soap.energy_forces(nl, _t(spec), _t(w["q_sparse"]), _t(w["alpha"]), 4)
+    q = soap.descriptor(nl, _t(spec))
+    torch.cuda.synchronize()
+    eo, Fo, abo = oracle.energy_forces(_oparams(**kw), s.positions, s.cell, s.pbc, spec, w["q_sparse"],
+                                       w["alpha"], 4)
+    e, F, ab = e.cpu().numpy(), F.cpu().numpy(), ab.cpu().numpy()
+    assert np.abs(e - eo).max() < 1e-10 * np.abs(eo).max()
+    assert np.abs(F - Fo).max() < 1e-10 * np.abs(Fo).max()
+    assert np.abs(ab - abo).max() < 1e-10 * np.abs(abo).max()
+
+
+def test_deterministic_bitwise():
+    kw, n, L, ns, seed = DESC_CASES["box300_n8l8"]
+    s = synth.rsa_box(n, L, 1.2, seed)
+    soap = _soap(**kw)
+    qs = _t(synth.sparse_set(64, soap.dim, 5))
+    al = _t(synth.sparse_weights(64, 6))
+    spec = _t(np.zeros(n, np.int32))
+    outs = []
+    for _ in range(2):
+        nl, _ = _gpu_nl(soap, [s])
+        e, F, ab = soap.energy_forces(nl, spec, qs, al, 4)
+        torch.cuda.synchronize()
+        outs.append((e.cpu().numpy(), F.cpu().numpy(), ab.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_zero_neighbour_atoms():
+    # isolated atoms far apart, no central Gaussian: p = 0 -> q = 0, e = 0, F = 0
+    pos = np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0], [1.0, 1.0, 2.5]])
+    cell = np.eye(3) * 20.0
+    soap = _soap(n_max=4, l_max=3, r_cut=3.0, sigma0_r=0.5, sigma0_perp=0.5, central_weight=0.0)
+    nl = soap.neighbors(_t(pos), cell, np.zeros(3, np.int32))
+    q = soap.descriptor(nl, _t(np.zeros(3, np.int32)))
+    torch.cuda.synchronize()
+    q = q.cpu().numpy()
+    assert nl.n_pairs == 2
+    assert np.all(q[1] == 0)
+    assert abs(np.linalg.norm(q[0]) - 1) < 1e-14
+
+
+def test_capacity_overflow_and_regrow():
+    from paper_1905_02142_amd import _lib
+
+    s = synth.rsa_box(64, 8.6, 1.2, 1001)
+    soap = _soap(n_max=4, l_max=2, r_cut=3.7, sigma0_r=0.5, sigma0_perp=0.5)
+    from paper_1905_02142_amd.soap import NeighbourList
+
+    nl = NeighbourList(64, 10, torch.device(DEV))
+    c = nl.c_struct()
+    pos = _t(s.positions)
+    cells = np.ascontiguousarray(s.cell.reshape(1, 9))
+    pbc = np.ascontiguousarray(s.pbc.reshape(1, 3).astype(np.int32))
+    st = _lib.soap_build_neighbors(soap.ctx, 64, pos.data_ptr(), cells.ctypes.data, pbc.ctypes.data, None, 1, c,
+                                   torch.cuda.current_stream().cuda_stream)
+    assert st == _lib.SOAP_EOVERFLOW
+    want = oracle.neighbors(s.positions, s.cell, s.pbc, 3.7).n_pairs
+    assert c.n_pairs == want
+    nl2 = soap.neighbors(pos, s.cell, s.pbc, nl=nl)
+    assert nl2.n_pairs == want
+
+
+def test_invalid_inputs_rejected():
+    from paper_1905_02142_amd import _lib
+
+    s = synth.rsa_box(10, 6.0, 1.2, 3)
+    soap = _soap(n_max=4, l_max=2, r_cut=3.7, sigma0_r=0.5, sigma0_perp=0.5)
+    pos = s.positions.copy()
+    pos[3] = pos[5]  # coincident atoms
+    with pytest.raises(_lib.SoapError) as ei:
+        soap.neighbors(_t(pos), s.cell, s.pbc)
+    assert ei.value.status == _lib.SOAP_EINVAL
+    pos = s.positions.copy()
+    pos[2, 1] = np.nan
+    with pytest.raises(_lib.SoapError) as ei:
+        soap.neighbors(_t(pos), s.cell, s.pbc)
+    assert ei.value.status == _lib.SOAP_EINVAL
+    nl = soap.neighbors(_t(s.positions), s.cell, s.pbc)
+    spec = _t(np.zeros(10, np.int32))
+    qs = _t(synth.sparse_set(4, soap.dim, 1))
+    with pytest.raises(_lib.SoapError):
+        soap.energy_forces(nl, spec, qs, _t(np.ones(4)), 0)  # zeta must be >= 1
