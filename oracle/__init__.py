@@ -125,6 +125,7 @@ def _lib(precision: str = "ld"):
     lib.or_amplitude.argtypes = [P(_Params), d, vp]
     lib.or_amplitude.restype = d
     lib.or_descriptor_dim.argtypes = [P(_Params)]
+    lib.or_num_threads.restype = i
     return lib
 
 
@@ -377,6 +378,11 @@ def gauss_basis_overlap(mu, s, sigma0):
     out = np.zeros(3)
     _lib().or_gauss_basis_overlap(mu, s, sigma0, _ptr(out))
     return out
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_lib().or_num_threads())
 
 
 def amplitude(p: Params, r):

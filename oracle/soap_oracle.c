@@ -32,6 +32,7 @@
  *   forces: the exact derivative of the above, by the chain rule, per pair.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -657,3 +658,14 @@ double or_amplitude(const or_params* P, double r, double* dA) {
 }
 
 int or_real_bits(void) { return (int)(sizeof(R) == sizeof(double) ? 53 : 64); }
+
+/* threads an OpenMP parallel region of this library uses */
+int or_num_threads(void) {
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
+}

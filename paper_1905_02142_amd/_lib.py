@@ -17,8 +17,9 @@ SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3 = 0, 1, 2, 3
 EXPORTED = (
     "soap_create", "soap_destroy", "soap_descriptor_dim", "soap_status_string", "soap_last_error",
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
-    "soap_radial_basis_table", "soap_workspace_bytes",
+    "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
 )
+STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather")
 
 
 class soap_params(ctypes.Structure):
@@ -83,6 +84,12 @@ def load(path: str = LIB_PATH):
     lib.gap_energy_forces.restype = i
     lib.soap_radial_basis_table.argtypes = [i, d, d, vp, vp]
     lib.soap_radial_basis_table.restype = i
+    lib.soap_profile.argtypes = [vp, i]
+    lib.soap_profile.restype = i
+    lib.soap_profile_read.argtypes = [vp, vp, vp]
+    lib.soap_profile_read.restype = i
+    lib.soap_stage_name.argtypes = [i]
+    lib.soap_stage_name.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -148,3 +155,17 @@ def gap_energy_forces(ctx, nl: soap_nlist, species, q_sparse, alpha, M, zeta, e_
 
 def soap_radial_basis_table(n_max: int, r_cut: float, sigma0_r: float, W, lam) -> None:
     check(load().soap_radial_basis_table(n_max, r_cut, sigma0_r, W, lam))
+
+
+def soap_profile(ctx, enable: bool) -> None:
+    check(load().soap_profile(ctx, 1 if enable else 0), ctx)
+
+
+def soap_profile_read(ctx) -> dict:
+    """{stage name: (milliseconds, launches)} accumulated since the last read."""
+    import numpy as np
+
+    ms = np.zeros(len(STAGES))
+    n = np.zeros(len(STAGES), dtype=np.int64)
+    check(load().soap_profile_read(ctx, ms.ctypes.data, n.ctypes.data), ctx)
+    return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(len(STAGES))}

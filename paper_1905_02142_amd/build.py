@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsoap.so")
 ARCH = os.environ.get("SOAP_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["neighbors.hip", "pair_kernels.hip", "gap_fp64.hip", "capi.hip"]
+HIP_SOURCES = ["neighbors.hip", "pair_kernels.hip", "gap_mfma.hip", "capi.hip"]
 HOST_SOURCES = ["tables.cpp"]
 
 HIPCC_FLAGS = [

@@ -38,9 +38,18 @@ struct soap_ctx {
   int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
   size_t pinned_bytes = 0;
   // neighbour build
-  Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, counts, scan_part, errflag;
+  Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_atoms, counts, scan_part,
+      errflag;
   // descriptor / adjoint
   Buf c, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
+  // stage timing
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  std::vector<Rec> prof;
+  std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
@@ -152,12 +161,52 @@ soap_status check_lds(soap_ctx* ctx) {
   return SOAP_OK;
 }
 
+hipEvent_t take_event(soap_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// records hipEvents around one kernel group while profiling is on
+struct StageTimer {
+  soap_ctx* ctx;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(soap_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
+    if (ctx->prof_on) {
+      a = take_event(ctx);
+      if (a && hipEventRecord(a, st) != hipSuccess) {
+        ctx->ev_pool.push_back(a);
+        a = nullptr;
+      }
+    }
+  }
+  ~StageTimer() { stop(); }
+  void stop() {
+    if (!a) return;
+    hipEvent_t b = take_event(ctx);
+    if (b && hipEventRecord(b, st) == hipSuccess) ctx->prof.push_back({stage, a, b});
+    else {
+      ctx->ev_pool.push_back(a);
+      if (b) ctx->ev_pool.push_back(b);
+    }
+    a = nullptr;
+  }
+};
+
 // forward descriptor into the context's buffers (c, q, |p|)
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
                     hipStream_t st) {
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms;
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * P.nch * P.LL);
+  StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
                                         species, (double*)ctx->c.p, q, pnorm, st));
   return SOAP_OK;
@@ -237,10 +286,15 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
 void soap_destroy(soap_ctx* ctx) {
   if (!ctx) return;
   Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
-                 &ctx->bin_cursor, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->c,
+                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->c,
                  &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp};
   for (Buf* b : bufs)
     if (b->p) hipFree(b->p);
+  for (auto& r : ctx->prof) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   if (ctx->dt) hipFree(ctx->dt);
   if (ctx->pinned) hipHostFree(ctx->pinned);
   delete ctx;
@@ -318,6 +372,7 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
   SOAP_ENSURE(ctx, ctx->bin_start, sizeof(int) * (n_bins + 1));
   SOAP_ENSURE(ctx, ctx->bin_cursor, sizeof(int) * n_bins);
   SOAP_ENSURE(ctx, ctx->bin_atoms, sizeof(int) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->bin_unsorted, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->counts, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->scan_part,
               sizeof(int) * (size_t)std::max(soap::scan_partials_needed(n_atoms), soap::scan_partials_needed(n_bins)));
@@ -335,6 +390,7 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
   SOAP_HIP(ctx, hipMemsetAsync(ctx->bin_cursor.p, 0, sizeof(int) * n_bins, st));
   SOAP_HIP(ctx, hipMemsetAsync(ctx->errflag.p, 0, sizeof(int) * 4, st));
   int* err = (int*)ctx->errflag.p;
+  StageTimer tm_count(ctx, SOAP_STAGE_NEIGHBORS, st);
   const soap::StructMeta* dmeta = (const soap::StructMeta*)ctx->meta.p;
   const int* dso = (const int*)ctx->so.p;
   if (n_atoms > 0) {
@@ -344,14 +400,16 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
   SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->bin_count.p, n_bins, (int*)ctx->bin_start.p,
                                      (int*)ctx->scan_part.p, st));
   if (n_atoms > 0) {
-    SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, n_bins, (const int*)ctx->atom_bin.p, (const int*)ctx->bin_start.p,
-                                         (int*)ctx->bin_cursor.p, (int*)ctx->bin_atoms.p, st));
+    SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, (const int*)ctx->atom_bin.p, (const int*)ctx->bin_start.p,
+                                         (int*)ctx->bin_cursor.p, (int*)ctx->bin_unsorted.p, (int*)ctx->bin_atoms.p,
+                                         st));
     SOAP_HIP(ctx, soap::launch_pairs(false, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
                                      (const int*)ctx->bin_atoms.p, (int*)ctx->counts.p, nullptr, 0, nullptr, nullptr,
                                      nullptr, nullptr, nullptr, nullptr, err, st));
   }
   SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->counts.p, n_atoms, nl->offsets, (int*)ctx->scan_part.p, st));
+  tm_count.stop();
   // read back the pair count and the error bits
   int* hb = ctx->pinned;
   SOAP_HIP(ctx, hipMemcpyAsync(hb, nl->offsets + n_atoms, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -373,6 +431,7 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
   }
   if (total > 0 && (!nl->j || !nl->img || !nl->rev || !nl->center || !nl->dx || !nl->dy || !nl->dz))
     return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
+  StageTimer tm_fill(ctx, SOAP_STAGE_NEIGHBORS, st);
   if (n_atoms > 0) {
     SOAP_HIP(ctx, soap::launch_pairs(true, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
@@ -414,10 +473,14 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
   SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, st)) != SOAP_OK) return s;
-  SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                          species, (const double*)ctx->c.p, (const double*)ctx->q.p,
-                                          (const double*)ctx->pnorm.p, q_bar, (double*)ctx->gx.p,
-                                          (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+  {
+    StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
+    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
+                                            species, (const double*)ctx->c.p, (const double*)ctx->q.p,
+                                            (const double*)ctx->pnorm.p, q_bar, (double*)ctx->gx.p,
+                                            (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+  }
+  StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
   SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
                                           (const double*)ctx->gy.p, (const double*)ctx->gz.p, pos_grad, true, st));
   return SOAP_OK;
@@ -433,7 +496,6 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   if (M < 1 || zeta < 1) return fail(ctx, SOAP_EINVAL, "M and zeta must be >= 1");
   if (!q_sparse || !alpha) return fail(ctx, SOAP_EINVAL, "null sparse set or weights");
   if (nl->n_atoms > 0 && (!species || !e_atom)) return fail(ctx, SOAP_EINVAL, "null species or energies");
-  if (ctx->prm.precision != SOAP_FP64) return fail(ctx, SOAP_ENOTSUP, "this precision mode is not built yet");
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
   if (N == 0) {
@@ -448,21 +510,67 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * N * P.K);
     qbar = (double*)ctx->qbar.p;
   }
-  SOAP_ENSURE(ctx, ctx->gapw, sizeof(double) * soap::gap_fp64_workspace_doubles((int)N, M));
-  SOAP_HIP(ctx, soap::launch_gap_fp64((int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta, e_atom, qbar,
-                                      alpha_grad, (double*)ctx->gapw.p, st));
+  const int prec = (int)ctx->prm.precision;
+  SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
+  {
+    StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
+    SOAP_HIP(ctx, soap::launch_gap_scores(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta,
+                                          e_atom, alpha_grad, ctx->gapw.p, st));
+  }
+  if (qbar) {
+    StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
+    SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, ctx->gapw.p, st));
+  }
   if (forces) {
     SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
-    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                            species, (const double*)ctx->c.p, (const double*)ctx->q.p,
-                                            (const double*)ctx->pnorm.p, qbar, (double*)ctx->gx.p,
-                                            (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+    {
+      StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
+      SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
+                                              species, (const double*)ctx->c.p, (const double*)ctx->q.p,
+                                              (const double*)ctx->pnorm.p, qbar, (double*)ctx->gx.p,
+                                              (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+    }
+    StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
                                             (const double*)ctx->gy.p, (const double*)ctx->gz.p, forces, false, st));
   }
   return SOAP_OK;
+}
+
+soap_status soap_profile(soap_ctx* ctx, int enable) {
+  if (!ctx) return SOAP_EINVAL;
+  ctx->prof_on = enable != 0;
+  return SOAP_OK;
+}
+
+soap_status soap_profile_read(soap_ctx* ctx, double* ms, long long* launches) {
+  if (!ctx || !ms || !launches) return SOAP_EINVAL;
+  for (int k = 0; k < SOAP_STAGE_COUNT; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  soap_status res = SOAP_OK;
+  for (auto& r : ctx->prof) {
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      res = fail(ctx, SOAP_EHIP, "event timing failed");
+    } else {
+      ms[r.stage] += t;
+      launches[r.stage] += 1;
+    }
+    ctx->ev_pool.push_back(r.a);
+    ctx->ev_pool.push_back(r.b);
+  }
+  ctx->prof.clear();
+  return res;
+}
+
+const char* soap_stage_name(int stage) {
+  static const char* names[SOAP_STAGE_COUNT] = {"neighbors", "descriptor", "gap_scores",
+                                                "gap_qbar", "pair_adjoint", "force_gather"};
+  return (stage >= 0 && stage < SOAP_STAGE_COUNT) ? names[stage] : "unknown";
 }
 
 soap_status soap_radial_basis_table(int n_max, double r_cut, double sigma0_r, double* W, double* lambda) {

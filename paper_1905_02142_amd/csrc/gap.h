@@ -1,14 +1,18 @@
-// Host interface of the GAP kernel contractions.
+// Host interface of the GAP kernel contractions (MFMA).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace soap {
 
-// FP64: e (N), Qbar (N x K, nullable), alpha_bar (M, nullable); work holds
-// gap_fp64_workspace_doubles(N, M) doubles.
-size_t gap_fp64_workspace_doubles(int N, int M);
-hipError_t launch_gap_fp64(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta,
-                           double* e, double* Qbar, double* alpha_bar, double* work, hipStream_t st);
+// prec: 0 FP64, 1 FP32, 2 BF16, 3 split BF16 (the soap_precision values).
+// The workspace holds the converted, zero-padded operands, G and the per-tile
+// partial sums.
+size_t gap_workspace_bytes(int N, int M, int K, int prec);
+// e (N) and alpha_bar (M, nullable); G stays in work for the qbar pass
+hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
+                             int zeta, double* e, double* alpha_bar, void* work, hipStream_t st);
+// Qbar (N x K) = G Q_s, from the operands the scores pass left in work
+hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, const void* work, hipStream_t st);
 
 }  // namespace soap

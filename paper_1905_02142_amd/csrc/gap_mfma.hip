@@ -1,0 +1,461 @@
+// GAP energy and its adjoint on the matrix cores (Sec. IV.A: e_i = sum_s alpha_s
+// k(i, s) with the dot-product SOAP kernel k = (q_i . q_s)^zeta of Sec. I).
+//
+//   scores:  S = Q Q_s^T  (N x M, contraction over the descriptor length K), then
+//            e_i = sum_s alpha_s S_is^zeta, alpha_bar_s = sum_i S_is^zeta and
+//            G_is = zeta alpha_s S_is^(zeta-1), stored in the operand precision;
+//   qbar:    Qbar = G Q_s (N x K, contraction over the M sparse points).
+//
+// The FP64 inputs are first converted once into zero-padded operand buffers
+// (Q: N x Kp, Q_s: Mp x Kp, Q_s^T: Kp x Mp; both contraction dimensions padded
+// to the K-tile), so the GEMM loop has no tail branches and loads 16 bytes per
+// lane.  Each 256-thread workgroup owns one BM x BN output tile split 2 x 2
+// over its four wavefronts; each K-tile is prefetched into registers while the
+// previous one is multiplied from LDS.  Precision policies:
+//   FP64    v_mfma_f64_16x16x4_f64, FP64 accumulation, 64 x 64 tiles
+//   F32     v_mfma_f32_16x16x4_f32, FP32 accumulation, 64 x 64 tiles
+//   BF16    v_mfma_f32_16x16x32_bf16, FP32 accumulation, 128 x 128 tiles
+//   BF16X3  a = a_hi + a_lo in BF16, a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
+// Row / column sums of the epilogue go to per-tile partial arrays that are
+// added in a fixed order, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "gap.h"
+
+namespace soap {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte move
+
+struct PF64 {
+  using T = double;
+  using Acc = d4;
+  static constexpr int BM = 64, BN = 64, KT = 32;
+  static constexpr bool kSplit = false;
+  static constexpr bool kRowsInterleaved = true;  // D[l/16 + 4r][l%16]
+};
+struct PF32 {
+  using T = float;
+  using Acc = f4;
+  static constexpr int BM = 64, BN = 64, KT = 32;
+  static constexpr bool kSplit = false;
+  static constexpr bool kRowsInterleaved = false;  // D[4(l/16) + r][l%16]
+};
+struct PBF16 {
+  using T = __bf16;
+  using Acc = f4;
+  static constexpr int BM = 128, BN = 128, KT = 32;
+  static constexpr bool kSplit = false;
+  static constexpr bool kRowsInterleaved = false;
+};
+struct PBF16X3 {
+  using T = __bf16;
+  using Acc = f4;
+  static constexpr int BM = 128, BN = 128, KT = 32;
+  static constexpr bool kSplit = true;
+  static constexpr bool kRowsInterleaved = false;
+};
+
+constexpr int kPad = 64;  // contraction dims are padded to a multiple of this (>= every KT)
+
+inline int padded(int x) { return (x + kPad - 1) / kPad * kPad; }
+
+template <typename T>
+__device__ inline T cvt(double x) {
+  return (T)x;
+}
+template <>
+__device__ inline __bf16 cvt<__bf16>(double x) {
+  return (__bf16)(float)x;
+}
+__device__ inline __bf16 cvt_lo(double x, __bf16 hi) { return (__bf16)(float)(x - (double)(float)hi); }
+template <typename T>
+__device__ inline T cvt_lo_any(double x, T hi) {
+  if constexpr (sizeof(T) == 2) return cvt_lo(x, hi);
+  else return (T)0;
+}
+
+// dst (rows_p x cols_p, pitch cols_p) = src (rows x cols) converted, zero padded;
+// transpose: dst[c][r] = src[r][c]
+template <typename T, bool SPLIT, bool TRANSPOSE>
+__global__ void k_convert(int rows, int cols, int rows_p, int cols_p, const double* __restrict__ src,
+                          T* __restrict__ dst, T* __restrict__ dst_lo) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)rows_p * cols_p) return;
+  const int r = (int)(e / cols_p), c = (int)(e % cols_p);
+  double x;
+  if (TRANSPOSE) x = (c < rows && r < cols) ? src[(size_t)c * cols + r] : 0.0;
+  else x = (r < rows && c < cols) ? src[(size_t)r * cols + c] : 0.0;
+  const T h = cvt<T>(x);
+  dst[e] = h;
+  if (SPLIT) dst_lo[e] = cvt_lo_any<T>(x, h);
+}
+
+template <typename P>
+struct Smem {
+  static constexpr int EPV = 16 / sizeof(typename P::T);  // elements per 16-byte vector
+  static constexpr int PITCH = P::KT + EPV;                // row pitch in elements (16-byte multiple)
+  alignas(16) typename P::T a[P::BM * PITCH];
+  alignas(16) typename P::T b[P::BN * PITCH];
+  alignas(16) typename P::T a_lo[P::kSplit ? P::BM * PITCH : 1];
+  alignas(16) typename P::T b_lo[P::kSplit ? P::BN * PITCH : 1];
+};
+
+// Register staging of one K-tile of a (rows x KT) block: 16-byte vectors
+template <typename P, int ROWS>
+struct Stage {
+  static constexpr int EPV = 16 / sizeof(typename P::T);
+  static constexpr int VPR = P::KT / EPV;         // vectors per row
+  static constexpr int NV = ROWS * VPR / 256;     // vectors per thread
+  u4 v[NV];
+  __device__ inline void load(const typename P::T* __restrict__ g, int ld, int row0, int nrows, int k0, int tid) {
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int idx = tid + 256 * t, r = idx / VPR, c = (idx % VPR) * EPV;
+      const int gr = row0 + r;
+      if (gr < nrows) v[t] = *(const u4*)(g + (size_t)gr * ld + k0 + c);
+      else v[t] = u4{0u, 0u, 0u, 0u};
+    }
+  }
+  __device__ inline void store(typename P::T* s, int tid) const {
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int idx = tid + 256 * t, r = idx / VPR, c = (idx % VPR) * EPV;
+      *(u4*)(s + r * Smem<P>::PITCH + c) = v[t];
+    }
+  }
+};
+
+template <typename P>
+struct Frag {
+  static constexpr int TM = P::BM / 32, TN = P::BN / 32;  // 16 x 16 tiles per wave
+};
+
+// acc[x][y] += A(wave rows x) B(wave cols y)^T over the K-tile in LDS
+template <typename P>
+__device__ inline void mma_ktile(const Smem<P>& sm, int wm, int wn, int lane,
+                                 typename P::Acc (&acc)[Frag<P>::TM][Frag<P>::TN]) {
+  constexpr int PITCH = Smem<P>::PITCH, TM = Frag<P>::TM, TN = Frag<P>::TN;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ra = wm * (P::BM / 2), rb = wn * (P::BN / 2);
+  if constexpr (sizeof(typename P::T) >= 4) {
+#pragma unroll
+    for (int ks = 0; ks < P::KT; ks += 4) {
+      typename P::T a[TM], b[TN];
+#pragma unroll
+      for (int x = 0; x < TM; ++x) a[x] = sm.a[(ra + x * 16 + r16) * PITCH + ks + kq];
+#pragma unroll
+      for (int y = 0; y < TN; ++y) b[y] = sm.b[(rb + y * 16 + r16) * PITCH + ks + kq];
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y) {
+          if constexpr (sizeof(typename P::T) == 8)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+          else
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+    }
+  } else {
+    b8 a[TM], b[TN], al[TM], bl[TN];
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      a[x] = *(const b8*)&sm.a[(ra + x * 16 + r16) * PITCH + 8 * kq];
+      if constexpr (P::kSplit) al[x] = *(const b8*)&sm.a_lo[(ra + x * 16 + r16) * PITCH + 8 * kq];
+    }
+#pragma unroll
+    for (int y = 0; y < TN; ++y) {
+      b[y] = *(const b8*)&sm.b[(rb + y * 16 + r16) * PITCH + 8 * kq];
+      if constexpr (P::kSplit) bl[y] = *(const b8*)&sm.b_lo[(rb + y * 16 + r16) * PITCH + 8 * kq];
+    }
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TN; ++y) {
+        if constexpr (P::kSplit) {
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], b[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bl[y], acc[x][y], 0, 0, 0);
+        }
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+      }
+  }
+}
+
+// C tile = A[row0.., :kdim] B[col0.., :kdim]^T into acc; A rows beyond arows and
+// B rows beyond brows read as zero.  kdim is a multiple of KT.
+template <typename P>
+__device__ inline void gemm_tile(Smem<P>& sm, const typename P::T* __restrict__ A, const typename P::T* __restrict__ A_lo,
+                                 int lda, int arows, const typename P::T* __restrict__ B,
+                                 const typename P::T* __restrict__ B_lo, int ldb, int brows, int kdim, int row0,
+                                 int col0, typename P::Acc (&acc)[Frag<P>::TM][Frag<P>::TN]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  Stage<P, P::BM> sa, sal;
+  Stage<P, P::BN> sb, sbl;
+  sa.load(A, lda, row0, arows, 0, tid);
+  sb.load(B, ldb, col0, brows, 0, tid);
+  if constexpr (P::kSplit) {
+    sal.load(A_lo, lda, row0, arows, 0, tid);
+    sbl.load(B_lo, ldb, col0, brows, 0, tid);
+  }
+  for (int k0 = 0; k0 < kdim; k0 += P::KT) {
+    sa.store(sm.a, tid);
+    sb.store(sm.b, tid);
+    if constexpr (P::kSplit) {
+      sal.store(sm.a_lo, tid);
+      sbl.store(sm.b_lo, tid);
+    }
+    __syncthreads();
+    if (k0 + P::KT < kdim) {  // prefetch the next K-tile while this one is multiplied
+      sa.load(A, lda, row0, arows, k0 + P::KT, tid);
+      sb.load(B, ldb, col0, brows, k0 + P::KT, tid);
+      if constexpr (P::kSplit) {
+        sal.load(A_lo, lda, row0, arows, k0 + P::KT, tid);
+        sbl.load(B_lo, ldb, col0, brows, k0 + P::KT, tid);
+      }
+    }
+    mma_ktile<P>(sm, wm, wn, lane, acc);
+    __syncthreads();
+  }
+}
+
+// row of element r of acc[x][.] within the wave's block
+template <typename P>
+__device__ inline int acc_row(int x, int r, int lane) {
+  return x * 16 + (P::kRowsInterleaved ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
+}
+
+__device__ inline double ipow(double x, int e) {
+  double r = 1.0;
+  for (int t = 0; t < e; ++t) r *= x;
+  return r;
+}
+
+// S = Q Q_s^T tile with the zeta epilogue: G (N x Mp) in the operand precision
+// (zero for padding columns), e_part[col_tile][i], ab_part[row_tile][s]
+template <typename P>
+__global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, const typename P::T* __restrict__ Qc,
+                                                const typename P::T* __restrict__ Qc_lo,
+                                                const typename P::T* __restrict__ Qsc,
+                                                const typename P::T* __restrict__ Qsc_lo,
+                                                const double* __restrict__ alpha, int zeta,
+                                                typename P::T* __restrict__ G, typename P::T* __restrict__ G_lo,
+                                                double* __restrict__ e_part, double* __restrict__ ab_part) {
+  using T = typename P::T;
+  constexpr int TM = Frag<P>::TM, TN = Frag<P>::TN;
+  __shared__ Smem<P> sm;
+  __shared__ double rowsum[2][P::BM];
+  __shared__ double colsum[2][P::BN];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  const int i0 = blockIdx.y * P::BM, s0 = blockIdx.x * P::BN;
+  typename P::Acc acc[TM][TN];
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y) acc[x][y] = typename P::Acc{};
+  gemm_tile<P>(sm, Qc, Qc_lo, Kp, N, Qsc, Qsc_lo, Kp, Mp, Kp, i0, s0, acc);
+  double rows[TM][4] = {}, cols[TN] = {};
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wm * (P::BM / 2) + acc_row<P>(x, r, lane);
+        const int gs = s0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
+        if (gi < N && gs < Mp) {
+          double g = 0.0;
+          if (gs < M) {
+            const double sv = (double)acc[x][y][r];
+            const double sz1 = ipow(sv, zeta - 1);
+            const double kv = sz1 * sv;
+            const double al = alpha[gs];
+            g = (double)zeta * al * sz1;
+            rows[x][r] = fma(al, kv, rows[x][r]);
+            cols[y] += kv;
+          }
+          const T gh = cvt<T>(g);
+          G[(size_t)gi * Mp + gs] = gh;
+          if constexpr (P::kSplit) G_lo[(size_t)gi * Mp + gs] = cvt_lo(g, gh);
+        }
+      }
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = rows[x][r];
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+      if ((lane & 15) == 0) rowsum[wn][wm * (P::BM / 2) + acc_row<P>(x, r, lane)] = v;
+    }
+#pragma unroll
+  for (int y = 0; y < TN; ++y) {
+    double v = cols[y];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < 16) colsum[wm][wn * (P::BN / 2) + y * 16 + lane] = v;
+  }
+  __syncthreads();
+  for (int t = tid; t < P::BM + P::BN; t += 256) {
+    if (t < P::BM) {
+      const int gi = i0 + t;
+      if (gi < N) e_part[(size_t)blockIdx.x * N + gi] = rowsum[0][t] + rowsum[1][t];
+    } else {
+      const int c = t - P::BM, gs = s0 + c;
+      if (gs < M) ab_part[(size_t)blockIdx.y * M + gs] = colsum[0][c] + colsum[1][c];
+    }
+  }
+}
+
+// Qbar tile = G (N x Mp) Q_s^T-converted (Kp x Mp)^T, written for descriptor columns < K
+template <typename P>
+__global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, const typename P::T* __restrict__ G,
+                                              const typename P::T* __restrict__ G_lo,
+                                              const typename P::T* __restrict__ QsT,
+                                              const typename P::T* __restrict__ QsT_lo, double* __restrict__ Qbar) {
+  constexpr int TM = Frag<P>::TM, TN = Frag<P>::TN;
+  __shared__ Smem<P> sm;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  const int i0 = blockIdx.y * P::BM, c0 = blockIdx.x * P::BN;
+  typename P::Acc acc[TM][TN];
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y) acc[x][y] = typename P::Acc{};
+  gemm_tile<P>(sm, G, G_lo, Mp, N, QsT, QsT_lo, Mp, Kp, Mp, i0, c0, acc);
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wm * (P::BM / 2) + acc_row<P>(x, r, lane);
+        const int gc = c0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
+        if (gi < N && gc < K) Qbar[(size_t)gi * K + gc] = (double)acc[x][y][r];
+      }
+}
+
+// out[j] = sum_t part[t * n + j], t = 0..nt-1 in order
+__global__ void k_sum_parts(int n, int nt, const double* __restrict__ part, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int t = 0; t < nt; ++t) s += part[(size_t)t * n + j];
+  out[j] = s;
+}
+
+// ---------------------------------------------------------------- workspace
+// [Qc | Qc_lo | Qsc | Qsc_lo | QsT | QsT_lo | G | G_lo | e_part | ab_part], 256-byte aligned pieces
+struct Layout {
+  size_t qc, qc_lo, qsc, qsc_lo, qst, qst_lo, g, g_lo, e_part, ab_part, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename P>
+Layout layout(int N, int M, int K) {
+  const size_t es = sizeof(typename P::T);
+  const size_t Kp = padded(K), Mp = padded(M);
+  const size_t nlo = P::kSplit ? 1 : 0;
+  const size_t nst = (Mp + P::BN - 1) / P::BN, nit = (N + P::BM - 1) / P::BM;
+  Layout L{};
+  size_t o = 0;
+  L.qc = o;
+  o += align256(es * N * Kp);
+  L.qc_lo = o;
+  o += align256(es * N * Kp * nlo);
+  L.qsc = o;
+  o += align256(es * Mp * Kp);
+  L.qsc_lo = o;
+  o += align256(es * Mp * Kp * nlo);
+  L.qst = o;
+  o += align256(es * Kp * Mp);
+  L.qst_lo = o;
+  o += align256(es * Kp * Mp * nlo);
+  L.g = o;
+  o += align256(es * N * Mp);
+  L.g_lo = o;
+  o += align256(es * N * Mp * nlo);
+  L.e_part = o;
+  o += align256(sizeof(double) * nst * N);
+  L.ab_part = o;
+  o += align256(sizeof(double) * nit * M);
+  L.total = o;
+  return L;
+}
+
+template <typename P>
+hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta,
+                       double* e, double* alpha_bar, void* work, hipStream_t st) {
+  using T = typename P::T;
+  const Layout L = layout<P>(N, M, K);
+  char* w = (char*)work;
+  const int Kp = padded(K), Mp = padded(M);
+  T *qc = (T*)(w + L.qc), *qc_lo = (T*)(w + L.qc_lo), *qsc = (T*)(w + L.qsc), *qsc_lo = (T*)(w + L.qsc_lo);
+  T *qst = (T*)(w + L.qst), *qst_lo = (T*)(w + L.qst_lo), *G = (T*)(w + L.g), *G_lo = (T*)(w + L.g_lo);
+  double *e_part = (double*)(w + L.e_part), *ab_part = (double*)(w + L.ab_part);
+  auto blocks = [](long long n) { return dim3((unsigned)((n + 255) / 256)); };
+  hipLaunchKernelGGL((k_convert<T, P::kSplit, false>), blocks((long long)N * Kp), dim3(256), 0, st, N, K, N, Kp, Q,
+                     qc, qc_lo);
+  hipLaunchKernelGGL((k_convert<T, P::kSplit, false>), blocks((long long)Mp * Kp), dim3(256), 0, st, M, K, Mp, Kp, Qs,
+                     qsc, qsc_lo);
+  hipLaunchKernelGGL((k_convert<T, P::kSplit, true>), blocks((long long)Kp * Mp), dim3(256), 0, st, M, K, Kp, Mp, Qs,
+                     qst, qst_lo);
+  const int nst = (Mp + P::BN - 1) / P::BN, nit = (N + P::BM - 1) / P::BM;
+  hipLaunchKernelGGL(k_scores<P>, dim3(nst, nit), dim3(256), 0, st, N, M, Mp, Kp, qc, qc_lo, qsc, qsc_lo, alpha, zeta,
+                     G, G_lo, e_part, ab_part);
+  hipLaunchKernelGGL(k_sum_parts, dim3((N + 255) / 256), dim3(256), 0, st, N, nst, e_part, e);
+  if (alpha_bar)
+    hipLaunchKernelGGL(k_sum_parts, dim3((M + 255) / 256), dim3(256), 0, st, M, nit, ab_part, alpha_bar);
+  return hipGetLastError();
+}
+
+template <typename P>
+hipError_t qbar_impl(int N, int M, int K, double* Qbar, const void* work, hipStream_t st) {
+  using T = typename P::T;
+  const Layout L = layout<P>(N, M, K);
+  const char* w = (const char*)work;
+  const int Kp = padded(K), Mp = padded(M);
+  const T *qst = (const T*)(w + L.qst), *qst_lo = (const T*)(w + L.qst_lo);
+  const T *G = (const T*)(w + L.g), *G_lo = (const T*)(w + L.g_lo);
+  const int nit = (N + P::BM - 1) / P::BM, nct = (Kp + P::BN - 1) / P::BN;
+  hipLaunchKernelGGL(k_qbar<P>, dim3(nct, nit), dim3(256), 0, st, N, K, Mp, Kp, G, G_lo, qst, qst_lo, Qbar);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t gap_workspace_bytes(int N, int M, int K, int prec) {
+  switch (prec) {
+    case 0: return layout<PF64>(N, M, K).total;
+    case 1: return layout<PF32>(N, M, K).total;
+    case 2: return layout<PBF16>(N, M, K).total;
+    default: return layout<PBF16X3>(N, M, K).total;
+  }
+}
+
+hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
+                             int zeta, double* e, double* alpha_bar, void* work, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  switch (prec) {
+    case 0: return scores_impl<PF64>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
+    case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
+    case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
+    default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
+  }
+}
+
+hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, const void* work, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  switch (prec) {
+    case 0: return qbar_impl<PF64>(N, M, K, Qbar, work, st);
+    case 1: return qbar_impl<PF32>(N, M, K, Qbar, work, st);
+    case 2: return qbar_impl<PBF16>(N, M, K, Qbar, work, st);
+    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, work, st);
+  }
+}
+
+}  // namespace soap

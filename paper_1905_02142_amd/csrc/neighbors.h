@@ -37,7 +37,7 @@ hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t
 int scan_partials_needed(int n);
 hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
                             int* atom_bin, int* atom_wrap, int* bin_count, int* err, hipStream_t st);
-hipError_t launch_fill_bins(int n_atoms, int n_bins, const int* atom_bin, const int* bin_start, int* bin_cursor,
+hipError_t launch_fill_bins(int n_atoms, const int* atom_bin, const int* bin_start, int* bin_cursor, int* unsorted,
                             int* bin_atoms, hipStream_t st);
 hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructMeta* meta, const int* so,
                         int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,

@@ -81,82 +81,130 @@ __global__ void k_fill_bins(int n_atoms, const int* __restrict__ atom_bin, const
   bin_atoms[bin_start[bin] + slot] = a;
 }
 
-// atoms of one bin in ascending index order (bins hold tens of atoms)
-__global__ void k_sort_bins(int n_bins, const int* __restrict__ bin_start, int* __restrict__ bin_atoms) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bins) return;
-  int s = bin_start[b], e = bin_start[b + 1];
-  for (int x = s + 1; x < e; ++x) {
-    int v = bin_atoms[x];
-    int y = x - 1;
-    while (y >= s && bin_atoms[y] > v) {
-      bin_atoms[y + 1] = bin_atoms[y];
-      --y;
-    }
-    bin_atoms[y + 1] = v;
-  }
+// place atom a at its rank (by index) among the atoms of its bin; `unsorted`
+// holds each bin's atoms in the arbitrary order the atomics produced
+__global__ void k_rank_bins(int n_atoms, const int* __restrict__ atom_bin, const int* __restrict__ bin_start,
+                            const int* __restrict__ unsorted, int* __restrict__ bin_atoms) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  const int bin = atom_bin[a];
+  const int s = bin_start[bin], e = bin_start[bin + 1];
+  int rank = 0;
+  for (int t = s; t < e; ++t) rank += unsorted[t] < a;
+  bin_atoms[s + rank] = a;
 }
 
+// One wavefront per centre atom.  The (2R+1)^3 slab offsets are taken 64 at a
+// time: lane b describes offset b (bin, lattice shift, atom count), a wave scan
+// turns the counts into a flat candidate range, and the lanes then sweep the
+// candidates 64 at a time.  Hits are compacted with a ballot, so the pair order
+// (offset order, then ascending atom index within a bin) is fixed.
 template <bool FILL>
-__global__ void k_pairs(int n_atoms, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
-                        const int* __restrict__ so, int n_struct, double rc2, const int* __restrict__ atom_bin,
-                        const int* __restrict__ atom_wrap, const int* __restrict__ bin_start,
-                        const int* __restrict__ bin_atoms, int* __restrict__ count, const int* __restrict__ offsets,
-                        long long capacity, int* __restrict__ nj, int* __restrict__ nimg, int* __restrict__ ncenter,
-                        double* __restrict__ ndx, double* __restrict__ ndy, double* __restrict__ ndz,
-                        int* __restrict__ err) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __restrict__ pos,
+                                               const StructMeta* __restrict__ meta, const int* __restrict__ so,
+                                               int n_struct, double rc2, const int* __restrict__ atom_bin,
+                                               const int* __restrict__ atom_wrap, const int* __restrict__ bin_start,
+                                               const int* __restrict__ bin_atoms, int* __restrict__ count,
+                                               const int* __restrict__ offsets, long long capacity,
+                                               int* __restrict__ nj, int* __restrict__ nimg,
+                                               int* __restrict__ ncenter, double* __restrict__ ndx,
+                                               double* __restrict__ ndy, double* __restrict__ ndz,
+                                               int* __restrict__ err) {
+  __shared__ int s_pref[4][65];   // inclusive scan of candidate counts
+  __shared__ int s_start[4][64];  // first bin_atoms slot of each offset
+  __shared__ int s_shift[4][64];  // lattice shift of each offset (packed)
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
   if (i >= n_atoms) return;
   const StructMeta& M = meta[find_structure(so, n_struct, i)];
   const double pix = pos[3 * i], piy = pos[3 * i + 1], piz = pos[3 * i + 2];
   const int local = atom_bin[i] - M.bin0;
-  const int bx = local % M.nbin[0], by = (local / M.nbin[0]) % M.nbin[1], bz = local / (M.nbin[0] * M.nbin[1]);
+  const int b0 = local % M.nbin[0], b1 = (local / M.nbin[0]) % M.nbin[1], b2 = local / (M.nbin[0] * M.nbin[1]);
   int wi[3];
   unpack_img(atom_wrap[i], wi);
-  int out = FILL ? offsets[i] : 0;
+  const int n0 = 2 * M.R[0] + 1, n1 = 2 * M.R[1] + 1, n2 = 2 * M.R[2] + 1;
+  const int n_off = n0 * n1 * n2;
+  long long out = FILL ? offsets[i] : 0;
   int cnt = 0;
-  for (int oz = -M.R[2]; oz <= M.R[2]; ++oz) {
-    const int uz = bz + oz, gz = M.pbc[2] ? floordiv(uz, M.nbin[2]) : 0, cz = uz - gz * M.nbin[2];
-    for (int oy = -M.R[1]; oy <= M.R[1]; ++oy) {
-      const int uy = by + oy, gy = M.pbc[1] ? floordiv(uy, M.nbin[1]) : 0, cy = uy - gy * M.nbin[1];
-      for (int ox = -M.R[0]; ox <= M.R[0]; ++ox) {
-        const int ux = bx + ox, gx = M.pbc[0] ? floordiv(ux, M.nbin[0]) : 0, cx = ux - gx * M.nbin[0];
-        const int bin = M.bin0 + (cz * M.nbin[1] + cy) * M.nbin[0] + cx;
-        for (int t = bin_start[bin]; t < bin_start[bin + 1]; ++t) {
-          const int j = bin_atoms[t];
-          int wj[3];
-          unpack_img(atom_wrap[j], wj);
-          const int T0 = gx - wj[0] + wi[0], T1 = gy - wj[1] + wi[1], T2 = gz - wj[2] + wi[2];
-          if (j == i && T0 == 0 && T1 == 0 && T2 == 0) continue;
+  for (int g0 = 0; g0 < n_off; g0 += 64) {
+    const int o = g0 + lane;
+    int len = 0, start = 0, shift = 0;
+    if (o < n_off) {
+      const int ox = o % n0 - M.R[0], oy = (o / n0) % n1 - M.R[1], oz = o / (n0 * n1) - M.R[2];
+      const int ux = b0 + ox, uy = b1 + oy, uz = b2 + oz;
+      const int gx = M.pbc[0] ? floordiv(ux, M.nbin[0]) : 0;
+      const int gy = M.pbc[1] ? floordiv(uy, M.nbin[1]) : 0;
+      const int gz = M.pbc[2] ? floordiv(uz, M.nbin[2]) : 0;
+      const int cx = ux - gx * M.nbin[0], cy = uy - gy * M.nbin[1], cz = uz - gz * M.nbin[2];
+      const int bin = M.bin0 + (cz * M.nbin[1] + cy) * M.nbin[0] + cx;
+      start = bin_start[bin];
+      len = bin_start[bin + 1] - start;
+      shift = pack_img(gx, gy, gz);
+    }
+    // inclusive wave scan of len
+    int incl = len;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    s_pref[wv][lane + 1] = incl;
+    if (lane == 0) s_pref[wv][0] = 0;
+    s_start[wv][lane] = start;
+    s_shift[wv][lane] = shift;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS writes visible to the wave
+    const int total = __shfl(incl, 63, 64);
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool hit = false;
+      int j = 0, T0 = 0, T1 = 0, T2 = 0;
+      double ddx = 0.0, ddy = 0.0, ddz = 0.0;
+      if (c < total) {
+        // offset b with s_pref[b] <= c < s_pref[b + 1]
+        int lo = 0, hi = 64;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pref[wv][mid] <= c) lo = mid;
+          else hi = mid;
+        }
+        j = bin_atoms[s_start[wv][lo] + (c - s_pref[wv][lo])];
+        int gsh[3], wj[3];
+        unpack_img(s_shift[wv][lo], gsh);
+        unpack_img(atom_wrap[j], wj);
+        T0 = gsh[0] - wj[0] + wi[0];
+        T1 = gsh[1] - wj[1] + wi[1];
+        T2 = gsh[2] - wj[2] + wi[2];
+        if (!(j == i && T0 == 0 && T1 == 0 && T2 == 0)) {
           // d = (r_j - r_i) + T cell, the same operation order for a pair and its reverse
           const double tx = T0 * M.cell[0] + T1 * M.cell[3] + T2 * M.cell[6];
           const double ty = T0 * M.cell[1] + T1 * M.cell[4] + T2 * M.cell[7];
           const double tz = T0 * M.cell[2] + T1 * M.cell[5] + T2 * M.cell[8];
-          const double ddx = (pos[3 * j] - pix) + tx;
-          const double ddy = (pos[3 * j + 1] - piy) + ty;
-          const double ddz = (pos[3 * j + 2] - piz) + tz;
+          ddx = (pos[3 * j] - pix) + tx;
+          ddy = (pos[3 * j + 1] - piy) + ty;
+          ddz = (pos[3 * j + 2] - piz) + tz;
           const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          if (r2 < rc2) {
-            if (r2 < 1e-16) atomicOr(err, kErrCoincident);
-            if (FILL) {
-              if (out < capacity) {
-                nj[out] = j;
-                nimg[out] = pack_img(T0, T1, T2);
-                ncenter[out] = i;
-                ndx[out] = ddx;
-                ndy[out] = ddy;
-                ndz[out] = ddz;
-              }
-              ++out;
-            } else {
-              ++cnt;
-            }
-          }
+          hit = r2 < rc2;
+          if (hit && r2 < 1e-16) atomicOr(err, kErrCoincident);
         }
       }
+      const unsigned long long mask = __ballot(hit);
+      if (FILL && hit) {
+        const long long q = out + __popcll(mask & ((1ull << lane) - 1ull));
+        if (q < capacity) {
+          nj[q] = j;
+          nimg[q] = pack_img(T0, T1, T2);
+          ncenter[q] = i;
+          ndx[q] = ddx;
+          ndy[q] = ddy;
+          ndz[q] = ddz;
+        }
+      }
+      out += __popcll(mask);
+      cnt += __popcll(mask);
     }
+    __builtin_amdgcn_wave_barrier();
   }
-  if (!FILL) count[i] = cnt;
+  if (!FILL && lane == 0) count[i] = cnt;
 }
 
 // rev[p]: the pair (j -> i, -T) in j's list
@@ -263,11 +311,12 @@ hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* me
   return hipGetLastError();
 }
 
-hipError_t launch_fill_bins(int n_atoms, int n_bins, const int* atom_bin, const int* bin_start, int* bin_cursor,
+hipError_t launch_fill_bins(int n_atoms, const int* atom_bin, const int* bin_start, int* bin_cursor, int* unsorted,
                             int* bin_atoms, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_bins, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, atom_bin, bin_start,
-                     bin_cursor, bin_atoms);
-  hipLaunchKernelGGL(k_sort_bins, dim3((n_bins + 127) / 128), dim3(128), 0, st, n_bins, bin_start, bin_atoms);
+                     bin_cursor, unsorted);
+  hipLaunchKernelGGL(k_rank_bins, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, atom_bin, bin_start,
+                     unsorted, bin_atoms);
   return hipGetLastError();
 }
 
@@ -275,7 +324,7 @@ hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructM
                         int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
                         const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
                         int* ncenter, double* ndx, double* ndy, double* ndz, int* err, hipStream_t st) {
-  dim3 g((n_atoms + 127) / 128), b(128);
+  dim3 g((n_atoms + 3) / 4), b(256);
   if (fill)
     hipLaunchKernelGGL(k_pairs<true>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
                        bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, err);

@@ -338,27 +338,40 @@ __global__ __launch_bounds__(64) void k_pair_adjoint(DevParams P, const DevTable
   }
 }
 
-// F_k = sum over k's pairs q of (g_q - g_rev(q)) (= -dE/dr_k); mode 1 adds -F_k into pos_grad
-__global__ void k_force_gather(int n_atoms, const int* __restrict__ offsets, const int* __restrict__ rev,
-                               const double* __restrict__ gx, const double* __restrict__ gy,
-                               const double* __restrict__ gz, double* __restrict__ out, int accumulate_grad) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_atoms) return;
+// F_k = sum over k's pairs q of (g_q - g_rev(q)) (= -dE/dr_k); mode 1 adds -F_k into
+// pos_grad.  16 lanes per atom stride over its pairs; the partial sums are
+// combined by a fixed butterfly, so the result is the same on every run.
+__global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets,
+                                                      const int* __restrict__ rev, const double* __restrict__ gx,
+                                                      const double* __restrict__ gy, const double* __restrict__ gz,
+                                                      double* __restrict__ out, int accumulate_grad) {
+  const int k = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & 15;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int q = offsets[k]; q < offsets[k + 1]; ++q) {
-    const int r = rev[q];
-    fx += gx[q] - gx[r];
-    fy += gy[q] - gy[r];
-    fz += gz[q] - gz[r];
+  if (k < n_atoms) {
+    for (int q = offsets[k] + sub; q < offsets[k + 1]; q += 16) {
+      const int r = rev[q];
+      fx += gx[q] - gx[r];
+      fy += gy[q] - gy[r];
+      fz += gz[q] - gz[r];
+    }
   }
-  if (accumulate_grad) {
-    out[3 * k] -= fx;
-    out[3 * k + 1] -= fy;
-    out[3 * k + 2] -= fz;
-  } else {
-    out[3 * k] = fx;
-    out[3 * k + 1] = fy;
-    out[3 * k + 2] = fz;
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) {
+    fx += __shfl_xor(fx, o, 16);
+    fy += __shfl_xor(fy, o, 16);
+    fz += __shfl_xor(fz, o, 16);
+  }
+  if (k < n_atoms && sub == 0) {
+    if (accumulate_grad) {
+      out[3 * k] -= fx;
+      out[3 * k + 1] -= fy;
+      out[3 * k + 2] -= fz;
+    } else {
+      out[3 * k] = fx;
+      out[3 * k + 1] = fy;
+      out[3 * k + 2] = fz;
+    }
   }
 }
 
@@ -435,7 +448,7 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
 hipError_t launch_force_gather(int n_atoms, const int* offsets, const int* rev, const double* gx, const double* gy,
                                const double* gz, double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 127) / 128), dim3(128), 0, st, n_atoms, offsets, rev, gx, gy, gz,
+  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 15) / 16), dim3(256), 0, st, n_atoms, offsets, rev, gx, gy, gz,
                      out, accumulate_grad ? 1 : 0);
   return hipGetLastError();
 }
