@@ -141,6 +141,11 @@ void build_ylm_tables(soap::DevTables& t) {
       const double den = (2.0 * l - 3.0) * l2m2;
       t.yb[k] = (num == 0.0) ? 0.0 : std::sqrt(num / den);
     }
+  for (int m = 0; m <= soap::kMaxL; ++m)
+    for (int l = m; l <= soap::kMaxL; ++l) {
+      t.ym_a[soap::ym_index(m, l)] = t.ya[soap::lm_tri(l, m)];
+      t.ym_b[soap::ym_index(m, l)] = t.yb[soap::lm_tri(l, m)];
+    }
 }
 
 soap_status check_nlist(soap_ctx* ctx, const soap_nlist* nl) {
@@ -208,7 +213,7 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * P.nch * P.LL);
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                        species, (double*)ctx->c.p, q, pnorm, st));
+                                        species, (double*)ctx->c.p, q, P.K, pnorm, st));
   return SOAP_OK;
 }
 
@@ -254,6 +259,7 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
   d.rc = p->r_cut;
   d.rs = p->r_soft;
   d.nf = p->n_f;
+  d.inv_rc = 1.0 / p->r_cut;
   d.s0r = p->sigma0_r;
   d.s0p = p->sigma0_perp;
   d.ar = p->alpha_r;
@@ -266,10 +272,12 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
     delete ctx;
     return SOAP_EINVAL;
   }
-  for (int i = 0; i < d.n * d.n; ++i) t.W[i] = W[i];
+  for (int k = 0; k < d.n; ++k)
+    for (int al = 0; al < d.n; ++al) t.W[k * soap::kMaxN + al] = W[k * d.n + al];
   for (int al = 1; al < d.n; ++al) t.invN[al - 1] = std::sqrt((2.0 * al + 5.0) / d.rc);
   for (int l = 0; l <= soap::kMaxL + 1; ++l) t.lw[l] = p->l_weight ? 1.0 : 2.0 * l + 1.0;
   build_ylm_tables(t);
+  soap::build_angular_tables(d, t);
   if (hipGetDevice(&ctx->device) != hipSuccess || hipMalloc((void**)&ctx->dt, sizeof(soap::DevTables)) != hipSuccess) {
     delete ctx;
     return SOAP_EHIP;
@@ -476,8 +484,8 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                            species, (const double*)ctx->c.p, (const double*)ctx->q.p,
-                                            (const double*)ctx->pnorm.p, q_bar, (double*)ctx->gx.p,
+                                            species, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                            (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->gx.p,
                                             (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
@@ -528,8 +536,8 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     {
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                              species, (const double*)ctx->c.p, (const double*)ctx->q.p,
-                                              (const double*)ctx->pnorm.p, qbar, (double*)ctx->gx.p,
+                                              species, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                              (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->gx.p,
                                               (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);

@@ -1,23 +1,25 @@
 // Descriptor forward and adjoint kernels (FP64 VALU).
 //
 // Forward, one 64-lane wavefront per centre atom i (Sec. II, Eqs. (05), (08), (09)):
-//   1. per-pair phase: lane t of a chunk of 16 neighbours computes
-//        B_k = 4 pi A b_k              (radial recursion, orthonormal transform)
-//        Ang_lm = w_l e_l Y_lm(u)      (ilexp and real spherical harmonics)
-//      and stages them in LDS;
-//   2. accumulation c[k][lm] += B_k Ang_lm: lane (pg, sl) owns the channels k of
-//      the lm slice sl and the neighbours of pair group pg, so every LDS read of
-//      a B row feeds LMS x n FMAs held in registers;
-//   3. the PG partial sums are combined by DPP quad shuffles, the central atom is
-//      added, c is stored (it is re-read by the adjoint), then p_{ab l} =
-//      sum_m c[a][lm] c[b][lm] is formed from c in LDS and normalised in place.
-// Channels of species s are accumulated together: neighbours are compacted per
-// species with a wave ballot, so one register tile serves every species block.
+//   1. per-pair phase: each lane takes one neighbour of a 64-neighbour chunk and
+//      computes B_k = 4 pi A b_k (radial recursion and orthonormal transform,
+//      staged in LDS) and w_l e_l (ilexp, kept in registers);
+//   2. the real spherical harmonics are produced in NP passes over fixed slices
+//      of the angular slots (m-major order), so only one slice of the
+//      64 x L^2 angular table sits in LDS at a time;
+//   3. accumulation c[k][lm] += B_k Ang_lm: lane (pg, sl) owns the channels k of
+//      the slots sl, sl + SL, .. of every pass and the neighbours of pair group
+//      pg, so one LDS read of a B row feeds NMAX FMAs per owned slot;
+//   4. the PG partial sums are combined by DPP quad shuffles, the central atom is
+//      added, c is stored (the adjoint re-reads it), and p_{ab l} =
+//      sum_m c[a][lm] c[b][lm] is formed from c in LDS and normalised.
+// Neighbours of species s are compacted with a wave ballot and accumulated
+// together, so one register tile serves every species block.
 //
 // Adjoint, one wavefront per centre atom:
-//   qbar -> vbar = (qbar - q (q.qbar)) / |p|  -> cbar = M c (M from vbar) in LDS,
-//   then one lane per neighbour recomputes B, dB/dr, e_l, de_l/dz, Y_lm, grad Y_lm
-//   and contracts them with cbar into the pair gradient g = dE/dd.
+//   qbar -> vbar = (qbar - q (q.qbar)) / |p| -> cbar = M c (M from vbar) in LDS,
+//   then one lane per neighbour recomputes B, dB/dr, e_l, de_l/dz, Y_lm and
+//   grad Y_lm and contracts them with cbar into the pair gradient g = dE/dd.
 // Forces are gathered per atom through the reverse-pair index: no atomics, so
 // FP64 results are bitwise reproducible.
 #include <hip/hip_runtime.h>
@@ -57,75 +59,97 @@ __device__ inline void ab_decode(int ab, int nch, int& a, int& b) {
   b = a + ab;
 }
 
-// real spherical harmonics with the gradient of their polynomial extension:
-// put(l, lm, Y, dY/dv_x, dY/dv_y, dY/dv_z)
-template <int LM, typename F>
-__device__ inline void real_ylm_grad(const DevTables* __restrict__ T, int lmax, double ux, double uy, double uz,
-                                     F&& put) {
-  double cr = 1.0, ci = 0.0;  // (u_x + i u_y)^m
-  double pr = 0.0, pi = 0.0;  // (u_x + i u_y)^(m-1)
+// Writes row[slot - s0] = we[l] Y(slot) for the angular slots s0 <= slot < s1.
+// Slot order: m = 0 (l = 0..lmax), then for m = 1..lmax and l = m..lmax the
+// pair (l, +m), (l, -m).  Y(l, +m) = Qbar_lm(u_z) Re (u_x + i u_y)^m,
+// Y(l, -m) = Qbar_lm(u_z) Im (u_x + i u_y)^m, Y(l, 0) = Qbar_l0(u_z), with
+// Qbar_lm = sqrt(2)^(m>0) N_lm d^m P_l/dz^m (pole-free; see the host tables).
+// recursion factors staged in LDS once per workgroup (m-major, see ym_index)
+struct YTab {
+  double a[kMaxLM];
+  double b[kMaxLM];
+  double mm[kMaxL + 2];
+};
+
+__device__ inline void stage_ytab(const DevTables* __restrict__ T, YTab& y, int lane) {
+  for (int t = lane; t < kMaxLM; t += 64) {
+    y.a[t] = T->ym_a[t];
+    y.b[t] = T->ym_b[t];
+  }
+  if (lane < kMaxL + 2) y.mm[lane] = T->ymm[lane];
+}
+
+template <int LMAX>
+__device__ inline void angular_slots(const YTab& Y, int lmax, double ux, double uy, double uz,
+                                     const double (&we)[LMAX + 1], int s0, int s1, double* __restrict__ row) {
+  double cr = 1.0, ci = 0.0;
+  int g = 0;
+  for (int m = 0; m <= lmax && g < s1; ++m) {
+    const int cnt = (m == 0) ? lmax + 1 : 2 * (lmax - m + 1);
+    if (g + cnt > s0) {
+      const double* ya = Y.a + ym_index(m, m) - m;  // ya[l] = factor of (l, m)
+      const double* yb = Y.b + ym_index(m, m) - m;
+      double q2 = 0.0, q1 = Y.mm[m];
+      int slot = g;
 #pragma unroll
-  for (int m = 0; m <= LM; ++m) {
-    if (m <= lmax) {
-      double q2 = 0.0, q1 = T->ymm[m];
-      double d2 = 0.0, d1 = 0.0;  // d/dz of Qbar
-#pragma unroll
-      for (int l = m; l <= LM; ++l) {
-        if (l <= lmax) {
-          double q, d;
-          if (l == m) {
-            q = q1;
-            d = d1;
-          } else {
-            const double a = T->ya[lm_tri(l, m)], b = T->yb[lm_tri(l, m)];
-            q = a * uz * q1 - b * q2;
-            d = a * (q1 + uz * d1) - b * d2;
+      for (int l = 0; l <= LMAX; ++l) {
+        if (l >= m && l <= lmax) {
+          double q = q1;
+          if (l > m) {
+            q = ya[l] * uz * q1 - yb[l] * q2;
             q2 = q1;
             q1 = q;
-            d2 = d1;
-            d1 = d;
           }
+          const double v = we[l] * q;
           if (m == 0) {
-            put(l, l * l + l, q, 0.0, 0.0, d);
+            if (slot >= s0 && slot < s1) row[slot - s0] = v;
+            slot += 1;
           } else {
-            const double fm = (double)m;
-            put(l, l * l + l + m, q * cr, q * fm * pr, -q * fm * pi, d * cr);
-            put(l, l * l + l - m, q * ci, q * fm * pi, q * fm * pr, d * ci);
+            if (slot >= s0 && slot < s1) row[slot - s0] = v * cr;
+            if (slot + 1 >= s0 && slot + 1 < s1) row[slot + 1 - s0] = v * ci;
+            slot += 2;
           }
         }
       }
     }
-    pr = cr;
-    pi = ci;
+    g += cnt;
     const double nr = cr * ux - ci * uy;
     ci = cr * uy + ci * ux;
     cr = nr;
   }
 }
 
-template <int NMAX, int LMAX, int PG>
+template <int NMAX, int LMAX, int PG, int NP>
+struct FwdShape {
+  static constexpr int LLM = (LMAX + 1) * (LMAX + 1);
+  static constexpr int S = (LLM + NP - 1) / NP;  // slots per pass
+  static constexpr int SL = 64 / PG;
+  static constexpr int LMSP = (S + SL - 1) / SL;
+  static constexpr int AST = S + 1;
+  static constexpr int BST = NMAX + 1;
+};
+
+template <int NMAX, int LMAX, int PG, int NP>
 __global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                   const int* __restrict__ offsets, const int* __restrict__ nj,
-                                                   const double* __restrict__ dx, const double* __restrict__ dy,
-                                                   const double* __restrict__ dz, const int* __restrict__ species,
-                                                   double* __restrict__ c_out, double* __restrict__ q_out,
-                                                   double* __restrict__ pnorm_out) {
-  constexpr int LLM = (LMAX + 1) * (LMAX + 1);
-  constexpr int SL = 64 / PG;
-  constexpr int LMS = (LLM + SL - 1) / SL;
-  constexpr int CH = 16;
-  constexpr int AST = LLM + 1;
-  constexpr int BST = NMAX + 1;
-  __shared__ double ang[CH * AST];
-  __shared__ double bsh[CH * BST];
+                                                      const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                      const double* __restrict__ dx, const double* __restrict__ dy,
+                                                      const double* __restrict__ dz, const int* __restrict__ species,
+                                                      double* __restrict__ c_out, double* __restrict__ q_out,
+                                                      int q_pitch, double* __restrict__ pnorm_out) {
+  using Sh = FwdShape<NMAX, LMAX, PG, NP>;
+  constexpr int S = Sh::S, SL = Sh::SL, LMSP = Sh::LMSP, AST = Sh::AST, BST = Sh::BST;
+  __shared__ double ang[64 * AST];
+  __shared__ double bsh[64 * BST];
   __shared__ double bc[NMAX];
   __shared__ int idx[64];
+  __shared__ YTab ytab;
   extern __shared__ double dyn[];
 
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
   const int lane = threadIdx.x;
   const int pg = lane % PG, sl = lane / PG;
+  stage_ytab(T, ytab, lane);
   const int n = P.n, LL = P.LL, nch = P.nch, LLP = LL + 1;
   double* csh = dyn;
   double* vsh = dyn + nch * LLP;
@@ -142,90 +166,92 @@ __global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables*
   __syncthreads();
 
   for (int s = 0; s < P.ns; ++s) {
-    double acc[LMS][NMAX];
+    double acc[NP][LMSP][NMAX];
 #pragma unroll
-    for (int kk = 0; kk < LMS; ++kk)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int k = 0; k < NMAX; ++k) acc[kk][k] = 0.0;
+      for (int kk = 0; kk < LMSP; ++kk)
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) acc[p][kk][k] = 0.0;
 
     for (int w0 = p0; w0 < p1; w0 += 64) {
-      const int p = w0 + lane;
-      const bool take = p < p1 && (P.ns == 1 || species[nj[p]] == s);
+      const int pp = w0 + lane;
+      const bool take = pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
       const unsigned long long mask = __ballot(take);
-      if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = p;
+      if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      for (int c0 = 0; c0 < cnt; c0 += CH) {
-        const int nc = min(CH, cnt - c0);
-        if (lane < nc) {
-          const int pp = idx[c0 + lane];
-          const double x = dx[pp], y = dy[pp], z = dz[pp];
-          const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-          double B[NMAX], dB[NMAX];
-          radial<NMAX, false>(P, T, r, B, dB);
+      if (cnt == 0) continue;
+      // per-pair phase: radial factors to LDS, w_l e_l in registers
+      double we[LMAX + 1];
 #pragma unroll
-          for (int k = 0; k < NMAX; ++k) bsh[lane * BST + k] = B[k];
-          const double sp = P.s0p + P.ap * r;
-          double e[LMAX + 1];
-          ilexp<LMAX>(r * r / (sp * sp), P.l, e);
-          double we[LMAX + 1];
+      for (int l = 0; l <= LMAX; ++l) we[l] = 0.0;
+      double ux = 0.0, uy = 0.0, uz = 1.0;
+      if (lane < cnt) {
+        const int q = idx[lane];
+        const double x = dx[q], y = dy[q], z = dz[q];
+        const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
+        ux = x * ir;
+        uy = y * ir;
+        uz = z * ir;
+        double B[NMAX], dB[NMAX];
+        radial<NMAX, false>(P, T, r, B, dB);
 #pragma unroll
-          for (int l = 0; l <= LMAX; ++l) we[l] = T->lw[l] * e[l];
-          double* row = ang + lane * AST;
-          real_ylm<LMAX>(T, P.l, x * ir, y * ir, z * ir, [&](int l, int lm, double v) { row[lm] = we[l] * v; });
-        }
-        __syncthreads();
+        for (int k = 0; k < NMAX; ++k) bsh[lane * BST + k] = B[k];
+        __builtin_amdgcn_sched_barrier(0);  // keep the radial and ilexp temporaries apart
+        const double sp = P.s0p + P.ap * r;
+        double e[LMAX + 1];
+        ilexp<LMAX>(r * r / (sp * sp), P.l, T->ilx_rec[1], T->ilx_rec[0], T->ilx_idf, e);
 #pragma unroll
-        for (int t = 0; t < CH / PG; ++t) {
-          const int pi = pg + PG * t;
-          if (pi < nc) {
+        for (int l = 0; l <= LMAX; ++l) we[l] = T->lw[l] * e[l];
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int s0 = p * S, s1 = min(s0 + S, LL);
+        if (s0 < LL) {
+          if (lane < cnt) angular_slots<LMAX>(ytab, P.l, ux, uy, uz, we, s0, s1, ang + lane * AST);
+          __syncthreads();
+          for (int t = 0; t < 64 / PG; ++t) {
+            const int pi = pg + PG * t;
+            if (pi >= cnt) break;
             double b[NMAX];
 #pragma unroll
             for (int k = 0; k < NMAX; ++k) b[k] = bsh[pi * BST + k];
 #pragma unroll
-            for (int kk = 0; kk < LMS; ++kk) {
-              const int lm = sl + SL * kk;
-              if (lm < LL) {
-                const double a = ang[pi * AST + lm];
+            for (int kk = 0; kk < LMSP; ++kk) {
+              const int sidx = sl + SL * kk;
+              if (s0 + sidx < s1) {
+                const double a = ang[pi * AST + sidx];
 #pragma unroll
-                for (int k = 0; k < NMAX; ++k) acc[kk][k] = fma(a, b[k], acc[kk][k]);
+                for (int k = 0; k < NMAX; ++k) acc[p][kk][k] = fma(a, b[k], acc[p][kk][k]);
               }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
       }
     }
-    // combine the pair groups
+    // combine the pair groups, add the central atom, scatter c into LDS
 #pragma unroll
-    for (int kk = 0; kk < LMS; ++kk)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int k = 0; k < NMAX; ++k) {
-        double v = acc[kk][k];
-        if (PG >= 2) v += dpp_move<kQuadXor1>(v);
-        if (PG >= 4) v += dpp_move<kQuadXor2>(v);
-        acc[kk][k] = v;
-      }
-    if (s == si && sl == 0) {
-#pragma unroll
-      for (int k = 0; k < NMAX; ++k) acc[0][k] += bc[k];
-    }
-#pragma unroll
-    for (int kk = 0; kk < LMS; ++kk) {
-      const int lm = sl + SL * kk;
-      if (lm < LL) {
+      for (int kk = 0; kk < LMSP; ++kk) {
+        const int slot = p * S + sl + SL * kk;
 #pragma unroll
         for (int k = 0; k < NMAX; ++k) {
-          if (k < n && (k % PG) == pg) {
-            const int ch = s * n + k;
-            c_out[((size_t)i * nch + ch) * LL + lm] = acc[kk][k];
-            csh[ch * LLP + lm] = acc[kk][k];
-          }
+          double v = acc[p][kk][k];
+          if (PG >= 2) v += dpp_move<kQuadXor1>(v);
+          if (PG >= 4) v += dpp_move<kQuadXor2>(v);
+          if (slot == 0 && s == si) v += bc[k];
+          if (sl + SL * kk < S && slot < LL && k < n && (k % PG) == pg) csh[(s * n + k) * LLP + T->slot_lm[slot]] = v;
         }
       }
-    }
   }
   __syncthreads();
+  for (int t = lane; t < nch * LL; t += 64) {
+    const int ch = t / LL, lm = t - ch * LL;
+    c_out[(size_t)i * nch * LL + t] = csh[ch * LLP + lm];
+  }
   // power spectrum p_{ab l} (real form of Eq. (09)), packed a <= b then l,
   // off-diagonal scaled by sqrt(2); then q = p / |p|
   const int L1 = P.l + 1;
@@ -245,91 +271,146 @@ __global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables*
   ss = wave_sum(ss);
   const double nrm = sqrt(ss);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int k = lane; k < P.K; k += 64) q_out[(size_t)i * P.K + k] = vsh[k] * inv;
+  for (int k = lane; k < q_pitch; k += 64) q_out[(size_t)i * q_pitch + k] = k < P.K ? vsh[k] * inv : 0.0;
   if (lane == 0 && pnorm_out) pnorm_out[i] = nrm;
 }
 
 template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                     const int* __restrict__ offsets, const int* __restrict__ nj,
-                                                     const double* __restrict__ dx, const double* __restrict__ dy,
-                                                     const double* __restrict__ dz, const int* __restrict__ species,
-                                                     const double* __restrict__ c, const double* __restrict__ q,
-                                                     const double* __restrict__ pnorm,
-                                                     const double* __restrict__ qbar, double* __restrict__ gx,
-                                                     double* __restrict__ gy, double* __restrict__ gz) {
+                                                        const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                        const double* __restrict__ dx, const double* __restrict__ dy,
+                                                        const double* __restrict__ dz,
+                                                        const int* __restrict__ species, const double* __restrict__ c,
+                                                        const double* __restrict__ q, int q_pitch,
+                                                        const double* __restrict__ pnorm,
+                                                        const double* __restrict__ qbar, int qbar_pitch,
+                                                        double* __restrict__ gx, double* __restrict__ gy,
+                                                        double* __restrict__ gz) {
   extern __shared__ double dyn[];
+  __shared__ YTab ytab;
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
   const int lane = threadIdx.x;
-  const int n = P.n, LL = P.LL, nch = P.nch, LLP = LL + 1, K = P.K, L1 = P.l + 1;
-  double* csh = dyn;
-  double* cbs = csh + nch * LLP;
-  double* vb = cbs + nch * LLP;
+  const int n = P.n, LL = P.LL, nch = P.nch, K = P.K, L1 = P.l + 1;
+  stage_ytab(T, ytab, lane);
+  const int CP = nch + (nch & 1);  // row pitch of the lm-major tables (16-byte rows)
+  double* ct = dyn;                // c[lm][ch]
+  double* cbt = ct + LL * CP;      // cbar[lm][ch]
+  double* vb = cbt + LL * CP;      // vbar (K)
   const int p0 = offsets[i], p1 = offsets[i + 1];
 
   for (int t = lane; t < nch * LL; t += 64) {
     const int ch = t / LL, lm = t - ch * LL;
-    csh[ch * LLP + lm] = c[(size_t)i * nch * LL + t];
+    ct[lm * CP + ch] = c[(size_t)i * nch * LL + t];
   }
   // vbar = (qbar - q (q . qbar)) / |p|
   const double nrm = pnorm[i];
   double dot = 0.0;
-  for (int k = lane; k < K; k += 64) dot = fma(q[(size_t)i * K + k], qbar[(size_t)i * K + k], dot);
+  for (int k = lane; k < K; k += 64) dot = fma(q[(size_t)i * q_pitch + k], qbar[(size_t)i * qbar_pitch + k], dot);
   dot = wave_sum(dot);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int k = lane; k < K; k += 64) vb[k] = (qbar[(size_t)i * K + k] - q[(size_t)i * K + k] * dot) * inv;
+  for (int k = lane; k < K; k += 64)
+    vb[k] = (qbar[(size_t)i * qbar_pitch + k] - q[(size_t)i * q_pitch + k] * dot) * inv;
   __syncthreads();
   // cbar[a][lm] = sum_b M_ab(l) c[b][lm]; M_aa = 2 vbar_(aa,l), M_ab = sqrt(2) vbar_(ab,l)
   for (int t = lane; t < nch * LL; t += 64) {
-    const int a = t / LL, lm = t - a * LL;
+    const int lm = t / nch, a = t - lm * nch;
     int l = 0;
     while ((l + 1) * (l + 1) <= lm) ++l;
     double s = 0.0;
     for (int b = 0; b < nch; ++b) {
       const int lo = a < b ? a : b, hi = a < b ? b : a;
       const double w = (a == b) ? 2.0 : kSqrt2;
-      s = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], csh[b * LLP + lm], s);
+      s = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], ct[lm * CP + b], s);
     }
-    cbs[a * LLP + lm] = s;
+    cbt[lm * CP + a] = s;
   }
   __syncthreads();
   for (int p = p0 + lane; p < p1; p += 64) {
     const double x = dx[p], y = dy[p], z = dz[p];
-    const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-    const double ux = x * ir, uy = y * ir, uz = z * ir;
-    double B[NMAX], dB[NMAX];
-    radial<NMAX, true>(P, T, r, B, dB);
-    const double sp = P.s0p + P.ap * r;
-    const double zz = r * r / (sp * sp);
-    const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
-    double e[LMAX + 2];
-    ilexp<LMAX + 1>(zz, P.l + 1, e);
     const int sj = P.ns == 1 ? 0 : species[nj[p]];
     if (sj < 0 || sj >= P.ns) {  // a label outside 0..n_species-1 contributes nothing
       gx[p] = gy[p] = gz[p] = 0.0;
       continue;
     }
-    const double* base = cbs + sj * n * LLP;
-    double gr = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-    real_ylm_grad<LMAX>(T, P.l, ux, uy, uz, [&](int l, int lm, double Y, double vx, double vy, double vz) {
-      double U = 0.0, V = 0.0;
+    const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
+    const double ux = x * ir, uy = y * ir, uz = z * ir;
+    double B[NMAX], dB[NMAX];
+    radial<NMAX, true>(P, T, r, B, dB);
+    __builtin_amdgcn_sched_barrier(0);  // keep the radial and ilexp temporaries apart
+    const double sp = P.s0p + P.ap * r;
+    const double zz = r * r / (sp * sp), izz = 1.0 / zz;
+    const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
+    double e[LMAX + 2];
+    ilexp<LMAX + 1>(zz, P.l + 1, T->ilx_rec[2], T->ilx_rec[1], T->ilx_idf, e);
+    double we[LMAX + 1], wd[LMAX + 1];
 #pragma unroll
-      for (int k = 0; k < NMAX; ++k) {
-        if (k < n) {
-          const double cb = base[k * LLP + lm];
-          U = fma(cb, dB[k], U);
-          V = fma(cb, B[k], V);
+    for (int l = 0; l <= LMAX; ++l) {
+      we[l] = T->lw[l] * e[l];
+      // d e_l / dz = e_{l+1} + (l/z - 1) e_l
+      wd[l] = T->lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr;
+    }
+    const double* base = cbt + sj * n;
+    double gr = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+    double cr = 1.0, ci = 0.0, pr = 0.0, pim = 0.0;  // (u_x + i u_y)^m and ^(m-1)
+    for (int m = 0; m <= P.l; ++m) {
+      const double* ya = ytab.a + ym_index(m, m) - m;
+      const double* yb = ytab.b + ym_index(m, m) - m;
+      double q2 = 0.0, q1 = ytab.mm[m], d2 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        if (l >= m && l <= P.l) {
+          double qv = q1, dv = d1;
+          if (l > m) {
+            const double a = ya[l], b = yb[l];
+            qv = a * uz * q1 - b * q2;
+            dv = a * (q1 + uz * d1) - b * d2;
+            q2 = q1;
+            q1 = qv;
+            d2 = d1;
+            d1 = dv;
+          }
+          // the two real harmonics of (l, m): cos part at l^2+l+m, sin part at l^2+l-m
+#pragma unroll
+          for (int part = 0; part < 2; ++part) {
+            if (part == 1 && m == 0) break;
+            const int lm = l * l + l + (part == 0 ? m : -m);
+            const double* cbr = base + lm * CP;
+            double U = 0.0, V = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMAX; ++k) {
+              if (k < n) {
+                U = fma(cbr[k], dB[k], U);
+                V = fma(cbr[k], B[k], V);
+              }
+            }
+            const double fm = (double)m;
+            double Y, vx, vy, vz;
+            if (part == 0) {
+              Y = qv * cr;
+              vx = qv * fm * pr;
+              vy = -qv * fm * pim;
+              vz = dv * cr;
+            } else {
+              Y = qv * ci;
+              vx = qv * fm * pim;
+              vy = qv * fm * pr;
+              vz = dv * ci;
+            }
+            gr = fma(U * we[l] + V * wd[l], Y, gr);
+            const double beta = we[l] * V;
+            tx = fma(beta, vx, tx);
+            ty = fma(beta, vy, ty);
+            tz = fma(beta, vz, tz);
+          }
         }
       }
-      const double wl = T->lw[l];
-      const double de = e[l + 1] + ((double)l / zz - 1.0) * e[l];
-      gr = fma(wl * (U * e[l] + V * de * dzdr), Y, gr);
-      const double beta = wl * e[l] * V;
-      tx = fma(beta, vx, tx);
-      ty = fma(beta, vy, ty);
-      tz = fma(beta, vz, tz);
-    });
+      pr = cr;
+      pim = ci;
+      const double nr = cr * ux - ci * uy;
+      ci = cr * uy + ci * ux;
+      cr = nr;
+    }
     // d u / d d = (I - u u^T) / r
     const double ut = ux * tx + uy * ty + uz * tz;
     gx[p] = gr * ux + (tx - ux * ut) * ir;
@@ -375,72 +456,70 @@ __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __
   }
 }
 
-template <int NMAX, int LMAX>
-hipError_t descriptor_impl(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                           const double* dx, const double* dy, const double* dz, const int* species, double* c,
-                           double* q, double* pnorm, hipStream_t st) {
-  const size_t dyn = sizeof(double) * ((size_t)P.nch * (P.LL + 1) + P.K);
-  if (LMAX <= 8)
-    hipLaunchKernelGGL((k_descriptor<NMAX, LMAX, 4>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj,
-                       dx, dy, dz, species, c, q, pnorm);
-  else
-    hipLaunchKernelGGL((k_descriptor<NMAX, LMAX, 2>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj,
-                       dx, dy, dz, species, c, q, pnorm);
-  return hipGetLastError();
+// compile-time (n_max, l_max) buckets: the kernels handle any n <= NMAX, l <= LMAX
+struct Bucket {
+  int n, l, pg, np;
+};
+// pg: pair groups per wave; np: angular passes (chosen so that each lane owns
+// one slot of every pass: ceil((l+1)^2 / np) <= 64 / pg)
+Bucket bucket_of(int n, int l) {
+  if (n <= 6 && l <= 6) return {6, 6, 2, 2};
+  if (n <= 8 && l <= 6) return {8, 6, 2, 2};
+  if (n <= 8 && l <= 8) return {8, 8, 2, 3};
+  if (n <= 10 && l <= 10) return {10, 10, 2, 4};
+  return {12, 12, 2, 6};
 }
 
-template <int NMAX, int LMAX>
-hipError_t adjoint_impl(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                        const double* dx, const double* dy, const double* dz, const int* species, const double* c,
-                        const double* q, const double* pnorm, const double* qbar, double* gx, double* gy, double* gz,
-                        hipStream_t st) {
-  const size_t dyn = sizeof(double) * (2 * (size_t)P.nch * (P.LL + 1) + P.K);
-  hipLaunchKernelGGL((k_pair_adjoint<NMAX, LMAX>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, dx,
-                     dy, dz, species, c, q, pnorm, qbar, gx, gy, gz);
-  return hipGetLastError();
-}
-
-// compile-time (n_max, l_max) buckets: the kernel handles any n <= NMAX, l <= LMAX
 template <typename F>
 hipError_t dispatch(int n, int l, F&& f) {
-  if (n <= 6 && l <= 6) return f.template operator()<6, 6>();
-  if (n <= 8 && l <= 6) return f.template operator()<8, 6>();
-  if (n <= 8 && l <= 8) return f.template operator()<8, 8>();
-  if (n <= 10 && l <= 10) return f.template operator()<10, 10>();
-  return f.template operator()<12, 12>();
+  const Bucket b = bucket_of(n, l);
+  if (b.n == 6) return f.template operator()<6, 6, 2, 2>();
+  if (b.n == 8 && b.l == 6) return f.template operator()<8, 6, 2, 2>();
+  if (b.n == 8) return f.template operator()<8, 8, 2, 3>();
+  if (b.n == 10) return f.template operator()<10, 10, 2, 4>();
+  return f.template operator()<12, 12, 2, 6>();
+}
+
+size_t fwd_dyn_bytes(const DevParams& P) { return sizeof(double) * ((size_t)P.nch * (P.LL + 1) + P.K); }
+size_t adj_dyn_bytes(const DevParams& P) {
+  const size_t CP = P.nch + (P.nch & 1);
+  return sizeof(double) * (2 * (size_t)P.LL * CP + P.K);
 }
 
 }  // namespace
 
-// static + dynamic LDS of one forward workgroup (static part of the (n, l) bucket used)
 size_t descriptor_lds_bytes(const DevParams& P) {
-  int NB = 12, LB = 12;
-  if (P.n <= 6 && P.l <= 6) NB = 6, LB = 6;
-  else if (P.n <= 8 && P.l <= 6) NB = 8, LB = 6;
-  else if (P.n <= 8 && P.l <= 8) NB = 8, LB = 8;
-  else if (P.n <= 10 && P.l <= 10) NB = 10, LB = 10;
-  const size_t stat = sizeof(double) * (16 * ((LB + 1) * (LB + 1) + 1) + 16 * (NB + 1) + NB) + 64 * sizeof(int);
-  return stat + sizeof(double) * ((size_t)P.nch * (P.LL + 1) + P.K);
+  const Bucket b = bucket_of(P.n, P.l);
+  const int LLM = (b.l + 1) * (b.l + 1), S = (LLM + b.np - 1) / b.np;
+  const size_t stat = sizeof(double) * (64 * (S + 1) + 64 * (b.n + 1) + b.n) + 64 * sizeof(int) + sizeof(YTab);
+  return stat + fwd_dyn_bytes(P);
 }
-size_t adjoint_lds_bytes(const DevParams& P) { return sizeof(double) * (2 * (size_t)P.nch * (P.LL + 1) + P.K); }
+size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P) + sizeof(YTab); }
 
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
                              const double* dx, const double* dy, const double* dz, const int* species, double* c,
-                             double* q, double* pnorm, hipStream_t st) {
+                             double* q, int q_pitch, double* pnorm, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  auto f = [&]<int N, int LM>() {
-    return descriptor_impl<N, LM>(P, T, n_atoms, offsets, nj, dx, dy, dz, species, c, q, pnorm, st);
+  const size_t dyn = fwd_dyn_bytes(P);
+  auto f = [&]<int N, int LM, int PG, int NP>() {
+    hipLaunchKernelGGL((k_descriptor<N, LM, PG, NP>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj,
+                       dx, dy, dz, species, c, q, q_pitch, pnorm);
+    return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
                                const int* nj, const double* dx, const double* dy, const double* dz,
-                               const int* species, const double* c, const double* q, const double* pnorm,
-                               const double* qbar, double* gx, double* gy, double* gz, hipStream_t st) {
+                               const int* species, const double* c, const double* q, int q_pitch,
+                               const double* pnorm, const double* qbar, int qbar_pitch, double* gx, double* gy,
+                               double* gz, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  auto f = [&]<int N, int LM>() {
-    return adjoint_impl<N, LM>(P, T, n_atoms, offsets, nj, dx, dy, dz, species, c, q, pnorm, qbar, gx, gy, gz, st);
+  const size_t dyn = adj_dyn_bytes(P);
+  auto f = [&]<int N, int LM, int PG, int NP>() {
+    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, dx, dy,
+                       dz, species, c, q, q_pitch, pnorm, qbar, qbar_pitch, gx, gy, gz);
+    return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
@@ -451,6 +530,27 @@ hipError_t launch_force_gather(int n_atoms, const int* offsets, const int* rev, 
   hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 15) / 16), dim3(256), 0, st, n_atoms, offsets, rev, gx, gy, gz,
                      out, accumulate_grad ? 1 : 0);
   return hipGetLastError();
+}
+
+void build_angular_tables(const DevParams& P, DevTables& T) {
+  int slot = 0;
+  for (int m = 0; m <= P.l; ++m)
+    for (int l = m; l <= P.l; ++l) {
+      if (m == 0) T.slot_lm[slot++] = (short)(l * l + l);
+      else {
+        T.slot_lm[slot++] = (short)(l * l + l + m);
+        T.slot_lm[slot++] = (short)(l * l + l - m);
+      }
+    }
+  for (int o = 0; o < 3; ++o) {
+    const int l = P.l - 1 + o;
+    for (int k = 0; k < kIlexpTerms; ++k) T.ilx_rec[o][k] = 1.0 / ((double)(k + 1) * (double)(2 * l + 2 * k + 3));
+  }
+  double df = 1.0;  // (2l+1)!!
+  for (int l = 0; l < kMaxL + 3; ++l) {
+    if (l > 0) df *= (double)(2 * l + 1);
+    T.ilx_idf[l] = 1.0 / df;
+  }
 }
 
 }  // namespace soap

@@ -19,15 +19,27 @@ constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 2) / 2;
 // at z = 24, 6e-7 at z = 5.76); there the two highest orders come from the power
 // series and the recursion runs downward, which is stable.
 constexpr double kIlexpSeriesBelow = 25.0;
+constexpr int kIlexpTerms = 40;  // series terms: relative tail < 1e-18 for z < 25, l <= 13
 
 // Read-only tables built on the host at context creation.
 struct DevTables {
-  double W[kMaxN * kMaxN];  // W[n * n_max + alpha]; alpha = n_max - 1 is the Gaussian function
+  double W[kMaxN * kMaxN];  // W[n * kMaxN + alpha]; alpha = n_max - 1 is the Gaussian function
   double invN[kMaxN];       // 1 / N_alpha for alpha = 1..n_max-1, stored at alpha - 1
   double lw[kMaxL + 2];     // w_l: 2l+1 (Eq. (08) as printed) or 1
   double ya[kMaxLM + 16];   // Legendre recursion factor a_lm, index l(l+1)/2 + m
   double yb[kMaxLM + 16];   // Legendre recursion factor b_lm
   double ymm[kMaxL + 2];    // seed Qbar_mm
+  // the same recursion factors in m-major order: ym_a[ym_index(m, l)], l = m..kMaxL
+  double ym_a[kMaxLM];
+  double ym_b[kMaxLM];
+  // ilexp power series: ilx_rec[o][k] = 1 / ((k+1) (2l + 2k + 3)) for the order
+  // l = l_max - 1 + o (o = 0, 1, 2), and ilx_idf[l] = 1 / (2l+1)!!
+  double ilx_rec[3][kIlexpTerms];
+  double ilx_idf[kMaxL + 3];
+  // angular slots: the (l, m) of the real spherical harmonics in the order the
+  // descriptor kernel produces them (m = 0: l = 0..l_max; then for each m > 0
+  // and l = m..l_max the pair (l, +m), (l, -m)); slot_lm[slot] = l^2 + l +- m
+  short slot_lm[(kMaxL + 1) * (kMaxL + 1)];
 };
 
 // Scalars of the hyper-parameters, passed by value to every kernel.
@@ -41,6 +53,7 @@ struct DevParams {
   int buffer;   // r_soft < r_cut
   int l_weight;
   double rc, rs, nf;
+  double inv_rc;
   double s0r, s0p, ar, ap, a;
   double cw;    // central-atom weight
 };
@@ -56,53 +69,58 @@ __device__ inline double erf_diff(double a, double b) {
   return erf(a) - erf(b);
 }
 
-// I_k = int_lo^hi (1 - t/rc)^k exp(-(t - mu)^2 / (2 s^2)) dt, k = 0..KM-1.
+// Streams I_k = int_lo^hi (1 - t/rc)^k exp(-(t - mu)^2 / (2 s^2)) dt for
+// k = 0..n+1 and adds, for the polynomial basis functions alpha = k - 2 >= 1,
+//   ba[alpha - 1]  += scale I_k / N_alpha
+//   dba[alpha - 1] += (dscale I_k + scale (dI_k/dmu dmu + dI_k/ds ds)) / N_alpha
+// where dscale, dmu, ds are the r-derivatives of scale, mu and s.
 // I_0 from erf, I_1 from the integration-by-parts identity with no k = -1 term,
 // then I_{k+2} = (k+1) s^2/rc^2 I_k + (1 - mu/rc) I_{k+1} + (s^2/rc) [u^{k+1} G]_lo^hi
-// (Eq. (04) multiplied through by N_alpha), u = 1 - t/rc.
-//
-// With DERIV, also the fixed-limit derivatives, from integrating dG/dmu = -dG/dt
-// by parts:
+// (Eq. (04) multiplied through by N_alpha), u = 1 - t/rc.  The fixed-limit
+// derivatives come from integrating dG/dmu = -dG/dt by parts:
 //   dI_k/dmu = -[u^k G]_lo^hi - (k/rc) I_{k-1}
 //   dI_k/ds  = (I_k - [u^k (t-mu) G]_lo^hi) / s - (k s/rc) dI_{k-1}/dmu
-// These avoid the cancellation of ((rc-mu) I_k - rc I_{k+1}) / s^2, which for
-// narrow Gaussians loses about two digits before W amplifies the error.
-template <int KM, bool DERIV>
-__device__ inline void overlap_integrals(double lo, double hi, double mu, double s, double rc, double (&I)[KM],
-                                         double (&dmu)[KM], double (&ds)[KM]) {
+// which avoid the cancellation of ((rc-mu) I_k - rc I_{k+1}) / s^2 (about two
+// digits for narrow Gaussians, before W amplifies the error).  Only the last
+// two terms are kept, so the stream needs a handful of registers.
+template <int NMAX, bool DERIV>
+__device__ inline void overlap_stream(const DevTables* __restrict__ T, int n, double lo, double hi, double mu,
+                                      double s, double rc, double scale, double dscale, double dmu_dr, double ds_dr,
+                                      double (&ba)[NMAX], double (&dba)[NMAX]) {
   const double s2 = s * s;
   const double is = 1.0 / (kSqrt2 * s);
   const double ah = (hi - mu) * is, al = (lo - mu) * is;
-  I[0] = s * kSqrtPiOver2 * erf_diff(ah, al);
   const double gh = exp(-ah * ah), gl = exp(-al * al);
   const double uh = 1.0 - hi / rc, ul = 1.0 - lo / rc;
   const double c1 = s2 / (rc * rc), c2 = 1.0 - mu / rc, c3 = s2 / rc;
-  I[1] = c3 * (gh - gl) + c2 * I[0];
-  double ph = uh * gh, pl = ul * gl;
+  const double th = (hi - mu) * gh, tl = (lo - mu) * gl;
+  const double krc = 1.0 / rc, is_ = 1.0 / s;
+  double Im2 = 0.0, Im1 = 0.0;   // I_{k-2}, I_{k-1}
+  double Dm1 = 0.0;              // dI_{k-1}/dmu
+  double qh = 1.0, ql = 1.0;     // u^k at the limits
+  double qh1 = 1.0, ql1 = 1.0;   // u^(k-1) at the limits (k >= 1)
 #pragma unroll
-  for (int k = 0; k + 2 < KM; ++k) {
-    I[k + 2] = (double)(k + 1) * c1 * I[k] + c2 * I[k + 1] + c3 * (ph - pl);
-    ph *= uh;
-    pl *= ul;
-  }
-  if (DERIV) {
-    const double th = (hi - mu) * gh, tl = (lo - mu) * gl;
-    const double is_ = 1.0 / s, krc = 1.0 / rc;
-    double qh = 1.0, ql = 1.0;  // u^k at the limits
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      const double bnd = qh * gh - ql * gl;
-      const double bt = qh * th - ql * tl;
-      if (k == 0) {
-        dmu[0] = -bnd;
-        ds[0] = (I[0] - bt) * is_;
-      } else {
-        dmu[k] = -bnd - (double)k * krc * I[k - 1];
-        ds[k] = (I[k] - bt) * is_ - (double)k * s * krc * dmu[k - 1];
-      }
-      qh *= uh;
-      ql *= ul;
+  for (int k = 0; k <= NMAX + 1; ++k) {
+    double I;
+    if (k == 0) I = s * kSqrtPiOver2 * erf_diff(ah, al);
+    else I = (double)(k - 1) * c1 * Im2 + c2 * Im1 + c3 * (qh1 * gh - ql1 * gl);
+    double Dmu = 0.0, Ds = 0.0;
+    if (DERIV) {
+      Dmu = -(qh * gh - ql * gl) - (double)k * krc * Im1;
+      Ds = (I - (qh * th - ql * tl)) * is_ - (double)k * s * krc * Dm1;
     }
+    if (k >= 3 && k - 2 < n) {
+      const double iN = T->invN[k - 3];
+      ba[k - 3] += scale * I * iN;
+      if (DERIV) dba[k - 3] += (dscale * I + scale * (Dmu * dmu_dr + Ds * ds_dr)) * iN;
+    }
+    Im2 = Im1;
+    Im1 = I;
+    Dm1 = Dmu;
+    qh1 = qh;
+    ql1 = ql;
+    qh *= uh;
+    ql *= ul;
   }
 }
 
@@ -131,41 +149,34 @@ __device__ inline void gauss_basis(double mu, double s, double s0, double& B, do
 template <int NMAX, bool DERIV>
 __device__ inline void radial(const DevParams& P, const DevTables* __restrict__ T, double r, double (&Bk)[NMAX],
                               double (&dBk)[NMAX]) {
-  constexpr int KM = NMAX + 2;  // b_alpha needs I_3..I_{n+1}
   const int n = P.n;
   const double s = P.s0r + P.ar * r;
-  double I[KM], Imu[KM], Is[KM];
-  overlap_integrals<KM, DERIV>(0.0, P.rs, r, s, P.rc, I, Imu, Is);
+  double ba[NMAX], dba[NMAX];
+#pragma unroll
+  for (int a = 0; a < NMAX; ++a) {
+    ba[a] = 0.0;
+    dba[a] = 0.0;
+  }
+  // [0, r_soft]: the neighbour's Gaussian itself (mu = r, width sigma_r(r))
+  overlap_stream<NMAX, DERIV>(T, n, 0.0, P.rs, r, s, P.rc, 1.0, 0.0, 1.0, P.ar, ba, dba);
   if (P.buffer) {
     // f(t) G(t) on [r_soft, r_hard] = C exp(-(t - mu')^2 / (2 s'^2))
     const double D = P.rc - P.rs, d2 = D * D / (P.nf * P.nf);
     const double s2 = s * s, sp2 = 1.0 / (1.0 / s2 + 1.0 / d2), sp = sqrt(sp2);
     const double mup = sp2 * (r / s2 + P.rs / d2);
     const double C = exp(-(r - P.rs) * (r - P.rs) / (2.0 * (s2 + d2)));
-    double J[KM], Jmu[KM], Js[KM];
-    overlap_integrals<KM, DERIV>(P.rs, P.rc, mup, sp, P.rc, J, Jmu, Js);
+    double dC = 0.0, dmup = 0.0, dsp = 0.0;
     if (DERIV) {
       const double dC_mu = -C * (r - P.rs) / (s2 + d2);
       const double dC_s = C * (r - P.rs) * (r - P.rs) * s / ((s2 + d2) * (s2 + d2));
       const double dsp_s = sp2 * sp / (s2 * s);
       const double dmup_mu = sp2 / s2;
       const double dmup_s = 2.0 * sp * dsp_s * (r / s2 + P.rs / d2) - 2.0 * sp2 * r / (s2 * s);
-#pragma unroll
-      for (int k = 0; k < KM; ++k) {
-        Imu[k] += dC_mu * J[k] + C * Jmu[k] * dmup_mu;
-        Is[k] += dC_s * J[k] + C * (Jmu[k] * dmup_s + Js[k] * dsp_s);
-      }
+      dC = dC_mu + dC_s * P.ar;
+      dmup = dmup_mu + dmup_s * P.ar;
+      dsp = dsp_s * P.ar;
     }
-#pragma unroll
-    for (int k = 0; k < KM; ++k) I[k] += C * J[k];
-  }
-  double ba[NMAX], dba[NMAX];
-#pragma unroll
-  for (int al = 1; al < NMAX; ++al) {
-    if (al < n) {
-      ba[al - 1] = I[al + 2] * T->invN[al - 1];
-      if (DERIV) dba[al - 1] = (Imu[al + 2] + Is[al + 2] * P.ar) * T->invN[al - 1];
-    }
+    overlap_stream<NMAX, DERIV>(T, n, P.rs, P.rc, mup, sp, P.rc, C, dC, dmup, dsp, ba, dba);
   }
   {
     double B, dBmu, dBs;
@@ -194,7 +205,7 @@ __device__ inline void radial(const DevParams& P, const DevTables* __restrict__ 
 #pragma unroll
       for (int al = 0; al < NMAX; ++al) {
         if (al < n) {
-          const double w = T->W[k * n + al];
+          const double w = T->W[k * kMaxN + al];
           acc = fma(w, ba[al], acc);
           if (DERIV) dacc = fma(w, dba[al], dacc);
         }
@@ -206,33 +217,39 @@ __device__ inline void radial(const DevParams& P, const DevTables* __restrict__ 
 }
 
 // e_l(z) = exp(-z) i_l(z) for l = 0..lmax (lmax <= LM), z > 0.
+// Large z: the recursion e_l = e_{l-2} - (2l-1)/z e_{l-1} upward from the
+// closed forms of e_0 and e_1 (Sec. III.C).  Small z, where that direction
+// loses digits: the power series of the two highest orders, with tabulated
+// reciprocals rec_top (order lmax) and rec_sub (order lmax - 1), then the same
+// recursion downward, which is stable.
 template <int LM>
-__device__ inline void ilexp(double z, int lmax, double (&e)[LM + 1]) {
+__device__ inline void ilexp(double z, int lmax, const double* __restrict__ rec_top,
+                             const double* __restrict__ rec_sub, const double* __restrict__ idf,
+                             double (&e)[LM + 1]) {
+  const double iz = 1.0 / z;
   if (lmax == 0 || z >= kIlexpSeriesBelow) {
     const double em = expm1(-2.0 * z);
-    e[0] = -em / (2.0 * z);
-    if (lmax >= 1) e[1] = (z - 1.0 + (em + 1.0) * (z + 1.0)) / (2.0 * z * z);
+    e[0] = -em * 0.5 * iz;
+    if (lmax >= 1) e[1] = (z - 1.0 + (em + 1.0) * (z + 1.0)) * 0.5 * iz * iz;
 #pragma unroll
     for (int l = 2; l <= LM; ++l)
-      if (l <= lmax) e[l] = e[l - 2] - (double)(2 * l - 1) / z * e[l - 1];
+      if (l <= lmax) e[l] = e[l - 2] - (double)(2 * l - 1) * iz * e[l - 1];
     return;
   }
-  // power series i_l(z) = z^l / (2l+1)!! sum_k (z^2/2)^k / (k! (2l+3)(2l+5)..(2l+2k+1))
-  // for l = lmax and lmax - 1, then e_{l-1} = e_{l+1} + (2l+1)/z e_l downward.
+  // i_l(z) = z^l / (2l+1)!! sum_k (z^2/2)^k / (k! (2l+3)(2l+5)..(2l+2k+1))
   const int L = lmax;
-  double t1 = 1.0;
-  for (int j = 1; j < L; ++j) t1 *= z / (double)(2 * j + 1);
-  double t0 = t1 * z / (double)(2 * L + 1);  // z^L / (2L+1)!!
+  double zl = 1.0;
+  for (int j = 1; j < L; ++j) zl *= z;
+  double t1 = zl * idf[L - 1];  // z^(L-1) / (2L-1)!!
+  double t0 = zl * z * idf[L];  // z^L / (2L+1)!!
   const double h = 0.5 * z * z;
   double s0 = 0.0, s1 = 0.0;
-  for (int k = 0; k < 200; ++k) {
+#pragma unroll
+  for (int k = 0; k < kIlexpTerms; ++k) {
     s0 += t0;
     s1 += t1;
-    const double n0 = t0 * h / ((double)(k + 1) * (double)(2 * L + 2 * k + 3));
-    const double n1 = t1 * h / ((double)(k + 1) * (double)(2 * L + 2 * k + 1));
-    if (n0 < 1e-17 * s0 && n1 < 1e-17 * s1 && n0 < t0) break;
-    t0 = n0;
-    t1 = n1;
+    t0 *= h * rec_top[k];
+    t1 *= h * rec_sub[k];
   }
   const double ez = exp(-z);
   double up = ez * s0, cur = ez * s1;  // e_L, e_{L-1}
@@ -244,7 +261,7 @@ __device__ inline void ilexp(double z, int lmax, double (&e)[LM + 1]) {
 #pragma unroll
   for (int l = LM - 1; l >= 1; --l) {
     if (l <= L - 1) {
-      const double nxt = up + (double)(2 * l + 1) / z * cur;  // e_{l-1}
+      const double nxt = up + (double)(2 * l + 1) * iz * cur;  // e_{l-1}
       e[l - 1] = nxt;
       up = cur;
       cur = nxt;
@@ -253,6 +270,8 @@ __device__ inline void ilexp(double z, int lmax, double (&e)[LM + 1]) {
 }
 
 __host__ __device__ constexpr int lm_tri(int l, int m) { return l * (l + 1) / 2 + m; }
+// m-major triangular index: entries l = m..kMaxL of column m are contiguous
+__host__ __device__ constexpr int ym_index(int m, int l) { return m * (kMaxL + 1) - m * (m - 1) / 2 + (l - m); }
 
 // Real spherical harmonics of a unit vector u (Condon-Shortley-free real form):
 //   Y[l^2 + l]     = Qbar_l0(u_z)
