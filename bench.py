@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--workload", default="box4096_n8l8")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, run a plain 512 MiB device-to-device copy three times "
+                         "(the reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -159,6 +162,14 @@ def main():
     d = per_stage[dom]
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"],
                 "unit": d["unit"], "frac": round(d["frac"], 4), "traffic": None}
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
