@@ -9,6 +9,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsoap.so")
+# an alternative build of the same library (e.g. other compile-time tuning) can be named here
+LIB_PATH = os.environ.get("SOAP_LIBRARY", LIB_PATH)
 
 SOAP_OK, SOAP_EINVAL, SOAP_ENOMEM, SOAP_EOVERFLOW, SOAP_EHIP, SOAP_ENOTSUP = 0, -1, -2, -3, -4, -5
 SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3 = 0, 1, 2, 3

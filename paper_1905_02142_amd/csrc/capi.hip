@@ -41,7 +41,7 @@ struct soap_ctx {
   Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_atoms, counts, scan_part,
       errflag;
   // descriptor / adjoint
-  Buf c, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
+  Buf rows, bc, c, cbar, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
   // stage timing
   struct Rec {
     int stage;
@@ -121,33 +121,6 @@ soap_status check_params(const soap_params* p, std::string& why) {
   return SOAP_OK;
 }
 
-void build_ylm_tables(soap::DevTables& t) {
-  // Qbar_mm = sqrt(2)^(m>0) N_mm (2m-1)!!, by Q_mm = Q_{m-1,m-1} sqrt((2m+1)/(2m))
-  double qmm = 0.28209479177387814;  // 1/sqrt(4 pi)
-  for (int m = 0; m <= soap::kMaxL + 1; ++m) {
-    if (m > 0) qmm *= std::sqrt((2.0 * m + 1.0) / (2.0 * m));
-    t.ymm[m] = (m > 0) ? qmm * std::sqrt(2.0) : qmm;
-  }
-  for (int l = 0; l <= soap::kMaxL; ++l)
-    for (int m = 0; m <= l; ++m) {
-      const int k = soap::lm_tri(l, m);
-      if (l == m) {
-        t.ya[k] = t.yb[k] = 0.0;
-        continue;
-      }
-      const double l2m2 = (double)(l * l - m * m);
-      t.ya[k] = std::sqrt((4.0 * l * l - 1.0) / l2m2);
-      const double num = ((double)((l - 1) * (l - 1) - m * m)) * (2.0 * l + 1.0);
-      const double den = (2.0 * l - 3.0) * l2m2;
-      t.yb[k] = (num == 0.0) ? 0.0 : std::sqrt(num / den);
-    }
-  for (int m = 0; m <= soap::kMaxL; ++m)
-    for (int l = m; l <= soap::kMaxL; ++l) {
-      t.ym_a[soap::ym_index(m, l)] = t.ya[soap::lm_tri(l, m)];
-      t.ym_b[soap::ym_index(m, l)] = t.yb[soap::lm_tri(l, m)];
-    }
-}
-
 soap_status check_nlist(soap_ctx* ctx, const soap_nlist* nl) {
   if (!nl) return fail(ctx, SOAP_EINVAL, "null neighbour list");
   if (nl->n_atoms < 0 || nl->n_pairs < 0) return fail(ctx, SOAP_EINVAL, "negative sizes in neighbour list");
@@ -207,13 +180,18 @@ struct StageTimer {
 
 // forward descriptor into the context's buffers (c, q, |p|)
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
-                    hipStream_t st) {
+                    bool deriv, hipStream_t st) {
   const soap::DevParams& P = ctx->dp;
-  const size_t N = (size_t)nl->n_atoms;
-  SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * P.nch * P.LL);
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
+  SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
+  SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (NP > 0 ? NP : 1) * soap::pair_row_doubles(P));
+  SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
-  SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                        species, (double*)ctx->c.p, q, P.K, pnorm, st));
+  SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, deriv,
+                                       (double*)ctx->bc.p, st));
+  SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
+                                        (const double*)ctx->rows.p, (const double*)ctx->bc.p, (double*)ctx->c.p, q,
+                                        P.K, pnorm, st));
   return SOAP_OK;
 }
 
@@ -276,7 +254,6 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
     for (int al = 0; al < d.n; ++al) t.W[k * soap::kMaxN + al] = W[k * d.n + al];
   for (int al = 1; al < d.n; ++al) t.invN[al - 1] = std::sqrt((2.0 * al + 5.0) / d.rc);
   for (int l = 0; l <= soap::kMaxL + 1; ++l) t.lw[l] = p->l_weight ? 1.0 : 2.0 * l + 1.0;
-  build_ylm_tables(t);
   soap::build_angular_tables(d, t);
   if (hipGetDevice(&ctx->device) != hipSuccess || hipMalloc((void**)&ctx->dt, sizeof(soap::DevTables)) != hipSuccess) {
     delete ctx;
@@ -294,7 +271,7 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
 void soap_destroy(soap_ctx* ctx) {
   if (!ctx) return;
   Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
-                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->c,
+                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c, &ctx->cbar,
                  &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp};
   for (Buf* b : bufs)
     if (b->p) hipFree(b->p);
@@ -462,7 +439,7 @@ soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* 
     SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * (size_t)nl->n_atoms);
     pn = (double*)ctx->pnorm.p;
   }
-  return forward(ctx, nl, species, q, pn, st);
+  return forward(ctx, nl, species, q, pn, false, st);
 }
 
 soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_bar,
@@ -480,12 +457,13 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
   SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
   SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
-  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, st)) != SOAP_OK) return s;
+  SOAP_ENSURE(ctx, ctx->cbar, sizeof(double) * N * soap::c_doubles_per_atom(P));
+  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, true, st)) != SOAP_OK) return s;
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
-    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                            species, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
-                                            (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->gx.p,
+    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
+                                            (const double*)ctx->rows.p, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                            (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->cbar.p, (double*)ctx->gx.p,
                                             (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
@@ -512,7 +490,8 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   }
   SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
   SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
-  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, st)) != SOAP_OK) return s;
+  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, forces != nullptr, st)) != SOAP_OK)
+    return s;
   double* qbar = nullptr;
   if (forces) {
     SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * N * P.K);
@@ -533,11 +512,12 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
+    SOAP_ENSURE(ctx, ctx->cbar, sizeof(double) * N * soap::c_doubles_per_atom(P));
     {
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
-      SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, nl->dx, nl->dy, nl->dz,
-                                              species, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
-                                              (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->gx.p,
+      SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
+                                              (const double*)ctx->rows.p, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                              (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->cbar.p, (double*)ctx->gx.p,
                                               (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);

@@ -207,24 +207,32 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
   if (!FILL && lane == 0) count[i] = cnt;
 }
 
-// rev[p]: the pair (j -> i, -T) in j's list
-__global__ void k_reverse(long long n_pairs, const int* __restrict__ offsets, const int* __restrict__ nj,
-                          const int* __restrict__ nimg, const int* __restrict__ ncenter, int* __restrict__ rev,
-                          int* __restrict__ err) {
-  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  const int i = ncenter[p], j = nj[p];
-  int T[3];
-  unpack_img(nimg[p], T);
-  const int want = pack_img(-T[0], -T[1], -T[2]);
-  int found = -1;
-  for (int q = offsets[j]; q < offsets[j + 1]; ++q)
-    if (nj[q] == i && nimg[q] == want) {
-      found = q;
-      break;
-    }
-  if (found < 0) atomicOr(err, kErrNoReverse);
-  rev[p] = found < 0 ? (int)p : found;
+// rev[p]: the pair (j -> i, -T) in j's list.  16 lanes per pair probe j's list
+// with coalesced loads; the match is unique, so the minimum over the lanes is it.
+__global__ __launch_bounds__(256) void k_reverse(long long n_pairs, const int* __restrict__ offsets,
+                                                 const int* __restrict__ nj, const int* __restrict__ nimg,
+                                                 const int* __restrict__ ncenter, int* __restrict__ rev,
+                                                 int* __restrict__ err) {
+  const long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sub = threadIdx.x & 15;
+  int found = 0x7fffffff;
+  if (p < n_pairs) {
+    const int i = ncenter[p], j = nj[p];
+    int T[3];
+    unpack_img(nimg[p], T);
+    const int want = pack_img(-T[0], -T[1], -T[2]);
+    for (int q = offsets[j] + sub; q < offsets[j + 1]; q += 16)
+      if (nj[q] == i && nimg[q] == want) {
+        found = q;
+        break;
+      }
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) found = min(found, __shfl_xor(found, o, 16));
+  if (p < n_pairs && sub == 0) {
+    if (found == 0x7fffffff) atomicOr(err, kErrNoReverse);
+    rev[p] = found == 0x7fffffff ? (int)p : found;
+  }
 }
 
 // ---------------------------------------------------------------- scan
@@ -337,8 +345,8 @@ hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructM
 hipError_t launch_reverse(long long n_pairs, const int* offsets, const int* nj, const int* nimg, const int* ncenter,
                           int* rev, int* err, hipStream_t st) {
   if (n_pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reverse, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, st, n_pairs, offsets, nj,
-                     nimg, ncenter, rev, err);
+  hipLaunchKernelGGL(k_reverse, dim3((unsigned)((n_pairs + 15) / 16)), dim3(256), 0, st, n_pairs, offsets, nj, nimg,
+                     ncenter, rev, err);
   return hipGetLastError();
 }
 

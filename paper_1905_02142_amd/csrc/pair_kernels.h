@@ -9,20 +9,31 @@ namespace soap {
 
 size_t descriptor_lds_bytes(const DevParams& P);
 size_t adjoint_lds_bytes(const DevParams& P);
+// c and cbar workspace per atom: [species][lm < LL + 1][k < NMAX] doubles (NMAX =
+// the compiled n_max bucket; the column lm = LL is a sink for unused records)
+size_t c_doubles_per_atom(const DevParams& P);
+// doubles per neighbour pair of the shared pair rows (radial, ilexp, azimuthal
+// factors and their r-derivatives)
+size_t pair_row_doubles(const DevParams& P);
 
-// c (n_atoms x nch x LL), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
+// pair rows for n_pairs neighbours (derivative part only if deriv) and the
+// central-atom radial factors bc (n_max doubles)
+hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
+                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, hipStream_t st);
+
+// c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                             const double* dx, const double* dy, const double* dz, const int* species, double* c,
-                             double* q, int q_pitch, double* pnorm, hipStream_t st);
+                             const int* species, const double* rows, const double* bc, double* c, double* q,
+                             int q_pitch, double* pnorm, hipStream_t st);
 
-// pair gradients g_p = dE/dd_p (SoA) from qbar = dE/dq and the forward c, q, |p|
+// pair gradients g_p = dE/dd_p (SoA) from qbar = dE/dq, the forward c, q, |p| and
+// the pair rows with derivatives; cbar is workspace of n_atoms x c_doubles_per_atom
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
-                               const int* nj, const double* dx, const double* dy, const double* dz,
-                               const int* species, const double* c, const double* q, int q_pitch,
-                               const double* pnorm, const double* qbar, int qbar_pitch, double* gx, double* gy,
-                               double* gz, hipStream_t st);
+                               const int* nj, const int* species, const double* rows, const double* c,
+                               const double* q, int q_pitch, const double* pnorm, const double* qbar, int qbar_pitch,
+                               double* cbar, double* gx, double* gy, double* gz, hipStream_t st);
 
-// angular slot order and ilexp series tables for these parameters
+// angular records (Qbar_lm polynomials) and ilexp series tables for these parameters
 void build_angular_tables(const DevParams& P, DevTables& T);
 
 // out = F (overwrite) or pos_grad -= F (accumulate_grad)

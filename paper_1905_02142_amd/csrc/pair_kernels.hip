@@ -1,28 +1,37 @@
 // Descriptor forward and adjoint kernels (FP64 VALU).
 //
-// Forward, one 64-lane wavefront per centre atom i (Sec. II, Eqs. (05), (08), (09)):
-//   1. per-pair phase: each lane takes one neighbour of a 64-neighbour chunk and
-//      computes B_k = 4 pi A b_k (radial recursion and orthonormal transform,
-//      staged in LDS) and w_l e_l (ilexp, kept in registers);
-//   2. the real spherical harmonics are produced in NP passes over fixed slices
-//      of the angular slots (m-major order), so only one slice of the
-//      64 x L^2 angular table sits in LDS at a time;
-//   3. accumulation c[k][lm] += B_k Ang_lm: lane (pg, sl) owns the channels k of
-//      the slots sl, sl + SL, .. of every pass and the neighbours of pair group
-//      pg, so one LDS read of a B row feeds NMAX FMAs per owned slot;
-//   4. the PG partial sums are combined by DPP quad shuffles, the central atom is
-//      added, c is stored (the adjoint re-reads it), and p_{ab l} =
-//      sum_m c[a][lm] c[b][lm] is formed from c in LDS and normalised.
-// Neighbours of species s are compacted with a wave ballot and accumulated
-// together, so one register tile serves every species block.
+// k_pair_prep, one thread per neighbour pair i -> j (d = r_j + T - r_i, r = |d|,
+// u = d / r): everything of Eq. (08) that depends on the pair alone, written to
+// a row in HBM that the forward and the adjoint kernels share:
+//   B_k = 4 pi A b_k          radial overlaps, Eqs. (02), (04), (19), (06), Eq. (15)
+//   w_l e_l                   ilexp, Sec. III.C
+//   (u_x + i u_y)^m, u_z      the azimuthal factors of the real harmonics
+// and, for forces, dB_k/dr, d(w_l e_l)/dr, u_x, u_y and 1/r.
 //
-// Adjoint, one wavefront per centre atom:
-//   qbar -> vbar = (qbar - q (q.qbar)) / |p| -> cbar = M c (M from vbar) in LDS,
-//   then one lane per neighbour recomputes B, dB/dr, e_l, de_l/dz, Y_lm and
-//   grad Y_lm and contracts them with cbar into the pair gradient g = dE/dd.
-// Forces are gathered per atom through the reverse-pair index: no atomics, so
-// FP64 results are bitwise reproducible.
+// k_descriptor, one 64-lane wavefront per centre atom.  Its neighbours of one
+// species are compacted with a wave ballot and their rows staged in LDS, 64 at
+// a time.  Lane (g, j), g = lane / 16, j = lane % 16: the four 16-lane groups
+// take four neighbours per step and lane j owns a fixed set of (l, m) records;
+// it evaluates Qbar_lm(u_z) as a short polynomial and accumulates both real
+// harmonics of each record times every B_k in registers:
+//   c_{k,lm} += B_k w_l e_l Y_lm                                    (Eq. (08))
+// The four groups are added with cross-row lane swaps, the central atom joins
+// l = 0, and c goes to HBM.  The power spectrum p_{ab l} = sum_m c_{a,lm} c_{b,lm}
+// (the real form of Eq. (09)), packed a <= b then l with sqrt(2) off the
+// diagonal, and q = p / |p| follow from c staged in LDS.
+//
+// Adjoint: k_cbar forms vbar = (qbar - q (q.qbar)) / |p| and cbar = M c
+// (M_aa = 2 vbar_aal, M_ab = sqrt(2) vbar_abl), the derivative of the power
+// spectrum and of the normalisation.  k_pair_adjoint stages the same rows and
+// lane (g, j) contracts its records' cbar (held in registers) with them:
+//   U_lm = sum_k cbar_{k,lm} dB_k/dr,  V_lm = sum_k cbar_{k,lm} B_k,
+//   dE/dd = sum_lm [(U_lm a_lm + V_lm da_lm/dr) u + V_lm w_l e_l (I - u u^T) grad_u Y_lm / r]
+// with a_lm = w_l e_l Y_lm; the 16 lanes of a group are summed by DPP.  Forces
+// are gathered per atom through the reverse-pair index: no atomics, so FP64
+// results are bitwise reproducible.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 #include "pair_kernels.h"
 #include "soap_device.h"
@@ -40,6 +49,37 @@ __device__ inline double dpp_move(double v) {
 }
 constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kRowRor4 = 0x124;  // rotate each 16-lane row by 4
+constexpr int kRowRor8 = 0x128;  // rotate each 16-lane row by 8
+
+// sum over the 16 lanes of each row; every lane of the row gets the total
+__device__ inline double row_sum(double v) {
+  v += dpp_move<kQuadXor1>(v);
+  v += dpp_move<kQuadXor2>(v);
+  v += dpp_move<kRowRor4>(v);
+  v += dpp_move<kRowRor8>(v);
+  return v;
+}
+
+// v(lane) + v(lane ^ 16) + v(lane ^ 32) + v(lane ^ 48): the four 16-lane rows
+// summed without LDS.  permlane16_swap(x, x) returns the rows {0,0,2,2} and
+// {1,1,3,3} of x, and permlane32_swap(x, x) the halves {0,0} and {1,1}, so each
+// pair of results sums to the partner sum.
+__device__ inline double sum_rows(double v) {
+  {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    v = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+  }
+  {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    v = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+  }
+  return v;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -59,209 +99,282 @@ __device__ inline void ab_decode(int ab, int nch, int& a, int& b) {
   b = a + ab;
 }
 
-// Writes row[slot - s0] = we[l] Y(slot) for the angular slots s0 <= slot < s1.
-// Slot order: m = 0 (l = 0..lmax), then for m = 1..lmax and l = m..lmax the
-// pair (l, +m), (l, -m).  Y(l, +m) = Qbar_lm(u_z) Re (u_x + i u_y)^m,
-// Y(l, -m) = Qbar_lm(u_z) Im (u_x + i u_y)^m, Y(l, 0) = Qbar_l0(u_z), with
-// Qbar_lm = sqrt(2)^(m>0) N_lm d^m P_l/dz^m (pole-free; see the host tables).
-// recursion factors staged in LDS once per workgroup (m-major, see ym_index)
-struct YTab {
-  double a[kMaxLM];
-  double b[kMaxLM];
-  double mm[kMaxL + 2];
-};
-
-__device__ inline void stage_ytab(const DevTables* __restrict__ T, YTab& y, int lane) {
-  for (int t = lane; t < kMaxLM; t += 64) {
-    y.a[t] = T->ym_a[t];
-    y.b[t] = T->ym_b[t];
-  }
-  if (lane < kMaxL + 2) y.mm[lane] = T->ymm[lane];
+__device__ inline int isqrt_small(int v) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= v) ++l;
+  return l;
 }
 
-template <int LMAX>
-__device__ inline void angular_slots(const YTab& Y, int lmax, double ux, double uy, double uz,
-                                     const double (&we)[LMAX + 1], int s0, int s1, double* __restrict__ row) {
-  double cr = 1.0, ci = 0.0;
-  int g = 0;
-  for (int m = 0; m <= lmax && g < s1; ++m) {
-    const int cnt = (m == 0) ? lmax + 1 : 2 * (lmax - m + 1);
-    if (g + cnt > s0) {
-      const double* ya = Y.a + ym_index(m, m) - m;  // ya[l] = factor of (l, m)
-      const double* yb = Y.b + ym_index(m, m) - m;
-      double q2 = 0.0, q1 = Y.mm[m];
-      int slot = g;
+constexpr int even(int w) { return w + (w & 1); }
+// LDS row strides: even (16-byte rows) and not a multiple of 8 doubles, so the
+// four rows read together by the four lane groups fall in different banks
+constexpr int pad_row(int w) {
+  w = even(w);
+  while (w % 16 == 0 || w % 16 == 8) w += 2;
+  return w;
+}
+
+template <int NMAX, int LMAX>
+struct Shape {
+  static constexpr int NREC = (LMAX + 1) * (LMAX + 2) / 2;
+  static constexpr int E = (NREC + kRecLanes - 1) / kRecLanes;  // records per lane
+  static constexpr int EP = E < 3 ? E : 3;                      // records per pass
+  static constexpr int NPASS = (E + EP - 1) / EP;
+  static constexpr int NC = LMAX / 2 + 1;  // polynomial terms in u_z^2
+  // pair row, forward part: (u_x + i u_y)^m (m = 0..LMAX) | B_k | w_l e_l | u_z
+  static constexpr int FZ = 0, FB = 2 * (LMAX + 1), FW = FB + NMAX, FU = FW + LMAX + 1;
+  static constexpr int FR = even(FU + 1);
+  // derivative part: dB_k/dr | d(w_l e_l)/dr | u_x u_y 1/r
+  static constexpr int XD = 0, XW = NMAX, XU = XW + LMAX + 1;
+  static constexpr int XR = even(XU + 3);
+  static constexpr int ROW = FR + XR;  // doubles per pair in HBM
+  // LDS staging: forward rows (FR) of CH pairs, adjoint rows (FR + XR) of ACH pairs
+  static constexpr int CH = 64, LFR = pad_row(FR);
+  static constexpr int ACH = 32, LAR = pad_row(FR + XR);
+};
+
+// the records of the 16 lanes (polynomial coefficients, (l, m, parity), c
+// columns), staged in LDS; lm < 0 (no harmonic) maps to the sink column LL
+template <int E, int NC>
+struct RecTab {
+  double cf[kRecLanes][E][NC];
+  int lmp[kRecLanes][E];
+  int lm[kRecLanes][E][2];
+};
+
+template <int E, int NC>
+__device__ inline void stage_records(const DevTables* __restrict__ T, RecTab<E, NC>& r, int LL, int lane) {
+  for (int x = lane; x < kRecLanes * E * NC; x += 64) {
+    const int j = x / (E * NC), e = (x / NC) % E, t = x % NC;
+    r.cf[j][e][t] = T->rec_coef[j][e][t];
+  }
+  for (int x = lane; x < kRecLanes * E; x += 64) {
+    const int j = x / E, e = x % E;
+    r.lmp[j][e] = T->rec_lmp[j][e];
+    const int lc = T->rec_lm[j][e][0], ls = T->rec_lm[j][e][1];
+    r.lm[j][e][0] = lc < 0 ? LL : lc;
+    r.lm[j][e][1] = ls < 0 ? LL : ls;
+  }
+}
+
+// one lane's records of a pass (records past E: zero polynomial, sink columns)
+template <int EP, int NC>
+struct Records {
+  double cf[EP][NC];
+  int l[EP], m[EP], par[EP];
+  int lmc[EP], lms[EP];
+};
+
+template <int E, int EP, int NC>
+__device__ inline void load_records(const RecTab<E, NC>& t, int j, int e0, int LL, Records<EP, NC>& R) {
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) {
-        if (l >= m && l <= lmax) {
-          double q = q1;
-          if (l > m) {
-            q = ya[l] * uz * q1 - yb[l] * q2;
-            q2 = q1;
-            q1 = q;
-          }
-          const double v = we[l] * q;
-          if (m == 0) {
-            if (slot >= s0 && slot < s1) row[slot - s0] = v;
-            slot += 1;
-          } else {
-            if (slot >= s0 && slot < s1) row[slot - s0] = v * cr;
-            if (slot + 1 >= s0 && slot + 1 < s1) row[slot + 1 - s0] = v * ci;
-            slot += 2;
-          }
-        }
-      }
-    }
-    g += cnt;
+  for (int e = 0; e < EP; ++e) {
+    const bool ok = e0 + e < E;
+    const int ee = ok ? e0 + e : 0;
+    const int info = ok ? t.lmp[j][ee] : 0;
+    R.l[e] = info & 255;
+    R.m[e] = (info >> 8) & 255;
+    R.par[e] = info >> 16;
+    R.lmc[e] = ok ? t.lm[j][ee][0] : LL;
+    R.lms[e] = ok ? t.lm[j][ee][1] : LL;
+#pragma unroll
+    for (int x = 0; x < NC; ++x) R.cf[e][x] = ok ? t.cf[j][ee][x] : 0.0;
+  }
+}
+
+template <int NMAX, int LMAX, bool DERIV>
+__global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int n_pairs,
+                                                     const double* __restrict__ dx, const double* __restrict__ dy,
+                                                     const double* __restrict__ dz, double* __restrict__ rows,
+                                                     double* __restrict__ bc) {
+  using S = Shape<NMAX, LMAX>;
+  __shared__ PairTab<NMAX, LMAX> tab;
+  stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, 256);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // central atom: a Gaussian at r = 0, where e_0 = 1, e_{l>0} = 0, Y_00 = 1 / sqrt(4 pi)
+    double B[NMAX], dB[NMAX];
+    radial<NMAX, false>(P, tab, 0.0, B, dB);
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * tab.lw[0] * 0.28209479177387814;
+  }
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_pairs) return;
+  const double x = dx[p], y = dy[p], z = dz[p];
+  const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
+  double* __restrict__ row = rows + (size_t)p * S::ROW;
+  double B[NMAX], dB[NMAX];
+  radial<NMAX, DERIV>(P, tab, r, B, dB);
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    row[S::FB + k] = B[k];
+    if (DERIV) row[S::FR + S::XD + k] = dB[k];
+  }
+  const double sp = P.s0p + P.ap * r;
+  const double zz = r * r / (sp * sp);
+  constexpr int LE = DERIV ? LMAX + 1 : LMAX;
+  double e[LE + 1];
+#pragma unroll
+  for (int l = 0; l <= LE; ++l) e[l] = 0.0;
+  ilexp<LE>(zz, P.l + (DERIV ? 1 : 0), tab.rec[DERIV ? 2 : 1], tab.rec[DERIV ? 1 : 0], tab.idf, e);
+  const double izz = 1.0 / zz;
+  const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
+#pragma unroll
+  for (int l = 0; l <= LMAX; ++l) {
+    row[S::FW + l] = tab.lw[l] * e[l];
+    // d e_l / dz = e_{l+1} + (l/z - 1) e_l
+    if (DERIV) row[S::FR + S::XW + l] = tab.lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr;
+  }
+  const double ux = x * ir, uy = y * ir, uz = z * ir;
+  double cr = 1.0, ci = 0.0;
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) {
+    row[S::FZ + 2 * m] = cr;
+    row[S::FZ + 2 * m + 1] = ci;
     const double nr = cr * ux - ci * uy;
     ci = cr * uy + ci * ux;
     cr = nr;
   }
+  row[S::FU] = uz;
+  if (DERIV) {
+    row[S::FR + S::XU] = ux;
+    row[S::FR + S::XU + 1] = uy;
+    row[S::FR + S::XU + 2] = ir;
+  }
 }
 
-template <int NMAX, int LMAX, int PG, int NP>
-struct FwdShape {
-  static constexpr int LLM = (LMAX + 1) * (LMAX + 1);
-  static constexpr int S = (LLM + NP - 1) / NP;  // slots per pass
-  static constexpr int SL = 64 / PG;
-  static constexpr int LMSP = (S + SL - 1) / SL;
-  static constexpr int AST = S + 1;
-  static constexpr int BST = NMAX + 1;
-};
+// copy the first `width` doubles (16-byte units) of the compacted pairs' rows into LDS
+__device__ inline void stage_rows(const double* __restrict__ rows, int row_stride, const int* idx, int cnt,
+                                  int width, double* __restrict__ dst, int dst_stride, int lane) {
+  const int units = width / 2;
+  for (int u = lane; u < cnt * units; u += 64) {
+    const int t = u / units, part = u - t * units;
+    const double2 v = *reinterpret_cast<const double2*>(rows + (size_t)idx[t] * row_stride + 2 * part);
+    *reinterpret_cast<double2*>(dst + t * dst_stride + 2 * part) = v;
+  }
+}
 
-template <int NMAX, int LMAX, int PG, int NP>
+template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                      const int* __restrict__ offsets, const int* __restrict__ nj,
-                                                      const double* __restrict__ dx, const double* __restrict__ dy,
-                                                      const double* __restrict__ dz, const int* __restrict__ species,
-                                                      double* __restrict__ c_out, double* __restrict__ q_out,
-                                                      int q_pitch, double* __restrict__ pnorm_out) {
-  using Sh = FwdShape<NMAX, LMAX, PG, NP>;
-  constexpr int S = Sh::S, SL = Sh::SL, LMSP = Sh::LMSP, AST = Sh::AST, BST = Sh::BST;
-  __shared__ double ang[64 * AST];
-  __shared__ double bsh[64 * BST];
-  __shared__ double bc[NMAX];
+                                                     const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                     const int* __restrict__ species, const double* __restrict__ rows,
+                                                     const double* __restrict__ bc_in, double* __restrict__ c_out,
+                                                     double* __restrict__ q_out, int q_pitch,
+                                                     double* __restrict__ pnorm_out) {
+  using S = Shape<NMAX, LMAX>;
+  constexpr int E = S::E, EP = S::EP, NC = S::NC, LFR = S::LFR;
+  extern __shared__ __align__(16) double dyn[];
   __shared__ int idx[64];
-  __shared__ YTab ytab;
-  extern __shared__ double dyn[];
+  __shared__ double bc[NMAX];
+  __shared__ RecTab<E, NC> rec;
 
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
-  const int lane = threadIdx.x;
-  const int pg = lane % PG, sl = lane / PG;
-  stage_ytab(T, ytab, lane);
-  const int n = P.n, LL = P.LL, nch = P.nch, LLP = LL + 1;
-  double* csh = dyn;
-  double* vsh = dyn + nch * LLP;
+  const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+  const int n = P.n, LL = P.LL, LLP = LL + 1, nch = P.nch;
   const int p0 = offsets[i], p1 = offsets[i + 1];
   const int si = P.ns == 1 ? 0 : species[i];
-
-  if (lane == 0) {
-    double B[NMAX], dB[NMAX];
-    radial<NMAX, false>(P, T, 0.0, B, dB);
-    // r = 0: e_0 = 1, e_{l>0} = 0 and Y_00 = 1 / sqrt(4 pi)
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * T->lw[0] * 0.28209479177387814;
-  }
-  __syncthreads();
+  double* __restrict__ ci_out = c_out + (size_t)i * P.ns * NMAX * LLP;
+  stage_records<E, NC>(T, rec, LL, lane);
+  if (lane < NMAX) bc[lane] = bc_in[lane];
 
   for (int s = 0; s < P.ns; ++s) {
-    double acc[NP][LMSP][NMAX];
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int kk = 0; kk < LMSP; ++kk)
-#pragma unroll
-        for (int k = 0; k < NMAX; ++k) acc[p][kk][k] = 0.0;
-
-    for (int w0 = p0; w0 < p1; w0 += 64) {
+    int w0 = p0;
+    bool first = true;
+    do {
       const int pp = w0 + lane;
       const bool take = pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
       const unsigned long long mask = __ballot(take);
+      __syncthreads();  // the previous chunk is done with idx and the rows
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      if (cnt == 0) continue;
-      // per-pair phase: radial factors to LDS, w_l e_l in registers
-      double we[LMAX + 1];
+      stage_rows(rows, S::ROW, idx, cnt, S::FR, dyn, LFR, lane);
+      __syncthreads();
+#pragma unroll 1
+      for (int pass = 0; pass < S::NPASS; ++pass) {
+        Records<EP, NC> R;
+        load_records<E, EP, NC>(rec, j, pass * EP, LL, R);
+        double acc[EP][2][NMAX];
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) we[l] = 0.0;
-      double ux = 0.0, uy = 0.0, uz = 1.0;
-      if (lane < cnt) {
-        const int q = idx[lane];
-        const double x = dx[q], y = dy[q], z = dz[q];
-        const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-        ux = x * ir;
-        uy = y * ir;
-        uz = z * ir;
-        double B[NMAX], dB[NMAX];
-        radial<NMAX, false>(P, T, r, B, dB);
+        for (int e = 0; e < EP; ++e)
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k) bsh[lane * BST + k] = B[k];
-        __builtin_amdgcn_sched_barrier(0);  // keep the radial and ilexp temporaries apart
-        const double sp = P.s0p + P.ap * r;
-        double e[LMAX + 1];
-        ilexp<LMAX>(r * r / (sp * sp), P.l, T->ilx_rec[1], T->ilx_rec[0], T->ilx_idf, e);
+          for (int k = 0; k < NMAX; ++k) acc[e][0][k] = acc[e][1][k] = 0.0;
+        for (int t = g; t < cnt; t += 4) {
+          const double* __restrict__ row = dyn + t * LFR;
+          double b[NMAX];
 #pragma unroll
-        for (int l = 0; l <= LMAX; ++l) we[l] = T->lw[l] * e[l];
-      }
+          for (int k = 0; k < NMAX; ++k) b[k] = row[S::FB + k];
+          const double uz = row[S::FU], x2 = uz * uz;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int s0 = p * S, s1 = min(s0 + S, LL);
-        if (s0 < LL) {
-          if (lane < cnt) angular_slots<LMAX>(ytab, P.l, ux, uy, uz, we, s0, s1, ang + lane * AST);
-          __syncthreads();
-          for (int t = 0; t < 64 / PG; ++t) {
-            const int pi = pg + PG * t;
-            if (pi >= cnt) break;
-            double b[NMAX];
+          for (int e = 0; e < EP; ++e) {
+            double Rv = R.cf[e][NC - 1];
 #pragma unroll
-            for (int k = 0; k < NMAX; ++k) b[k] = bsh[pi * BST + k];
+            for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, R.cf[e][t2]);
+            const double Q = R.par[e] ? uz * Rv : Rv;
+            const double a = row[S::FW + R.l[e]] * Q;
+            const double a0 = a * row[S::FZ + 2 * R.m[e]], a1 = a * row[S::FZ + 2 * R.m[e] + 1];
 #pragma unroll
-            for (int kk = 0; kk < LMSP; ++kk) {
-              const int sidx = sl + SL * kk;
-              if (s0 + sidx < s1) {
-                const double a = ang[pi * AST + sidx];
+            for (int k = 0; k < NMAX; ++k) {
+              acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
+              acc[e][1][k] = fma(a1, b[k], acc[e][1][k]);
+            }
+          }
+        }
+        // add the four groups' partial sums; group 0 writes (first chunk) or adds
 #pragma unroll
-                for (int k = 0; k < NMAX; ++k) acc[p][kk][k] = fma(a, b[k], acc[p][kk][k]);
+        for (int e = 0; e < EP; ++e)
+#pragma unroll
+          for (int k = 0; k < NMAX; ++k) {
+            acc[e][0][k] = sum_rows(acc[e][0][k]);
+            acc[e][1][k] = sum_rows(acc[e][1][k]);
+          }
+        // c of species s: LL + 1 columns lm (the last one a sink) of NMAX channels
+        double* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
+        if (g == 0) {
+#pragma unroll
+          for (int e = 0; e < EP; ++e) {
+            double* __restrict__ dc = cs + R.lmc[e] * NMAX;
+            double* __restrict__ ds = cs + R.lms[e] * NMAX;
+            if (first) {
+              const bool central = R.lmc[e] == 0 && s == si;
+#pragma unroll
+              for (int k = 0; k < NMAX; ++k) {
+                dc[k] = acc[e][0][k] + (central ? bc[k] : 0.0);
+                ds[k] = acc[e][1][k];
+              }
+            } else {
+#pragma unroll
+              for (int k = 0; k < NMAX; ++k) {
+                dc[k] += acc[e][0][k];
+                ds[k] += acc[e][1][k];
               }
             }
           }
-          __syncthreads();
         }
       }
-    }
-    // combine the pair groups, add the central atom, scatter c into LDS
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int kk = 0; kk < LMSP; ++kk) {
-        const int slot = p * S + sl + SL * kk;
-#pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-          double v = acc[p][kk][k];
-          if (PG >= 2) v += dpp_move<kQuadXor1>(v);
-          if (PG >= 4) v += dpp_move<kQuadXor2>(v);
-          if (slot == 0 && s == si) v += bc[k];
-          if (sl + SL * kk < S && slot < LL && k < n && (k % PG) == pg) csh[(s * n + k) * LLP + T->slot_lm[slot]] = v;
-        }
-      }
+      first = false;
+      w0 += 64;
+    } while (w0 < p1);
+  }
+  __threadfence_block();
+  __syncthreads();
+  // power spectrum from c staged in LDS as csh[a * LL + lm], a = s n + k; p in vsh
+  double* csh = dyn;
+  double* vsh = dyn + nch * LL;
+  for (int t = lane; t < nch * LL; t += 64) {
+    const int a = t / LL, lm = t - a * LL, sa = a / n;
+    csh[t] = ci_out[((size_t)sa * LLP + lm) * NMAX + (a - sa * n)];
   }
   __syncthreads();
-  for (int t = lane; t < nch * LL; t += 64) {
-    const int ch = t / LL, lm = t - ch * LL;
-    c_out[(size_t)i * nch * LL + t] = csh[ch * LLP + lm];
-  }
-  // power spectrum p_{ab l} (real form of Eq. (09)), packed a <= b then l,
-  // off-diagonal scaled by sqrt(2); then q = p / |p|
   const int L1 = P.l + 1;
   double ss = 0.0;
   for (int k = lane; k < P.K; k += 64) {
     const int ab = k / L1, l = k - ab * L1;
     int a, b;
     ab_decode(ab, nch, a, b);
-    const double* ca = csh + a * LLP + l * l;
-    const double* cb = csh + b * LLP + l * l;
+    const double* ca = csh + a * LL + l * l;
+    const double* cb = csh + b * LL + l * l;
     double v = 0.0;
     for (int m = 0; m < 2 * l + 1; ++m) v = fma(ca[m], cb[m], v);
     if (a != b) v *= kSqrt2;
@@ -271,151 +384,184 @@ __global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables*
   ss = wave_sum(ss);
   const double nrm = sqrt(ss);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int k = lane; k < q_pitch; k += 64) q_out[(size_t)i * q_pitch + k] = k < P.K ? vsh[k] * inv : 0.0;
+  double* __restrict__ qi = q_out + (size_t)i * q_pitch;
+  for (int k = lane; k < q_pitch; k += 64) qi[k] = k < P.K ? vsh[k] * inv : 0.0;
   if (lane == 0 && pnorm_out) pnorm_out[i] = nrm;
+}
+
+// vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm}, written
+// in the padded layout of c ([species][lm < LL + 1][k < NMAX]) with zeros in the
+// sink column lm = LL and in the channels k >= n_max
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const double* __restrict__ c,
+                                             const double* __restrict__ q, int q_pitch,
+                                             const double* __restrict__ pnorm, const double* __restrict__ qbar,
+                                             int qbar_pitch, double* __restrict__ cbar) {
+  extern __shared__ __align__(16) double dyn[];
+  const int i = blockIdx.x;
+  if (i >= n_atoms) return;
+  const int lane = threadIdx.x;
+  const int n = P.n, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
+  const size_t per_atom = (size_t)P.ns * NMAX * LLP;
+  double* csh = dyn;  // csh[a * LL + lm], a = s n + k
+  double* vb = dyn + nch * LL;
+  const double* ci = c + (size_t)i * per_atom;
+  for (int t = lane; t < nch * LL; t += 64) {
+    const int a = t / LL, lm = t - a * LL, sa = a / n;
+    csh[t] = ci[((size_t)sa * LLP + lm) * NMAX + (a - sa * n)];
+  }
+  const double* qi = q + (size_t)i * q_pitch;
+  const double* qb = qbar + (size_t)i * qbar_pitch;
+  double dot = 0.0;
+  for (int k = lane; k < K; k += 64) dot = fma(qi[k], qb[k], dot);
+  dot = wave_sum(dot);
+  const double nrm = pnorm[i];
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int k = lane; k < K; k += 64) vb[k] = (qb[k] - qi[k] * dot) * inv;
+  __syncthreads();
+  double* co = cbar + (size_t)i * per_atom;
+  for (int t = lane; t < (int)per_atom; t += 64) {
+    const int col = t / NMAX, k = t - col * NMAX, sa = col / LLP, lm = col - sa * LLP;
+    double s = 0.0;
+    if (k < n && lm < LL) {
+      const int a = sa * n + k, l = isqrt_small(lm);
+      for (int b = 0; b < nch; ++b) {
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        const double w = (a == b) ? 2.0 : kSqrt2;
+        s = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], csh[b * LL + lm], s);
+      }
+    }
+    co[t] = s;
+  }
 }
 
 template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                        const int* __restrict__ offsets, const int* __restrict__ nj,
-                                                        const double* __restrict__ dx, const double* __restrict__ dy,
-                                                        const double* __restrict__ dz,
-                                                        const int* __restrict__ species, const double* __restrict__ c,
-                                                        const double* __restrict__ q, int q_pitch,
-                                                        const double* __restrict__ pnorm,
-                                                        const double* __restrict__ qbar, int qbar_pitch,
-                                                        double* __restrict__ gx, double* __restrict__ gy,
-                                                        double* __restrict__ gz) {
-  extern __shared__ double dyn[];
-  __shared__ YTab ytab;
+                                                       const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                       const int* __restrict__ species,
+                                                       const double* __restrict__ rows,
+                                                       const double* __restrict__ cbar, double* __restrict__ gx,
+                                                       double* __restrict__ gy, double* __restrict__ gz) {
+  using S = Shape<NMAX, LMAX>;
+  constexpr int E = S::E, EP = S::EP, NC = S::NC, LAR = S::LAR, ACH = S::ACH;
+  constexpr int XB = S::FR;  // derivative part of a staged row
+  extern __shared__ __align__(16) double dyn[];
+  __shared__ int idx[64];
+  __shared__ RecTab<E, NC> rec;
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
-  const int lane = threadIdx.x;
-  const int n = P.n, LL = P.LL, nch = P.nch, K = P.K, L1 = P.l + 1;
-  stage_ytab(T, ytab, lane);
-  const int CP = nch + (nch & 1);  // row pitch of the lm-major tables (16-byte rows)
-  double* ct = dyn;                // c[lm][ch]
-  double* cbt = ct + LL * CP;      // cbar[lm][ch]
-  double* vb = cbt + LL * CP;      // vbar (K)
+  const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+  const int LL = P.LL, LLP = LL + 1;
   const int p0 = offsets[i], p1 = offsets[i + 1];
+  double* gacc = dyn + ACH * LAR;  // per-neighbour (S_r, S_x, S_y, S_z)
+  stage_records<E, NC>(T, rec, LL, lane);
 
-  for (int t = lane; t < nch * LL; t += 64) {
-    const int ch = t / LL, lm = t - ch * LL;
-    ct[lm * CP + ch] = c[(size_t)i * nch * LL + t];
-  }
-  // vbar = (qbar - q (q . qbar)) / |p|
-  const double nrm = pnorm[i];
-  double dot = 0.0;
-  for (int k = lane; k < K; k += 64) dot = fma(q[(size_t)i * q_pitch + k], qbar[(size_t)i * qbar_pitch + k], dot);
-  dot = wave_sum(dot);
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int k = lane; k < K; k += 64)
-    vb[k] = (qbar[(size_t)i * qbar_pitch + k] - q[(size_t)i * q_pitch + k] * dot) * inv;
-  __syncthreads();
-  // cbar[a][lm] = sum_b M_ab(l) c[b][lm]; M_aa = 2 vbar_(aa,l), M_ab = sqrt(2) vbar_(ab,l)
-  for (int t = lane; t < nch * LL; t += 64) {
-    const int lm = t / nch, a = t - lm * nch;
-    int l = 0;
-    while ((l + 1) * (l + 1) <= lm) ++l;
-    double s = 0.0;
-    for (int b = 0; b < nch; ++b) {
-      const int lo = a < b ? a : b, hi = a < b ? b : a;
-      const double w = (a == b) ? 2.0 : kSqrt2;
-      s = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], ct[lm * CP + b], s);
+  if (P.ns > 1)  // a neighbour label outside 0..n_species-1 contributes nothing
+    for (int p = p0 + lane; p < p1; p += 64) {
+      const int sj = species[nj[p]];
+      if (sj < 0 || sj >= P.ns) gx[p] = gy[p] = gz[p] = 0.0;
     }
-    cbt[lm * CP + a] = s;
-  }
-  __syncthreads();
-  for (int p = p0 + lane; p < p1; p += 64) {
-    const double x = dx[p], y = dy[p], z = dz[p];
-    const int sj = P.ns == 1 ? 0 : species[nj[p]];
-    if (sj < 0 || sj >= P.ns) {  // a label outside 0..n_species-1 contributes nothing
-      gx[p] = gy[p] = gz[p] = 0.0;
-      continue;
-    }
-    const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-    const double ux = x * ir, uy = y * ir, uz = z * ir;
-    double B[NMAX], dB[NMAX];
-    radial<NMAX, true>(P, T, r, B, dB);
-    __builtin_amdgcn_sched_barrier(0);  // keep the radial and ilexp temporaries apart
-    const double sp = P.s0p + P.ap * r;
-    const double zz = r * r / (sp * sp), izz = 1.0 / zz;
-    const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
-    double e[LMAX + 2];
-    ilexp<LMAX + 1>(zz, P.l + 1, T->ilx_rec[2], T->ilx_rec[1], T->ilx_idf, e);
-    double we[LMAX + 1], wd[LMAX + 1];
+
+  for (int s = 0; s < P.ns; ++s) {
+    const double* __restrict__ cbs = cbar + ((size_t)i * P.ns + s) * LLP * NMAX;
+    for (int w0 = p0; w0 < p1; w0 += ACH) {
+      const int pp = w0 + lane;
+      const bool take = lane < ACH && pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
+      const unsigned long long mask = __ballot(take);
+      __syncthreads();
+      if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
+      const int cnt = __popcll(mask);
+      __syncthreads();
+      if (cnt == 0) continue;
+      stage_rows(rows, S::ROW, idx, cnt, S::ROW, dyn, LAR, lane);
+      __syncthreads();
+#pragma unroll 1
+      for (int pass = 0; pass < S::NPASS; ++pass) {
+        Records<EP, NC> R;
+        load_records<E, EP, NC>(rec, j, pass * EP, LL, R);
+        double cb[EP][2][NMAX];  // zero in the sink column and the channels k >= n_max
 #pragma unroll
-    for (int l = 0; l <= LMAX; ++l) {
-      we[l] = T->lw[l] * e[l];
-      // d e_l / dz = e_{l+1} + (l/z - 1) e_l
-      wd[l] = T->lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr;
-    }
-    const double* base = cbt + sj * n;
-    double gr = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-    double cr = 1.0, ci = 0.0, pr = 0.0, pim = 0.0;  // (u_x + i u_y)^m and ^(m-1)
-    for (int m = 0; m <= P.l; ++m) {
-      const double* ya = ytab.a + ym_index(m, m) - m;
-      const double* yb = ytab.b + ym_index(m, m) - m;
-      double q2 = 0.0, q1 = ytab.mm[m], d2 = 0.0, d1 = 0.0;
+        for (int e = 0; e < EP; ++e)
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) {
-        if (l >= m && l <= P.l) {
-          double qv = q1, dv = d1;
-          if (l > m) {
-            const double a = ya[l], b = yb[l];
-            qv = a * uz * q1 - b * q2;
-            dv = a * (q1 + uz * d1) - b * d2;
-            q2 = q1;
-            q1 = qv;
-            d2 = d1;
-            d1 = dv;
+          for (int k = 0; k < NMAX; ++k) {
+            cb[e][0][k] = cbs[R.lmc[e] * NMAX + k];
+            cb[e][1][k] = cbs[R.lms[e] * NMAX + k];
           }
-          // the two real harmonics of (l, m): cos part at l^2+l+m, sin part at l^2+l-m
+        for (int t = g; t < cnt; t += 4) {
+          const double* __restrict__ row = dyn + t * LAR;
+          double b[NMAX], db[NMAX];
 #pragma unroll
-          for (int part = 0; part < 2; ++part) {
-            if (part == 1 && m == 0) break;
-            const int lm = l * l + l + (part == 0 ? m : -m);
-            const double* cbr = base + lm * CP;
-            double U = 0.0, V = 0.0;
+          for (int k = 0; k < NMAX; ++k) {
+            b[k] = row[S::FB + k];
+            db[k] = row[XB + S::XD + k];
+          }
+          const double uz = row[S::FU], x2 = uz * uz;
+          double sr = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+          for (int e = 0; e < EP; ++e) {
+            // Qbar_lm and its derivative: Q = x^par R(x^2)
+            double Rv = R.cf[e][NC - 1], Rd = 0.0;
+#pragma unroll
+            for (int t2 = NC - 2; t2 >= 0; --t2) {
+              Rd = fma(Rd, x2, Rv);
+              Rv = fma(Rv, x2, R.cf[e][t2]);
+            }
+            const double Q = R.par[e] ? uz * Rv : Rv;
+            const double Qd = R.par[e] ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
+            const int l = R.l[e], m = R.m[e], m1 = m > 0 ? m - 1 : 0;
+            const double we = row[S::FW + l], wd = row[XB + S::XW + l];
+            const double zr = row[S::FZ + 2 * m], zi = row[S::FZ + 2 * m + 1];
+            const double zr1 = row[S::FZ + 2 * m1], zi1 = row[S::FZ + 2 * m1 + 1];
+            double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
 #pragma unroll
             for (int k = 0; k < NMAX; ++k) {
-              if (k < n) {
-                U = fma(cbr[k], dB[k], U);
-                V = fma(cbr[k], B[k], V);
-              }
+              U0 = fma(cb[e][0][k], db[k], U0);
+              V0 = fma(cb[e][0][k], b[k], V0);
+              U1 = fma(cb[e][1][k], db[k], U1);
+              V1 = fma(cb[e][1][k], b[k], V1);
             }
             const double fm = (double)m;
-            double Y, vx, vy, vz;
-            if (part == 0) {
-              Y = qv * cr;
-              vx = qv * fm * pr;
-              vy = -qv * fm * pim;
-              vz = dv * cr;
+            sr = fma(Q, fma(fma(U0, we, V0 * wd), zr, fma(U1, we, V1 * wd) * zi), sr);
+            const double W0 = V0 * we, W1 = V1 * we;
+            const double qm = Q * fm;
+            sx = fma(qm, fma(W0, zr1, W1 * zi1), sx);
+            sy = fma(qm, fma(W1, zr1, -W0 * zi1), sy);
+            sz = fma(Qd, fma(W0, zr, W1 * zi), sz);
+          }
+          sr = row_sum(sr);
+          sx = row_sum(sx);
+          sy = row_sum(sy);
+          sz = row_sum(sz);
+          if (j == 0) {
+            double* ga = gacc + 4 * t;
+            if (pass == 0) {
+              ga[0] = sr;
+              ga[1] = sx;
+              ga[2] = sy;
+              ga[3] = sz;
             } else {
-              Y = qv * ci;
-              vx = qv * fm * pim;
-              vy = qv * fm * pr;
-              vz = dv * ci;
+              ga[0] += sr;
+              ga[1] += sx;
+              ga[2] += sy;
+              ga[3] += sz;
             }
-            gr = fma(U * we[l] + V * wd[l], Y, gr);
-            const double beta = we[l] * V;
-            tx = fma(beta, vx, tx);
-            ty = fma(beta, vy, ty);
-            tz = fma(beta, vz, tz);
           }
         }
       }
-      pr = cr;
-      pim = ci;
-      const double nr = cr * ux - ci * uy;
-      ci = cr * uy + ci * ux;
-      cr = nr;
+      __syncthreads();
+      if (lane < cnt) {
+        const double* row = dyn + lane * LAR;
+        const double ux = row[XB + S::XU], uy = row[XB + S::XU + 1], uz = row[S::FU], ir = row[XB + S::XU + 2];
+        const double* ga = gacc + 4 * lane;
+        const double sr = ga[0], sx = ga[1], sy = ga[2], sz = ga[3];
+        // d u / d d = (I - u u^T) / r
+        const double ut = ux * sx + uy * sy + uz * sz;
+        const int p = idx[lane];
+        gx[p] = sr * ux + (sx - ux * ut) * ir;
+        gy[p] = sr * uy + (sy - uy * ut) * ir;
+        gz[p] = sr * uz + (sz - uz * ut) * ir;
+      }
     }
-    // d u / d d = (I - u u^T) / r
-    const double ut = ux * tx + uy * ty + uz * tz;
-    gx[p] = gr * ux + (tx - ux * ut) * ir;
-    gy[p] = gr * uy + (ty - uy * ut) * ir;
-    gz[p] = gr * uz + (tz - uz * ut) * ir;
   }
 }
 
@@ -458,67 +604,115 @@ __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __
 
 // compile-time (n_max, l_max) buckets: the kernels handle any n <= NMAX, l <= LMAX
 struct Bucket {
-  int n, l, pg, np;
+  int n, l;
 };
-// pg: pair groups per wave; np: angular passes (chosen so that each lane owns
-// one slot of every pass: ceil((l+1)^2 / np) <= 64 / pg)
 Bucket bucket_of(int n, int l) {
-  if (n <= 6 && l <= 6) return {6, 6, 2, 2};
-  if (n <= 8 && l <= 6) return {8, 6, 2, 2};
-  if (n <= 8 && l <= 8) return {8, 8, 2, 3};
-  if (n <= 10 && l <= 10) return {10, 10, 2, 4};
-  return {12, 12, 2, 6};
+  if (n <= 6 && l <= 6) return {6, 6};
+  if (n <= 8 && l <= 6) return {8, 6};
+  if (n <= 8 && l <= 8) return {8, 8};
+  if (n <= 10 && l <= 10) return {10, 10};
+  return {12, 12};
 }
 
 template <typename F>
 hipError_t dispatch(int n, int l, F&& f) {
   const Bucket b = bucket_of(n, l);
-  if (b.n == 6) return f.template operator()<6, 6, 2, 2>();
-  if (b.n == 8 && b.l == 6) return f.template operator()<8, 6, 2, 2>();
-  if (b.n == 8) return f.template operator()<8, 8, 2, 3>();
-  if (b.n == 10) return f.template operator()<10, 10, 2, 4>();
-  return f.template operator()<12, 12, 2, 6>();
+  if (b.n == 6) return f.template operator()<6, 6>();
+  if (b.n == 8 && b.l == 6) return f.template operator()<8, 6>();
+  if (b.n == 8) return f.template operator()<8, 8>();
+  if (b.n == 10) return f.template operator()<10, 10>();
+  return f.template operator()<12, 12>();
 }
 
-size_t fwd_dyn_bytes(const DevParams& P) { return sizeof(double) * ((size_t)P.nch * (P.LL + 1) + P.K); }
-size_t adj_dyn_bytes(const DevParams& P) {
-  const size_t CP = P.nch + (P.nch & 1);
-  return sizeof(double) * (2 * (size_t)P.LL * CP + P.K);
+template <typename F>
+size_t dispatch_size(int n, int l, F&& f) {
+  const Bucket b = bucket_of(n, l);
+  if (b.n == 6) return f.template operator()<6, 6>();
+  if (b.n == 8 && b.l == 6) return f.template operator()<8, 6>();
+  if (b.n == 8) return f.template operator()<8, 8>();
+  if (b.n == 10) return f.template operator()<10, 10>();
+  return f.template operator()<12, 12>();
 }
+
+size_t fwd_dyn_bytes(const DevParams& P) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
+    using S = Shape<N, LM>;
+    const size_t rows = (size_t)S::CH * S::LFR, epi = (size_t)P.nch * P.LL + P.K;
+    return sizeof(double) * (rows > epi ? rows : epi);
+  });
+}
+size_t adj_dyn_bytes(const DevParams& P) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
+    using S = Shape<N, LM>;
+    return sizeof(double) * ((size_t)S::ACH * S::LAR + 4 * S::ACH);
+  });
+}
+size_t rec_bytes(const DevParams& P) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
+    using S = Shape<N, LM>;
+    return sizeof(RecTab<S::E, S::NC>);
+  });
+}
+size_t cbar_dyn_bytes(const DevParams& P) { return sizeof(double) * ((size_t)P.nch * P.LL + P.K); }
 
 }  // namespace
 
-size_t descriptor_lds_bytes(const DevParams& P) {
-  const Bucket b = bucket_of(P.n, P.l);
-  const int LLM = (b.l + 1) * (b.l + 1), S = (LLM + b.np - 1) / b.np;
-  const size_t stat = sizeof(double) * (64 * (S + 1) + 64 * (b.n + 1) + b.n) + 64 * sizeof(int) + sizeof(YTab);
-  return stat + fwd_dyn_bytes(P);
+size_t c_doubles_per_atom(const DevParams& P) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return (size_t)P.ns * N * (P.LL + 1); });
 }
-size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P) + sizeof(YTab); }
+size_t pair_row_doubles(const DevParams& P) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return (size_t)Shape<N, LM>::ROW; });
+}
+
+size_t descriptor_lds_bytes(const DevParams& P) {
+  return fwd_dyn_bytes(P) + rec_bytes(P) + 64 * sizeof(int) + kMaxN * sizeof(double);
+}
+size_t adjoint_lds_bytes(const DevParams& P) {
+  const size_t a = adj_dyn_bytes(P) + rec_bytes(P) + 64 * sizeof(int), b = cbar_dyn_bytes(P);
+  return a > b ? a : b;
+}
+
+hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
+                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, hipStream_t st) {
+  const int blocks = (int)((n_pairs + 255) / 256) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
+  auto f = [&]<int N, int LM>() {
+    if (deriv)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(256), 0, st, P, T, (int)n_pairs, dx, dy, dz,
+                         rows, bc);
+    else
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(256), 0, st, P, T, (int)n_pairs, dx, dy, dz,
+                         rows, bc);
+    return hipGetLastError();
+  };
+  return dispatch(P.n, P.l, f);
+}
 
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                             const double* dx, const double* dy, const double* dz, const int* species, double* c,
-                             double* q, int q_pitch, double* pnorm, hipStream_t st) {
+                             const int* species, const double* rows, const double* bc, double* c, double* q,
+                             int q_pitch, double* pnorm, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = fwd_dyn_bytes(P);
-  auto f = [&]<int N, int LM, int PG, int NP>() {
-    hipLaunchKernelGGL((k_descriptor<N, LM, PG, NP>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj,
-                       dx, dy, dz, species, c, q, q_pitch, pnorm);
+  auto f = [&]<int N, int LM>() {
+    hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
+                       rows, bc, c, q, q_pitch, pnorm);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
-                               const int* nj, const double* dx, const double* dy, const double* dz,
-                               const int* species, const double* c, const double* q, int q_pitch,
-                               const double* pnorm, const double* qbar, int qbar_pitch, double* gx, double* gy,
-                               double* gz, hipStream_t st) {
+                               const int* nj, const int* species, const double* rows, const double* c,
+                               const double* q, int q_pitch, const double* pnorm, const double* qbar, int qbar_pitch,
+                               double* cbar, double* gx, double* gy, double* gz, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = adj_dyn_bytes(P);
-  auto f = [&]<int N, int LM, int PG, int NP>() {
-    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, dx, dy,
-                       dz, species, c, q, q_pitch, pnorm, qbar, qbar_pitch, gx, gy, gz);
+  auto f = [&]<int N, int LM>() {
+    hipLaunchKernelGGL((k_cbar<N>), dim3(n_atoms), dim3(64), cbar_dyn_bytes(P), st, P, n_atoms, c, q, q_pitch, pnorm,
+                       qbar, qbar_pitch, cbar);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
+                       rows, cbar, gx, gy, gz);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
@@ -533,15 +727,7 @@ hipError_t launch_force_gather(int n_atoms, const int* offsets, const int* rev, 
 }
 
 void build_angular_tables(const DevParams& P, DevTables& T) {
-  int slot = 0;
-  for (int m = 0; m <= P.l; ++m)
-    for (int l = m; l <= P.l; ++l) {
-      if (m == 0) T.slot_lm[slot++] = (short)(l * l + l);
-      else {
-        T.slot_lm[slot++] = (short)(l * l + l + m);
-        T.slot_lm[slot++] = (short)(l * l + l - m);
-      }
-    }
+  // ilexp series factors for the two top orders
   for (int o = 0; o < 3; ++o) {
     const int l = P.l - 1 + o;
     for (int k = 0; k < kIlexpTerms; ++k) T.ilx_rec[o][k] = 1.0 / ((double)(k + 1) * (double)(2 * l + 2 * k + 3));
@@ -550,6 +736,46 @@ void build_angular_tables(const DevParams& P, DevTables& T) {
   for (int l = 0; l < kMaxL + 3; ++l) {
     if (l > 0) df *= (double)(2 * l + 1);
     T.ilx_idf[l] = 1.0 / df;
+  }
+  // Qbar_lm polynomials in extended precision from the three-term recursion
+  //   Qbar_mm = sqrt(2)^(m>0) (4 pi)^(-1/2) prod_{k<=m} sqrt((2k+1)/(2k)),
+  //   Qbar_lm = a_lm x Qbar_{l-1,m} - b_lm Qbar_{l-2,m},
+  //   a_lm = sqrt((4l^2-1)/(l^2-m^2)),  b_lm = sqrt(((l-1)^2-m^2)(2l+1)/((2l-3)(l^2-m^2)))
+  for (int jj = 0; jj < kRecLanes; ++jj)
+    for (int e = 0; e < kMaxRec; ++e) {
+      for (int t = 0; t < kPolyTerms; ++t) T.rec_coef[jj][e][t] = 0.0;
+      T.rec_lmp[jj][e] = 0;
+      T.rec_lm[jj][e][0] = T.rec_lm[jj][e][1] = -1;
+    }
+  int rec = 0;
+  long double qmm = 0.28209479177387814347403972578038629L;  // (4 pi)^(-1/2)
+  for (int m = 0; m <= P.l; ++m) {
+    if (m > 0) qmm *= std::sqrt((2.0L * m + 1.0L) / (2.0L * m));
+    const long double seed = m > 0 ? qmm * 1.41421356237309504880168872420969808L : qmm;
+    long double q2[kMaxL + 2] = {}, q1[kMaxL + 2] = {}, qc[kMaxL + 2] = {};  // coefficients of x^d
+    for (int l = m; l <= P.l; ++l) {
+      for (int d = 0; d <= kMaxL + 1; ++d) qc[d] = 0.0L;
+      if (l == m) {
+        qc[0] = seed;
+      } else {
+        const long double l2m2 = (long double)(l * l - m * m);
+        const long double a = std::sqrt((4.0L * l * l - 1.0L) / l2m2);
+        const long double num = (long double)((l - 1) * (l - 1) - m * m) * (2.0L * l + 1.0L);
+        const long double b = num == 0.0L ? 0.0L : std::sqrt(num / ((2.0L * l - 3.0L) * l2m2));
+        for (int d = 0; d <= kMaxL; ++d) qc[d + 1] += a * q1[d];
+        for (int d = 0; d <= kMaxL + 1; ++d) qc[d] -= b * q2[d];
+      }
+      const int par = (l - m) & 1, jj = rec % kRecLanes, e = rec / kRecLanes;
+      for (int t = 0; 2 * t + par <= l - m; ++t) T.rec_coef[jj][e][t] = (double)qc[2 * t + par];
+      T.rec_lmp[jj][e] = l | (m << 8) | (par << 16);
+      T.rec_lm[jj][e][0] = (short)(l * l + l + m);
+      T.rec_lm[jj][e][1] = (short)(m > 0 ? l * l + l - m : -1);
+      ++rec;
+      for (int d = 0; d <= kMaxL + 1; ++d) {
+        q2[d] = q1[d];
+        q1[d] = qc[d];
+      }
+    }
   }
 }
 

@@ -15,6 +15,9 @@ namespace soap {
 constexpr int kMaxN = 12;
 constexpr int kMaxL = 12;
 constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 2) / 2;
+constexpr int kRecLanes = 16;               // lanes sharing one neighbour in the pair kernels
+constexpr int kMaxRec = (kMaxLM + kRecLanes - 1) / kRecLanes;  // (l, m) records per lane
+constexpr int kPolyTerms = kMaxL / 2 + 1;
 // ilexp: below this z the upward l-recursion loses digits (about 1e-13 relative
 // at z = 24, 6e-7 at z = 5.76); there the two highest orders come from the power
 // series and the recursion runs downward, which is stable.
@@ -26,20 +29,20 @@ struct DevTables {
   double W[kMaxN * kMaxN];  // W[n * kMaxN + alpha]; alpha = n_max - 1 is the Gaussian function
   double invN[kMaxN];       // 1 / N_alpha for alpha = 1..n_max-1, stored at alpha - 1
   double lw[kMaxL + 2];     // w_l: 2l+1 (Eq. (08) as printed) or 1
-  double ya[kMaxLM + 16];   // Legendre recursion factor a_lm, index l(l+1)/2 + m
-  double yb[kMaxLM + 16];   // Legendre recursion factor b_lm
-  double ymm[kMaxL + 2];    // seed Qbar_mm
-  // the same recursion factors in m-major order: ym_a[ym_index(m, l)], l = m..kMaxL
-  double ym_a[kMaxLM];
-  double ym_b[kMaxLM];
   // ilexp power series: ilx_rec[o][k] = 1 / ((k+1) (2l + 2k + 3)) for the order
   // l = l_max - 1 + o (o = 0, 1, 2), and ilx_idf[l] = 1 / (2l+1)!!
   double ilx_rec[3][kIlexpTerms];
   double ilx_idf[kMaxL + 3];
-  // angular slots: the (l, m) of the real spherical harmonics in the order the
-  // descriptor kernel produces them (m = 0: l = 0..l_max; then for each m > 0
-  // and l = m..l_max the pair (l, +m), (l, -m)); slot_lm[slot] = l^2 + l +- m
-  short slot_lm[(kMaxL + 1) * (kMaxL + 1)];
+  // Angular records.  The real harmonics of one (l, m) are
+  //   Y(l, +m) = Qbar_lm(u_z) Re (u_x + i u_y)^m,  Y(l, -m) = Qbar_lm(u_z) Im (u_x + i u_y)^m
+  // with Qbar_lm = sqrt(2)^(m>0) N_lm d^m P_l/dz^m, a polynomial of degree l - m
+  // and parity (l - m) mod 2: Qbar_lm(x) = x^par sum_i rec_coef[i] x^(2i).  No
+  // 1/sin(theta) appears, so the poles need no special rule.  Record e of lane
+  // j (16 lanes) is entry [j][e]; unused records have zero coefficients and
+  // lm = -1.
+  double rec_coef[kRecLanes][kMaxRec][kPolyTerms];
+  int rec_lmp[kRecLanes][kMaxRec];     // l | m << 8 | par << 16
+  short rec_lm[kRecLanes][kMaxRec][2];  // c index l^2+l+m (cos part) and l^2+l-m (sin part; -1 for m = 0)
 };
 
 // Scalars of the hyper-parameters, passed by value to every kernel.
@@ -57,6 +60,28 @@ struct DevParams {
   double s0r, s0p, ar, ap, a;
   double cw;    // central-atom weight
 };
+
+// The per-pair tables of one (n_max, l_max) bucket, staged in LDS once per
+// workgroup so that the radial transform and the ilexp series read them with
+// broadcast LDS loads instead of holding them in scalar registers.
+template <int NMAX, int LMAX>
+struct PairTab {
+  double W[NMAX][NMAX];
+  double invN[NMAX];
+  double lw[LMAX + 2];
+  double rec[3][kIlexpTerms];
+  double idf[LMAX + 3];
+};
+
+template <int NMAX, int LMAX>
+__device__ inline void stage_pair_tables(const DevTables* __restrict__ T, PairTab<NMAX, LMAX>& t, int lane,
+                                         int nthreads) {
+  for (int x = lane; x < NMAX * NMAX; x += nthreads) t.W[x / NMAX][x % NMAX] = T->W[(x / NMAX) * kMaxN + x % NMAX];
+  for (int x = lane; x < NMAX; x += nthreads) t.invN[x] = T->invN[x];
+  for (int x = lane; x < LMAX + 2; x += nthreads) t.lw[x] = T->lw[x];
+  for (int x = lane; x < 3 * kIlexpTerms; x += nthreads) t.rec[x / kIlexpTerms][x % kIlexpTerms] = T->ilx_rec[x / kIlexpTerms][x % kIlexpTerms];
+  for (int x = lane; x < LMAX + 3; x += nthreads) t.idf[x] = T->ilx_idf[x];
+}
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrt2 = 1.41421356237309504880;
@@ -83,8 +108,8 @@ __device__ inline double erf_diff(double a, double b) {
 // which avoid the cancellation of ((rc-mu) I_k - rc I_{k+1}) / s^2 (about two
 // digits for narrow Gaussians, before W amplifies the error).  Only the last
 // two terms are kept, so the stream needs a handful of registers.
-template <int NMAX, bool DERIV>
-__device__ inline void overlap_stream(const DevTables* __restrict__ T, int n, double lo, double hi, double mu,
+template <int NMAX, bool DERIV, typename Tab>
+__device__ inline void overlap_stream(const Tab& T, int n, double lo, double hi, double mu,
                                       double s, double rc, double scale, double dscale, double dmu_dr, double ds_dr,
                                       double (&ba)[NMAX], double (&dba)[NMAX]) {
   const double s2 = s * s;
@@ -110,7 +135,7 @@ __device__ inline void overlap_stream(const DevTables* __restrict__ T, int n, do
       Ds = (I - (qh * th - ql * tl)) * is_ - (double)k * s * krc * Dm1;
     }
     if (k >= 3 && k - 2 < n) {
-      const double iN = T->invN[k - 3];
+      const double iN = T.invN[k - 3];
       ba[k - 3] += scale * I * iN;
       if (DERIV) dba[k - 3] += (dscale * I + scale * (Dmu * dmu_dr + Ds * ds_dr)) * iN;
     }
@@ -146,9 +171,8 @@ __device__ inline void gauss_basis(double mu, double s, double s0, double& B, do
 // Radial factor of one neighbour at distance r:
 //   Bk[k] = 4 pi A(r) b_k(r), k < n_max, b = W b_alpha   (Eqs. (01), (08), (15))
 // and, with DERIV, dBk[k] = d Bk[k] / dr (through mu = r, sigma_r(r) and A(r)).
-template <int NMAX, bool DERIV>
-__device__ inline void radial(const DevParams& P, const DevTables* __restrict__ T, double r, double (&Bk)[NMAX],
-                              double (&dBk)[NMAX]) {
+template <int NMAX, bool DERIV, typename Tab>
+__device__ inline void radial(const DevParams& P, const Tab& T, double r, double (&Bk)[NMAX], double (&dBk)[NMAX]) {
   const int n = P.n;
   const double s = P.s0r + P.ar * r;
   double ba[NMAX], dba[NMAX];
@@ -205,7 +229,7 @@ __device__ inline void radial(const DevParams& P, const DevTables* __restrict__ 
 #pragma unroll
       for (int al = 0; al < NMAX; ++al) {
         if (al < n) {
-          const double w = T->W[k * kMaxN + al];
+          const double w = T.W[k][al];
           acc = fma(w, ba[al], acc);
           if (DERIV) dacc = fma(w, dba[al], dacc);
         }
@@ -266,49 +290,6 @@ __device__ inline void ilexp(double z, int lmax, const double* __restrict__ rec_
       up = cur;
       cur = nxt;
     }
-  }
-}
-
-__host__ __device__ constexpr int lm_tri(int l, int m) { return l * (l + 1) / 2 + m; }
-// m-major triangular index: entries l = m..kMaxL of column m are contiguous
-__host__ __device__ constexpr int ym_index(int m, int l) { return m * (kMaxL + 1) - m * (m - 1) / 2 + (l - m); }
-
-// Real spherical harmonics of a unit vector u (Condon-Shortley-free real form):
-//   Y[l^2 + l]     = Qbar_l0(u_z)
-//   Y[l^2 + l + m] = Qbar_lm(u_z) Re (u_x + i u_y)^m,  m > 0
-//   Y[l^2 + l - m] = Qbar_lm(u_z) Im (u_x + i u_y)^m,  m > 0
-// with Qbar_lm = sqrt(2)^(m>0) N_lm d^m P_l / dz^m: no 1/sin(theta) appears, so the
-// poles need no special rule.  Per l this is an orthogonal transform of the
-// complex Y*_lm, which leaves the power spectrum of Eq. (09) unchanged.
-// The callback receives (l, lm index, value) in an order fixed at compile time.
-template <int LM, typename F>
-__device__ inline void real_ylm(const DevTables* __restrict__ T, int lmax, double ux, double uy, double uz, F&& put) {
-  double cr = 1.0, ci = 0.0;  // (u_x + i u_y)^m
-#pragma unroll
-  for (int m = 0; m <= LM; ++m) {
-    if (m <= lmax) {
-      double q2 = 0.0, q1 = T->ymm[m];  // Qbar_{m-1,m} = 0, Qbar_mm
-#pragma unroll
-      for (int l = m; l <= LM; ++l) {
-        if (l <= lmax) {
-          double q;
-          if (l == m) q = q1;
-          else {
-            q = T->ya[lm_tri(l, m)] * uz * q1 - T->yb[lm_tri(l, m)] * q2;
-            q2 = q1;
-            q1 = q;
-          }
-          if (m == 0) put(l, l * l + l, q);
-          else {
-            put(l, l * l + l + m, q * cr);
-            put(l, l * l + l - m, q * ci);
-          }
-        }
-      }
-    }
-    const double nr = cr * ux - ci * uy;
-    ci = cr * uy + ci * ux;
-    cr = nr;
   }
 }
 
