@@ -186,7 +186,8 @@ typedef enum {
   SOAP_STAGE_GAP_QBAR = 3,      /* Qbar = G Q_s */
   SOAP_STAGE_PAIR_ADJOINT = 4,  /* cbar and the per-pair gradients */
   SOAP_STAGE_FORCE_GATHER = 5,  /* per-atom force sums */
-  SOAP_STAGE_COUNT = 6
+  SOAP_STAGE_GAP_FUSED = 6,     /* S, the zeta epilogue and Qbar = G Q_s in one pass (16/32-bit modes) */
+  SOAP_STAGE_COUNT = 7
 } soap_stage;
 soap_status soap_profile(soap_ctx* ctx, int enable);
 soap_status soap_profile_read(soap_ctx* ctx, double* ms /* host */, long long* launches /* host */);

@@ -21,7 +21,7 @@ EXPORTED = (
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
 )
-STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather")
+STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused")
 
 
 class soap_params(ctypes.Structure):

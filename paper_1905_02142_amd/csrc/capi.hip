@@ -36,6 +36,8 @@ struct soap_ctx {
   std::string err;
   long long ws_bytes = 0;
   int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
+  std::vector<char> meta_host;  // the structure geometry last uploaded, and where
+  void* meta_dev = nullptr;
   size_t pinned_bytes = 0;
   // neighbour build
   Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_atoms, counts, scan_part,
@@ -349,8 +351,9 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
     M.atom1 = so[s + 1];
     n_bins += nb_total;
   }
-  SOAP_ENSURE(ctx, ctx->meta, sizeof(soap::StructMeta) * n_structures);
-  SOAP_ENSURE(ctx, ctx->so, sizeof(int) * (n_structures + 1));
+  const size_t meta_cap0 = ctx->meta.cap;
+  SOAP_ENSURE(ctx, ctx->meta, sizeof(soap::StructMeta) * n_structures + sizeof(int) * (n_structures + 1));
+  if (ctx->meta.cap != meta_cap0) ctx->meta_dev = nullptr;  // a new allocation holds nothing yet
   SOAP_ENSURE(ctx, ctx->atom_bin, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->atom_wrap, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->bin_count, sizeof(int) * n_bins);
@@ -368,16 +371,19 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
   char* stage = (char*)ctx->pinned;
   std::memcpy(stage, meta.data(), sizeof(soap::StructMeta) * n_structures);
   std::memcpy(stage + sizeof(soap::StructMeta) * n_structures, so.data(), sizeof(int) * (n_structures + 1));
-  SOAP_HIP(ctx, hipMemcpyAsync(ctx->meta.p, stage, sizeof(soap::StructMeta) * n_structures, hipMemcpyHostToDevice, st));
-  SOAP_HIP(ctx, hipMemcpyAsync(ctx->so.p, stage + sizeof(soap::StructMeta) * n_structures,
-                               sizeof(int) * (n_structures + 1), hipMemcpyHostToDevice, st));
-  SOAP_HIP(ctx, hipMemsetAsync(ctx->bin_count.p, 0, sizeof(int) * n_bins, st));
-  SOAP_HIP(ctx, hipMemsetAsync(ctx->bin_cursor.p, 0, sizeof(int) * n_bins, st));
-  SOAP_HIP(ctx, hipMemsetAsync(ctx->errflag.p, 0, sizeof(int) * 4, st));
+  // the structure geometry is uploaded only when it differs from what the device holds
+  if (ctx->meta.p != ctx->meta_dev || ctx->meta_host.size() != up ||
+      std::memcmp(ctx->meta_host.data(), stage, up) != 0) {
+    SOAP_HIP(ctx, hipMemcpyAsync(ctx->meta.p, stage, up, hipMemcpyHostToDevice, st));
+    ctx->meta_host.assign(stage, stage + up);
+    ctx->meta_dev = ctx->meta.p;
+  }
+  SOAP_HIP(ctx, soap::launch_init_build(n_bins, (int*)ctx->bin_count.p, (int*)ctx->bin_cursor.p,
+                                        (int*)ctx->errflag.p, st));
   int* err = (int*)ctx->errflag.p;
   StageTimer tm_count(ctx, SOAP_STAGE_NEIGHBORS, st);
   const soap::StructMeta* dmeta = (const soap::StructMeta*)ctx->meta.p;
-  const int* dso = (const int*)ctx->so.p;
+  const int* dso = (const int*)((const char*)ctx->meta.p + sizeof(soap::StructMeta) * n_structures);
   if (n_atoms > 0) {
     SOAP_HIP(ctx, soap::launch_bin_atoms(n_atoms, pos, dmeta, dso, n_structures, (int*)ctx->atom_bin.p,
                                          (int*)ctx->atom_wrap.p, (int*)ctx->bin_count.p, err, st));
@@ -498,15 +504,22 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     qbar = (double*)ctx->qbar.p;
   }
   const int prec = (int)ctx->prm.precision;
-  SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
-  {
-    StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
-    SOAP_HIP(ctx, soap::launch_gap_scores(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta,
-                                          e_atom, alpha_grad, ctx->gapw.p, st));
-  }
-  if (qbar) {
-    StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
-    SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, ctx->gapw.p, st));
+  if (qbar && soap::gap_fused_supported(P.K, prec)) {
+    SOAP_ENSURE(ctx, ctx->gapw, soap::gap_fused_workspace_bytes((int)N, M, P.K, prec));
+    StageTimer tm(ctx, SOAP_STAGE_GAP_FUSED, st);
+    SOAP_HIP(ctx, soap::launch_gap_fused(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta, e_atom,
+                                         alpha_grad, qbar, ctx->gapw.p, st));
+  } else {
+    SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
+    {
+      StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
+      SOAP_HIP(ctx, soap::launch_gap_scores(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta,
+                                            e_atom, alpha_grad, ctx->gapw.p, st));
+    }
+    if (qbar) {
+      StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
+      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, ctx->gapw.p, st));
+    }
   }
   if (forces) {
     SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
@@ -556,8 +569,8 @@ soap_status soap_profile_read(soap_ctx* ctx, double* ms, long long* launches) {
 }
 
 const char* soap_stage_name(int stage) {
-  static const char* names[SOAP_STAGE_COUNT] = {"neighbors", "descriptor", "gap_scores",
-                                                "gap_qbar", "pair_adjoint", "force_gather"};
+  static const char* names[SOAP_STAGE_COUNT] = {"neighbors",    "descriptor",   "gap_scores", "gap_qbar",
+                                                "pair_adjoint", "force_gather", "gap_fused"};
   return (stage >= 0 && stage < SOAP_STAGE_COUNT) ? names[stage] : "unknown";
 }
 

@@ -15,4 +15,11 @@ hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, con
 // Qbar (N x K) = G Q_s, from the operands the scores pass left in work
 hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, const void* work, hipStream_t st);
 
+// Fused scores + Qbar (prec 1..3, padded K <= 352): e, alpha_bar (nullable) and
+// Qbar in one pass with no N x M intermediate in HBM
+bool gap_fused_supported(int K, int prec);
+size_t gap_fused_workspace_bytes(int N, int M, int K, int prec);
+hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
+                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, hipStream_t st);
+
 }  // namespace soap

@@ -20,6 +20,8 @@
 // added in a fixed order, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gap.h"
 
 namespace soap {
@@ -347,13 +349,373 @@ __global__ void k_sum_parts(int n, int nt, const double* __restrict__ part, doub
   out[j] = s;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- fused pass
+// Scores, zeta epilogue and Qbar in one kernel for the 16- and 32-bit operand
+// modes when the padded descriptor fits in LDS (K <= kFusedK).  Workgroup
+// (rb, sp) keeps rows [rb BM, rb BM + BM) of Q converted in LDS and walks the
+// sparse points of slice sp in chunks of BN:
+//   S = Q_blk Q_s,c^T                 (MFMA, contraction over K)
+//   e_i += alpha_s S^zeta,  column sums of S^zeta -> ab_part[rb][s],
+//   G = zeta alpha_s S^(zeta-1)        (registers -> LDS, operand precision)
+//   Qbar_blk += G Q_s,c                (MFMA, contraction over the chunk)
+// so G never goes to HBM.  Slices are combined by k_gap_reduce in a fixed order.
+constexpr int kFusedK = 352;  // padded descriptor length limit (multiple of 32)
+constexpr int kFusedTNq = 6;  // Qbar column tiles per wavefront: 4 x 6 x 16 = 384 >= kFusedK
+
+struct FB16 {
+  using T = __bf16;
+  using Acc = f4;
+  static constexpr int BM = 64, BN = 64, KSTEP = 32;
+  static constexpr bool kSplit = false;
+};
+struct FB16X3 {
+  using T = __bf16;
+  using Acc = f4;
+  static constexpr int BM = 32, BN = 32, KSTEP = 32;
+  static constexpr bool kSplit = true;
+};
+struct FF32 {
+  using T = float;
+  using Acc = f4;
+  static constexpr int BM = 32, BN = 32, KSTEP = 4;
+  static constexpr bool kSplit = false;
+};
+
+template <typename F>
+struct FusedSmem {
+  using T = typename F::T;
+  static constexpr int EPV = 16 / sizeof(T);
+  static constexpr int PQ = kFusedK + EPV;  // row pitch over the descriptor
+  static constexpr int PS = F::BN + EPV;    // row pitch over the sparse points of a chunk
+  static constexpr int NL = F::kSplit ? 1 : 0;
+  alignas(16) T q[F::BM * PQ];
+  alignas(16) T q_lo[NL ? F::BM * PQ : 1];
+  alignas(16) T qs[F::BN * PQ];
+  alignas(16) T qs_lo[NL ? F::BN * PQ : 1];
+  alignas(16) T qst[kFusedK * PS];
+  alignas(16) T qst_lo[NL ? kFusedK * PS : 1];
+  alignas(16) T g[F::BM * PS];
+  alignas(16) T g_lo[NL ? F::BM * PS : 1];
+  double colsum[2][F::BN];
+  double rowsum[2][F::BM];
+  double alpha[F::BN];
+};
+
+// acc[x][y] += A[a0 + 16x .., k0 ..) B^T[b0 + 16y .., k0 ..)^T: one MFMA k-step from LDS;
+// tiles y with b0 + 16y >= bcap are skipped (uniform per wavefront)
+template <typename F, int TM, int TN>
+__device__ inline void fused_step(const typename F::T* A, const typename F::T* A_lo, int pa, int a0,
+                                  const typename F::T* B, const typename F::T* B_lo, int pb, int b0, int bcap,
+                                  int k0, int lane, typename F::Acc (&acc)[TM][TN]) {
+  const int r16 = lane & 15, kq = lane >> 4;
+  if constexpr (sizeof(typename F::T) == 4) {
+    float a[TM], b[TN];
+#pragma unroll
+    for (int x = 0; x < TM; ++x) a[x] = A[(a0 + 16 * x + r16) * pa + k0 + kq];
+#pragma unroll
+    for (int y = 0; y < TN; ++y) b[y] = (b0 + 16 * y < bcap) ? B[(b0 + 16 * y + r16) * pb + k0 + kq] : 0.0f;
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TN; ++y)
+        if (b0 + 16 * y < bcap) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+  } else {
+    b8 a[TM], al[TM], b[TN], bl[TN];
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      a[x] = *(const b8*)&A[(a0 + 16 * x + r16) * pa + k0 + 8 * kq];
+      if constexpr (F::kSplit) al[x] = *(const b8*)&A_lo[(a0 + 16 * x + r16) * pa + k0 + 8 * kq];
+    }
+#pragma unroll
+    for (int y = 0; y < TN; ++y) {
+      if (b0 + 16 * y < bcap) {
+        b[y] = *(const b8*)&B[(b0 + 16 * y + r16) * pb + k0 + 8 * kq];
+        if constexpr (F::kSplit) bl[y] = *(const b8*)&B_lo[(b0 + 16 * y + r16) * pb + k0 + 8 * kq];
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TN; ++y)
+        if (b0 + 16 * y < bcap) {
+          if constexpr (F::kSplit) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], b[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bl[y], acc[x][y], 0, 0, 0);
+          }
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+  }
+}
+
+// A rows x cols tile of T (row pitch ld in HBM, lp in LDS) held in registers as
+// 16-byte vectors, NV per thread at most (rows * cols <= 256 * NV * 16 / sizeof(T)):
+// load() issues every global read before any is used, store() writes LDS.
+template <typename T, int NV>
+struct RegTile {
+  u4 v[NV];
+  __device__ inline void load(const T* __restrict__ g, int ld, int rows, int cols, int tid) {
+    constexpr int EPV = 16 / sizeof(T);
+    const int vpr = cols / EPV;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int x = tid + 256 * t, r = x / vpr, c = (x - r * vpr) * EPV;
+      if (r < rows) v[t] = *(const u4*)(g + (size_t)r * ld + c);
+    }
+  }
+  __device__ inline void store(T* s, int lp, int rows, int cols, int tid) const {
+    constexpr int EPV = 16 / sizeof(T);
+    const int vpr = cols / EPV;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int x = tid + 256 * t, r = x / vpr, c = (x - r * vpr) * EPV;
+      if (r < rows) *(u4*)(s + r * lp + c) = v[t];
+    }
+  }
+};
+
+template <typename F>
+__global__ __launch_bounds__(256) void k_gap_fused(int N, int M, int K, int Kf, int Mp, int chunks_per_slice,
+                                                   const double* __restrict__ Q,
+                                                   const typename F::T* __restrict__ QsC,
+                                                   const typename F::T* __restrict__ QsC_lo,
+                                                   const typename F::T* __restrict__ QsT,
+                                                   const typename F::T* __restrict__ QsT_lo,
+                                                   const double* __restrict__ alpha, int zeta,
+                                                   double* __restrict__ e_out, float* __restrict__ qbar_part,
+                                                   double* __restrict__ qbar_out, double* __restrict__ ab_part) {
+  using T = typename F::T;
+  using Sm = FusedSmem<F>;
+  constexpr int BM = F::BM, BN = F::BN, TMs = BM / 32, TNs = BN / 32, TMq = BM / 16;
+  extern __shared__ __align__(16) unsigned char fused_raw[];
+  Sm& sm = *reinterpret_cast<Sm*>(fused_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  const int rb = blockIdx.x, sp = blockIdx.y, nsp = gridDim.y;
+  const int i0 = rb * BM;
+  const int Kq = (K + 15) / 16 * 16;
+  // Q rows of this block, converted and zero padded to Kf (loads batched eight deep)
+  for (int t0 = tid; t0 < BM * Kf; t0 += 256 * 8) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + 256 * u, r = t / Kf, k = t - r * Kf;
+      x[u] = (t < BM * Kf && i0 + r < N && k < K) ? Q[(size_t)(i0 + r) * K + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + 256 * u, r = t / Kf, k = t - r * Kf;
+      if (t < BM * Kf) {
+        const T h = cvt<T>(x[u]);
+        sm.q[r * Sm::PQ + k] = h;
+        if constexpr (F::kSplit) sm.q_lo[r * Sm::PQ + k] = cvt_lo_any<T>(x[u], h);
+      }
+    }
+  }
+  typename F::Acc aq[TMq][kFusedTNq];
+#pragma unroll
+  for (int x = 0; x < TMq; ++x)
+#pragma unroll
+    for (int y = 0; y < kFusedTNq; ++y) aq[x][y] = typename F::Acc{};
+  double rows[TMs][4] = {};
+  const int c_begin = sp * chunks_per_slice;
+  const int c_end = min(c_begin + chunks_per_slice, Mp / BN);
+  // the next chunk's Q_s rows and Q_s^T columns are loaded into registers while
+  // the current chunk is multiplied
+  constexpr int EPV = 16 / sizeof(T);
+  constexpr int NV = (BN * kFusedK / EPV + 255) / 256;
+  RegTile<T, NV> rq, rt, rq_lo, rt_lo;
+  double ra = 0.0;
+  auto fetch = [&](int c) {
+    const int s0 = c * BN;
+    rq.load(QsC + (size_t)s0 * Kf, Kf, BN, Kf, tid);
+    rt.load(QsT + s0, Mp, Kf, BN, tid);
+    if constexpr (F::kSplit) {
+      rq_lo.load(QsC_lo + (size_t)s0 * Kf, Kf, BN, Kf, tid);
+      rt_lo.load(QsT_lo + s0, Mp, Kf, BN, tid);
+    }
+    ra = (tid < BN && s0 + tid < M) ? alpha[s0 + tid] : 0.0;
+  };
+  if (c_begin < c_end) fetch(c_begin);
+  for (int c = c_begin; c < c_end; ++c) {
+    const int s0 = c * BN;
+    __syncthreads();  // the previous chunk is done with qs, qst, g and alpha
+    rq.store(sm.qs, Sm::PQ, BN, Kf, tid);
+    rt.store(sm.qst, Sm::PS, Kf, BN, tid);
+    if constexpr (F::kSplit) {
+      rq_lo.store(sm.qs_lo, Sm::PQ, BN, Kf, tid);
+      rt_lo.store(sm.qst_lo, Sm::PS, Kf, BN, tid);
+    }
+    if (tid < BN) sm.alpha[tid] = ra;
+    __syncthreads();
+    if (c + 1 < c_end) fetch(c + 1);
+    // S = Q_blk Q_s,c^T: wave (wm, wn) owns rows wm BM/2 .., sparse points wn BN/2 ..
+    typename F::Acc as[TMs][TNs];
+#pragma unroll
+    for (int x = 0; x < TMs; ++x)
+#pragma unroll
+      for (int y = 0; y < TNs; ++y) as[x][y] = typename F::Acc{};
+    for (int k0 = 0; k0 < Kf; k0 += F::KSTEP)
+      fused_step<F, TMs, TNs>(sm.q, sm.q_lo, Sm::PQ, wm * (BM / 2), sm.qs, sm.qs_lo, Sm::PQ, wn * (BN / 2), BN, k0,
+                              lane, as);
+    // zeta epilogue: G to LDS, row sums in registers, column sums per chunk
+    double cols[TNs] = {};
+#pragma unroll
+    for (int x = 0; x < TMs; ++x)
+#pragma unroll
+      for (int y = 0; y < TNs; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wm * (BM / 2) + 16 * x + 4 * (lane >> 4) + r;
+          const int col = wn * (BN / 2) + 16 * y + (lane & 15);
+          double gv = 0.0;
+          if (s0 + col < M) {
+            const double sv = (double)as[x][y][r];
+            const double sz1 = ipow(sv, zeta - 1);
+            const double kv = sz1 * sv;
+            const double al = sm.alpha[col];
+            gv = (double)zeta * al * sz1;
+            if (i0 + row < N) {
+              rows[x][r] = fma(al, kv, rows[x][r]);
+              cols[y] += kv;
+            }
+          }
+          const T gh = cvt<T>(gv);
+          sm.g[row * Sm::PS + col] = gh;
+          if constexpr (F::kSplit) sm.g_lo[row * Sm::PS + col] = cvt_lo_any<T>(gv, gh);
+        }
+#pragma unroll
+    for (int y = 0; y < TNs; ++y) {
+      double v = cols[y];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (lane < 16) sm.colsum[wm][wn * (BN / 2) + 16 * y + lane] = v;
+    }
+    __syncthreads();
+    if (tid < BN && s0 + tid < M) ab_part[(size_t)rb * M + s0 + tid] = sm.colsum[0][tid] + sm.colsum[1][tid];
+    // Qbar_blk += G Q_s,c: wave wv owns descriptor columns 96 wv ..
+    for (int k0 = 0; k0 < BN; k0 += F::KSTEP)
+      fused_step<F, TMq, kFusedTNq>(sm.g, sm.g_lo, Sm::PS, 0, sm.qst, sm.qst_lo, Sm::PS, wv * 16 * kFusedTNq, Kq, k0,
+                                    lane, aq);
+  }
+  // e: rows summed over the 16 lanes of a column group and the two wn waves
+#pragma unroll
+  for (int x = 0; x < TMs; ++x)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = rows[x][r];
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+      if ((lane & 15) == 0) sm.rowsum[wn][wm * (BM / 2) + 16 * x + 4 * (lane >> 4) + r] = v;
+    }
+  __syncthreads();
+  if (tid < BM && i0 + tid < N) {
+    const double v = sm.rowsum[0][tid] + sm.rowsum[1][tid];
+    e_out[(size_t)sp * N + i0 + tid] = v;
+  }
+#pragma unroll
+  for (int x = 0; x < TMq; ++x)
+#pragma unroll
+    for (int y = 0; y < kFusedTNq; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * x + 4 * (lane >> 4) + r;
+        const int col = wv * 16 * kFusedTNq + 16 * y + (lane & 15);
+        if (i0 + row < N && col < K) {
+          if (nsp == 1) qbar_out[(size_t)(i0 + row) * K + col] = (double)aq[x][y][r];
+          else qbar_part[((size_t)sp * N + i0 + row) * K + col] = aq[x][y][r];
+        }
+      }
+}
+
+// e[i] = sum_sp e_part[sp][i]; Qbar = sum_sp qbar_part[sp] (when nsp > 1); ab[s] = sum_rb ab_part[rb][s],
+// all in a fixed order
+__global__ void k_gap_reduce(int N, int K, int M, int nsp, int nrb, const double* __restrict__ e_part,
+                             const float* __restrict__ qbar_part, const double* __restrict__ ab_part,
+                             double* __restrict__ e, double* __restrict__ qbar, double* __restrict__ ab) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nq = nsp > 1 ? (long long)N * K : 0;
+  if (t < nq) {
+    double v = 0.0;
+    for (int s = 0; s < nsp; ++s) v += (double)qbar_part[(size_t)s * N * K + t];
+    qbar[t] = v;
+  } else if (t < nq + N) {
+    const int i = (int)(t - nq);
+    double v = 0.0;
+    for (int s = 0; s < nsp; ++s) v += e_part[(size_t)s * N + i];
+    e[i] = v;
+  } else if (t < nq + N + M && ab) {
+    const int j = (int)(t - nq - N);
+    double v = 0.0;
+    for (int r = 0; r < nrb; ++r) v += ab_part[(size_t)r * M + j];
+    ab[j] = v;
+  }
+}
+
+struct FusedLayout {
+  size_t qsc, qsc_lo, qst, qst_lo, e_part, qbar_part, ab_part, total;
+  int Kf, Mp, nrb, nsp, cps;
+};
+
+template <typename F>
+FusedLayout fused_layout(int N, int M, int K) {
+  FusedLayout L{};
+  const size_t es = sizeof(typename F::T);
+  L.Kf = (K + 31) / 32 * 32;
+  L.Mp = padded(M);
+  L.nrb = (N + F::BM - 1) / F::BM;
+  const int nchunks = L.Mp / F::BN;
+  L.nsp = std::min(nchunks, std::max(1, (512 + L.nrb - 1) / L.nrb));
+  L.cps = (nchunks + L.nsp - 1) / L.nsp;
+  L.nsp = (nchunks + L.cps - 1) / L.cps;
+  const size_t nlo = F::kSplit ? 1 : 0;
+  size_t o = 0;
+  L.qsc = o;
+  o += align256(es * L.Mp * L.Kf);
+  L.qsc_lo = o;
+  o += align256(es * L.Mp * L.Kf * nlo);
+  L.qst = o;
+  o += align256(es * L.Kf * L.Mp);
+  L.qst_lo = o;
+  o += align256(es * L.Kf * L.Mp * nlo);
+  L.e_part = o;
+  o += align256(sizeof(double) * (size_t)L.nsp * N);
+  L.qbar_part = o;
+  o += align256(L.nsp > 1 ? sizeof(float) * (size_t)L.nsp * N * K : 0);
+  L.ab_part = o;
+  o += align256(sizeof(double) * (size_t)L.nrb * M);
+  L.total = o;
+  return L;
+}
+
+template <typename F>
+hipError_t fused_impl(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta, double* e,
+                      double* alpha_bar, double* Qbar, void* work, hipStream_t st) {
+  using T = typename F::T;
+  const FusedLayout L = fused_layout<F>(N, M, K);
+  char* w = (char*)work;
+  T *qsc = (T*)(w + L.qsc), *qsc_lo = (T*)(w + L.qsc_lo), *qst = (T*)(w + L.qst), *qst_lo = (T*)(w + L.qst_lo);
+  double *e_part = (double*)(w + L.e_part), *ab_part = (double*)(w + L.ab_part);
+  float* qbar_part = (float*)(w + L.qbar_part);
+  auto blocks = [](long long n) { return dim3((unsigned)((n + 255) / 256)); };
+  hipLaunchKernelGGL((k_convert<T, F::kSplit, false>), blocks((long long)L.Mp * L.Kf), dim3(256), 0, st, M, K, L.Mp,
+                     L.Kf, Qs, qsc, qsc_lo);
+  hipLaunchKernelGGL((k_convert<T, F::kSplit, true>), blocks((long long)L.Kf * L.Mp), dim3(256), 0, st, M, K, L.Kf,
+                     L.Mp, Qs, qst, qst_lo);
+  hipLaunchKernelGGL(k_gap_fused<F>, dim3(L.nrb, L.nsp), dim3(256), sizeof(FusedSmem<F>), st, N, M, K, L.Kf, L.Mp,
+                     L.cps, Q, qsc, qsc_lo, qst, qst_lo, alpha, zeta, e_part, qbar_part, Qbar, ab_part);
+  const long long nred = (L.nsp > 1 ? (long long)N * K : 0) + N + M;
+  hipLaunchKernelGGL(k_gap_reduce, blocks(nred), dim3(256), 0, st, N, K, M, L.nsp, L.nrb, e_part, qbar_part, ab_part,
+                     e, Qbar, alpha_bar);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- workspace
 // [Qc | Qc_lo | Qsc | Qsc_lo | QsT | QsT_lo | G | G_lo | e_part | ab_part], 256-byte aligned pieces
 struct Layout {
   size_t qc, qc_lo, qsc, qsc_lo, qst, qst_lo, g, g_lo, e_part, ab_part, total;
 };
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 template <typename P>
 Layout layout(int N, int M, int K) {
@@ -445,6 +807,36 @@ hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, con
     case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
     case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
     default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
+  }
+}
+
+bool gap_fused_supported(int K, int prec) { return prec != 0 && (K + 31) / 32 * 32 <= kFusedK; }
+
+size_t gap_fused_workspace_bytes(int N, int M, int K, int prec) {
+  switch (prec) {
+    case 1: return fused_layout<FF32>(N, M, K).total;
+    case 2: return fused_layout<FB16>(N, M, K).total;
+    default: return fused_layout<FB16X3>(N, M, K).total;
+  }
+}
+
+hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
+                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  static bool attr_set[4] = {false, false, false, false};
+  auto run = [&]<typename F>() {
+    if (!attr_set[prec]) {  // opt in to more than 64 KB of LDS per workgroup
+      hipError_t a = hipFuncSetAttribute((const void*)k_gap_fused<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)sizeof(FusedSmem<F>));
+      if (a != hipSuccess) return a;
+      attr_set[prec] = true;
+    }
+    return fused_impl<F>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, Qbar, work, st);
+  };
+  switch (prec) {
+    case 1: return run.template operator()<FF32>();
+    case 2: return run.template operator()<FB16>();
+    default: return run.template operator()<FB16X3>();
   }
 }
 

@@ -33,6 +33,8 @@ __host__ __device__ inline void unpack_img(int v, int* t) {
   t[2] = (v & 1023) - 512;
 }
 
+// zero bin_count[0..n_bins), bin_cursor[0..n_bins) and err[0..4)
+hipError_t launch_init_build(int n_bins, int* bin_count, int* bin_cursor, int* err, hipStream_t st);
 hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t st);
 int scan_partials_needed(int n);
 hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,

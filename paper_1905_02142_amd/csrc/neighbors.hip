@@ -300,9 +300,63 @@ __global__ void k_scan_final(int n, const int* __restrict__ in, const int* __res
   }
 }
 
+// one workgroup for n + 1 <= kScanSingle: out[0..n], out[n] = total
+constexpr int kScanSingleThreads = 1024, kScanSingleItems = 16;
+constexpr int kScanSingle = kScanSingleThreads * kScanSingleItems;
+
+__global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(int n, const int* __restrict__ in,
+                                                                     int* __restrict__ out) {
+  __shared__ int sh[kScanSingleThreads];
+  const int t = threadIdx.x;
+  const int per = (n + 1 + kScanSingleThreads - 1) / kScanSingleThreads;
+  const int base = t * per;
+  int v[kScanSingleItems];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanSingleItems; ++k) {
+    v[k] = (k < per && base + k < n) ? in[base + k] : 0;
+    s += v[k];
+  }
+  sh[t] = s;
+  __syncthreads();
+  for (int o = 1; o < kScanSingleThreads; o <<= 1) {
+    const int x = (t >= o) ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  int ex = sh[t] - s;
+#pragma unroll
+  for (int k = 0; k < kScanSingleItems; ++k) {
+    if (k < per && base + k <= n) out[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+// zero the bin counters, the bin cursors and the error word before a build
+__global__ void k_init_build(int n_bins, int* __restrict__ bin_count, int* __restrict__ bin_cursor,
+                             int* __restrict__ err) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_bins) {
+    bin_count[t] = 0;
+    bin_cursor[t] = 0;
+  }
+  if (t < 4) err[t] = 0;
+}
+
 }  // namespace
 
+hipError_t launch_init_build(int n_bins, int* bin_count, int* bin_cursor, int* err, hipStream_t st) {
+  const int n = n_bins > 4 ? n_bins : 4;
+  hipLaunchKernelGGL(k_init_build, dim3((n + 255) / 256), dim3(256), 0, st, n_bins, bin_count, bin_cursor, err);
+  return hipGetLastError();
+}
+
 hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t st) {
+  if (n + 1 <= kScanSingle) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanSingleThreads), 0, st, n, in, out);
+    return hipGetLastError();
+  }
   const int nb = (n + kScanTile) / kScanTile;  // at least one block, covers index n
   hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kScanThreads), 0, st, n, in, part);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, nb, part);
