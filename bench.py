@@ -73,8 +73,11 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="box4096_n8l8")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "f32", "bf16", "bf16x3"])
+    ap.add_argument("--precision", default="bf16", choices=["fp64", "f32", "bf16", "bf16x3"],
+                    help="GAP contraction precision (the rest of the path is FP64); the FP64 path is timed "
+                         "alongside any other mode and the force error against it reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, run a plain 512 MiB device-to-device copy three times "
                          "(the reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -106,6 +109,8 @@ def main():
             soap.neighbors(st["pos"], s.cell, s.pbc, nl=nl)
             soap.energy_forces(nl, st["spec"], st["qs"], st["al"], w["zeta"], out=(e, F, ab))
 
+        tuning = soap.tuning if args.no_autotune else soap.autotune(nl, st["spec"], st["qs"], st["al"], w["zeta"])
+
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -122,7 +127,7 @@ def main():
         torch.cuda.synchronize()
         _lib.soap_profile(soap.ctx, False)
         stages = _lib.soap_profile_read(soap.ctx)
-        res = dict(st=st, soap=soap, w=w, s=s, N=N, nl=nl, M=M, stages=stages,
+        res = dict(st=st, soap=soap, w=w, s=s, N=N, nl=nl, M=M, stages=stages, tuning=tuning,
                    ms=(t1 - t0) * 1e3 / steps, value=N * steps / (t1 - t0),
                    e=e.cpu().numpy(), F=F.cpu().numpy(), ab=ab.cpu().numpy())
         return res
@@ -204,7 +209,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "n_pairs": P, "r_cut": w["r_cut"], "n_max": n,
                    "l_max": w["l_max"], "n_species": w["n_species"], "M": M, "zeta": w["zeta"], "K": K,
-                   "precision": args.precision},
+                   "precision": args.precision, "tuning": main_run["tuning"]},
         "roofline": roofline,
         "fp64_path": fp64_path,
         "stages": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}

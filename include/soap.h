@@ -196,6 +196,38 @@ const char* soap_stage_name(int stage);
 /* Bytes of device workspace the context currently holds. */
 long long soap_workspace_bytes(const soap_ctx* ctx);
 
+/* ------------------------------------------------------------------ tuning
+ * Launch-shape choices that change speed, not the method.  Every setting
+ * computes the same quantities; settings that change the order of the GAP
+ * sums (two-pass vs fused, number of slices) agree to the rounding of the
+ * operand precision and meet the same bounds.  For a fixed setting every
+ * result is bitwise reproducible.
+ *   gap_fused   0: scores pass then Qbar pass; 1: one fused pass (16/32-bit
+ *               modes with K <= 352; ignored otherwise)
+ *   gap_slices  fused pass: target number of workgroups; the sparse set is
+ *               split into slices until the grid reaches it (0: 512)
+ *   prep_block  threads per block of the per-pair row kernel: 64, 128 or 256
+ */
+typedef struct {
+  int gap_fused;
+  int gap_slices;
+  int prep_block;
+} soap_tuning;
+
+/* Current setting of ctx (host struct).  SOAP_EINVAL on null arguments. */
+soap_status soap_get_tuning(const soap_ctx* ctx, soap_tuning* out /* host */);
+/* Install a setting; SOAP_EINVAL if a field is out of range. */
+soap_status soap_set_tuning(soap_ctx* ctx, const soap_tuning* t /* host */);
+/* Autotuner: times gap_energy_forces (energies and forces) on the caller's
+ * inputs for each candidate of each field in turn (coordinate search, `repeats`
+ * timed calls per candidate after one warm-up, HIP events on `stream`), keeps
+ * the fastest, installs it in ctx and returns it in *chosen (host, nullable).
+ * Outputs go to context-owned scratch; the call synchronises `stream`.  Errors
+ * as gap_energy_forces. */
+soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_sparse,
+                          const double* alpha, int M, int zeta, int repeats, soap_tuning* chosen /* host */,
+                          hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,6 +20,7 @@ EXPORTED = (
     "soap_create", "soap_destroy", "soap_descriptor_dim", "soap_status_string", "soap_last_error",
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
+    "soap_get_tuning", "soap_set_tuning", "soap_autotune",
 )
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused")
 
@@ -32,6 +33,13 @@ class soap_params(ctypes.Structure):
         ("alpha_r", ctypes.c_double), ("alpha_perp", ctypes.c_double), ("a", ctypes.c_double),
         ("central_weight", ctypes.c_double), ("l_weight", ctypes.c_int), ("precision", ctypes.c_int),
     ]
+
+
+class soap_tuning(ctypes.Structure):
+    _fields_ = [("gap_fused", ctypes.c_int), ("gap_slices", ctypes.c_int), ("prep_block", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"gap_fused": self.gap_fused, "gap_slices": self.gap_slices, "prep_block": self.prep_block}
 
 
 class soap_nlist(ctypes.Structure):
@@ -92,6 +100,12 @@ def load(path: str = LIB_PATH):
     lib.soap_profile_read.restype = i
     lib.soap_stage_name.argtypes = [i]
     lib.soap_stage_name.restype = ctypes.c_char_p
+    lib.soap_get_tuning.argtypes = [vp, P(soap_tuning)]
+    lib.soap_get_tuning.restype = i
+    lib.soap_set_tuning.argtypes = [vp, P(soap_tuning)]
+    lib.soap_set_tuning.restype = i
+    lib.soap_autotune.argtypes = [vp, P(soap_nlist), vp, vp, vp, i, i, i, P(soap_tuning), vp]
+    lib.soap_autotune.restype = i
     _lib = lib
     return lib
 
@@ -171,3 +185,20 @@ def soap_profile_read(ctx) -> dict:
     n = np.zeros(len(STAGES), dtype=np.int64)
     check(load().soap_profile_read(ctx, ms.ctypes.data, n.ctypes.data), ctx)
     return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(len(STAGES))}
+
+
+def soap_get_tuning(ctx) -> soap_tuning:
+    t = soap_tuning()
+    check(load().soap_get_tuning(ctx, ctypes.byref(t)), ctx)
+    return t
+
+
+def soap_set_tuning(ctx, t: soap_tuning) -> None:
+    check(load().soap_set_tuning(ctx, ctypes.byref(t)), ctx)
+
+
+def soap_autotune(ctx, nl: soap_nlist, species, q_sparse, alpha, M, zeta, repeats, stream) -> soap_tuning:
+    t = soap_tuning()
+    check(load().soap_autotune(ctx, ctypes.byref(nl), species, q_sparse, alpha, M, zeta, repeats, ctypes.byref(t),
+                               stream), ctx)
+    return t

@@ -38,6 +38,9 @@ struct soap_ctx {
   int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
+  long long row_pitch = 0;  // pair rows: field-major with this pitch (pairs)
+  soap_tuning tune{0, 0, 256};
+  Buf tune_out;  // scratch outputs of the autotuner
   size_t pinned_bytes = 0;
   // neighbour build
   Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_atoms, counts, scan_part,
@@ -186,13 +189,15 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
-  SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (NP > 0 ? NP : 1) * soap::pair_row_doubles(P));
+  ctx->row_pitch = (long long)((NP + 63) / 64 * 64 + 64);
+  SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (size_t)ctx->row_pitch * soap::pair_row_doubles(P));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
-  SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, deriv,
-                                       (double*)ctx->bc.p, st));
+  SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, ctx->row_pitch,
+                                       deriv, (double*)ctx->bc.p, ctx->tune.prep_block, st));
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
-                                        (const double*)ctx->rows.p, (const double*)ctx->bc.p, (double*)ctx->c.p, q,
+                                        (const double*)ctx->rows.p, ctx->row_pitch, (const double*)ctx->bc.p,
+                                        (double*)ctx->c.p, q,
                                         P.K, pnorm, st));
   return SOAP_OK;
 }
@@ -274,7 +279,7 @@ void soap_destroy(soap_ctx* ctx) {
   if (!ctx) return;
   Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
                  &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c, &ctx->cbar,
-                 &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp};
+                 &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp, &ctx->tune_out};
   for (Buf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& r : ctx->prof) {
@@ -468,7 +473,7 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
-                                            (const double*)ctx->rows.p, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                            (const double*)ctx->rows.p, ctx->row_pitch, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
                                             (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->cbar.p, (double*)ctx->gx.p,
                                             (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
@@ -504,11 +509,12 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     qbar = (double*)ctx->qbar.p;
   }
   const int prec = (int)ctx->prm.precision;
-  if (qbar && soap::gap_fused_supported(P.K, prec)) {
-    SOAP_ENSURE(ctx, ctx->gapw, soap::gap_fused_workspace_bytes((int)N, M, P.K, prec));
+  if (qbar && ctx->tune.gap_fused && soap::gap_fused_supported(P.K, prec)) {
+    const int target = ctx->tune.gap_slices > 0 ? ctx->tune.gap_slices : 512;
+    SOAP_ENSURE(ctx, ctx->gapw, soap::gap_fused_workspace_bytes((int)N, M, P.K, prec, target));
     StageTimer tm(ctx, SOAP_STAGE_GAP_FUSED, st);
     SOAP_HIP(ctx, soap::launch_gap_fused(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta, e_atom,
-                                         alpha_grad, qbar, ctx->gapw.p, st));
+                                         alpha_grad, qbar, ctx->gapw.p, target, st));
   } else {
     SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
     {
@@ -529,7 +535,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     {
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
-                                              (const double*)ctx->rows.p, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                              (const double*)ctx->rows.p, ctx->row_pitch, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
                                               (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->cbar.p, (double*)ctx->gx.p,
                                               (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
@@ -537,6 +543,85 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
                                             (const double*)ctx->gy.p, (const double*)ctx->gz.p, forces, false, st));
   }
+  return SOAP_OK;
+}
+
+soap_status soap_get_tuning(const soap_ctx* ctx, soap_tuning* out) {
+  if (!ctx || !out) return SOAP_EINVAL;
+  *out = ctx->tune;
+  return SOAP_OK;
+}
+
+soap_status soap_set_tuning(soap_ctx* ctx, const soap_tuning* t) {
+  if (!ctx || !t) return SOAP_EINVAL;
+  if ((t->gap_fused != 0 && t->gap_fused != 1) || t->gap_slices < 0 || t->gap_slices > (1 << 20) ||
+      (t->prep_block != 64 && t->prep_block != 128 && t->prep_block != 256))
+    return fail(ctx, SOAP_EINVAL, "tuning field out of range");
+  ctx->tune = *t;
+  return SOAP_OK;
+}
+
+soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_sparse,
+                          const double* alpha, int M, int zeta, int repeats, soap_tuning* chosen, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  if (!nl || repeats < 1) return fail(ctx, SOAP_EINVAL, "null neighbour list or repeats < 1");
+  const size_t N = (size_t)std::max(0, nl->n_atoms);
+  SOAP_ENSURE(ctx, ctx->tune_out, sizeof(double) * (4 * N + (size_t)std::max(M, 0) + 1));
+  double* e = (double*)ctx->tune_out.p;
+  double* F = e + N;
+  double* ab = F + 3 * N;
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    ctx->prof_on = prof;
+    return fail(ctx, SOAP_EHIP, "event creation failed");
+  }
+  auto time_it = [&](float& ms) -> soap_status {
+    soap_status s = gap_energy_forces(ctx, nl, species, q_sparse, alpha, M, zeta, e, F, ab, st);  // warm-up
+    if (s != SOAP_OK) return s;
+    if (hipEventRecord(a, st) != hipSuccess) return fail(ctx, SOAP_EHIP, "event record failed");
+    for (int r = 0; r < repeats; ++r)
+      if ((s = gap_energy_forces(ctx, nl, species, q_sparse, alpha, M, zeta, e, F, ab, st)) != SOAP_OK) return s;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      return fail(ctx, SOAP_EHIP, "event timing failed");
+    return SOAP_OK;
+  };
+  soap_tuning best = ctx->tune;
+  float best_ms = 0.0f;
+  soap_status s = time_it(best_ms);
+  const bool fusable = soap::gap_fused_supported(ctx->dp.K, (int)ctx->prm.precision);
+  struct Axis {
+    int soap_tuning::*field;
+    std::vector<int> cand;
+  };
+  const std::vector<Axis> axes = {
+      {&soap_tuning::prep_block, {64, 128, 256}},
+      {&soap_tuning::gap_fused, fusable ? std::vector<int>{0, 1} : std::vector<int>{0}},
+      {&soap_tuning::gap_slices, fusable ? std::vector<int>{256, 512, 1024, 2048} : std::vector<int>{}},
+  };
+  for (const Axis& ax : axes) {
+    if (s != SOAP_OK) break;
+    if (ax.field == &soap_tuning::gap_slices && !best.gap_fused) continue;
+    for (int v : ax.cand) {
+      if (v == best.*ax.field) continue;
+      ctx->tune = best;
+      ctx->tune.*ax.field = v;
+      float ms = 0.0f;
+      if ((s = time_it(ms)) != SOAP_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = ctx->tune;
+      }
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  ctx->tune = best;
+  ctx->prof_on = prof;
+  if (s != SOAP_OK) return s;
+  if (chosen) *chosen = best;
   return SOAP_OK;
 }
 

@@ -18,8 +18,10 @@ hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, const vo
 // Fused scores + Qbar (prec 1..3, padded K <= 352): e, alpha_bar (nullable) and
 // Qbar in one pass with no N x M intermediate in HBM
 bool gap_fused_supported(int K, int prec);
-size_t gap_fused_workspace_bytes(int N, int M, int K, int prec);
+// target: number of workgroups the sparse-set slices should fill
+size_t gap_fused_workspace_bytes(int N, int M, int K, int prec, int target);
 hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, hipStream_t st);
+                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, int target,
+                            hipStream_t st);
 
 }  // namespace soap

@@ -658,14 +658,14 @@ struct FusedLayout {
 };
 
 template <typename F>
-FusedLayout fused_layout(int N, int M, int K) {
+FusedLayout fused_layout(int N, int M, int K, int target) {
   FusedLayout L{};
   const size_t es = sizeof(typename F::T);
   L.Kf = (K + 31) / 32 * 32;
   L.Mp = padded(M);
   L.nrb = (N + F::BM - 1) / F::BM;
   const int nchunks = L.Mp / F::BN;
-  L.nsp = std::min(nchunks, std::max(1, (512 + L.nrb - 1) / L.nrb));
+  L.nsp = std::min(nchunks, std::max(1, (target + L.nrb - 1) / L.nrb));
   L.cps = (nchunks + L.nsp - 1) / L.nsp;
   L.nsp = (nchunks + L.cps - 1) / L.cps;
   const size_t nlo = F::kSplit ? 1 : 0;
@@ -690,9 +690,9 @@ FusedLayout fused_layout(int N, int M, int K) {
 
 template <typename F>
 hipError_t fused_impl(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta, double* e,
-                      double* alpha_bar, double* Qbar, void* work, hipStream_t st) {
+                      double* alpha_bar, double* Qbar, void* work, int target, hipStream_t st) {
   using T = typename F::T;
-  const FusedLayout L = fused_layout<F>(N, M, K);
+  const FusedLayout L = fused_layout<F>(N, M, K, target);
   char* w = (char*)work;
   T *qsc = (T*)(w + L.qsc), *qsc_lo = (T*)(w + L.qsc_lo), *qst = (T*)(w + L.qst), *qst_lo = (T*)(w + L.qst_lo);
   double *e_part = (double*)(w + L.e_part), *ab_part = (double*)(w + L.ab_part);
@@ -812,16 +812,17 @@ hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, con
 
 bool gap_fused_supported(int K, int prec) { return prec != 0 && (K + 31) / 32 * 32 <= kFusedK; }
 
-size_t gap_fused_workspace_bytes(int N, int M, int K, int prec) {
+size_t gap_fused_workspace_bytes(int N, int M, int K, int prec, int target) {
   switch (prec) {
-    case 1: return fused_layout<FF32>(N, M, K).total;
-    case 2: return fused_layout<FB16>(N, M, K).total;
-    default: return fused_layout<FB16X3>(N, M, K).total;
+    case 1: return fused_layout<FF32>(N, M, K, target).total;
+    case 2: return fused_layout<FB16>(N, M, K, target).total;
+    default: return fused_layout<FB16X3>(N, M, K, target).total;
   }
 }
 
 hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, hipStream_t st) {
+                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, int target,
+                            hipStream_t st) {
   if (N == 0) return hipSuccess;
   static bool attr_set[4] = {false, false, false, false};
   auto run = [&]<typename F>() {
@@ -831,7 +832,7 @@ hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, cons
       if (a != hipSuccess) return a;
       attr_set[prec] = true;
     }
-    return fused_impl<F>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, Qbar, work, st);
+    return fused_impl<F>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, Qbar, work, target, st);
   };
   switch (prec) {
     case 1: return run.template operator()<FF32>();

@@ -186,24 +186,33 @@ template <int NMAX, int LMAX, bool DERIV>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int n_pairs,
                                                      const double* __restrict__ dx, const double* __restrict__ dy,
                                                      const double* __restrict__ dz, double* __restrict__ rows,
-                                                     double* __restrict__ bc) {
+                                                     long long pitch, double* __restrict__ bc) {
   using S = Shape<NMAX, LMAX>;
   __shared__ PairTab<NMAX, LMAX> tab;
-  stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, 256);
+  stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, blockDim.x);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // central atom: a Gaussian at r = 0, where e_0 = 1, e_{l>0} = 0, Y_00 = 1 / sqrt(4 pi)
     double B[NMAX], dB[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;
     radial<NMAX, false>(P, tab, 0.0, B, dB);
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * tab.lw[0] * 0.28209479177387814;
   }
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   const double x = dx[p], y = dy[p], z = dz[p];
   const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-  double* __restrict__ row = rows + (size_t)p * S::ROW;
+  // field f of pair p at rows[f * pitch + p]: every store of a wavefront is contiguous
+  struct FieldRow {
+    double* base;
+    long long pitch;
+    __device__ double& operator[](int f) const { return base[(size_t)f * pitch]; }
+  } row{rows + p, pitch};
   double B[NMAX], dB[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
   radial<NMAX, DERIV>(P, tab, r, B, dB);
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
@@ -243,22 +252,37 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   }
 }
 
-// copy the first `width` doubles (16-byte units) of the compacted pairs' rows into LDS
-__device__ inline void stage_rows(const double* __restrict__ rows, int row_stride, const int* idx, int cnt,
-                                  int width, double* __restrict__ dst, int dst_stride, int lane) {
-  const int units = width / 2;
-  for (int u = lane; u < cnt * units; u += 64) {
-    const int t = u / units, part = u - t * units;
-    const double2 v = *reinterpret_cast<const double2*>(rows + (size_t)idx[t] * row_stride + 2 * part);
-    *reinterpret_cast<double2*>(dst + t * dst_stride + 2 * part) = v;
+// gather fields [0, WIDTH) of the compacted pairs from the field-major rows
+// (field f of pair p at rows[f * pitch + p]) into LDS rows of dst_stride doubles;
+// a wavefront moves 16 pairs x 4 fields per load, and every load of a lane is
+// issued before its stores
+template <int WIDTH>
+__device__ inline void stage_rows(const double* __restrict__ rows, long long pitch, const int* idx, int cnt,
+                                  double* __restrict__ dst, int dst_stride, int lane) {
+  constexpr int NF = (WIDTH + 3) / 4;
+  const int t16 = lane & 15, f4 = lane >> 4;
+  for (int t0 = 0; t0 < cnt; t0 += 16) {
+    const int t = t0 + t16;
+    if (t < cnt) {
+      const double* __restrict__ src = rows + (size_t)f4 * pitch + idx[t];
+      double v[NF];
+#pragma unroll
+      for (int u = 0; u < NF; ++u)
+        if (f4 + 4 * u < WIDTH) v[u] = src[(size_t)(4 * u) * pitch];
+      double* d = dst + t * dst_stride + f4;
+#pragma unroll
+      for (int u = 0; u < NF; ++u)
+        if (f4 + 4 * u < WIDTH) d[4 * u] = v[u];
+    }
   }
 }
 
 template <int NMAX, int LMAX>
-__global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
+__global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
                                                      const int* __restrict__ offsets, const int* __restrict__ nj,
                                                      const int* __restrict__ species, const double* __restrict__ rows,
-                                                     const double* __restrict__ bc_in, double* __restrict__ c_out,
+                                                     long long pitch, const double* __restrict__ bc_in,
+                                                     double* __restrict__ c_out,
                                                      double* __restrict__ q_out, int q_pitch,
                                                      double* __restrict__ pnorm_out) {
   using S = Shape<NMAX, LMAX>;
@@ -289,7 +313,7 @@ __global__ __launch_bounds__(64) void k_descriptor(DevParams P, const DevTables*
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      stage_rows(rows, S::ROW, idx, cnt, S::FR, dyn, LFR, lane);
+      stage_rows<S::FR>(rows, pitch, idx, cnt, dyn, LFR, lane);
       __syncthreads();
 #pragma unroll 1
       for (int pass = 0; pass < S::NPASS; ++pass) {
@@ -401,15 +425,13 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
   const int lane = threadIdx.x;
-  const int n = P.n, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
-  const size_t per_atom = (size_t)P.ns * NMAX * LLP;
-  double* csh = dyn;  // csh[a * LL + lm], a = s n + k
-  double* vb = dyn + nch * LL;
+  const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
+  const int per_atom = ns * NMAX * LLP;
+  double* csh = dyn;  // c of atom i in its HBM layout [species][lm][k]
+  double* vb = dyn + per_atom;
   const double* ci = c + (size_t)i * per_atom;
-  for (int t = lane; t < nch * LL; t += 64) {
-    const int a = t / LL, lm = t - a * LL, sa = a / n;
-    csh[t] = ci[((size_t)sa * LLP + lm) * NMAX + (a - sa * n)];
-  }
+  for (int t = lane; t < per_atom / 2; t += 64)
+    reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci)[t];
   const double* qi = q + (size_t)i * q_pitch;
   const double* qb = qbar + (size_t)i * qbar_pitch;
   double dot = 0.0;
@@ -419,27 +441,45 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int k = lane; k < K; k += 64) vb[k] = (qb[k] - qi[k] * dot) * inv;
   __syncthreads();
+  // lane per column (s, lm): cbar_{(s,k), lm} = sum_{(sb,kb)} M_{(s,k),(sb,kb)}(l) c_{(sb,kb), lm}
   double* co = cbar + (size_t)i * per_atom;
-  for (int t = lane; t < (int)per_atom; t += 64) {
-    const int col = t / NMAX, k = t - col * NMAX, sa = col / LLP, lm = col - sa * LLP;
-    double s = 0.0;
-    if (k < n && lm < LL) {
-      const int a = sa * n + k, l = isqrt_small(lm);
-      for (int b = 0; b < nch; ++b) {
-        const int lo = a < b ? a : b, hi = a < b ? b : a;
-        const double w = (a == b) ? 2.0 : kSqrt2;
-        s = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], csh[b * LL + lm], s);
+  for (int col = lane; col < ns * LLP; col += 64) {
+    const int s = col / LLP, lm = col - s * LLP;
+    double acc[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+    if (lm < LL) {
+      const int l = isqrt_small(lm);
+      for (int sb = 0; sb < ns; ++sb) {
+        double cv[NMAX];
+#pragma unroll
+        for (int kb = 0; kb < NMAX; ++kb) cv[kb] = kb < n ? csh[(sb * LLP + lm) * NMAX + kb] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+          const int a = s * n + k;
+#pragma unroll
+          for (int kb = 0; kb < NMAX; ++kb) {
+            const int b = sb * n + kb;
+            if (k < n && kb < n) {
+              const int lo = a < b ? a : b, hi = a < b ? b : a;
+              const double w = (a == b) ? 2.0 : kSqrt2;
+              acc[k] = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], cv[kb], acc[k]);
+            }
+          }
+        }
       }
     }
-    co[t] = s;
+    double* dst = co + (size_t)col * NMAX;
+#pragma unroll
+    for (int k = 0; k < NMAX; k += 2) reinterpret_cast<double2*>(dst)[k / 2] = double2{acc[k], acc[k + 1]};
   }
 }
 
 template <int NMAX, int LMAX>
-__global__ __launch_bounds__(64) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
+__global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
                                                        const int* __restrict__ offsets, const int* __restrict__ nj,
                                                        const int* __restrict__ species,
-                                                       const double* __restrict__ rows,
+                                                       const double* __restrict__ rows, long long pitch,
                                                        const double* __restrict__ cbar, double* __restrict__ gx,
                                                        double* __restrict__ gy, double* __restrict__ gz) {
   using S = Shape<NMAX, LMAX>;
@@ -473,7 +513,7 @@ __global__ __launch_bounds__(64) void k_pair_adjoint(DevParams P, const DevTable
       const int cnt = __popcll(mask);
       __syncthreads();
       if (cnt == 0) continue;
-      stage_rows(rows, S::ROW, idx, cnt, S::ROW, dyn, LAR, lane);
+      stage_rows<S::ROW>(rows, pitch, idx, cnt, dyn, LAR, lane);
       __syncthreads();
 #pragma unroll 1
       for (int pass = 0; pass < S::NPASS; ++pass) {
@@ -653,7 +693,7 @@ size_t rec_bytes(const DevParams& P) {
     return sizeof(RecTab<S::E, S::NC>);
   });
 }
-size_t cbar_dyn_bytes(const DevParams& P) { return sizeof(double) * ((size_t)P.nch * P.LL + P.K); }
+size_t cbar_dyn_bytes(const DevParams& P) { return sizeof(double) * (c_doubles_per_atom(P) + P.K); }
 
 }  // namespace
 
@@ -673,37 +713,39 @@ size_t adjoint_lds_bytes(const DevParams& P) {
 }
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
-                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, hipStream_t st) {
-  const int blocks = (int)((n_pairs + 255) / 256) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
+                            const double* dy, const double* dz, double* rows, long long pitch, bool deriv, double* bc,
+                            int block, hipStream_t st) {
+  if (block != 64 && block != 128) block = 256;
+  const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
   auto f = [&]<int N, int LM>() {
     if (deriv)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(256), 0, st, P, T, (int)n_pairs, dx, dy, dz,
-                         rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx, dy, dz,
+                         rows, pitch, bc);
     else
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(256), 0, st, P, T, (int)n_pairs, dx, dy, dz,
-                         rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx, dy, dz,
+                         rows, pitch, bc);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                             const int* species, const double* rows, const double* bc, double* c, double* q,
-                             int q_pitch, double* pnorm, hipStream_t st) {
+                             const int* species, const double* rows, long long pitch, const double* bc, double* c,
+                             double* q, int q_pitch, double* pnorm, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
     hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
-                       rows, bc, c, q, q_pitch, pnorm);
+                       rows, pitch, bc, c, q, q_pitch, pnorm);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
-                               const int* nj, const int* species, const double* rows, const double* c,
-                               const double* q, int q_pitch, const double* pnorm, const double* qbar, int qbar_pitch,
-                               double* cbar, double* gx, double* gy, double* gz, hipStream_t st) {
+                               const int* nj, const int* species, const double* rows, long long pitch,
+                               const double* c, const double* q, int q_pitch, const double* pnorm, const double* qbar,
+                               int qbar_pitch, double* cbar, double* gx, double* gy, double* gz, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
@@ -712,7 +754,7 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
-                       rows, cbar, gx, gy, gz);
+                       rows, pitch, cbar, gx, gy, gz);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);

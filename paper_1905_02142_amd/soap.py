@@ -168,3 +168,21 @@ class Soap:
         _lib.gap_energy_forces(self.ctx, nl.c_struct(), sp.data_ptr(), qs.data_ptr(), al.data_ptr(), M, int(zeta),
                                e.data_ptr(), _ptr(F), _ptr(ab), _stream())
         return e, F, ab
+
+    # ---------------------------------------------------------------- tuning
+    @property
+    def tuning(self) -> dict:
+        return _lib.soap_get_tuning(self.ctx).as_dict()
+
+    def set_tuning(self, gap_fused: int = 0, gap_slices: int = 0, prep_block: int = 256) -> None:
+        _lib.soap_set_tuning(self.ctx, _lib.soap_tuning(gap_fused, gap_slices, prep_block))
+
+    def autotune(self, nl: NeighbourList, species: torch.Tensor, q_sparse: torch.Tensor, alpha: torch.Tensor,
+                 zeta: int, repeats: int = 3) -> dict:
+        """soap_autotune on these inputs; installs and returns the fastest setting."""
+        qs = q_sparse.to(torch.float64).contiguous()
+        al = alpha.to(torch.float64).contiguous()
+        sp = species.to(torch.int32).contiguous()
+        t = _lib.soap_autotune(self.ctx, nl.c_struct(), sp.data_ptr(), qs.data_ptr(), al.data_ptr(), qs.shape[0],
+                               int(zeta), int(repeats), _stream())
+        return t.as_dict()

@@ -1,0 +1,81 @@
+"""Launch-shape tuning: every setting meets the bounds of its precision against
+the oracle, FP64 results do not depend on the setting at all, and the
+autotuner installs the setting it returns."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+KW = dict(n_max=8, l_max=6, r_cut=4.5, sigma0_r=0.5, sigma0_perp=0.5)
+BOUNDS = {"fp64": 1e-10, "bf16": 5e-2}
+SETTINGS = [dict(gap_fused=0, gap_slices=0, prep_block=256), dict(gap_fused=0, gap_slices=0, prep_block=64),
+            dict(gap_fused=1, gap_slices=256, prep_block=128), dict(gap_fused=1, gap_slices=2048, prep_block=256)]
+
+
+@pytest.fixture(scope="module")
+def case():
+    s = synth.rsa_box(400, 16.0, 1.2, 1203)
+    p = oracle.Params(**KW)
+    qs = synth.sparse_set(150, p.dim, 91)
+    al = synth.sparse_weights(150, 92)
+    spec = np.zeros(s.n_atoms, np.int32)
+    eo, Fo, abo = oracle.energy_forces(p, s.positions, s.cell, s.pbc, spec, qs, al, 3)
+    return s, spec, qs, al, eo, Fo, abo
+
+
+def _t(a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_every_setting_within_bounds(case, prec):
+    from paper_1905_02142_amd import Soap, SoapParams
+
+    s, spec, qs, al, eo, Fo, abo = case
+    soap = Soap(SoapParams(precision=prec, **KW))
+    nl = soap.neighbors(_t(s.positions), s.cell, s.pbc)
+    outs = []
+    for t in SETTINGS:
+        soap.set_tuning(**t)
+        assert soap.tuning == t
+        e, F, ab = soap.energy_forces(nl, _t(spec), _t(qs), _t(al), 3)
+        torch.cuda.synchronize()
+        e, F, ab = e.cpu().numpy(), F.cpu().numpy(), ab.cpu().numpy()
+        b = BOUNDS[prec]
+        assert np.abs(e - eo).max() <= b * np.abs(eo).max(), t
+        assert np.abs(F - Fo).max() <= b * np.abs(Fo).max(), t
+        assert np.abs(ab - abo).max() <= b * np.abs(abo).max(), t
+        outs.append((e, F, ab))
+    if prec == "fp64":  # no setting changes FP64 arithmetic
+        for o in outs[1:]:
+            assert all(np.array_equal(x, y) for x, y in zip(o, outs[0]))
+
+
+def test_invalid_setting_rejected():
+    from paper_1905_02142_amd import Soap, SoapParams, _lib
+
+    soap = Soap(SoapParams(**KW))
+    with pytest.raises(_lib.SoapError):
+        soap.set_tuning(prep_block=100)
+    with pytest.raises(_lib.SoapError):
+        soap.set_tuning(gap_fused=2)
+
+
+def test_autotune_installs_its_choice(case):
+    from paper_1905_02142_amd import Soap, SoapParams
+
+    s, spec, qs, al, eo, Fo, abo = case
+    soap = Soap(SoapParams(precision="bf16", **KW))
+    nl = soap.neighbors(_t(s.positions), s.cell, s.pbc)
+    chosen = soap.autotune(nl, _t(spec), _t(qs), _t(al), 3, repeats=2)
+    print("autotune chose", chosen)
+    assert soap.tuning == chosen
+    assert chosen["prep_block"] in (64, 128, 256) and chosen["gap_fused"] in (0, 1)
+    e, F, _ = soap.energy_forces(nl, _t(spec), _t(qs), _t(al), 3)
+    torch.cuda.synchronize()
+    assert np.abs(F.cpu().numpy() - Fo).max() <= 5e-2 * np.abs(Fo).max()
