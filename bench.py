@@ -48,18 +48,34 @@ def workload_setup(name, precision, dev):
     return st
 
 
-def algorithmic_work(stage, N, P, M, K, n, L2, nch):
-    """(amount, unit) of algorithmic work of one launch of a stage."""
+# stages that are exactly one kernel (the roofline is quoted for one kernel)
+SINGLE_KERNEL = {"descriptor": "k_descriptor", "pair_adjoint": "k_pair_adjoint", "pair_prep": "k_pair_prep",
+                 "cbar": "k_cbar", "gap_qbar": "k_qbar", "force_gather": "k_force_gather"}
+
+
+def algorithmic_work(stage, N, P, M, K, n, l_max, nch):
+    """(amount, unit) of the algorithmic work of one launch of a stage.
+
+    Floating-point counts are the method's own arithmetic (FMA = 2 flop), not the
+    instructions a kernel happens to issue; bytes are the unavoidable HBM traffic."""
+    L2 = (l_max + 1) ** 2
+    nab = nch * (nch + 1) // 2
     if stage in ("gap_scores", "gap_qbar"):
         return 2.0 * N * M * K, "flop"
     if stage == "gap_fused":  # both contractions in one pass
         return 4.0 * N * M * K, "flop"
+    if stage == "pair_prep":
+        # per pair: overlap recursion (~5 FMA per order), orthonormal transform (n^2 FMA),
+        # derivative of both, ilexp (~4 FMA per order) and its derivative, azimuthal powers
+        return P * 2.0 * (2 * (5 * (n + 3) + n * n) + 8 * (l_max + 2) + 4 * (l_max + 1)), "flop"
     if stage == "descriptor":
-        # c accumulation (2 n L^2 per pair) + power spectrum (nch(nch+1)/2 L^2 FMAs per atom)
-        return 2.0 * P * n * L2 + 2.0 * N * nch * (nch + 1) / 2 * L2, "flop"
+        # c accumulation (n L^2 FMA per pair, Eq. (08)) + power spectrum (L^2 FMA per channel pair, Eq. (09))
+        return 2.0 * P * n * L2 + 2.0 * N * nab * L2, "flop"
+    if stage == "cbar":
+        return 2.0 * N * nch * nch * L2, "flop"
     if stage == "pair_adjoint":
-        # two contractions of cbar with B and dB/dr per pair (U and V), plus cbar = M c per atom
-        return 4.0 * P * n * L2 + 2.0 * N * nch * nch * L2, "flop"
+        # U and V contractions (2 n L^2 FMA per pair) and the gradient terms (~5 FMA per slot)
+        return 2.0 * P * (2 * n * L2 + 5 * L2), "flop"
     if stage == "force_gather":
         return P * (4 + 2 * 24) + N * 24 + (N + 1) * 4, "byte"
     if stage == "neighbors":
@@ -114,20 +130,28 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        # per-stage times from a short pass with every stage's events
+        _lib.soap_profile_read(soap.ctx)
+        _lib.soap_profile(soap.ctx, True)
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        _lib.soap_profile(soap.ctx, False)
+        stages = _lib.soap_profile_read(soap.ctx)
+        per_step = {k: v[0] / 5.0 for k, v in stages.items() if v[1] and k in SINGLE_KERNEL}
+        dominant = max(per_step, key=per_step.get)
+        # the timed region records events around the dominant kernel only
+        _lib.soap_profile_stages(soap.ctx, [dominant])
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        # per-stage times from a separate pass (the stage events are not in the timed loop)
-        _lib.soap_profile_read(soap.ctx)  # drop anything recorded so far
-        _lib.soap_profile(soap.ctx, True)
-        for _ in range(min(steps, 10)):
-            step()
-        torch.cuda.synchronize()
         _lib.soap_profile(soap.ctx, False)
-        stages = _lib.soap_profile_read(soap.ctx)
-        res = dict(st=st, soap=soap, w=w, s=s, N=N, nl=nl, M=M, stages=stages, tuning=tuning,
+        timed = _lib.soap_profile_read(soap.ctx)[dominant]
+        res = dict(st=st, soap=soap, w=w, s=s, N=N, nl=nl, M=M, stages=stages, tuning=tuning, dominant=dominant,
+                   dominant_ms=timed[0] / timed[1],
                    ms=(t1 - t0) * 1e3 / steps, value=N * steps / (t1 - t0),
                    e=e.cpu().numpy(), F=F.cpu().numpy(), ab=ab.cpu().numpy())
         return res
@@ -146,40 +170,37 @@ def main():
                      "energy_max_abs_err": float(np.abs(main_run["e"] - ref["e"]).max()),
                      "rms_force_eV_per_A": float(np.sqrt(np.mean(ref["F"] ** 2)))}
 
-    # roofline of every stage; the dominant one goes in "roofline"
+    # roofline of every stage (from the per-stage pass); the dominant kernel's, timed inside the
+    # timed region, goes in "roofline"
     P, K = nl.n_pairs, soap.dim
-    n, L2, nch = w["n_max"], (w["l_max"] + 1) ** 2, w["n_max"] * w["n_species"]
+    n, l_max, nch = w["n_max"], w["l_max"], w["n_max"] * w["n_species"]
     gemm_peak = {"fp64": PEAK["fp64_TFs"], "f32": PEAK["fp32_TFs"], "bf16": PEAK["bf16_TFs"],
                  "bf16x3": PEAK["bf16_TFs"]}[args.precision]
+
+    def rate(name, avg_ms):
+        work, unit = algorithmic_work(name, N, P, M, K, n, l_max, nch)
+        if unit == "flop":
+            bound, peak, u = ("mfma", gemm_peak, "TFLOP/s") if name.startswith("gap") else ("alu", PEAK["fp64_TFs"],
+                                                                                           "TFLOP/s")
+            achieved = work / (avg_ms * 1e-3) / 1e12
+        else:
+            bound, peak, u = "hbm", PEAK["hbm_GBs"], "GB/s"
+            achieved = work / (avg_ms * 1e-3) / 1e9
+        return bound, peak, u, achieved
+
     per_stage = {}
     for name, (tot, cnt) in stages.items():
         if cnt == 0:
             continue
         avg_ms = tot / cnt
-        work, unit = algorithmic_work(name, N, P, M, K, n, L2, nch)
-        if unit == "flop":
-            if name.startswith("gap"):
-                bound, peak, u = "mfma", gemm_peak, "TFLOP/s"
-            else:
-                bound, peak, u = "alu", PEAK["fp64_TFs"], "TFLOP/s"
-            achieved = work / (avg_ms * 1e-3) / 1e12
-        else:
-            bound, peak, u = "hbm", PEAK["hbm_GBs"], "GB/s"
-            achieved = work / (avg_ms * 1e-3) / 1e9
-        per_stage[name] = dict(avg_ms=avg_ms, launches=cnt, share=avg_ms * cnt / (ms * min(args.steps, 10)),
-                               bound=bound, achieved=achieved, peak=peak, unit=u, frac=achieved / peak)
-    dom = max(per_stage, key=lambda k: per_stage[k]["avg_ms"] * per_stage[k]["launches"])
-    d = per_stage[dom]
-    roofline = {"kernel": dom, "bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"],
-                "unit": d["unit"], "frac": round(d["frac"], 4), "traffic": None}
-
-    if args.calibrate_copy:
-        src = torch.ones(1 << 26, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        bound, peak, u, achieved = rate(name, avg_ms)
+        per_stage[name] = dict(avg_ms=avg_ms, launches_per_step=cnt / 5.0, share=tot / 5.0 / ms, bound=bound,
+                               achieved=achieved, peak=peak, unit=u, frac=achieved / peak)
+    dom = main_run["dominant"]
+    bound, peak, u, achieved = rate(dom, main_run["dominant_ms"])
+    roofline = {"kernel": SINGLE_KERNEL[dom], "bound": bound, "achieved": round(achieved, 3), "peak": peak,
+                "unit": u, "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_ms": round(main_run["dominant_ms"], 5)}
 
     cpu = None
     if not args.no_cpu_baseline:

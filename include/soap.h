@@ -174,22 +174,27 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
 soap_status soap_radial_basis_table(int n_max, double r_cut, double sigma0_r, double* W, double* lambda);
 
 /* Per-stage device timing.  soap_profile(ctx, 1) makes every later call record a
- * pair of hipEvents around each kernel group, on the stream that group is
- * launched on; soap_profile(ctx, 0) stops recording.  soap_profile_read
+ * pair of hipEvents around each stage, on the stream that stage is launched
+ * on; soap_profile(ctx, 0) stops recording.  soap_profile_stages(ctx, mask)
+ * records only the stages whose bit (1 << stage) is set.  soap_profile_read
  * waits for the recorded events, writes per stage the summed milliseconds and
  * the number of launches (host arrays of SOAP_STAGE_COUNT entries) and clears
- * the record.  Recording adds two event records per kernel group. */
+ * the record.  Recording adds two event records per timed stage.  Stages 1, 4,
+ * 7 and 8 are one kernel each. */
 typedef enum {
   SOAP_STAGE_NEIGHBORS = 0,     /* cell list, pair count and fill, reverse index */
-  SOAP_STAGE_DESCRIPTOR = 1,    /* c_nlm, power spectrum, q */
-  SOAP_STAGE_GAP_SCORES = 2,    /* S = Q Q_s^T with the zeta epilogue: e, G, dE/dalpha */
+  SOAP_STAGE_DESCRIPTOR = 1,    /* c_nlm, power spectrum, q (one kernel) */
+  SOAP_STAGE_GAP_SCORES = 2,    /* operand conversion, S = Q Q_s^T with the zeta epilogue: e, G, dE/dalpha */
   SOAP_STAGE_GAP_QBAR = 3,      /* Qbar = G Q_s */
-  SOAP_STAGE_PAIR_ADJOINT = 4,  /* cbar and the per-pair gradients */
+  SOAP_STAGE_PAIR_ADJOINT = 4,  /* the per-pair gradients (one kernel) */
   SOAP_STAGE_FORCE_GATHER = 5,  /* per-atom force sums */
   SOAP_STAGE_GAP_FUSED = 6,     /* S, the zeta epilogue and Qbar = G Q_s in one pass (16/32-bit modes) */
-  SOAP_STAGE_COUNT = 7
+  SOAP_STAGE_PAIR_PREP = 7,     /* per-pair radial, ilexp and azimuthal factors (one kernel) */
+  SOAP_STAGE_CBAR = 8,          /* vbar and cbar = M c, the power-spectrum adjoint (one kernel) */
+  SOAP_STAGE_COUNT = 9
 } soap_stage;
 soap_status soap_profile(soap_ctx* ctx, int enable);
+soap_status soap_profile_stages(soap_ctx* ctx, unsigned mask);
 soap_status soap_profile_read(soap_ctx* ctx, double* ms /* host */, long long* launches /* host */);
 const char* soap_stage_name(int stage);
 

@@ -20,9 +20,10 @@ EXPORTED = (
     "soap_create", "soap_destroy", "soap_descriptor_dim", "soap_status_string", "soap_last_error",
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
-    "soap_get_tuning", "soap_set_tuning", "soap_autotune",
+    "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
 )
-STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused")
+STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
+          "pair_prep", "cbar")
 
 
 class soap_params(ctypes.Structure):
@@ -100,6 +101,8 @@ def load(path: str = LIB_PATH):
     lib.soap_profile_read.restype = i
     lib.soap_stage_name.argtypes = [i]
     lib.soap_stage_name.restype = ctypes.c_char_p
+    lib.soap_profile_stages.argtypes = [vp, ctypes.c_uint]
+    lib.soap_profile_stages.restype = i
     lib.soap_get_tuning.argtypes = [vp, P(soap_tuning)]
     lib.soap_get_tuning.restype = i
     lib.soap_set_tuning.argtypes = [vp, P(soap_tuning)]
@@ -175,6 +178,14 @@ def soap_radial_basis_table(n_max: int, r_cut: float, sigma0_r: float, W, lam) -
 
 def soap_profile(ctx, enable: bool) -> None:
     check(load().soap_profile(ctx, 1 if enable else 0), ctx)
+
+
+def soap_profile_stages(ctx, names) -> None:
+    """Record events only around the named stages."""
+    mask = 0
+    for n in names:
+        mask |= 1 << STAGES.index(n)
+    check(load().soap_profile_stages(ctx, mask), ctx)
 
 
 def soap_profile_read(ctx) -> dict:

@@ -38,7 +38,6 @@ struct soap_ctx {
   int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
-  long long row_pitch = 0;  // pair rows: field-major with this pitch (pairs)
   soap_tuning tune{0, 0, 256};
   Buf tune_out;  // scratch outputs of the autotuner
   size_t pinned_bytes = 0;
@@ -52,7 +51,7 @@ struct soap_ctx {
     int stage;
     hipEvent_t a, b;
   };
-  bool prof_on = false;
+  unsigned prof_mask = 0;  // stages whose events are recorded
   std::vector<Rec> prof;
   std::vector<hipEvent_t> ev_pool;
 };
@@ -162,7 +161,7 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t a = nullptr;
   StageTimer(soap_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
-    if (ctx->prof_on) {
+    if ((ctx->prof_mask >> stage) & 1u) {
       a = take_event(ctx);
       if (a && hipEventRecord(a, st) != hipSuccess) {
         ctx->ev_pool.push_back(a);
@@ -189,15 +188,16 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
-  ctx->row_pitch = (long long)((NP + 63) / 64 * 64 + 64);
-  SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (size_t)ctx->row_pitch * soap::pair_row_doubles(P));
+  SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (NP > 0 ? NP : 1) * soap::pair_row_doubles(P));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
+  {
+    StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
+    SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, deriv,
+                                         (double*)ctx->bc.p, ctx->tune.prep_block, st));
+  }
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
-  SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, ctx->row_pitch,
-                                       deriv, (double*)ctx->bc.p, ctx->tune.prep_block, st));
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
-                                        (const double*)ctx->rows.p, ctx->row_pitch, (const double*)ctx->bc.p,
-                                        (double*)ctx->c.p, q,
+                                        (const double*)ctx->rows.p, (const double*)ctx->bc.p, (double*)ctx->c.p, q,
                                         P.K, pnorm, st));
   return SOAP_OK;
 }
@@ -402,7 +402,7 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
     SOAP_HIP(ctx, soap::launch_pairs(false, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
                                      (const int*)ctx->bin_atoms.p, (int*)ctx->counts.p, nullptr, 0, nullptr, nullptr,
-                                     nullptr, nullptr, nullptr, nullptr, err, st));
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, err, st));
   }
   SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->counts.p, n_atoms, nl->offsets, (int*)ctx->scan_part.p, st));
   tm_count.stop();
@@ -432,7 +432,7 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
     SOAP_HIP(ctx, soap::launch_pairs(true, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
                                      (const int*)ctx->bin_atoms.p, nullptr, nl->offsets, nl->capacity, nl->j, nl->img,
-                                     nl->center, nl->dx, nl->dy, nl->dz, err, st));
+                                     nl->center, nl->dx, nl->dy, nl->dz, nl->rev, err, st));
     SOAP_HIP(ctx, soap::launch_reverse(total, nl->offsets, nl->j, nl->img, nl->center, nl->rev, err, st));
   }
   return SOAP_OK;
@@ -471,11 +471,15 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   SOAP_ENSURE(ctx, ctx->cbar, sizeof(double) * N * soap::c_doubles_per_atom(P));
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, true, st)) != SOAP_OK) return s;
   {
+    {
+      StageTimer tm(ctx, SOAP_STAGE_CBAR, st);
+      SOAP_HIP(ctx, soap::launch_cbar(P, nl->n_atoms, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                      (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->cbar.p, st));
+    }
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
-                                            (const double*)ctx->rows.p, ctx->row_pitch, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
-                                            (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->cbar.p, (double*)ctx->gx.p,
-                                            (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+                                            (const double*)ctx->rows.p, (const double*)ctx->cbar.p,
+                                            (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
   SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
@@ -533,11 +537,15 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->cbar, sizeof(double) * N * soap::c_doubles_per_atom(P));
     {
+      {
+        StageTimer tm(ctx, SOAP_STAGE_CBAR, st);
+        SOAP_HIP(ctx, soap::launch_cbar(P, nl->n_atoms, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
+                                        (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->cbar.p, st));
+      }
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
-                                              (const double*)ctx->rows.p, ctx->row_pitch, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
-                                              (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->cbar.p, (double*)ctx->gx.p,
-                                              (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+                                              (const double*)ctx->rows.p, (const double*)ctx->cbar.p,
+                                              (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
@@ -570,11 +578,11 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
   double* e = (double*)ctx->tune_out.p;
   double* F = e + N;
   double* ab = F + 3 * N;
-  const bool prof = ctx->prof_on;
-  ctx->prof_on = false;
+  const unsigned prof = ctx->prof_mask;
+  ctx->prof_mask = 0;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-    ctx->prof_on = prof;
+    ctx->prof_mask = prof;
     return fail(ctx, SOAP_EHIP, "event creation failed");
   }
   auto time_it = [&](float& ms) -> soap_status {
@@ -619,7 +627,7 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
   hipEventDestroy(a);
   hipEventDestroy(b);
   ctx->tune = best;
-  ctx->prof_on = prof;
+  ctx->prof_mask = prof;
   if (s != SOAP_OK) return s;
   if (chosen) *chosen = best;
   return SOAP_OK;
@@ -627,7 +635,13 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
 
 soap_status soap_profile(soap_ctx* ctx, int enable) {
   if (!ctx) return SOAP_EINVAL;
-  ctx->prof_on = enable != 0;
+  ctx->prof_mask = enable ? ~0u : 0u;
+  return SOAP_OK;
+}
+
+soap_status soap_profile_stages(soap_ctx* ctx, unsigned mask) {
+  if (!ctx) return SOAP_EINVAL;
+  ctx->prof_mask = mask;
   return SOAP_OK;
 }
 
@@ -654,8 +668,8 @@ soap_status soap_profile_read(soap_ctx* ctx, double* ms, long long* launches) {
 }
 
 const char* soap_stage_name(int stage) {
-  static const char* names[SOAP_STAGE_COUNT] = {"neighbors",    "descriptor",   "gap_scores", "gap_qbar",
-                                                "pair_adjoint", "force_gather", "gap_fused"};
+  static const char* names[SOAP_STAGE_COUNT] = {"neighbors",    "descriptor",   "gap_scores", "gap_qbar", "pair_adjoint",
+                                                "force_gather", "gap_fused",    "pair_prep",  "cbar"};
   return (stage >= 0 && stage < SOAP_STAGE_COUNT) ? names[stage] : "unknown";
 }
 

@@ -97,6 +97,40 @@ __global__ void k_convert(int rows, int cols, int rows_p, int cols_p, const doub
   if (SPLIT) dst_lo[e] = cvt_lo_any<T>(x, h);
 }
 
+// the three operand conversions of one GAP call in one launch: Q (N x Kp), Q_s
+// (Mp x Kp) and Q_s^T (Kp x Mp), zero padded
+template <typename T, bool SPLIT>
+__global__ void k_convert3(int N, int M, int K, int Kp, int Mp, const double* __restrict__ Q,
+                           const double* __restrict__ Qs, T* __restrict__ qc, T* __restrict__ qc_lo,
+                           T* __restrict__ qsc, T* __restrict__ qsc_lo, T* __restrict__ qst, T* __restrict__ qst_lo) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n1 = (long long)N * Kp, n2 = (long long)Mp * Kp;
+  double x;
+  T* dst;
+  T* dlo;
+  if (e < n1) {
+    const int r = (int)(e / Kp), c = (int)(e - (long long)r * Kp);
+    x = c < K ? Q[(size_t)r * K + c] : 0.0;
+    dst = qc;
+    dlo = qc_lo;
+  } else if ((e -= n1) < n2) {
+    const int r = (int)(e / Kp), c = (int)(e - (long long)r * Kp);
+    x = (r < M && c < K) ? Qs[(size_t)r * K + c] : 0.0;
+    dst = qsc;
+    dlo = qsc_lo;
+  } else if ((e -= n2) < n2) {
+    const int r = (int)(e / Mp), c = (int)(e - (long long)r * Mp);  // dst[r][c] = Qs[c][r]
+    x = (c < M && r < K) ? Qs[(size_t)c * K + r] : 0.0;
+    dst = qst;
+    dlo = qst_lo;
+  } else {
+    return;
+  }
+  const T h = cvt<T>(x);
+  dst[e] = h;
+  if (SPLIT) dlo[e] = cvt_lo_any<T>(x, h);
+}
+
 template <typename P>
 struct Smem {
   static constexpr int EPV = 16 / sizeof(typename P::T);  // elements per 16-byte vector
@@ -340,13 +374,27 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, cons
       }
 }
 
-// out[j] = sum_t part[t * n + j], t = 0..nt-1 in order
-__global__ void k_sum_parts(int n, int nt, const double* __restrict__ part, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// e[i] = sum_t e_part[t][i] (t < nte) and, if ab, ab[j] = sum_t ab_part[t][j] (t < nta),
+// each in a fixed order; the loads of eight terms are issued together
+__device__ inline double ordered_sum(const double* __restrict__ part, int n, int nt, int j) {
   double s = 0.0;
-  for (int t = 0; t < nt; ++t) s += part[(size_t)t * n + j];
-  out[j] = s;
+  int t = 0;
+  for (; t + 8 <= nt; t += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(t + u) * n + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; t < nt; ++t) s += part[(size_t)t * n + j];
+  return s;
+}
+
+__global__ void k_sum_parts2(int N, int nte, const double* __restrict__ e_part, double* __restrict__ e, int M, int nta,
+                             const double* __restrict__ ab_part, double* __restrict__ ab) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) e[j] = ordered_sum(e_part, N, nte, j);
+  else if (ab && j < N + M) ab[j - N] = ordered_sum(ab_part, M, nta, j - N);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -760,18 +808,13 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
   T *qst = (T*)(w + L.qst), *qst_lo = (T*)(w + L.qst_lo), *G = (T*)(w + L.g), *G_lo = (T*)(w + L.g_lo);
   double *e_part = (double*)(w + L.e_part), *ab_part = (double*)(w + L.ab_part);
   auto blocks = [](long long n) { return dim3((unsigned)((n + 255) / 256)); };
-  hipLaunchKernelGGL((k_convert<T, P::kSplit, false>), blocks((long long)N * Kp), dim3(256), 0, st, N, K, N, Kp, Q,
-                     qc, qc_lo);
-  hipLaunchKernelGGL((k_convert<T, P::kSplit, false>), blocks((long long)Mp * Kp), dim3(256), 0, st, M, K, Mp, Kp, Qs,
-                     qsc, qsc_lo);
-  hipLaunchKernelGGL((k_convert<T, P::kSplit, true>), blocks((long long)Kp * Mp), dim3(256), 0, st, M, K, Kp, Mp, Qs,
-                     qst, qst_lo);
+  hipLaunchKernelGGL((k_convert3<T, P::kSplit>), blocks((long long)N * Kp + 2LL * Mp * Kp), dim3(256), 0, st, N, M,
+                     K, Kp, Mp, Q, Qs, qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
   const int nst = (Mp + P::BN - 1) / P::BN, nit = (N + P::BM - 1) / P::BM;
   hipLaunchKernelGGL(k_scores<P>, dim3(nst, nit), dim3(256), 0, st, N, M, Mp, Kp, qc, qc_lo, qsc, qsc_lo, alpha, zeta,
                      G, G_lo, e_part, ab_part);
-  hipLaunchKernelGGL(k_sum_parts, dim3((N + 255) / 256), dim3(256), 0, st, N, nst, e_part, e);
-  if (alpha_bar)
-    hipLaunchKernelGGL(k_sum_parts, dim3((M + 255) / 256), dim3(256), 0, st, M, nit, ab_part, alpha_bar);
+  hipLaunchKernelGGL(k_sum_parts2, dim3((N + M + 255) / 256), dim3(256), 0, st, N, nst, e_part, e, M, nit, ab_part,
+                     alpha_bar);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ hipError_t launch_fill_bins(int n_atoms, const int* atom_bin, const int* bin_sta
 hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructMeta* meta, const int* so,
                         int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
                         const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
-                        int* ncenter, double* ndx, double* ndy, double* ndz, int* err, hipStream_t st);
+                        int* ncenter, double* ndx, double* ndy, double* ndz, int* nrev, int* err, hipStream_t st);
 hipError_t launch_reverse(long long n_pairs, const int* offsets, const int* nj, const int* nimg, const int* ncenter,
                           int* rev, int* err, hipStream_t st);
 

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
                                                int* __restrict__ nj, int* __restrict__ nimg,
                                                int* __restrict__ ncenter, double* __restrict__ ndx,
                                                double* __restrict__ ndy, double* __restrict__ ndz,
-                                               int* __restrict__ err) {
+                                               int* __restrict__ nrev, int* __restrict__ err) {
   __shared__ int s_pref[4][65];   // inclusive scan of candidate counts
   __shared__ int s_start[4][64];  // first bin_atoms slot of each offset
   __shared__ int s_shift[4][64];  // lattice shift of each offset (packed)
@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
           nj[q] = j;
           nimg[q] = pack_img(T0, T1, T2);
           ncenter[q] = i;
+          nrev[q] = (int)q;  // until the reverse search sets it
           ndx[q] = ddx;
           ndy[q] = ddy;
           ndz[q] = ddz;
@@ -207,8 +208,11 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
   if (!FILL && lane == 0) count[i] = cnt;
 }
 
-// rev[p]: the pair (j -> i, -T) in j's list.  16 lanes per pair probe j's list
-// with coalesced loads; the match is unique, so the minimum over the lanes is it.
+// rev[p]: the pair (j -> i, -T) in j's list.  Only pairs with i < j search (16
+// lanes probe j's list with coalesced loads; the match is unique, so the
+// minimum over the lanes is it) and set both directions; pairs with i == j (a
+// periodic image of the centre) search their own list; pairs with i > j are
+// set by their partner.  Every rev entry starts as the pair itself.
 __global__ __launch_bounds__(256) void k_reverse(long long n_pairs, const int* __restrict__ offsets,
                                                  const int* __restrict__ nj, const int* __restrict__ nimg,
                                                  const int* __restrict__ ncenter, int* __restrict__ rev,
@@ -216,22 +220,32 @@ __global__ __launch_bounds__(256) void k_reverse(long long n_pairs, const int* _
   const long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
   int found = 0x7fffffff;
+  bool searched = false;
+  int i = 0, j = 0;
   if (p < n_pairs) {
-    const int i = ncenter[p], j = nj[p];
-    int T[3];
-    unpack_img(nimg[p], T);
-    const int want = pack_img(-T[0], -T[1], -T[2]);
-    for (int q = offsets[j] + sub; q < offsets[j + 1]; q += 16)
-      if (nj[q] == i && nimg[q] == want) {
-        found = q;
-        break;
-      }
+    i = ncenter[p];
+    j = nj[p];
+    if (i <= j) {
+      searched = true;
+      int T[3];
+      unpack_img(nimg[p], T);
+      const int want = pack_img(-T[0], -T[1], -T[2]);
+      for (int q = offsets[j] + sub; q < offsets[j + 1]; q += 16)
+        if (nj[q] == i && nimg[q] == want) {
+          found = q;
+          break;
+        }
+    }
   }
 #pragma unroll
   for (int o = 8; o >= 1; o >>= 1) found = min(found, __shfl_xor(found, o, 16));
-  if (p < n_pairs && sub == 0) {
-    if (found == 0x7fffffff) atomicOr(err, kErrNoReverse);
-    rev[p] = found == 0x7fffffff ? (int)p : found;
+  if (searched && sub == 0) {
+    if (found == 0x7fffffff) {
+      atomicOr(err, kErrNoReverse);
+    } else {
+      rev[p] = found;
+      if (i < j) rev[found] = (int)p;
+    }
   }
 }
 
@@ -385,14 +399,14 @@ hipError_t launch_fill_bins(int n_atoms, const int* atom_bin, const int* bin_sta
 hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructMeta* meta, const int* so,
                         int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
                         const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
-                        int* ncenter, double* ndx, double* ndy, double* ndz, int* err, hipStream_t st) {
+                        int* ncenter, double* ndx, double* ndy, double* ndz, int* nrev, int* err, hipStream_t st) {
   dim3 g((n_atoms + 3) / 4), b(256);
   if (fill)
     hipLaunchKernelGGL(k_pairs<true>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
-                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, err);
+                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, nrev, err);
   else
     hipLaunchKernelGGL(k_pairs<false>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
-                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, err);
+                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, nrev, err);
   return hipGetLastError();
 }
 

@@ -16,24 +16,26 @@ size_t c_doubles_per_atom(const DevParams& P);
 // factors and their r-derivatives)
 size_t pair_row_doubles(const DevParams& P);
 
-// pair rows for n_pairs neighbours (derivative part only if deriv), field-major:
-// field f of pair p at rows[f * pitch + p], pitch >= n_pairs; and the
-// central-atom radial factors bc (n_max doubles)
+// pair rows (pair_row_doubles each, pair-major) for n_pairs neighbours, the
+// derivative part only if deriv, and the central-atom radial factors bc
+// (n_max doubles); block: threads per block (64, 128 or 256)
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
-                            const double* dy, const double* dz, double* rows, long long pitch, bool deriv, double* bc,
-                            int block, hipStream_t st);
+                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, int block,
+                            hipStream_t st);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                             const int* species, const double* rows, long long pitch, const double* bc, double* c,
-                             double* q, int q_pitch, double* pnorm, hipStream_t st);
+                             const int* species, const double* rows, const double* bc, double* c, double* q,
+                             int q_pitch, double* pnorm, hipStream_t st);
 
-// pair gradients g_p = dE/dd_p (SoA) from qbar = dE/dq, the forward c, q, |p| and
-// the pair rows with derivatives; cbar is workspace of n_atoms x c_doubles_per_atom
+// cbar (n_atoms x c_doubles_per_atom) from qbar = dE/dq and the forward c, q, |p|
+hipError_t launch_cbar(const DevParams& P, int n_atoms, const double* c, const double* q, int q_pitch,
+                       const double* pnorm, const double* qbar, int qbar_pitch, double* cbar, hipStream_t st);
+
+// pair gradients g_p = dE/dd_p (SoA) from cbar and the pair rows with derivatives
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
-                               const int* nj, const int* species, const double* rows, long long pitch,
-                               const double* c, const double* q, int q_pitch, const double* pnorm, const double* qbar,
-                               int qbar_pitch, double* cbar, double* gx, double* gy, double* gz, hipStream_t st);
+                               const int* nj, const int* species, const double* rows, const double* cbar, double* gx,
+                               double* gy, double* gz, hipStream_t st);
 
 // angular records (Qbar_lm polynomials) and ilexp series tables for these parameters
 void build_angular_tables(const DevParams& P, DevTables& T);

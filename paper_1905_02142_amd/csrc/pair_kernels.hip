@@ -106,6 +106,7 @@ __device__ inline int isqrt_small(int v) {
 }
 
 constexpr int even(int w) { return w + (w & 1); }
+constexpr int kDenseM = 4096;  // cbar: largest (l_max + 1) n_ch^2 expanded densely in LDS
 // LDS row strides: even (16-byte rows) and not a multiple of 8 doubles, so the
 // four rows read together by the four lane groups fall in different banks
 constexpr int pad_row(int w) {
@@ -186,7 +187,7 @@ template <int NMAX, int LMAX, bool DERIV>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int n_pairs,
                                                      const double* __restrict__ dx, const double* __restrict__ dy,
                                                      const double* __restrict__ dz, double* __restrict__ rows,
-                                                     long long pitch, double* __restrict__ bc) {
+                                                     double* __restrict__ bc) {
   using S = Shape<NMAX, LMAX>;
   __shared__ PairTab<NMAX, LMAX> tab;
   stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, blockDim.x);
@@ -204,20 +205,17 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   if (p >= n_pairs) return;
   const double x = dx[p], y = dy[p], z = dz[p];
   const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-  // field f of pair p at rows[f * pitch + p]: every store of a wavefront is contiguous
-  struct FieldRow {
-    double* base;
-    long long pitch;
-    __device__ double& operator[](int f) const { return base[(size_t)f * pitch]; }
-  } row{rows + p, pitch};
+  // the pair's row (S::ROW doubles) is written as 16-byte pairs of adjacent fields
+  double* __restrict__ row = rows + (size_t)p * S::ROW;
+  auto st2 = [&](int f, double a, double b) { *reinterpret_cast<double2*>(row + f) = double2{a, b}; };
   double B[NMAX], dB[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
   radial<NMAX, DERIV>(P, tab, r, B, dB);
 #pragma unroll
-  for (int k = 0; k < NMAX; ++k) {
-    row[S::FB + k] = B[k];
-    if (DERIV) row[S::FR + S::XD + k] = dB[k];
+  for (int k = 0; k < NMAX; k += 2) {
+    st2(S::FB + k, B[k], B[k + 1]);
+    if (DERIV) st2(S::FR + S::XD + k, dB[k], dB[k + 1]);
   }
   const double sp = P.s0p + P.ap * r;
   const double zz = r * r / (sp * sp);
@@ -228,52 +226,46 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   ilexp<LE>(zz, P.l + (DERIV ? 1 : 0), tab.rec[DERIV ? 2 : 1], tab.rec[DERIV ? 1 : 0], tab.idf, e);
   const double izz = 1.0 / zz;
   const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
+  const double ux = x * ir, uy = y * ir, uz = z * ir;
+  // w_l e_l, l = 0..LMAX, followed by u_z; d(w_l e_l)/dr followed by u_x, u_y, 1/r
+  double we[LMAX + 2], wd[LMAX + 4];
 #pragma unroll
   for (int l = 0; l <= LMAX; ++l) {
-    row[S::FW + l] = tab.lw[l] * e[l];
+    we[l] = tab.lw[l] * e[l];
     // d e_l / dz = e_{l+1} + (l/z - 1) e_l
-    if (DERIV) row[S::FR + S::XW + l] = tab.lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr;
+    if (DERIV) wd[l] = tab.lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr;
   }
-  const double ux = x * ir, uy = y * ir, uz = z * ir;
+  we[LMAX + 1] = uz;
+  wd[LMAX + 1] = ux;
+  wd[LMAX + 2] = uy;
+  wd[LMAX + 3] = ir;
+#pragma unroll
+  for (int l = 0; l < LMAX + 2; l += 2) st2(S::FW + l, we[l], l + 1 < LMAX + 2 ? we[l + 1] : 0.0);
+  if (DERIV) {
+#pragma unroll
+    for (int l = 0; l < LMAX + 4; l += 2) st2(S::FR + S::XW + l, wd[l], l + 1 < LMAX + 4 ? wd[l + 1] : 0.0);
+  }
   double cr = 1.0, ci = 0.0;
 #pragma unroll
   for (int m = 0; m <= LMAX; ++m) {
-    row[S::FZ + 2 * m] = cr;
-    row[S::FZ + 2 * m + 1] = ci;
+    st2(S::FZ + 2 * m, cr, ci);
     const double nr = cr * ux - ci * uy;
     ci = cr * uy + ci * ux;
     cr = nr;
   }
-  row[S::FU] = uz;
-  if (DERIV) {
-    row[S::FR + S::XU] = ux;
-    row[S::FR + S::XU + 1] = uy;
-    row[S::FR + S::XU + 2] = ir;
-  }
 }
 
-// gather fields [0, WIDTH) of the compacted pairs from the field-major rows
-// (field f of pair p at rows[f * pitch + p]) into LDS rows of dst_stride doubles;
-// a wavefront moves 16 pairs x 4 fields per load, and every load of a lane is
-// issued before its stores
-template <int WIDTH>
-__device__ inline void stage_rows(const double* __restrict__ rows, long long pitch, const int* idx, int cnt,
-                                  double* __restrict__ dst, int dst_stride, int lane) {
-  constexpr int NF = (WIDTH + 3) / 4;
-  const int t16 = lane & 15, f4 = lane >> 4;
-  for (int t0 = 0; t0 < cnt; t0 += 16) {
-    const int t = t0 + t16;
-    if (t < cnt) {
-      const double* __restrict__ src = rows + (size_t)f4 * pitch + idx[t];
-      double v[NF];
-#pragma unroll
-      for (int u = 0; u < NF; ++u)
-        if (f4 + 4 * u < WIDTH) v[u] = src[(size_t)(4 * u) * pitch];
-      double* d = dst + t * dst_stride + f4;
-#pragma unroll
-      for (int u = 0; u < NF; ++u)
-        if (f4 + 4 * u < WIDTH) d[4 * u] = v[u];
-    }
+// copy the rows (WIDTH doubles from the start of each pair-major row of ROW
+// doubles) of the compacted pairs into LDS rows of dst_stride doubles, 16 bytes
+// per lane and load
+template <int WIDTH, int ROW>
+__device__ inline void stage_rows(const double* __restrict__ rows, const int* idx, int cnt, double* __restrict__ dst,
+                                  int dst_stride, int lane) {
+  constexpr int UNITS = WIDTH / 2;
+  for (int u = lane; u < cnt * UNITS; u += 64) {
+    const int t = u / UNITS, part = u - t * UNITS;
+    const double2 v = *reinterpret_cast<const double2*>(rows + (size_t)idx[t] * ROW + 2 * part);
+    *reinterpret_cast<double2*>(dst + t * dst_stride + 2 * part) = v;
   }
 }
 
@@ -281,7 +273,7 @@ template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
                                                      const int* __restrict__ offsets, const int* __restrict__ nj,
                                                      const int* __restrict__ species, const double* __restrict__ rows,
-                                                     long long pitch, const double* __restrict__ bc_in,
+                                                     const double* __restrict__ bc_in,
                                                      double* __restrict__ c_out,
                                                      double* __restrict__ q_out, int q_pitch,
                                                      double* __restrict__ pnorm_out) {
@@ -313,7 +305,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams 
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      stage_rows<S::FR>(rows, pitch, idx, cnt, dyn, LFR, lane);
+      stage_rows<S::FR, S::ROW>(rows, idx, cnt, dyn, LFR, lane);
       __syncthreads();
 #pragma unroll 1
       for (int pass = 0; pass < S::NPASS; ++pass) {
@@ -383,29 +375,33 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams 
   }
   __threadfence_block();
   __syncthreads();
-  // power spectrum from c staged in LDS as csh[a * LL + lm], a = s n + k; p in vsh
+  // power spectrum from c staged in LDS in its HBM layout [species][lm][k]: lane per
+  // channel pair (a, b), a <= b, all l; p in vsh
+  const int per_atom = P.ns * NMAX * LLP;
   double* csh = dyn;
-  double* vsh = dyn + nch * LL;
-  for (int t = lane; t < nch * LL; t += 64) {
-    const int a = t / LL, lm = t - a * LL, sa = a / n;
-    csh[t] = ci_out[((size_t)sa * LLP + lm) * NMAX + (a - sa * n)];
-  }
+  double* vsh = dyn + per_atom;
+  for (int t = lane; t < per_atom / 2; t += 64)
+    reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci_out)[t];
   __syncthreads();
-  const int L1 = P.l + 1;
+  const int L1 = P.l + 1, nab = nch * (nch + 1) / 2;
   double ss = 0.0;
-  for (int k = lane; k < P.K; k += 64) {
-    const int ab = k / L1, l = k - ab * L1;
+  for (int ab = lane; ab < nab; ab += 64) {
     int a, b;
     ab_decode(ab, nch, a, b);
-    const double* ca = csh + a * LL + l * l;
-    const double* cb = csh + b * LL + l * l;
-    double v = 0.0;
-    for (int m = 0; m < 2 * l + 1; ++m) v = fma(ca[m], cb[m], v);
-    if (a != b) v *= kSqrt2;
-    vsh[k] = v;
-    ss = fma(v, v, ss);
+    const int sa = a / n, sb = b / n;
+    const double* ca = csh + sa * LLP * NMAX + (a - sa * n);
+    const double* cb = csh + sb * LLP * NMAX + (b - sb * n);
+    const double scale = a != b ? kSqrt2 : 1.0;
+    for (int l = 0; l < L1; ++l) {
+      double v = 0.0;
+      for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) v = fma(ca[lm * NMAX], cb[lm * NMAX], v);
+      v *= scale;
+      vsh[ab * L1 + l] = v;
+      ss = fma(v, v, ss);
+    }
   }
   ss = wave_sum(ss);
+  __syncthreads();
   const double nrm = sqrt(ss);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   double* __restrict__ qi = q_out + (size_t)i * q_pitch;
@@ -441,13 +437,31 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int k = lane; k < K; k += 64) vb[k] = (qb[k] - qi[k] * dot) * inv;
   __syncthreads();
-  // lane per column (s, lm): cbar_{(s,k), lm} = sum_{(sb,kb)} M_{(s,k),(sb,kb)}(l) c_{(sb,kb), lm}
+  // cbar_{(s,k), lm} = sum_{(sb,kb)} M_{(s,k),(sb,kb)}(l) c_{(sb,kb), lm}; with few channels
+  // the matrices M(l) are expanded densely in LDS first, so the products read rows
+  // of M without index arithmetic
+  const bool dense = L1 * nch * nch <= kDenseM;
+  double* Ml = vb + K;  // [l][a][b]
+  if (dense) {
+    for (int r = lane; r < nch * nch; r += 64) {  // one division per (a, b), all l
+      const int a = r / nch, b = r - a * nch;
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      const double w = a == b ? 2.0 : kSqrt2;
+      const double* src = vb + ab_index(lo, hi, nch) * L1;
+      for (int l = 0; l < L1; ++l) Ml[l * nch * nch + r] = w * src[l];
+    }
+    __syncthreads();
+  }
+  // task = (column (s, lm), half of the NMAX channels)
+  constexpr int KH = NMAX / 2;
   double* co = cbar + (size_t)i * per_atom;
-  for (int col = lane; col < ns * LLP; col += 64) {
-    const int s = col / LLP, lm = col - s * LLP;
-    double acc[NMAX];
+  const double inv_llp = 1.0 / (double)LLP;
+  for (int task = lane; task < 2 * ns * LLP; task += 64) {
+    const int col = task >> 1, h = task & 1;
+    const int s = (int)(((double)col + 0.5) * inv_llp), lm = col - s * LLP;  // exact for these sizes
+    double acc[KH];
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+    for (int kk = 0; kk < KH; ++kk) acc[kk] = 0.0;
     if (lm < LL) {
       const int l = isqrt_small(lm);
       for (int sb = 0; sb < ns; ++sb) {
@@ -455,23 +469,31 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
 #pragma unroll
         for (int kb = 0; kb < NMAX; ++kb) cv[kb] = kb < n ? csh[(sb * LLP + lm) * NMAX + kb] : 0.0;
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-          const int a = s * n + k;
+        for (int kk = 0; kk < KH; ++kk) {
+          const int k = h * KH + kk, a = s * n + k;
+          if (k < n) {
+            if (dense) {
+              const double* mrow = Ml + (l * nch + a) * nch + sb * n;
 #pragma unroll
-          for (int kb = 0; kb < NMAX; ++kb) {
-            const int b = sb * n + kb;
-            if (k < n && kb < n) {
-              const int lo = a < b ? a : b, hi = a < b ? b : a;
-              const double w = (a == b) ? 2.0 : kSqrt2;
-              acc[k] = fma(w * vb[ab_index(lo, hi, nch) * L1 + l], cv[kb], acc[k]);
+              for (int kb = 0; kb < NMAX; ++kb)
+                if (kb < n) acc[kk] = fma(mrow[kb], cv[kb], acc[kk]);
+            } else {
+#pragma unroll
+              for (int kb = 0; kb < NMAX; ++kb) {
+                const int b = sb * n + kb;
+                if (kb < n) {
+                  const int lo = a < b ? a : b, hi = a < b ? b : a;
+                  acc[kk] = fma((a == b ? 2.0 : kSqrt2) * vb[ab_index(lo, hi, nch) * L1 + l], cv[kb], acc[kk]);
+                }
+              }
             }
           }
         }
       }
     }
-    double* dst = co + (size_t)col * NMAX;
+    double* dst = co + (size_t)col * NMAX + h * KH;
 #pragma unroll
-    for (int k = 0; k < NMAX; k += 2) reinterpret_cast<double2*>(dst)[k / 2] = double2{acc[k], acc[k + 1]};
+    for (int kk = 0; kk < KH; ++kk) dst[kk] = acc[kk];
   }
 }
 
@@ -479,7 +501,7 @@ template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
                                                        const int* __restrict__ offsets, const int* __restrict__ nj,
                                                        const int* __restrict__ species,
-                                                       const double* __restrict__ rows, long long pitch,
+                                                       const double* __restrict__ rows,
                                                        const double* __restrict__ cbar, double* __restrict__ gx,
                                                        double* __restrict__ gy, double* __restrict__ gz) {
   using S = Shape<NMAX, LMAX>;
@@ -513,7 +535,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParam
       const int cnt = __popcll(mask);
       __syncthreads();
       if (cnt == 0) continue;
-      stage_rows<S::ROW>(rows, pitch, idx, cnt, dyn, LAR, lane);
+      stage_rows<S::ROW, S::ROW>(rows, idx, cnt, dyn, LAR, lane);
       __syncthreads();
 #pragma unroll 1
       for (int pass = 0; pass < S::NPASS; ++pass) {
@@ -677,7 +699,7 @@ size_t dispatch_size(int n, int l, F&& f) {
 size_t fwd_dyn_bytes(const DevParams& P) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
     using S = Shape<N, LM>;
-    const size_t rows = (size_t)S::CH * S::LFR, epi = (size_t)P.nch * P.LL + P.K;
+    const size_t rows = (size_t)S::CH * S::LFR, epi = (size_t)P.ns * N * (P.LL + 1) + P.K;
     return sizeof(double) * (rows > epi ? rows : epi);
   });
 }
@@ -693,7 +715,10 @@ size_t rec_bytes(const DevParams& P) {
     return sizeof(RecTab<S::E, S::NC>);
   });
 }
-size_t cbar_dyn_bytes(const DevParams& P) { return sizeof(double) * (c_doubles_per_atom(P) + P.K); }
+size_t cbar_dyn_bytes(const DevParams& P) {
+  const size_t m = (size_t)(P.l + 1) * P.nch * P.nch;
+  return sizeof(double) * (c_doubles_per_atom(P) + P.K + (m <= (size_t)kDenseM ? m : 0));
+}
 
 }  // namespace
 
@@ -713,48 +738,54 @@ size_t adjoint_lds_bytes(const DevParams& P) {
 }
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
-                            const double* dy, const double* dz, double* rows, long long pitch, bool deriv, double* bc,
-                            int block, hipStream_t st) {
+                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, int block,
+                            hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
   const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
   auto f = [&]<int N, int LM>() {
     if (deriv)
       hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx, dy, dz,
-                         rows, pitch, bc);
+                         rows, bc);
     else
       hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx, dy, dz,
-                         rows, pitch, bc);
+                         rows, bc);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
-                             const int* species, const double* rows, long long pitch, const double* bc, double* c,
-                             double* q, int q_pitch, double* pnorm, hipStream_t st) {
+                             const int* species, const double* rows, const double* bc, double* c, double* q,
+                             int q_pitch, double* pnorm, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
     hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
-                       rows, pitch, bc, c, q, q_pitch, pnorm);
+                       rows, bc, c, q, q_pitch, pnorm);
+    return hipGetLastError();
+  };
+  return dispatch(P.n, P.l, f);
+}
+
+hipError_t launch_cbar(const DevParams& P, int n_atoms, const double* c, const double* q, int q_pitch,
+                       const double* pnorm, const double* qbar, int qbar_pitch, double* cbar, hipStream_t st) {
+  if (n_atoms == 0) return hipSuccess;
+  auto f = [&]<int N, int LM>() {
+    hipLaunchKernelGGL((k_cbar<N>), dim3(n_atoms), dim3(64), cbar_dyn_bytes(P), st, P, n_atoms, c, q, q_pitch, pnorm,
+                       qbar, qbar_pitch, cbar);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
-                               const int* nj, const int* species, const double* rows, long long pitch,
-                               const double* c, const double* q, int q_pitch, const double* pnorm, const double* qbar,
-                               int qbar_pitch, double* cbar, double* gx, double* gy, double* gz, hipStream_t st) {
+                               const int* nj, const int* species, const double* rows, const double* cbar, double* gx,
+                               double* gy, double* gz, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_cbar<N>), dim3(n_atoms), dim3(64), cbar_dyn_bytes(P), st, P, n_atoms, c, q, q_pitch, pnorm,
-                       qbar, qbar_pitch, cbar);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
-                       rows, pitch, cbar, gx, gy, gz);
+                       rows, cbar, gx, gy, gz);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
