@@ -38,7 +38,7 @@ struct soap_ctx {
   int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
-  soap_tuning tune{0, 0, 256};
+  soap_tuning tune{0, 0, 256, 0};
   Buf tune_out;  // scratch outputs of the autotuner
   size_t pinned_bytes = 0;
   // neighbour build
@@ -193,7 +193,7 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
     SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, deriv,
-                                         (double*)ctx->bc.p, ctx->tune.prep_block, st));
+                                         (double*)ctx->bc.p, ctx->tune.prep_block, ctx->tune.prep_staged != 0, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
@@ -563,7 +563,8 @@ soap_status soap_get_tuning(const soap_ctx* ctx, soap_tuning* out) {
 soap_status soap_set_tuning(soap_ctx* ctx, const soap_tuning* t) {
   if (!ctx || !t) return SOAP_EINVAL;
   if ((t->gap_fused != 0 && t->gap_fused != 1) || t->gap_slices < 0 || t->gap_slices > (1 << 20) ||
-      (t->prep_block != 64 && t->prep_block != 128 && t->prep_block != 256))
+      (t->prep_block != 64 && t->prep_block != 128 && t->prep_block != 256) ||
+      (t->prep_staged != 0 && t->prep_staged != 1))
     return fail(ctx, SOAP_EINVAL, "tuning field out of range");
   ctx->tune = *t;
   return SOAP_OK;
@@ -605,6 +606,7 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
     std::vector<int> cand;
   };
   const std::vector<Axis> axes = {
+      {&soap_tuning::prep_staged, {0, 1}},
       {&soap_tuning::prep_block, {64, 128, 256}},
       {&soap_tuning::gap_fused, fusable ? std::vector<int>{0, 1} : std::vector<int>{0}},
       {&soap_tuning::gap_slices, fusable ? std::vector<int>{256, 512, 1024, 2048} : std::vector<int>{}},

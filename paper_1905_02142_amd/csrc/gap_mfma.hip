@@ -61,6 +61,15 @@ struct PBF16X3 {
   static constexpr bool kSplit = true;
   static constexpr bool kRowsInterleaved = false;
 };
+// the Qbar pass (N x K output, K ~ 300) in 64 x 64 tiles, so that it fills the chip
+template <typename P>
+struct QbarTile : P {
+  static constexpr int BM = 64, BN = 64;
+};
+template <>
+struct QbarTile<PF64> : PF64 {};
+template <>
+struct QbarTile<PF32> : PF32 {};
 
 constexpr int kPad = 64;  // contraction dims are padded to a multiple of this (>= every KT)
 
@@ -826,8 +835,9 @@ hipError_t qbar_impl(int N, int M, int K, double* Qbar, const void* work, hipStr
   const int Kp = padded(K), Mp = padded(M);
   const T *qst = (const T*)(w + L.qst), *qst_lo = (const T*)(w + L.qst_lo);
   const T *G = (const T*)(w + L.g), *G_lo = (const T*)(w + L.g_lo);
-  const int nit = (N + P::BM - 1) / P::BM, nct = (Kp + P::BN - 1) / P::BN;
-  hipLaunchKernelGGL(k_qbar<P>, dim3(nct, nit), dim3(256), 0, st, N, K, Mp, Kp, G, G_lo, qst, qst_lo, Qbar);
+  using Q = QbarTile<P>;
+  const int nit = (N + Q::BM - 1) / Q::BM, nct = (Kp + Q::BN - 1) / Q::BN;
+  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit), dim3(256), 0, st, N, K, Mp, Kp, G, G_lo, qst, qst_lo, Qbar);
   return hipGetLastError();
 }
 

@@ -18,10 +18,11 @@ size_t pair_row_doubles(const DevParams& P);
 
 // pair rows (pair_row_doubles each, pair-major) for n_pairs neighbours, the
 // derivative part only if deriv, and the central-atom radial factors bc
-// (n_max doubles); block: threads per block (64, 128 or 256)
+// (n_max doubles); block: threads per block (64, 128 or 256); staged: rows
+// collected in LDS and written out in whole-row pieces
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
                             const double* dy, const double* dz, double* rows, bool deriv, double* bc, int block,
-                            hipStream_t st);
+                            bool staged, hipStream_t st);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,

@@ -183,13 +183,25 @@ __device__ inline void load_records(const RecTab<E, NC>& t, int j, int e0, int L
   }
 }
 
-template <int NMAX, int LMAX, bool DERIV>
+// STAGED: the block first collects its rows in LDS (stride PRS, odd, so the
+// per-thread writes do not collide) and then writes them out as 16-byte pieces
+// of consecutive rows, so each store covers a few whole rows instead of 64
+// scattered pieces.
+template <int NMAX, int LMAX>
+constexpr int prep_stride() {
+  using S = Shape<NMAX, LMAX>;
+  return (S::FR > S::XR ? S::FR : S::XR) | 1;
+}
+
+template <int NMAX, int LMAX, bool DERIV, bool STAGED>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int n_pairs,
                                                      const double* __restrict__ dx, const double* __restrict__ dy,
                                                      const double* __restrict__ dz, double* __restrict__ rows,
                                                      double* __restrict__ bc) {
   using S = Shape<NMAX, LMAX>;
+  constexpr int PRS = prep_stride<NMAX, LMAX>();
   __shared__ PairTab<NMAX, LMAX> tab;
+  extern __shared__ double prow[];  // STAGED: blockDim.x rows of PRS doubles
   stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, blockDim.x);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -202,21 +214,14 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
     for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * tab.lw[0] * 0.28209479177387814;
   }
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  const double x = dx[p], y = dy[p], z = dz[p];
+  if (!STAGED && p >= n_pairs) return;
+  const bool live = p < n_pairs;
+  const double x = live ? dx[p] : 1.0, y = live ? dy[p] : 0.0, z = live ? dz[p] : 0.0;
   const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-  // the pair's row (S::ROW doubles) is written as 16-byte pairs of adjacent fields
-  double* __restrict__ row = rows + (size_t)p * S::ROW;
-  auto st2 = [&](int f, double a, double b) { *reinterpret_cast<double2*>(row + f) = double2{a, b}; };
   double B[NMAX], dB[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
   radial<NMAX, DERIV>(P, tab, r, B, dB);
-#pragma unroll
-  for (int k = 0; k < NMAX; k += 2) {
-    st2(S::FB + k, B[k], B[k + 1]);
-    if (DERIV) st2(S::FR + S::XD + k, dB[k], dB[k + 1]);
-  }
   const double sp = P.s0p + P.ap * r;
   const double zz = r * r / (sp * sp);
   constexpr int LE = DERIV ? LMAX + 1 : LMAX;
@@ -239,19 +244,69 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   wd[LMAX + 1] = ux;
   wd[LMAX + 2] = uy;
   wd[LMAX + 3] = ir;
+  if constexpr (!STAGED) {
+    // the pair's row written directly as 16-byte pairs of adjacent fields
+    double* __restrict__ row = rows + (size_t)p * S::ROW;
+    auto st2 = [&](int f, double a, double b) { *reinterpret_cast<double2*>(row + f) = double2{a, b}; };
 #pragma unroll
-  for (int l = 0; l < LMAX + 2; l += 2) st2(S::FW + l, we[l], l + 1 < LMAX + 2 ? we[l + 1] : 0.0);
-  if (DERIV) {
+    for (int k = 0; k < NMAX; k += 2) {
+      st2(S::FB + k, B[k], B[k + 1]);
+      if (DERIV) st2(S::FR + S::XD + k, dB[k], dB[k + 1]);
+    }
 #pragma unroll
-    for (int l = 0; l < LMAX + 4; l += 2) st2(S::FR + S::XW + l, wd[l], l + 1 < LMAX + 4 ? wd[l + 1] : 0.0);
-  }
-  double cr = 1.0, ci = 0.0;
+    for (int l = 0; l < LMAX + 2; l += 2) st2(S::FW + l, we[l], we[l + 1]);
+    if (DERIV) {
 #pragma unroll
-  for (int m = 0; m <= LMAX; ++m) {
-    st2(S::FZ + 2 * m, cr, ci);
-    const double nr = cr * ux - ci * uy;
-    ci = cr * uy + ci * ux;
-    cr = nr;
+      for (int l = 0; l < LMAX + 4; l += 2) st2(S::FR + S::XW + l, wd[l], wd[l + 1]);
+    }
+    double cr = 1.0, ci = 0.0;
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) {
+      st2(S::FZ + 2 * m, cr, ci);
+      const double nr = cr * ux - ci * uy;
+      ci = cr * uy + ci * ux;
+      cr = nr;
+    }
+  } else {
+    const int tid = threadIdx.x, nb = blockDim.x;
+    const long long p0 = (long long)blockIdx.x * nb;
+    const int nvalid = (int)min((long long)nb, (long long)n_pairs - p0);
+    double* my = prow + tid * PRS;
+    // forward part
+    double cr = 1.0, ci = 0.0;
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) {
+      my[S::FZ + 2 * m] = cr;
+      my[S::FZ + 2 * m + 1] = ci;
+      const double nr = cr * ux - ci * uy;
+      ci = cr * uy + ci * ux;
+      cr = nr;
+    }
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) my[S::FB + k] = B[k];
+#pragma unroll
+    for (int l = 0; l < LMAX + 2; ++l) my[S::FW + l] = we[l];
+    __syncthreads();
+    constexpr int UF = S::FR / 2;
+    for (int u = tid; u < nvalid * UF; u += nb) {
+      const int t = u / UF, part = u - t * UF;
+      const double* src = prow + t * PRS + 2 * part;
+      *reinterpret_cast<double2*>(rows + (size_t)(p0 + t) * S::ROW + 2 * part) = double2{src[0], src[1]};
+    }
+    if (DERIV) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) my[S::XD + k] = dB[k];
+#pragma unroll
+      for (int l = 0; l < LMAX + 4; ++l) my[S::XW + l] = wd[l];
+      __syncthreads();
+      constexpr int UX = S::XR / 2;
+      for (int u = tid; u < nvalid * UX; u += nb) {
+        const int t = u / UX, part = u - t * UX;
+        const double* src = prow + t * PRS + 2 * part;
+        *reinterpret_cast<double2*>(rows + (size_t)(p0 + t) * S::ROW + S::FR + 2 * part) = double2{src[0], src[1]};
+      }
+    }
   }
 }
 
@@ -423,11 +478,8 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
   const int lane = threadIdx.x;
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const int per_atom = ns * NMAX * LLP;
-  double* csh = dyn;  // c of atom i in its HBM layout [species][lm][k]
-  double* vb = dyn + per_atom;
-  const double* ci = c + (size_t)i * per_atom;
-  for (int t = lane; t < per_atom / 2; t += 64)
-    reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci)[t];
+  double* vb = dyn;
+  const double* __restrict__ csh = c + (size_t)i * per_atom;  // c of atom i, [species][lm][k], read in place
   const double* qi = q + (size_t)i * q_pitch;
   const double* qb = qbar + (size_t)i * qbar_pitch;
   double dot = 0.0;
@@ -717,7 +769,7 @@ size_t rec_bytes(const DevParams& P) {
 }
 size_t cbar_dyn_bytes(const DevParams& P) {
   const size_t m = (size_t)(P.l + 1) * P.nch * P.nch;
-  return sizeof(double) * (c_doubles_per_atom(P) + P.K + (m <= (size_t)kDenseM ? m : 0));
+  return sizeof(double) * (P.K + (m <= (size_t)kDenseM ? m : 0));
 }
 
 }  // namespace
@@ -739,16 +791,24 @@ size_t adjoint_lds_bytes(const DevParams& P) {
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
                             const double* dy, const double* dz, double* rows, bool deriv, double* bc, int block,
-                            hipStream_t st) {
+                            bool staged, hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
+  if (staged && block > 128) block = 128;  // the staging buffer stays under 64 KB
   const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
   auto f = [&]<int N, int LM>() {
-    if (deriv)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx, dy, dz,
-                         rows, bc);
+    const size_t lds = staged ? sizeof(double) * (size_t)block * prep_stride<N, LM>() : 0;
+    if (deriv && staged)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true>), dim3(blocks), dim3(block), lds, st, P, T, (int)n_pairs, dx,
+                         dy, dz, rows, bc);
+    else if (deriv)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx,
+                         dy, dz, rows, bc);
+    else if (staged)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true>), dim3(blocks), dim3(block), lds, st, P, T, (int)n_pairs,
+                         dx, dy, dz, rows, bc);
     else
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx, dy, dz,
-                         rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs,
+                         dx, dy, dz, rows, bc);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
