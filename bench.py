@@ -94,6 +94,9 @@ def main():
                          "alongside any other mode and the force error against it reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--sync-neighbors", action="store_true",
+                    help="read the pair count back to the host in every step (soap_build_neighbors) instead of "
+                         "leaving it on the device (soap_build_neighbors_async, checked after the timed region)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, run a plain 512 MiB device-to-device copy three times "
                          "(the reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -108,6 +111,7 @@ def main():
     import torch
 
     from paper_1905_02142_amd import _lib
+    from paper_1905_02142_amd.soap import NeighbourList
 
     dev = torch.device("cuda:0")
 
@@ -116,13 +120,21 @@ def main():
         soap, w, s = st["soap"], st["w"], st["s"]
         N = s.n_atoms
         nl = soap.neighbors(st["pos"], s.cell, s.pbc)
+        n_pairs = nl.n_pairs
+        if not args.sync_neighbors:
+            # a list with a 25 % reserve over the current count, as a dynamics run would keep
+            nl = NeighbourList(N, n_pairs + n_pairs // 4 + 256, dev)
+            soap.neighbors(st["pos"], s.cell, s.pbc, nl=nl)
         M = w["M"]
         e = torch.empty(N, dtype=torch.float64, device=dev)
         F = torch.empty(N, 3, dtype=torch.float64, device=dev)
         ab = torch.empty(M, dtype=torch.float64, device=dev)
 
         def step():
-            soap.neighbors(st["pos"], s.cell, s.pbc, nl=nl)
+            if args.sync_neighbors:
+                soap.neighbors(st["pos"], s.cell, s.pbc, nl=nl)
+            else:
+                soap.neighbors_async(st["pos"], s.cell, s.pbc, nl)
             soap.energy_forces(nl, st["spec"], st["qs"], st["al"], w["zeta"], out=(e, F, ab))
 
         tuning = soap.tuning if args.no_autotune else soap.autotune(nl, st["spec"], st["qs"], st["al"], w["zeta"])
@@ -148,6 +160,8 @@ def main():
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if not args.sync_neighbors:  # the last build's count and error bits (raises on overflow or bad input)
+            assert soap.check_neighbors(nl) == n_pairs
         _lib.soap_profile(soap.ctx, False)
         timed = _lib.soap_profile_read(soap.ctx)[dominant]
         res = dict(st=st, soap=soap, w=w, s=s, N=N, nl=nl, M=M, stages=stages, tuning=tuning, dominant=dominant,
@@ -230,7 +244,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "n_pairs": P, "r_cut": w["r_cut"], "n_max": n,
                    "l_max": w["l_max"], "n_species": w["n_species"], "M": M, "zeta": w["zeta"], "K": K,
-                   "precision": args.precision, "tuning": main_run["tuning"]},
+                   "precision": args.precision, "tuning": main_run["tuning"],
+                   "neighbour_build": "sync" if args.sync_neighbors else "async, count checked after the timed steps"},
         "roofline": roofline,
         "fp64_path": fp64_path,
         "stages": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}

@@ -83,7 +83,9 @@ typedef struct {
 typedef struct soap_ctx soap_ctx;
 
 /* Neighbour list in CSR form, all arrays caller-allocated DEVICE memory.
- * Centre atom i owns pairs offsets[i] .. offsets[i+1]-1, sorted by (j, image).
+ * Centre atom i owns pairs offsets[i] .. offsets[i+1]-1 in a fixed order
+ * (neighbouring cell-list bins in a fixed sequence, atoms by index inside a
+ * bin), the same on every build of the same input.
  * For pair p: j[p] neighbour atom, (dx,dy,dz)[p] = r_j + T - r_i, img[p] the
  * lattice image T packed as ((Tx+512) << 20 | (Ty+512) << 10 | (Tz+512)),
  * rev[p] the index of the reverse pair (j -> i, -T), center[p] = i.
@@ -91,7 +93,8 @@ typedef struct soap_ctx soap_ctx;
 typedef struct {
   int n_atoms;
   int n_structures;
-  long long n_pairs;     /* written by soap_build_neighbors */
+  long long n_pairs;     /* written by soap_build_neighbors; SOAP_PAIRS_DEFERRED after
+                            soap_build_neighbors_async (the count is offsets[n_atoms]) */
   long long capacity;    /* set by the caller */
   int32_t* offsets;
   int32_t* j;
@@ -102,6 +105,13 @@ typedef struct {
   double* dy;
   double* dz;
 } soap_nlist;
+
+/* n_pairs of a list whose pair count is still on the device only.  The entry
+ * points accept such a list: they size their work by `capacity` and every
+ * kernel reads min(offsets[n_atoms], capacity) pairs and cuts each atom's range
+ * at the capacity, so they never touch memory beyond it, even when the build
+ * overflowed (the results are then meaningless; soap_neighbors_check says so). */
+#define SOAP_PAIRS_DEFERRED (-1LL)
 
 /* Validate `p` and build the basis tables.  Returns SOAP_EINVAL for n_max
  * outside 2..12, l_max outside 0..12, n_species < 1, non-positive r_cut or
@@ -126,14 +136,40 @@ const char* soap_last_error(const soap_ctx* ctx);
  *   struct_offsets n_structures + 1 atom offsets (host); NULL means one structure
  *   nl             in: capacity and arrays; out: n_pairs and the arrays
  *   required_pairs (host, nullable) receives the pair count
- * Reads the pair count back to the host (one stream synchronisation).  If it
- * exceeds nl->capacity, returns SOAP_EOVERFLOW, sets *required_pairs and
- * nl->n_pairs, and leaves the per-pair arrays undefined.  Coincident atoms
- * (distance < 1e-8) or non-finite positions return SOAP_EINVAL.
+ * Reads the pair count back to the host (one stream synchronisation, after the
+ * whole build is enqueued).  If it exceeds nl->capacity, returns
+ * SOAP_EOVERFLOW, sets *required_pairs to the count and nl->n_pairs to 0, and
+ * leaves the per-pair arrays undefined.  Coincident atoms (distance < 1e-8) or
+ * non-finite positions return SOAP_EINVAL.
  */
 soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
                                  const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
                                  soap_nlist* nl, long long* required_pairs, hipStream_t stream);
+
+/*
+ * The same build with no host synchronisation, for steps that must not stall
+ * the host (and for stream capture into a HIP graph): every kernel is enqueued
+ * on `stream`; the pair count stays on the device at offsets[n_atoms], and
+ * nl->n_pairs is set to SOAP_PAIRS_DEFERRED.  Pairs are written only below
+ * nl->capacity, so an undersized list is safe but holds an incomplete result.
+ * Host-side argument errors are returned at once; device-side findings
+ * (overflow, non-finite or coincident positions) are reported by
+ * soap_neighbors_check.  Under stream capture the structure geometry must equal
+ * that of the previous build on this context (its upload is not captured), and
+ * the workspace must already be large enough (an earlier call outside capture).
+ */
+soap_status soap_build_neighbors_async(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                       const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                       soap_nlist* nl, hipStream_t stream);
+
+/*
+ * Waits for `stream` and reports the most recent build on this context into
+ * `nl`: *n_pairs (host, nullable) receives the pair count; returns SOAP_OK,
+ * SOAP_EOVERFLOW if the count exceeds nl->capacity, or SOAP_EINVAL for
+ * non-finite or coincident positions (the same checks as soap_build_neighbors).
+ * nl is not modified.
+ */
+soap_status soap_neighbors_check(soap_ctx* ctx, const soap_nlist* nl, long long* n_pairs, hipStream_t stream);
 
 /*
  * Descriptors q (n_atoms x K, FP64) of every atom of `nl`, and |p| (n_atoms,

@@ -14,6 +14,7 @@ LIB_PATH = os.environ.get("SOAP_LIBRARY", LIB_PATH)
 
 SOAP_OK, SOAP_EINVAL, SOAP_ENOMEM, SOAP_EOVERFLOW, SOAP_EHIP, SOAP_ENOTSUP = 0, -1, -2, -3, -4, -5
 SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3 = 0, 1, 2, 3
+SOAP_PAIRS_DEFERRED = -1
 
 # every function include/soap.h declares
 EXPORTED = (
@@ -21,6 +22,7 @@ EXPORTED = (
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
     "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
+    "soap_build_neighbors_async", "soap_neighbors_check",
 )
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
           "pair_prep", "cbar")
@@ -89,6 +91,10 @@ def load(path: str = LIB_PATH):
     lib.soap_workspace_bytes.restype = ll
     lib.soap_build_neighbors.argtypes = [vp, i, vp, vp, vp, vp, i, P(soap_nlist), P(ll), vp]
     lib.soap_build_neighbors.restype = i
+    lib.soap_build_neighbors_async.argtypes = [vp, i, vp, vp, vp, vp, i, P(soap_nlist), vp]
+    lib.soap_build_neighbors_async.restype = i
+    lib.soap_neighbors_check.argtypes = [vp, P(soap_nlist), P(ll), vp]
+    lib.soap_neighbors_check.restype = i
     lib.soap_descriptor.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
     lib.soap_descriptor.restype = i
     lib.soap_descriptor_grad.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
@@ -158,6 +164,22 @@ def soap_build_neighbors(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_struct
         return st
     check(st, ctx)
     return st
+
+
+def soap_build_neighbors_async(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl: soap_nlist,
+                               stream) -> None:
+    """Enqueues the build; nl.n_pairs becomes SOAP_PAIRS_DEFERRED."""
+    check(load().soap_build_neighbors_async(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures,
+                                            ctypes.byref(nl), stream), ctx)
+
+
+def soap_neighbors_check(ctx, nl: soap_nlist, stream) -> tuple[int, int]:
+    """(status, pair count) of the last build: SOAP_OK or SOAP_EOVERFLOW; other failures raise."""
+    n = ctypes.c_longlong(0)
+    st = load().soap_neighbors_check(ctx, ctypes.byref(nl), ctypes.byref(n), stream)
+    if st != SOAP_EOVERFLOW:
+        check(st, ctx)
+    return st, n.value
 
 
 def soap_descriptor(ctx, nl: soap_nlist, species, q, p_norm, stream) -> None:

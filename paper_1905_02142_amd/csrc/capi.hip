@@ -35,7 +35,10 @@ struct soap_ctx {
   int device = 0;
   std::string err;
   long long ws_bytes = 0;
-  int* pinned = nullptr;  // host-pinned words for small read-backs / uploads
+  int* pinned = nullptr;  // host-pinned staging for structure-geometry uploads
+  hipEvent_t pinned_ev = nullptr;  // completes when the last upload from the staging has been read
+  int* report = nullptr;  // host-pinned pair count and error bits, written by a kernel
+  int* report_dev = nullptr;  // the same memory as the device addresses it
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
   soap_tuning tune{0, 0, 256, 0};
@@ -95,6 +98,7 @@ bool ensure(soap_ctx* ctx, Buf& b, size_t bytes) {
 
 bool ensure_pinned(soap_ctx* ctx, size_t bytes) {
   if (ctx->pinned_bytes >= bytes) return true;
+  if (ctx->pinned_ev && hipEventSynchronize(ctx->pinned_ev) != hipSuccess) return false;
   if (ctx->pinned) hipHostFree(ctx->pinned);
   ctx->pinned = nullptr;
   ctx->pinned_bytes = 0;
@@ -125,13 +129,22 @@ soap_status check_params(const soap_params* p, std::string& why) {
   return SOAP_OK;
 }
 
+// Pairs the kernels may touch: the count, or the capacity while the count is
+// still on the device (then every kernel cuts its pair ranges there).
+long long pair_bound(const soap_nlist* nl) { return nl->n_pairs >= 0 ? nl->n_pairs : nl->capacity; }
+const int* pair_count(const soap_nlist* nl) {
+  return nl->n_pairs == SOAP_PAIRS_DEFERRED ? nl->offsets + nl->n_atoms : nullptr;
+}
+
 soap_status check_nlist(soap_ctx* ctx, const soap_nlist* nl) {
   if (!nl) return fail(ctx, SOAP_EINVAL, "null neighbour list");
-  if (nl->n_atoms < 0 || nl->n_pairs < 0) return fail(ctx, SOAP_EINVAL, "negative sizes in neighbour list");
+  if (nl->n_atoms < 0 || nl->capacity < 0 || (nl->n_pairs < 0 && nl->n_pairs != SOAP_PAIRS_DEFERRED))
+    return fail(ctx, SOAP_EINVAL, "negative sizes in neighbour list");
   if (nl->n_pairs > nl->capacity) return fail(ctx, SOAP_EINVAL, "neighbour list holds more pairs than its capacity");
-  if (nl->n_pairs > 2147483647LL) return fail(ctx, SOAP_ENOTSUP, "more than 2^31-1 pairs");
-  if (nl->n_atoms > 0 && !nl->offsets) return fail(ctx, SOAP_EINVAL, "null offsets");
-  if (nl->n_pairs > 0 && (!nl->j || !nl->dx || !nl->dy || !nl->dz || !nl->rev))
+  if (pair_bound(nl) > 2147483647LL) return fail(ctx, SOAP_ENOTSUP, "more than 2^31-1 pairs");
+  if (!nl->offsets && (nl->n_atoms > 0 || nl->n_pairs == SOAP_PAIRS_DEFERRED))
+    return fail(ctx, SOAP_EINVAL, "null offsets");
+  if (pair_bound(nl) > 0 && (!nl->j || !nl->dx || !nl->dy || !nl->dz || !nl->rev))
     return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
   return SOAP_OK;
 }
@@ -186,17 +199,18 @@ struct StageTimer {
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
                     bool deriv, hipStream_t st) {
   const soap::DevParams& P = ctx->dp;
-  const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
   SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (NP > 0 ? NP : 1) * soap::pair_row_doubles(P));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
-    SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, nl->n_pairs, nl->dx, nl->dy, nl->dz, (double*)ctx->rows.p, deriv,
-                                         (double*)ctx->bc.p, ctx->tune.prep_block, ctx->tune.prep_staged != 0, st));
+    SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, (long long)NP, pair_count(nl), nl->dx, nl->dy, nl->dz,
+                                         (double*)ctx->rows.p, deriv, (double*)ctx->bc.p, ctx->tune.prep_block,
+                                         ctx->tune.prep_staged != 0, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
-  SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
+  SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                         (const double*)ctx->rows.p, (const double*)ctx->bc.p, (double*)ctx->c.p, q,
                                         P.K, pnorm, st));
   return SOAP_OK;
@@ -288,19 +302,33 @@ void soap_destroy(soap_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   if (ctx->dt) hipFree(ctx->dt);
+  if (ctx->pinned_ev) {
+    hipEventSynchronize(ctx->pinned_ev);
+    hipEventDestroy(ctx->pinned_ev);
+  }
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  if (ctx->report) hipHostFree(ctx->report);
   delete ctx;
 }
 
-soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
-                                 const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
-                                 soap_nlist* nl, long long* required_pairs, hipStream_t st) {
-  if (!ctx) return SOAP_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Everything of a neighbour build up to the filled list, enqueued on st with no
+// host synchronisation.  The pair count stays on the device (offsets[n_atoms]);
+// the fill and the reverse search write only below the capacity, so a list that
+// overflows is detected afterwards, from the count, without any access beyond it.
+soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells, const int32_t* pbc,
+                          const int32_t* struct_offsets, int n_structures, soap_nlist* nl, hipStream_t st) {
   if (!nl || !cells || !pbc || n_atoms < 0 || n_structures < 1)
     return fail(ctx, SOAP_EINVAL, "null argument or non-positive structure count");
   if (n_atoms > 0 && !pos) return fail(ctx, SOAP_EINVAL, "null positions");
   if (!nl->offsets) return fail(ctx, SOAP_EINVAL, "null offsets array");
   if (nl->capacity < 0) return fail(ctx, SOAP_EINVAL, "negative capacity");
+  if (nl->capacity > 2147483647LL) return fail(ctx, SOAP_ENOTSUP, "capacity above 2^31-1 pairs");
+  if (nl->capacity > 0 && (!nl->j || !nl->img || !nl->rev || !nl->center || !nl->dx || !nl->dy || !nl->dz))
+    return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
   const double rc = ctx->dp.rc;
   // per-structure cell-list geometry
   std::vector<soap::StructMeta> meta(n_structures);
@@ -356,8 +384,12 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
     M.atom1 = so[s + 1];
     n_bins += nb_total;
   }
+  const size_t up = sizeof(soap::StructMeta) * n_structures + sizeof(int) * (n_structures + 1);
+  std::vector<char> img(up);
+  std::memcpy(img.data(), meta.data(), sizeof(soap::StructMeta) * n_structures);
+  std::memcpy(img.data() + sizeof(soap::StructMeta) * n_structures, so.data(), sizeof(int) * (n_structures + 1));
   const size_t meta_cap0 = ctx->meta.cap;
-  SOAP_ENSURE(ctx, ctx->meta, sizeof(soap::StructMeta) * n_structures + sizeof(int) * (n_structures + 1));
+  SOAP_ENSURE(ctx, ctx->meta, up);
   if (ctx->meta.cap != meta_cap0) ctx->meta_dev = nullptr;  // a new allocation holds nothing yet
   SOAP_ENSURE(ctx, ctx->atom_bin, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->atom_wrap, sizeof(int) * n_atoms);
@@ -370,23 +402,25 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
   SOAP_ENSURE(ctx, ctx->scan_part,
               sizeof(int) * (size_t)std::max(soap::scan_partials_needed(n_atoms), soap::scan_partials_needed(n_bins)));
   SOAP_ENSURE(ctx, ctx->errflag, sizeof(int) * 4);
-  const size_t up = sizeof(soap::StructMeta) * n_structures + sizeof(int) * (n_structures + 1);
-  // pinned staging: the previous call synchronised before returning, so it is free to reuse
-  if (!ensure_pinned(ctx, std::max<size_t>(up, 64))) return fail(ctx, SOAP_ENOMEM, "pinned allocation failed");
-  char* stage = (char*)ctx->pinned;
-  std::memcpy(stage, meta.data(), sizeof(soap::StructMeta) * n_structures);
-  std::memcpy(stage + sizeof(soap::StructMeta) * n_structures, so.data(), sizeof(int) * (n_structures + 1));
   // the structure geometry is uploaded only when it differs from what the device holds
-  if (ctx->meta.p != ctx->meta_dev || ctx->meta_host.size() != up ||
-      std::memcmp(ctx->meta_host.data(), stage, up) != 0) {
-    SOAP_HIP(ctx, hipMemcpyAsync(ctx->meta.p, stage, up, hipMemcpyHostToDevice, st));
-    ctx->meta_host.assign(stage, stage + up);
+  if (ctx->meta.p != ctx->meta_dev || ctx->meta_host != img) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(ctx, SOAP_ENOTSUP, "new structure geometry during stream capture (build once outside it first)");
+    if (!ensure_pinned(ctx, std::max<size_t>(up, 64))) return fail(ctx, SOAP_ENOMEM, "pinned allocation failed");
+    // the staging may still be read by the previous upload
+    if (ctx->pinned_ev) SOAP_HIP(ctx, hipEventSynchronize(ctx->pinned_ev));
+    else SOAP_HIP(ctx, hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
+    std::memcpy(ctx->pinned, img.data(), up);
+    SOAP_HIP(ctx, hipMemcpyAsync(ctx->meta.p, ctx->pinned, up, hipMemcpyHostToDevice, st));
+    SOAP_HIP(ctx, hipEventRecord(ctx->pinned_ev, st));
+    ctx->meta_host.swap(img);
     ctx->meta_dev = ctx->meta.p;
   }
   SOAP_HIP(ctx, soap::launch_init_build(n_bins, (int*)ctx->bin_count.p, (int*)ctx->bin_cursor.p,
                                         (int*)ctx->errflag.p, st));
   int* err = (int*)ctx->errflag.p;
-  StageTimer tm_count(ctx, SOAP_STAGE_NEIGHBORS, st);
+  StageTimer tm(ctx, SOAP_STAGE_NEIGHBORS, st);
   const soap::StructMeta* dmeta = (const soap::StructMeta*)ctx->meta.p;
   const int* dso = (const int*)((const char*)ctx->meta.p + sizeof(soap::StructMeta) * n_structures);
   if (n_atoms > 0) {
@@ -405,37 +439,79 @@ soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, 
                                      nullptr, nullptr, nullptr, nullptr, nullptr, err, st));
   }
   SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->counts.p, n_atoms, nl->offsets, (int*)ctx->scan_part.p, st));
-  tm_count.stop();
-  // read back the pair count and the error bits
-  int* hb = ctx->pinned;
-  SOAP_HIP(ctx, hipMemcpyAsync(hb, nl->offsets + n_atoms, sizeof(int), hipMemcpyDeviceToHost, st));
-  SOAP_HIP(ctx, hipMemcpyAsync(hb + 1, err, sizeof(int), hipMemcpyDeviceToHost, st));
-  SOAP_HIP(ctx, hipStreamSynchronize(st));
-  const long long total = hb[0];
-  const int eb = hb[1];
-  nl->n_atoms = n_atoms;
-  nl->n_structures = n_structures;
-  if (eb & soap::kErrNonFinite) return fail(ctx, SOAP_EINVAL, "non-finite atomic position");
-  if (eb & soap::kErrCoincident) return fail(ctx, SOAP_EINVAL, "coincident atoms (distance below 1e-8)");
-  if (eb & soap::kErrFarOutside) return fail(ctx, SOAP_EINVAL, "atom more than 500 cells outside its cell");
-  if (total < 0) return fail(ctx, SOAP_ENOTSUP, "pair count overflows 32-bit offsets");
-  if (required_pairs) *required_pairs = total;
-  nl->n_pairs = total;
-  if (total > nl->capacity) {
-    nl->n_pairs = 0;
-    return fail(ctx, SOAP_EOVERFLOW, "neighbour list capacity too small");
-  }
-  if (total > 0 && (!nl->j || !nl->img || !nl->rev || !nl->center || !nl->dx || !nl->dy || !nl->dz))
-    return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
-  StageTimer tm_fill(ctx, SOAP_STAGE_NEIGHBORS, st);
-  if (n_atoms > 0) {
+  if (n_atoms > 0 && nl->capacity > 0) {
     SOAP_HIP(ctx, soap::launch_pairs(true, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
                                      (const int*)ctx->bin_atoms.p, nullptr, nl->offsets, nl->capacity, nl->j, nl->img,
                                      nl->center, nl->dx, nl->dy, nl->dz, nl->rev, err, st));
-    SOAP_HIP(ctx, soap::launch_reverse(total, nl->offsets, nl->j, nl->img, nl->center, nl->rev, err, st));
+    SOAP_HIP(ctx, soap::launch_reverse(nl->capacity, nl->offsets + n_atoms, nl->offsets, nl->j, nl->img, nl->center,
+                                       nl->rev, err, st));
   }
+  nl->n_atoms = n_atoms;
+  nl->n_structures = n_structures;
+  nl->n_pairs = SOAP_PAIRS_DEFERRED;
   return SOAP_OK;
+}
+
+// Waits for the last build on st and reads its pair count and error bits (one
+// kernel writes both into pinned host memory).  Input errors come first, then
+// capacity overflow (required_pairs holds the count needed), then the
+// reverse-pair consistency check.
+soap_status read_report(soap_ctx* ctx, const soap_nlist* nl, long long* total_out, hipStream_t st) {
+  if (!ctx->report) {
+    if (hipHostMalloc((void**)&ctx->report, 64, hipHostMallocDefault) != hipSuccess) {
+      ctx->report = nullptr;
+      return fail(ctx, SOAP_ENOMEM, "pinned allocation failed");
+    }
+    if (hipHostGetDevicePointer((void**)&ctx->report_dev, ctx->report, 0) != hipSuccess) {
+      hipHostFree(ctx->report);
+      ctx->report = nullptr;
+      return fail(ctx, SOAP_EHIP, "pinned report buffer has no device address");
+    }
+  }
+  if (!ctx->errflag.p) return fail(ctx, SOAP_EINVAL, "no neighbour build on this context");
+  SOAP_HIP(ctx, soap::launch_report(nl->offsets + nl->n_atoms, (const int*)ctx->errflag.p, ctx->report_dev, st));
+  SOAP_HIP(ctx, hipStreamSynchronize(st));
+  const long long total = ((volatile int*)ctx->report)[0];
+  const int eb = ((volatile int*)ctx->report)[1];
+  if (total_out) *total_out = total;
+  if (eb & soap::kErrNonFinite) return fail(ctx, SOAP_EINVAL, "non-finite atomic position");
+  if (eb & soap::kErrCoincident) return fail(ctx, SOAP_EINVAL, "coincident atoms (distance below 1e-8)");
+  if (eb & soap::kErrFarOutside) return fail(ctx, SOAP_EINVAL, "atom more than 500 cells outside its cell");
+  if (total < 0) return fail(ctx, SOAP_ENOTSUP, "pair count overflows 32-bit offsets");
+  if (total > nl->capacity) return fail(ctx, SOAP_EOVERFLOW, "neighbour list capacity too small");
+  if (eb & soap::kErrNoReverse) return fail(ctx, SOAP_EHIP, "a pair without its reverse (internal error)");
+  return SOAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+soap_status soap_build_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                 const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                 soap_nlist* nl, long long* required_pairs, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = enqueue_build(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl, st);
+  if (s != SOAP_OK) return s;
+  long long total = 0;
+  s = read_report(ctx, nl, &total, st);
+  if (required_pairs) *required_pairs = total;
+  nl->n_pairs = s == SOAP_OK ? total : 0;
+  return s;
+}
+
+soap_status soap_build_neighbors_async(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                       const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                       soap_nlist* nl, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  return enqueue_build(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl, st);
+}
+
+soap_status soap_neighbors_check(soap_ctx* ctx, const soap_nlist* nl, long long* n_pairs, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  if (!nl || !nl->offsets || nl->n_atoms < 0) return fail(ctx, SOAP_EINVAL, "null or empty neighbour list");
+  return read_report(ctx, nl, n_pairs, st);
 }
 
 soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* p_norm,
@@ -462,7 +538,7 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   if (nl->n_atoms == 0) return SOAP_OK;
   if (!species || !q_bar || !pos_grad) return fail(ctx, SOAP_EINVAL, "null species, q_bar or pos_grad");
   const soap::DevParams& P = ctx->dp;
-  const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
   SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
   SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
@@ -477,12 +553,12 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
                                       (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->cbar.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
-    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
+    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                             (const double*)ctx->rows.p, (const double*)ctx->cbar.p,
                                             (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
-  SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
+  SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
                                           (const double*)ctx->gy.p, (const double*)ctx->gz.p, pos_grad, true, st));
   return SOAP_OK;
 }
@@ -498,7 +574,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   if (!q_sparse || !alpha) return fail(ctx, SOAP_EINVAL, "null sparse set or weights");
   if (nl->n_atoms > 0 && (!species || !e_atom)) return fail(ctx, SOAP_EINVAL, "null species or energies");
   const soap::DevParams& P = ctx->dp;
-  const size_t N = (size_t)nl->n_atoms, NP = (size_t)nl->n_pairs;
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   if (N == 0) {
     if (alpha_grad) SOAP_HIP(ctx, hipMemsetAsync(alpha_grad, 0, sizeof(double) * M, st));
     return SOAP_OK;
@@ -543,12 +619,12 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
                                         (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->cbar.p, st));
       }
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
-      SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, nl->j, species,
+      SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                               (const double*)ctx->rows.p, (const double*)ctx->cbar.p,
                                               (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
-    SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, nl->rev, (const double*)ctx->gx.p,
+    SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
                                             (const double*)ctx->gy.p, (const double*)ctx->gz.p, forces, false, st));
   }
   return SOAP_OK;

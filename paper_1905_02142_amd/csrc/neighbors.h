@@ -45,7 +45,10 @@ hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructM
                         int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
                         const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
                         int* ncenter, double* ndx, double* ndy, double* ndz, int* nrev, int* err, hipStream_t st);
-hipError_t launch_reverse(long long n_pairs, const int* offsets, const int* nj, const int* nimg, const int* ncenter,
-                          int* rev, int* err, hipStream_t st);
+// pairs 0..min(*count, bound) (count nullptr: 0..bound); list ranges are cut at bound
+hipError_t launch_reverse(long long bound, const int* count, const int* offsets, const int* nj, const int* nimg,
+                          const int* ncenter, int* rev, int* err, hipStream_t st);
+// out[0] = *total, out[1] = *err, written by one kernel (out may be mapped host memory)
+hipError_t launch_report(const int* total, const int* err, int* out, hipStream_t st);
 
 }  // namespace soap

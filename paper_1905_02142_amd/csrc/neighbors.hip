@@ -213,10 +213,15 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
 // minimum over the lanes is it) and set both directions; pairs with i == j (a
 // periodic image of the centre) search their own list; pairs with i > j are
 // set by their partner.  Every rev entry starts as the pair itself.
-__global__ __launch_bounds__(256) void k_reverse(long long n_pairs, const int* __restrict__ offsets,
-                                                 const int* __restrict__ nj, const int* __restrict__ nimg,
-                                                 const int* __restrict__ ncenter, int* __restrict__ rev,
-                                                 int* __restrict__ err) {
+// With a device-side count (count != nullptr) the pairs are the first
+// min(*count, bound) entries and every list range is cut at bound, so a list
+// that overflowed its capacity is searched only where it was written.
+__global__ __launch_bounds__(256) void k_reverse(long long bound, const int* __restrict__ count,
+                                                 const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                 const int* __restrict__ nimg, const int* __restrict__ ncenter,
+                                                 int* __restrict__ rev, int* __restrict__ err) {
+  const long long n_pairs = count ? min(bound, (long long)max(*count, 0)) : bound;
+  const int cap = (int)min(bound, 2147483647LL);
   const long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
   int found = 0x7fffffff;
@@ -230,7 +235,8 @@ __global__ __launch_bounds__(256) void k_reverse(long long n_pairs, const int* _
       int T[3];
       unpack_img(nimg[p], T);
       const int want = pack_img(-T[0], -T[1], -T[2]);
-      for (int q = offsets[j] + sub; q < offsets[j + 1]; q += 16)
+      const int q1 = min(offsets[j + 1], cap);
+      for (int q = min(offsets[j], cap) + sub; q < q1; q += 16)
         if (nj[q] == i && nimg[q] == want) {
           found = q;
           break;
@@ -358,7 +364,20 @@ __global__ void k_init_build(int n_bins, int* __restrict__ bin_count, int* __res
   if (t < 4) err[t] = 0;
 }
 
+// out[0] = pair count, out[1] = error bits of the last build (out may be host-pinned memory)
+__global__ void k_report(const int* __restrict__ total, const int* __restrict__ err, int* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = *total;
+    out[1] = *err;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_report(const int* total, const int* err, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, st, total, err, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_init_build(int n_bins, int* bin_count, int* bin_cursor, int* err, hipStream_t st) {
   const int n = n_bins > 4 ? n_bins : 4;
@@ -410,11 +429,11 @@ hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructM
   return hipGetLastError();
 }
 
-hipError_t launch_reverse(long long n_pairs, const int* offsets, const int* nj, const int* nimg, const int* ncenter,
-                          int* rev, int* err, hipStream_t st) {
-  if (n_pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reverse, dim3((unsigned)((n_pairs + 15) / 16)), dim3(256), 0, st, n_pairs, offsets, nj, nimg,
-                     ncenter, rev, err);
+hipError_t launch_reverse(long long bound, const int* count, const int* offsets, const int* nj, const int* nimg,
+                          const int* ncenter, int* rev, int* err, hipStream_t st) {
+  if (bound == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reverse, dim3((unsigned)((bound + 15) / 16)), dim3(256), 0, st, bound, count, offsets, nj,
+                     nimg, ncenter, rev, err);
   return hipGetLastError();
 }
 

@@ -16,16 +16,22 @@ size_t c_doubles_per_atom(const DevParams& P);
 // factors and their r-derivatives)
 size_t pair_row_doubles(const DevParams& P);
 
-// pair rows (pair_row_doubles each, pair-major) for n_pairs neighbours, the
-// derivative part only if deriv, and the central-atom radial factors bc
-// (n_max doubles); block: threads per block (64, 128 or 256); staged: rows
-// collected in LDS and written out in whole-row pieces
-hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
-                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, int block,
-                            bool staged, hipStream_t st);
+// Every per-pair launch takes a pair bound: the exact pair count, or the list
+// capacity when the count is still on the device.  Per-atom kernels cut each
+// atom's range at the bound, so an overflowed list is read only where written.
+
+// pair rows (pair_row_doubles each, pair-major) for n_pairs neighbours (or, with
+// count non-null, for min(*count, n_pairs)), the derivative part only if deriv,
+// and the central-atom radial factors bc (n_max doubles); block: threads per
+// block (64, 128 or 256); staged: rows collected in LDS and written out in
+// whole-row pieces
+hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
+                            const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
+                            int block, bool staged, hipStream_t st);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
-hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
+hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
+                             const int* nj,
                              const int* species, const double* rows, const double* bc, double* c, double* q,
                              int q_pitch, double* pnorm, hipStream_t st);
 
@@ -34,7 +40,7 @@ hipError_t launch_cbar(const DevParams& P, int n_atoms, const double* c, const d
                        const double* pnorm, const double* qbar, int qbar_pitch, double* cbar, hipStream_t st);
 
 // pair gradients g_p = dE/dd_p (SoA) from cbar and the pair rows with derivatives
-hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
+hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                                const int* nj, const int* species, const double* rows, const double* cbar, double* gx,
                                double* gy, double* gz, hipStream_t st);
 
@@ -42,7 +48,7 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
 void build_angular_tables(const DevParams& P, DevTables& T);
 
 // out = F (overwrite) or pos_grad -= F (accumulate_grad)
-hipError_t launch_force_gather(int n_atoms, const int* offsets, const int* rev, const double* gx, const double* gy,
+hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
                                const double* gz, double* out, bool accumulate_grad, hipStream_t st);
 
 }  // namespace soap

@@ -194,14 +194,17 @@ constexpr int prep_stride() {
 }
 
 template <int NMAX, int LMAX, bool DERIV, bool STAGED>
-__global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int n_pairs,
-                                                     const double* __restrict__ dx, const double* __restrict__ dy,
-                                                     const double* __restrict__ dz, double* __restrict__ rows,
-                                                     double* __restrict__ bc) {
+__global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
+                                                     const int* __restrict__ count, const double* __restrict__ dx,
+                                                     const double* __restrict__ dy, const double* __restrict__ dz,
+                                                     double* __restrict__ rows, double* __restrict__ bc) {
   using S = Shape<NMAX, LMAX>;
   constexpr int PRS = prep_stride<NMAX, LMAX>();
   __shared__ PairTab<NMAX, LMAX> tab;
   extern __shared__ double prow[];  // STAGED: blockDim.x rows of PRS doubles
+  // pairs 0..n_pairs: the bound, or the device-side count cut at the bound
+  const int n_pairs = count ? min(bound, max(*count, 0)) : bound;
+  if (blockIdx.x > 0 && (int)(blockIdx.x * blockDim.x) >= n_pairs) return;  // block 0 also writes bc
   stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, blockDim.x);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -326,7 +329,8 @@ __device__ inline void stage_rows(const double* __restrict__ rows, const int* id
 
 template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                     const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                     const int* __restrict__ offsets, int bound,
+                                                     const int* __restrict__ nj,
                                                      const int* __restrict__ species, const double* __restrict__ rows,
                                                      const double* __restrict__ bc_in,
                                                      double* __restrict__ c_out,
@@ -343,7 +347,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams 
   if (i >= n_atoms) return;
   const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
   const int n = P.n, LL = P.LL, LLP = LL + 1, nch = P.nch;
-  const int p0 = offsets[i], p1 = offsets[i + 1];
+  const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
   const int si = P.ns == 1 ? 0 : species[i];
   double* __restrict__ ci_out = c_out + (size_t)i * P.ns * NMAX * LLP;
   stage_records<E, NC>(T, rec, LL, lane);
@@ -551,7 +555,8 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
 
 template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                       const int* __restrict__ offsets, const int* __restrict__ nj,
+                                                       const int* __restrict__ offsets, int bound,
+                                                       const int* __restrict__ nj,
                                                        const int* __restrict__ species,
                                                        const double* __restrict__ rows,
                                                        const double* __restrict__ cbar, double* __restrict__ gx,
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParam
   if (i >= n_atoms) return;
   const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
   const int LL = P.LL, LLP = LL + 1;
-  const int p0 = offsets[i], p1 = offsets[i + 1];
+  const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
   double* gacc = dyn + ACH * LAR;  // per-neighbour (S_r, S_x, S_y, S_z)
   stage_records<E, NC>(T, rec, LL, lane);
 
@@ -682,7 +687,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParam
 // F_k = sum over k's pairs q of (g_q - g_rev(q)) (= -dE/dr_k); mode 1 adds -F_k into
 // pos_grad.  16 lanes per atom stride over its pairs; the partial sums are
 // combined by a fixed butterfly, so the result is the same on every run.
-__global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets,
+__global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets, int bound,
                                                       const int* __restrict__ rev, const double* __restrict__ gx,
                                                       const double* __restrict__ gy, const double* __restrict__ gz,
                                                       double* __restrict__ out, int accumulate_grad) {
@@ -690,7 +695,8 @@ __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __
   const int sub = threadIdx.x & 15;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   if (k < n_atoms) {
-    for (int q = offsets[k] + sub; q < offsets[k + 1]; q += 16) {
+    const int q1 = min(offsets[k + 1], bound);
+    for (int q = min(offsets[k], bound) + sub; q < q1; q += 16) {
       const int r = rev[q];
       fx += gx[q] - gx[r];
       fy += gy[q] - gy[r];
@@ -789,38 +795,40 @@ size_t adjoint_lds_bytes(const DevParams& P) {
   return a > b ? a : b;
 }
 
-hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const double* dx,
-                            const double* dy, const double* dz, double* rows, bool deriv, double* bc, int block,
-                            bool staged, hipStream_t st) {
+hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
+                            const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
+                            int block, bool staged, hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
   if (staged && block > 128) block = 128;  // the staging buffer stays under 64 KB
   const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
   auto f = [&]<int N, int LM>() {
     const size_t lds = staged ? sizeof(double) * (size_t)block * prep_stride<N, LM>() : 0;
+    const int np = (int)n_pairs;
     if (deriv && staged)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true>), dim3(blocks), dim3(block), lds, st, P, T, (int)n_pairs, dx,
-                         dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true>), dim3(blocks), dim3(block), lds, st, P, T, np, count, dx, dy,
+                         dz, rows, bc);
     else if (deriv)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs, dx,
-                         dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
+                         dz, rows, bc);
     else if (staged)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true>), dim3(blocks), dim3(block), lds, st, P, T, (int)n_pairs,
-                         dx, dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true>), dim3(blocks), dim3(block), lds, st, P, T, np, count, dx,
+                         dy, dz, rows, bc);
     else
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false>), dim3(blocks), dim3(block), 0, st, P, T, (int)n_pairs,
-                         dx, dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx,
+                         dy, dz, rows, bc);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
-hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, const int* nj,
+hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
+                             const int* nj,
                              const int* species, const double* rows, const double* bc, double* c, double* q,
                              int q_pitch, double* pnorm, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
+    hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
                        rows, bc, c, q, q_pitch, pnorm);
     return hipGetLastError();
   };
@@ -838,23 +846,23 @@ hipError_t launch_cbar(const DevParams& P, int n_atoms, const double* c, const d
   return dispatch(P.n, P.l, f);
 }
 
-hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets,
+hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                                const int* nj, const int* species, const double* rows, const double* cbar, double* gx,
                                double* gy, double* gz, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, nj, species,
+    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
                        rows, cbar, gx, gy, gz);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
-hipError_t launch_force_gather(int n_atoms, const int* offsets, const int* rev, const double* gx, const double* gy,
+hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
                                const double* gz, double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 15) / 16), dim3(256), 0, st, n_atoms, offsets, rev, gx, gy, gz,
+  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 15) / 16), dim3(256), 0, st, n_atoms, offsets, bound, rev, gx, gy, gz,
                      out, accumulate_grad ? 1 : 0);
   return hipGetLastError();
 }

@@ -75,6 +75,11 @@ class NeighbourList:
         self.dy = torch.empty(cap, dtype=torch.float64, device=dev)
         self.dz = torch.empty(cap, dtype=torch.float64, device=dev)
 
+    @property
+    def deferred(self) -> bool:
+        """True while the pair count is on the device only (after an async build)."""
+        return self.n_pairs == _lib.SOAP_PAIRS_DEFERRED
+
     def c_struct(self) -> _lib.soap_nlist:
         return _lib.soap_nlist(self.n_atoms, self.n_structures, self.n_pairs, self.capacity,
                                _ptr(self.offsets), _ptr(self.j), _ptr(self.img), _ptr(self.rev),
@@ -82,6 +87,8 @@ class NeighbourList:
 
     def image(self) -> torch.Tensor:
         """Lattice translations T of the pairs, shape (n_pairs, 3)."""
+        if self.deferred:
+            raise RuntimeError("pair count not read back yet: call Soap.check_neighbors first")
         v = self.img[: self.n_pairs].to(torch.int64)
         return torch.stack([((v >> 20) & 1023) - 512, ((v >> 10) & 1023) - 512, (v & 1023) - 512], 1)
 
@@ -131,6 +138,31 @@ class Soap:
             nl.n_structures = ns
             return nl
         raise _lib.SoapError(_lib.SOAP_EOVERFLOW, "neighbour list still overflows after growing")
+
+    def neighbors_async(self, positions: torch.Tensor, cells, pbc, nl: NeighbourList,
+                        struct_offsets=None) -> NeighbourList:
+        """soap_build_neighbors_async into an existing list: no host synchronisation,
+        nl.n_pairs becomes SOAP_PAIRS_DEFERRED until check_neighbors."""
+        pos = positions.contiguous()
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.shape[0] == nl.n_atoms
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 9))
+        pbc = np.ascontiguousarray(np.asarray(pbc, dtype=np.int32).reshape(-1, 3))
+        so = None if struct_offsets is None else np.ascontiguousarray(np.asarray(struct_offsets, dtype=np.int32))
+        c = nl.c_struct()
+        _lib.soap_build_neighbors_async(self.ctx, nl.n_atoms, pos.data_ptr(), cells.ctypes.data, pbc.ctypes.data,
+                                        None if so is None else so.ctypes.data, cells.shape[0], c, _stream())
+        nl.n_pairs = int(c.n_pairs)
+        nl.n_structures = cells.shape[0]
+        return nl
+
+    def check_neighbors(self, nl: NeighbourList) -> int:
+        """soap_neighbors_check: waits for the stream, stores and returns the pair count of
+        the last build; raises SoapError on overflow or invalid positions."""
+        st, n = _lib.soap_neighbors_check(self.ctx, nl.c_struct(), _stream())
+        if st == _lib.SOAP_EOVERFLOW:
+            raise _lib.SoapError(st, f"neighbour list needs {n} pairs, capacity {nl.capacity}")
+        nl.n_pairs = n
+        return n
 
     # ---------------------------------------------------------------- descriptor
     def descriptor(self, nl: NeighbourList, species: torch.Tensor, with_norm: bool = False):
