@@ -240,24 +240,26 @@ long long soap_workspace_bytes(const soap_ctx* ctx);
 /* ------------------------------------------------------------------ tuning
  * Launch-shape choices that change speed, not the method.  Every setting
  * computes the same quantities and meets the same bounds; settings that change
- * the order of the GAP sums (two-pass vs fused, number of slices) or select a
- * separately compiled per-pair kernel (prep_staged) agree to the rounding of
- * the operand precision.  For a fixed setting every result is bitwise
- * reproducible.
+ * the order of the GAP sums (two-pass vs fused, number of slices) agree to the
+ * rounding of the operand precision; cell_split changes the order of each
+ * atom's pairs in the neighbour list (not the set of pairs or their vectors),
+ * hence the order of the per-atom sums; prep_block changes nothing in the
+ * results.  For a fixed setting every result is bitwise reproducible.
  *   gap_fused   0: scores pass then Qbar pass; 1: one fused pass (16/32-bit
  *               modes with K <= 352; ignored otherwise)
  *   gap_slices  fused pass: target number of workgroups; the sparse set is
  *               split into slices until the grid reaches it (0: 512)
  *   prep_block  threads per block of the per-pair row kernel: 64, 128 or 256
- *   prep_staged 1: the per-pair rows are collected in LDS and written out in
- *               whole-row pieces (blocks of at most 128 threads); 0: each
- *               thread writes its own row
+ *   cell_split  cell-list bins of width >= r_cut / cell_split along each
+ *               periodic axis (1, 2 or 3); a centre scans (2 cell_split + 1)^3
+ *               bins, fewer candidate atoms for larger values.  Takes effect at
+ *               the next neighbour build.
  */
 typedef struct {
   int gap_fused;
   int gap_slices;
   int prep_block;
-  int prep_staged;
+  int cell_split;
 } soap_tuning;
 
 /* Current setting of ctx (host struct).  SOAP_EINVAL on null arguments. */

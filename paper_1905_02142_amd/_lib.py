@@ -40,11 +40,10 @@ class soap_params(ctypes.Structure):
 
 class soap_tuning(ctypes.Structure):
     _fields_ = [("gap_fused", ctypes.c_int), ("gap_slices", ctypes.c_int), ("prep_block", ctypes.c_int),
-                ("prep_staged", ctypes.c_int)]
+                ("cell_split", ctypes.c_int)]
 
     def as_dict(self) -> dict:
-        return {"gap_fused": self.gap_fused, "gap_slices": self.gap_slices, "prep_block": self.prep_block,
-                "prep_staged": self.prep_staged}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class soap_nlist(ctypes.Structure):

@@ -41,7 +41,7 @@ struct soap_ctx {
   int* report_dev = nullptr;  // the same memory as the device addresses it
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
-  soap_tuning tune{0, 0, 256, 0};
+  soap_tuning tune{0, 0, 256, 2};
   Buf tune_out;  // scratch outputs of the autotuner
   size_t pinned_bytes = 0;
   // neighbour build
@@ -201,13 +201,12 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
-  SOAP_ENSURE(ctx, ctx->rows, sizeof(double) * (NP > 0 ? NP : 1) * soap::pair_row_doubles(P));
+  SOAP_ENSURE(ctx, ctx->rows, soap::pair_rows_bytes(P, (long long)NP));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
     SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, (long long)NP, pair_count(nl), nl->dx, nl->dy, nl->dz,
-                                         (double*)ctx->rows.p, deriv, (double*)ctx->bc.p, ctx->tune.prep_block,
-                                         ctx->tune.prep_staged != 0, st));
+                                         (double*)ctx->rows.p, deriv, (double*)ctx->bc.p, ctx->tune.prep_block, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
@@ -367,7 +366,8 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
       const double w = std::fabs(det) / std::sqrt(cx * cx + cy * cy + cz * cz);
       M.pbc[a] = pbc[3 * s + a] ? 1 : 0;
       if (M.pbc[a]) {
-        int nb = (int)std::floor(w / (rc * (1.0 + 2e-9)));
+        // bins of width >= r_cut / cell_split: a centre scans (2 cell_split + 1)^3 of them
+        int nb = (int)std::floor(w * ctx->tune.cell_split / (rc * (1.0 + 2e-9)));
         if (nb < 1) nb = 1;
         if (nb > 256) nb = 256;
         M.nbin[a] = nb;
@@ -417,22 +417,30 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
     ctx->meta_host.swap(img);
     ctx->meta_dev = ctx->meta.p;
   }
-  SOAP_HIP(ctx, soap::launch_init_build(n_bins, (int*)ctx->bin_count.p, (int*)ctx->bin_cursor.p,
-                                        (int*)ctx->errflag.p, st));
   int* err = (int*)ctx->errflag.p;
   StageTimer tm(ctx, SOAP_STAGE_NEIGHBORS, st);
   const soap::StructMeta* dmeta = (const soap::StructMeta*)ctx->meta.p;
   const int* dso = (const int*)((const char*)ctx->meta.p + sizeof(soap::StructMeta) * n_structures);
-  if (n_atoms > 0) {
-    SOAP_HIP(ctx, soap::launch_bin_atoms(n_atoms, pos, dmeta, dso, n_structures, (int*)ctx->atom_bin.p,
-                                         (int*)ctx->atom_wrap.p, (int*)ctx->bin_count.p, err, st));
-  }
-  SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->bin_count.p, n_bins, (int*)ctx->bin_start.p,
-                                     (int*)ctx->scan_part.p, st));
-  if (n_atoms > 0) {
-    SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, (const int*)ctx->atom_bin.p, (const int*)ctx->bin_start.p,
-                                         (int*)ctx->bin_cursor.p, (int*)ctx->bin_unsorted.p, (int*)ctx->bin_atoms.p,
+  if (soap::bin_small_fits(n_atoms, n_bins)) {
+    // the cell list of a small system in one launch
+    SOAP_HIP(ctx, soap::launch_bin_small(n_atoms, pos, dmeta, dso, n_structures, n_bins, (int*)ctx->atom_bin.p,
+                                         (int*)ctx->atom_wrap.p, (int*)ctx->bin_start.p, (int*)ctx->bin_atoms.p, err,
                                          st));
+  } else {
+    SOAP_HIP(ctx, soap::launch_init_build(n_bins, (int*)ctx->bin_count.p, (int*)ctx->bin_cursor.p, err, st));
+    if (n_atoms > 0) {
+      SOAP_HIP(ctx, soap::launch_bin_atoms(n_atoms, pos, dmeta, dso, n_structures, (int*)ctx->atom_bin.p,
+                                           (int*)ctx->atom_wrap.p, (int*)ctx->bin_count.p, err, st));
+    }
+    SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->bin_count.p, n_bins, (int*)ctx->bin_start.p,
+                                       (int*)ctx->scan_part.p, st));
+    if (n_atoms > 0) {
+      SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, (const int*)ctx->atom_bin.p, (const int*)ctx->bin_start.p,
+                                           (int*)ctx->bin_cursor.p, (int*)ctx->bin_unsorted.p,
+                                           (int*)ctx->bin_atoms.p, st));
+    }
+  }
+  if (n_atoms > 0) {
     SOAP_HIP(ctx, soap::launch_pairs(false, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
                                      (const int*)ctx->bin_atoms.p, (int*)ctx->counts.p, nullptr, 0, nullptr, nullptr,
@@ -639,8 +647,8 @@ soap_status soap_get_tuning(const soap_ctx* ctx, soap_tuning* out) {
 soap_status soap_set_tuning(soap_ctx* ctx, const soap_tuning* t) {
   if (!ctx || !t) return SOAP_EINVAL;
   if ((t->gap_fused != 0 && t->gap_fused != 1) || t->gap_slices < 0 || t->gap_slices > (1 << 20) ||
-      (t->prep_block != 64 && t->prep_block != 128 && t->prep_block != 256) ||
-      (t->prep_staged != 0 && t->prep_staged != 1))
+      (t->prep_block != 64 && t->prep_block != 128 && t->prep_block != 256) || t->cell_split < 1 ||
+      t->cell_split > 3)
     return fail(ctx, SOAP_EINVAL, "tuning field out of range");
   ctx->tune = *t;
   return SOAP_OK;
@@ -682,7 +690,6 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
     std::vector<int> cand;
   };
   const std::vector<Axis> axes = {
-      {&soap_tuning::prep_staged, {0, 1}},
       {&soap_tuning::prep_block, {64, 128, 256}},
       {&soap_tuning::gap_fused, fusable ? std::vector<int>{0, 1} : std::vector<int>{0}},
       {&soap_tuning::gap_slices, fusable ? std::vector<int>{256, 512, 1024, 2048} : std::vector<int>{}},

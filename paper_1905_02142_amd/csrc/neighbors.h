@@ -33,6 +33,18 @@ __host__ __device__ inline void unpack_img(int v, int* t) {
   t[2] = (v & 1023) - 512;
 }
 
+// one-workgroup cell list for small systems (bin_small_fits)
+constexpr int kSmallAtoms = 16384;
+constexpr int kSmallBins = 16384;
+constexpr int kSmallBinThreads = 1024;
+constexpr int kSmallBinLds = 150 * 1024;  // dynamic LDS opt-in of one workgroup
+bool bin_small_fits(int n_atoms, int n_bins);
+// err[0..4) cleared; atom_bin, atom_wrap, bin_start (n_bins + 1) and bin_atoms
+// (atoms of each bin by ascending index) written
+hipError_t launch_bin_small(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
+                            int n_bins, int* atom_bin, int* atom_wrap, int* bin_start, int* bin_atoms, int* err,
+                            hipStream_t st);
+
 // zero bin_count[0..n_bins), bin_cursor[0..n_bins) and err[0..4)
 hipError_t launch_init_build(int n_bins, int* bin_count, int* bin_cursor, int* err, hipStream_t st);
 hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t st);

@@ -32,11 +32,10 @@ __device__ inline int find_structure(const int* __restrict__ so, int ns, int a) 
   return lo;
 }
 
-__global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
-                            const int* __restrict__ so, int n_struct, int* __restrict__ atom_bin,
-                            int* __restrict__ atom_wrap, int* __restrict__ bin_count, int* __restrict__ err) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n_atoms) return;
+// bin of atom a (global bin index) and the lattice wrap that brings it into its cell
+__device__ inline void locate_atom(int a, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
+                                   const int* __restrict__ so, int n_struct, int* __restrict__ err, int& bin_out,
+                                   int& wrap_out) {
   const StructMeta& M = meta[find_structure(so, n_struct, a)];
   double p[3] = {pos[3 * a], pos[3 * a + 1], pos[3 * a + 2]};
   if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
@@ -66,10 +65,101 @@ __global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const S
       b[x] = 0;
     }
   }
-  int bin = M.bin0 + (b[2] * M.nbin[1] + b[1]) * M.nbin[0] + b[0];
+  bin_out = M.bin0 + (b[2] * M.nbin[1] + b[1]) * M.nbin[0] + b[0];
+  wrap_out = pack_img(w[0], w[1], w[2]);
+}
+
+__global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
+                            const int* __restrict__ so, int n_struct, int* __restrict__ atom_bin,
+                            int* __restrict__ atom_wrap, int* __restrict__ bin_count, int* __restrict__ err) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  int bin, wrap;
+  locate_atom(a, pos, meta, so, n_struct, err, bin, wrap);
   atom_bin[a] = bin;
-  atom_wrap[a] = pack_img(w[0], w[1], w[2]);
+  atom_wrap[a] = wrap;
   atomicAdd(&bin_count[bin], 1);
+}
+
+// The whole cell list of a small system in one workgroup: error word cleared,
+// atoms binned, bin counts scanned into bin_start, atoms placed by LDS cursors
+// and then ranked by index inside each bin; the same result as k_init_build ..
+// k_rank_bins in five launches.  Each thread keeps its atoms' bins in
+// registers; counts, starts and the unsorted bin contents live in LDS
+// (4 (n_atoms + 2 n_bins) bytes of dynamic LDS).
+__global__ __launch_bounds__(kSmallBinThreads) void k_bin_small(int n_atoms, const double* __restrict__ pos,
+                                                                const StructMeta* __restrict__ meta,
+                                                                const int* __restrict__ so, int n_struct, int n_bins,
+                                                                int* __restrict__ atom_bin, int* __restrict__ atom_wrap,
+                                                                int* __restrict__ bin_start,
+                                                                int* __restrict__ bin_atoms, int* __restrict__ err) {
+  constexpr int PER = kSmallAtoms / kSmallBinThreads;  // atoms per thread at most
+  extern __shared__ int lds[];
+  int* cnt = lds;               // n_bins: counts, then cursors
+  int* start = lds + n_bins;    // n_bins
+  int* unsorted = lds + 2 * n_bins;  // n_atoms; its first kSmallBinThreads words serve the scan first
+  int* part = unsorted;
+  const int t = threadIdx.x;
+  for (int b = t; b < n_bins; b += kSmallBinThreads) cnt[b] = 0;
+  if (t < 4) err[t] = 0;
+  __syncthreads();
+  int mybin[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int a = t + k * kSmallBinThreads;
+    mybin[k] = -1;
+    if (a < n_atoms) {
+      int wrap;
+      locate_atom(a, pos, meta, so, n_struct, err, mybin[k], wrap);
+      atom_bin[a] = mybin[k];
+      atom_wrap[a] = wrap;
+      atomicAdd(&cnt[mybin[k]], 1);
+    }
+  }
+  __syncthreads();
+  // exclusive scan: thread t owns bins t*per .. t*per+per-1
+  const int per = (n_bins + kSmallBinThreads - 1) / kSmallBinThreads;
+  int sum = 0;
+  for (int k = 0; k < per; ++k) {
+    const int b = t * per + k;
+    if (b < n_bins) sum += cnt[b];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < kSmallBinThreads; o <<= 1) {
+    const int x = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  int run = part[t] - sum;
+  const int total = part[kSmallBinThreads - 1];
+  for (int k = 0; k < per; ++k) {
+    const int b = t * per + k;
+    if (b < n_bins) {
+      const int c = cnt[b];
+      bin_start[b] = run;
+      start[b] = run;
+      cnt[b] = run;  // from here on the placement cursor
+      run += c;
+    }
+  }
+  if (t == 0) bin_start[n_bins] = total;
+  __syncthreads();  // the scan is done with `part` before `unsorted` is written
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (mybin[k] >= 0) unsorted[atomicAdd(&cnt[mybin[k]], 1)] = t + k * kSmallBinThreads;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (mybin[k] >= 0) {
+      const int a = t + k * kSmallBinThreads;
+      const int s0 = start[mybin[k]], e0 = cnt[mybin[k]];  // the cursor ends at the bin's end
+      int rank = 0;
+      for (int q = s0; q < e0; ++q) rank += unsorted[q] < a;
+      bin_atoms[s0 + rank] = a;
+    }
+  }
 }
 
 __global__ void k_fill_bins(int n_atoms, const int* __restrict__ atom_bin, const int* __restrict__ bin_start,
@@ -210,7 +300,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
 
 // rev[p]: the pair (j -> i, -T) in j's list.  Only pairs with i < j search (16
 // lanes probe j's list with coalesced loads; the match is unique, so the
-// minimum over the lanes is it) and set both directions; pairs with i == j (a
+// minimum over the probes is it) and set both directions; pairs with i == j (a
 // periodic image of the centre) search their own list; pairs with i > j are
 // set by their partner.  Every rev entry starts as the pair itself.
 // With a device-side count (count != nullptr) the pairs are the first
@@ -235,12 +325,20 @@ __global__ __launch_bounds__(256) void k_reverse(long long bound, const int* __r
       int T[3];
       unpack_img(nimg[p], T);
       const int want = pack_img(-T[0], -T[1], -T[2]);
+      // four probes per lane in flight: the list is swept 64 entries per round
       const int q1 = min(offsets[j + 1], cap);
-      for (int q = min(offsets[j], cap) + sub; q < q1; q += 16)
-        if (nj[q] == i && nimg[q] == want) {
-          found = q;
-          break;
+      for (int q0 = min(offsets[j], cap) + sub; q0 < q1; q0 += 64) {
+        int cj[4], ci[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + 16 * u;
+          cj[u] = q < q1 ? nj[q] : -1;
+          ci[u] = q < q1 ? nimg[q] : 0;
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (cj[u] == i && ci[u] == want) found = min(found, q0 + 16 * u);
+      }
     }
   }
 #pragma unroll
@@ -398,6 +496,32 @@ hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t
 }
 
 int scan_partials_needed(int n) { return (n + kScanTile) / kScanTile; }
+
+size_t bin_small_lds_bytes(int n_atoms, int n_bins) {
+  const int a = n_atoms > kSmallBinThreads ? n_atoms : kSmallBinThreads;
+  return sizeof(int) * ((size_t)a + 2 * (size_t)n_bins);
+}
+
+bool bin_small_fits(int n_atoms, int n_bins) {
+  return n_atoms > 0 && n_atoms <= kSmallAtoms && n_bins <= kSmallBins &&
+         bin_small_lds_bytes(n_atoms, n_bins) <= kSmallBinLds;
+}
+
+hipError_t launch_bin_small(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
+                            int n_bins, int* atom_bin, int* atom_wrap, int* bin_start, int* bin_atoms, int* err,
+                            hipStream_t st) {
+  if (!bin_small_fits(n_atoms, n_bins)) return hipErrorInvalidValue;
+  static bool attr = false;  // LDS beyond 64 KB needs the opt-in once per process
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_bin_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             kSmallBinLds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_bin_small, dim3(1), dim3(kSmallBinThreads), bin_small_lds_bytes(n_atoms, n_bins), st, n_atoms,
+                     pos, meta, so, n_struct, n_bins, atom_bin, atom_wrap, bin_start, bin_atoms, err);
+  return hipGetLastError();
+}
 
 hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
                             int* atom_bin, int* atom_wrap, int* bin_count, int* err, hipStream_t st) {

@@ -20,14 +20,15 @@ size_t pair_row_doubles(const DevParams& P);
 // capacity when the count is still on the device.  Per-atom kernels cut each
 // atom's range at the bound, so an overflowed list is read only where written.
 
-// pair rows (pair_row_doubles each, pair-major) for n_pairs neighbours (or, with
-// count non-null, for min(*count, n_pairs)), the derivative part only if deriv,
-// and the central-atom radial factors bc (n_max doubles); block: threads per
-// block (64, 128 or 256); staged: rows collected in LDS and written out in
-// whole-row pieces
+// pair rows (pair_row_doubles fields each; blocks of 64 pairs stored
+// field-major, pair_rows_bytes in all) for n_pairs neighbours (or, with count
+// non-null, for min(*count, n_pairs)), the derivative fields only if deriv, and
+// the central-atom radial factors bc (n_max doubles); block: threads per block
+// (64, 128 or 256)
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
-                            int block, bool staged, hipStream_t st);
+                            int block, hipStream_t st);
+size_t pair_rows_bytes(const DevParams& P, long long n_pairs);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,

@@ -1,34 +1,37 @@
 // Descriptor forward and adjoint kernels (FP64 VALU).
 //
 // k_pair_prep, one thread per neighbour pair i -> j (d = r_j + T - r_i, r = |d|,
-// u = d / r): everything of Eq. (08) that depends on the pair alone, written to
-// a row in HBM that the forward and the adjoint kernels share:
+// u = d / r): everything of Eq. (08) that depends on the pair alone, written as
+// the pair's fields in HBM (blocks of 64 pairs, field-major, so every store and
+// every per-lane load of a field is one contiguous run) that the forward and the
+// adjoint kernels share:
 //   B_k = 4 pi A b_k          radial overlaps, Eqs. (02), (04), (19), (06), Eq. (15)
 //   w_l e_l                   ilexp, Sec. III.C
 //   (u_x + i u_y)^m, u_z      the azimuthal factors of the real harmonics
 // and, for forces, dB_k/dr, d(w_l e_l)/dr, u_x, u_y and 1/r.
 //
 // k_descriptor, one 64-lane wavefront per centre atom.  Its neighbours of one
-// species are compacted with a wave ballot and their rows staged in LDS, 64 at
-// a time.  Lane (g, j), g = lane / 16, j = lane % 16: the four 16-lane groups
-// take four neighbours per step and lane j owns a fixed set of (l, m) records;
-// it evaluates Qbar_lm(u_z) as a short polynomial and accumulates both real
-// harmonics of each record times every B_k in registers:
+// species are compacted with a wave ballot and their fields staged in LDS, 32
+// at a time.  Each lane owns one (l, m) record (two for l_max >= 10) and takes the
+// neighbours one after the other: it evaluates Qbar_lm(u_z) as a short
+// polynomial and accumulates both real harmonics of its record times every B_k
+// in registers:
 //   c_{k,lm} += B_k w_l e_l Y_lm                                    (Eq. (08))
-// The four groups are added with cross-row lane swaps, the central atom joins
-// l = 0, and c goes to HBM.  The power spectrum p_{ab l} = sum_m c_{a,lm} c_{b,lm}
+// so no cross-lane sum is needed; the central atom joins l = 0 and c goes to
+// HBM.  The power spectrum p_{ab l} = sum_m c_{a,lm} c_{b,lm}
 // (the real form of Eq. (09)), packed a <= b then l with sqrt(2) off the
 // diagonal, and q = p / |p| follow from c staged in LDS.
 //
 // Adjoint: k_cbar forms vbar = (qbar - q (q.qbar)) / |p| and cbar = M c
 // (M_aa = 2 vbar_aal, M_ab = sqrt(2) vbar_abl), the derivative of the power
-// spectrum and of the normalisation.  k_pair_adjoint stages the same rows and
-// lane (g, j) contracts its records' cbar (held in registers) with them:
+// spectrum and of the normalisation.  k_pair_adjoint takes one pair per lane:
+// the lane reads its pair's fields and runs over every record (l, m), with the
+// cbar of the neighbour's species and the record table read from LDS:
 //   U_lm = sum_k cbar_{k,lm} dB_k/dr,  V_lm = sum_k cbar_{k,lm} B_k,
 //   dE/dd = sum_lm [(U_lm a_lm + V_lm da_lm/dr) u + V_lm w_l e_l (I - u u^T) grad_u Y_lm / r]
-// with a_lm = w_l e_l Y_lm; the 16 lanes of a group are summed by DPP.  Forces
-// are gathered per atom through the reverse-pair index: no atomics, so FP64
-// results are bitwise reproducible.
+// with a_lm = w_l e_l Y_lm, summed in the lane's registers.  Forces are gathered
+// per atom through the reverse-pair index: no atomics, so FP64 results are
+// bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,47 +42,6 @@
 namespace soap {
 
 namespace {
-
-template <int CTRL>
-__device__ inline double dpp_move(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
-constexpr int kRowRor4 = 0x124;  // rotate each 16-lane row by 4
-constexpr int kRowRor8 = 0x128;  // rotate each 16-lane row by 8
-
-// sum over the 16 lanes of each row; every lane of the row gets the total
-__device__ inline double row_sum(double v) {
-  v += dpp_move<kQuadXor1>(v);
-  v += dpp_move<kQuadXor2>(v);
-  v += dpp_move<kRowRor4>(v);
-  v += dpp_move<kRowRor8>(v);
-  return v;
-}
-
-// v(lane) + v(lane ^ 16) + v(lane ^ 32) + v(lane ^ 48): the four 16-lane rows
-// summed without LDS.  permlane16_swap(x, x) returns the rows {0,0,2,2} and
-// {1,1,3,3} of x, and permlane32_swap(x, x) the halves {0,0} and {1,1}, so each
-// pair of results sums to the partner sum.
-__device__ inline double sum_rows(double v) {
-  {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    v = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
-  }
-  {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    v = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
-  }
-  return v;
-}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -107,20 +69,10 @@ __device__ inline int isqrt_small(int v) {
 
 constexpr int even(int w) { return w + (w & 1); }
 constexpr int kDenseM = 4096;  // cbar: largest (l_max + 1) n_ch^2 expanded densely in LDS
-// LDS row strides: even (16-byte rows) and not a multiple of 8 doubles, so the
-// four rows read together by the four lane groups fall in different banks
-constexpr int pad_row(int w) {
-  w = even(w);
-  while (w % 16 == 0 || w % 16 == 8) w += 2;
-  return w;
-}
-
 template <int NMAX, int LMAX>
 struct Shape {
   static constexpr int NREC = (LMAX + 1) * (LMAX + 2) / 2;
-  static constexpr int E = (NREC + kRecLanes - 1) / kRecLanes;  // records per lane
-  static constexpr int EP = E < 3 ? E : 3;                      // records per pass
-  static constexpr int NPASS = (E + EP - 1) / EP;
+  static constexpr int E2 = (NREC + 63) / 64;  // records per lane of the forward kernel
   static constexpr int NC = LMAX / 2 + 1;  // polynomial terms in u_z^2
   // pair row, forward part: (u_x + i u_y)^m (m = 0..LMAX) | B_k | w_l e_l | u_z
   static constexpr int FZ = 0, FB = 2 * (LMAX + 1), FW = FB + NMAX, FU = FW + LMAX + 1;
@@ -128,80 +80,49 @@ struct Shape {
   // derivative part: dB_k/dr | d(w_l e_l)/dr | u_x u_y 1/r
   static constexpr int XD = 0, XW = NMAX, XU = XW + LMAX + 1;
   static constexpr int XR = even(XU + 3);
-  static constexpr int ROW = FR + XR;  // doubles per pair in HBM
-  // LDS staging: forward rows (FR) of CH pairs, adjoint rows (FR + XR) of ACH pairs
-  static constexpr int CH = 64, LFR = pad_row(FR);
-  static constexpr int ACH = 32, LAR = pad_row(FR + XR);
+  // HBM: blocks of 64 pairs, field-major inside a block (field f of pair p at
+  // (p / 64) * ROW * 64 + f * 64 + p % 64)
+  static constexpr int ROW = FR + XR;  // doubles per pair
+  // forward kernel: fields of CH pairs staged in LDS rows of FRP doubles (even,
+  // for 16-byte reads, and 2 mod 4, so the staging writes spread over the banks)
+  static constexpr int CH = 32, FRP = FR | 2;
 };
 
-// the records of the 16 lanes (polynomial coefficients, (l, m, parity), c
-// columns), staged in LDS; lm < 0 (no harmonic) maps to the sink column LL
-template <int E, int NC>
-struct RecTab {
-  double cf[kRecLanes][E][NC];
-  int lmp[kRecLanes][E];
-  int lm[kRecLanes][E][2];
+// records lane + 64 e (e < E2) of a whole wave, read straight from the tables;
+// records past NREC: zero polynomial, sink columns
+template <int E2, int NC>
+struct LaneRecords {
+  double cf[E2][NC];
+  int l[E2], m[E2], par[E2], lmc[E2], lms[E2];
 };
 
-template <int E, int NC>
-__device__ inline void stage_records(const DevTables* __restrict__ T, RecTab<E, NC>& r, int LL, int lane) {
-  for (int x = lane; x < kRecLanes * E * NC; x += 64) {
-    const int j = x / (E * NC), e = (x / NC) % E, t = x % NC;
-    r.cf[j][e][t] = T->rec_coef[j][e][t];
-  }
-  for (int x = lane; x < kRecLanes * E; x += 64) {
-    const int j = x / E, e = x % E;
-    r.lmp[j][e] = T->rec_lmp[j][e];
-    const int lc = T->rec_lm[j][e][0], ls = T->rec_lm[j][e][1];
-    r.lm[j][e][0] = lc < 0 ? LL : lc;
-    r.lm[j][e][1] = ls < 0 ? LL : ls;
-  }
-}
-
-// one lane's records of a pass (records past E: zero polynomial, sink columns)
-template <int EP, int NC>
-struct Records {
-  double cf[EP][NC];
-  int l[EP], m[EP], par[EP];
-  int lmc[EP], lms[EP];
-};
-
-template <int E, int EP, int NC>
-__device__ inline void load_records(const RecTab<E, NC>& t, int j, int e0, int LL, Records<EP, NC>& R) {
+template <int E2, int NC>
+__device__ inline void lane_records(const DevTables* __restrict__ T, int lane, int nrec, int LL,
+                                    LaneRecords<E2, NC>& R) {
 #pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    const bool ok = e0 + e < E;
-    const int ee = ok ? e0 + e : 0;
-    const int info = ok ? t.lmp[j][ee] : 0;
+  for (int e = 0; e < E2; ++e) {
+    const int r = lane + 64 * e;
+    const bool ok = r < nrec;
+    const int jj = ok ? r % kRecLanes : 0, slot = ok ? r / kRecLanes : 0;
+    const int info = ok ? T->rec_lmp[jj][slot] : 0;
     R.l[e] = info & 255;
     R.m[e] = (info >> 8) & 255;
     R.par[e] = info >> 16;
-    R.lmc[e] = ok ? t.lm[j][ee][0] : LL;
-    R.lms[e] = ok ? t.lm[j][ee][1] : LL;
+    const int lc = ok ? T->rec_lm[jj][slot][0] : -1, ls = ok ? T->rec_lm[jj][slot][1] : -1;
+    R.lmc[e] = lc < 0 ? LL : lc;
+    R.lms[e] = ls < 0 ? LL : ls;
 #pragma unroll
-    for (int x = 0; x < NC; ++x) R.cf[e][x] = ok ? t.cf[j][ee][x] : 0.0;
+    for (int x = 0; x < NC; ++x) R.cf[e][x] = ok ? T->rec_coef[jj][slot][x] : 0.0;
   }
 }
 
-// STAGED: the block first collects its rows in LDS (stride PRS, odd, so the
-// per-thread writes do not collide) and then writes them out as 16-byte pieces
-// of consecutive rows, so each store covers a few whole rows instead of 64
-// scattered pieces.
-template <int NMAX, int LMAX>
-constexpr int prep_stride() {
-  using S = Shape<NMAX, LMAX>;
-  return (S::FR > S::XR ? S::FR : S::XR) | 1;
-}
-
-template <int NMAX, int LMAX, bool DERIV, bool STAGED>
+template <int NMAX, int LMAX, bool DERIV>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
                                                      const int* __restrict__ count, const double* __restrict__ dx,
                                                      const double* __restrict__ dy, const double* __restrict__ dz,
                                                      double* __restrict__ rows, double* __restrict__ bc) {
   using S = Shape<NMAX, LMAX>;
-  constexpr int PRS = prep_stride<NMAX, LMAX>();
   __shared__ PairTab<NMAX, LMAX> tab;
-  extern __shared__ double prow[];  // STAGED: blockDim.x rows of PRS doubles
   // pairs 0..n_pairs: the bound, or the device-side count cut at the bound
   const int n_pairs = count ? min(bound, max(*count, 0)) : bound;
   if (blockIdx.x > 0 && (int)(blockIdx.x * blockDim.x) >= n_pairs) return;  // block 0 also writes bc
@@ -217,9 +138,8 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
     for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * tab.lw[0] * 0.28209479177387814;
   }
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!STAGED && p >= n_pairs) return;
-  const bool live = p < n_pairs;
-  const double x = live ? dx[p] : 1.0, y = live ? dy[p] : 0.0, z = live ? dz[p] : 0.0;
+  if (p >= n_pairs) return;
+  const double x = dx[p], y = dy[p], z = dz[p];
   const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
   double B[NMAX], dB[NMAX];
 #pragma unroll
@@ -235,202 +155,138 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   const double izz = 1.0 / zz;
   const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
   const double ux = x * ir, uy = y * ir, uz = z * ir;
-  // w_l e_l, l = 0..LMAX, followed by u_z; d(w_l e_l)/dr followed by u_x, u_y, 1/r
-  double we[LMAX + 2], wd[LMAX + 4];
+  // field f of this pair: one coalesced 512-byte segment per field for each 64 pairs
+  double* __restrict__ row = rows + (size_t)(p >> 6) * (S::ROW * 64) + (p & 63);
+  auto st = [&](int f, double v) { row[f * 64] = v; };
 #pragma unroll
-  for (int l = 0; l <= LMAX; ++l) {
-    we[l] = tab.lw[l] * e[l];
-    // d e_l / dz = e_{l+1} + (l/z - 1) e_l
-    if (DERIV) wd[l] = tab.lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr;
+  for (int k = 0; k < NMAX; ++k) st(S::FB + k, B[k]);
+#pragma unroll
+  for (int l = 0; l <= LMAX; ++l) st(S::FW + l, tab.lw[l] * e[l]);
+  st(S::FU, uz);
+  double cr = 1.0, ci = 0.0;
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) {
+    st(S::FZ + 2 * m, cr);
+    st(S::FZ + 2 * m + 1, ci);
+    const double nr = cr * ux - ci * uy;
+    ci = cr * uy + ci * ux;
+    cr = nr;
   }
-  we[LMAX + 1] = uz;
-  wd[LMAX + 1] = ux;
-  wd[LMAX + 2] = uy;
-  wd[LMAX + 3] = ir;
-  if constexpr (!STAGED) {
-    // the pair's row written directly as 16-byte pairs of adjacent fields
-    double* __restrict__ row = rows + (size_t)p * S::ROW;
-    auto st2 = [&](int f, double a, double b) { *reinterpret_cast<double2*>(row + f) = double2{a, b}; };
+  if (DERIV) {
 #pragma unroll
-    for (int k = 0; k < NMAX; k += 2) {
-      st2(S::FB + k, B[k], B[k + 1]);
-      if (DERIV) st2(S::FR + S::XD + k, dB[k], dB[k + 1]);
-    }
+    for (int k = 0; k < NMAX; ++k) st(S::FR + S::XD + k, dB[k]);
+    // d e_l / dz = e_{l+1} + (l/z - 1) e_l
 #pragma unroll
-    for (int l = 0; l < LMAX + 2; l += 2) st2(S::FW + l, we[l], we[l + 1]);
-    if (DERIV) {
-#pragma unroll
-      for (int l = 0; l < LMAX + 4; l += 2) st2(S::FR + S::XW + l, wd[l], wd[l + 1]);
-    }
-    double cr = 1.0, ci = 0.0;
-#pragma unroll
-    for (int m = 0; m <= LMAX; ++m) {
-      st2(S::FZ + 2 * m, cr, ci);
-      const double nr = cr * ux - ci * uy;
-      ci = cr * uy + ci * ux;
-      cr = nr;
-    }
-  } else {
-    const int tid = threadIdx.x, nb = blockDim.x;
-    const long long p0 = (long long)blockIdx.x * nb;
-    const int nvalid = (int)min((long long)nb, (long long)n_pairs - p0);
-    double* my = prow + tid * PRS;
-    // forward part
-    double cr = 1.0, ci = 0.0;
-#pragma unroll
-    for (int m = 0; m <= LMAX; ++m) {
-      my[S::FZ + 2 * m] = cr;
-      my[S::FZ + 2 * m + 1] = ci;
-      const double nr = cr * ux - ci * uy;
-      ci = cr * uy + ci * ux;
-      cr = nr;
-    }
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k) my[S::FB + k] = B[k];
-#pragma unroll
-    for (int l = 0; l < LMAX + 2; ++l) my[S::FW + l] = we[l];
-    __syncthreads();
-    constexpr int UF = S::FR / 2;
-    for (int u = tid; u < nvalid * UF; u += nb) {
-      const int t = u / UF, part = u - t * UF;
-      const double* src = prow + t * PRS + 2 * part;
-      *reinterpret_cast<double2*>(rows + (size_t)(p0 + t) * S::ROW + 2 * part) = double2{src[0], src[1]};
-    }
-    if (DERIV) {
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < NMAX; ++k) my[S::XD + k] = dB[k];
-#pragma unroll
-      for (int l = 0; l < LMAX + 4; ++l) my[S::XW + l] = wd[l];
-      __syncthreads();
-      constexpr int UX = S::XR / 2;
-      for (int u = tid; u < nvalid * UX; u += nb) {
-        const int t = u / UX, part = u - t * UX;
-        const double* src = prow + t * PRS + 2 * part;
-        *reinterpret_cast<double2*>(rows + (size_t)(p0 + t) * S::ROW + S::FR + 2 * part) = double2{src[0], src[1]};
-      }
-    }
+    for (int l = 0; l <= LMAX; ++l)
+      st(S::FR + S::XW + l, tab.lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr);
+    st(S::FR + S::XU, ux);
+    st(S::FR + S::XU + 1, uy);
+    st(S::FR + S::XU + 2, ir);
   }
 }
 
-// copy the rows (WIDTH doubles from the start of each pair-major row of ROW
-// doubles) of the compacted pairs into LDS rows of dst_stride doubles, 16 bytes
-// per lane and load
-template <int WIDTH, int ROW>
-__device__ inline void stage_rows(const double* __restrict__ rows, const int* idx, int cnt, double* __restrict__ dst,
-                                  int dst_stride, int lane) {
-  constexpr int UNITS = WIDTH / 2;
-  for (int u = lane; u < cnt * UNITS; u += 64) {
-    const int t = u / UNITS, part = u - t * UNITS;
-    const double2 v = *reinterpret_cast<const double2*>(rows + (size_t)idx[t] * ROW + 2 * part);
-    *reinterpret_cast<double2*>(dst + t * dst_stride + 2 * part) = v;
+// fields 0..WIDTH-1 of the compacted pairs idx[0..cnt) copied into LDS rows,
+// dst[t * STRIDE + f]; for consecutive pairs each field is one or two
+// contiguous runs in HBM
+template <int WIDTH, int ROW, int CH, int STRIDE>
+__device__ inline void stage_fields(const double* __restrict__ rows, const int* idx, int cnt,
+                                    double* __restrict__ dst, int lane) {
+  for (int u = lane; u < WIDTH * CH; u += 64) {
+    const int f = u / CH, t = u % CH;
+    if (t < cnt) {
+      const int p = idx[t];
+      dst[t * STRIDE + f] = rows[(size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63)];
+    }
   }
 }
 
 template <int NMAX, int LMAX>
-__global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_descriptor(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                     const int* __restrict__ offsets, int bound,
-                                                     const int* __restrict__ nj,
-                                                     const int* __restrict__ species, const double* __restrict__ rows,
-                                                     const double* __restrict__ bc_in,
-                                                     double* __restrict__ c_out,
-                                                     double* __restrict__ q_out, int q_pitch,
-                                                     double* __restrict__ pnorm_out) {
+__global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams P, const DevTables* __restrict__ T,
+                                                                     int n_atoms, const int* __restrict__ offsets,
+                                                                     int bound, const int* __restrict__ nj,
+                                                                     const int* __restrict__ species,
+                                                                     const double* __restrict__ rows,
+                                                                     const double* __restrict__ bc_in,
+                                                                     double* __restrict__ c_out,
+                                                                     double* __restrict__ q_out, int q_pitch,
+                                                                     double* __restrict__ pnorm_out) {
   using S = Shape<NMAX, LMAX>;
-  constexpr int E = S::E, EP = S::EP, NC = S::NC, LFR = S::LFR;
+  constexpr int E2 = S::E2, NC = S::NC, CH = S::CH, FRP = S::FRP;
   extern __shared__ __align__(16) double dyn[];
-  __shared__ int idx[64];
-  __shared__ double bc[NMAX];
-  __shared__ RecTab<E, NC> rec;
+  __shared__ int idx[CH];
 
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
-  const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+  const int lane = threadIdx.x;
   const int n = P.n, LL = P.LL, LLP = LL + 1, nch = P.nch;
   const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
   const int si = P.ns == 1 ? 0 : species[i];
   double* __restrict__ ci_out = c_out + (size_t)i * P.ns * NMAX * LLP;
-  stage_records<E, NC>(T, rec, LL, lane);
-  if (lane < NMAX) bc[lane] = bc_in[lane];
+  LaneRecords<E2, NC> R;
+  lane_records<E2, NC>(T, lane, S::NREC, LL, R);
 
   for (int s = 0; s < P.ns; ++s) {
-    int w0 = p0;
-    bool first = true;
-    do {
+    double acc[E2][2][NMAX];
+#pragma unroll
+    for (int e = 0; e < E2; ++e)
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) acc[e][0][k] = acc[e][1][k] = 0.0;
+    for (int w0 = p0; w0 < p1; w0 += CH) {
       const int pp = w0 + lane;
-      const bool take = pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
+      const bool take = lane < CH && pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
       const unsigned long long mask = __ballot(take);
       __syncthreads();  // the previous chunk is done with idx and the rows
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      stage_rows<S::FR, S::ROW>(rows, idx, cnt, dyn, LFR, lane);
+      stage_fields<S::FR, S::ROW, CH, FRP>(rows, idx, cnt, dyn, lane);
       __syncthreads();
-#pragma unroll 1
-      for (int pass = 0; pass < S::NPASS; ++pass) {
-        Records<EP, NC> R;
-        load_records<E, EP, NC>(rec, j, pass * EP, LL, R);
-        double acc[EP][2][NMAX];
+#pragma unroll 2
+      for (int t = 0; t < cnt; ++t) {
+        const double* __restrict__ rt = dyn + t * FRP;
+        auto row = [&](int f) { return rt[f]; };
+        double b[NMAX];
 #pragma unroll
-        for (int e = 0; e < EP; ++e)
-#pragma unroll
-          for (int k = 0; k < NMAX; ++k) acc[e][0][k] = acc[e][1][k] = 0.0;
-        for (int t = g; t < cnt; t += 4) {
-          const double* __restrict__ row = dyn + t * LFR;
-          double b[NMAX];
-#pragma unroll
-          for (int k = 0; k < NMAX; ++k) b[k] = row[S::FB + k];
-          const double uz = row[S::FU], x2 = uz * uz;
-#pragma unroll
-          for (int e = 0; e < EP; ++e) {
-            double Rv = R.cf[e][NC - 1];
-#pragma unroll
-            for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, R.cf[e][t2]);
-            const double Q = R.par[e] ? uz * Rv : Rv;
-            const double a = row[S::FW + R.l[e]] * Q;
-            const double a0 = a * row[S::FZ + 2 * R.m[e]], a1 = a * row[S::FZ + 2 * R.m[e] + 1];
-#pragma unroll
-            for (int k = 0; k < NMAX; ++k) {
-              acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
-              acc[e][1][k] = fma(a1, b[k], acc[e][1][k]);
-            }
-          }
+        for (int k = 0; k < NMAX; k += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(rt + S::FB + k);
+          b[k] = v.x;
+          b[k + 1] = v.y;
         }
-        // add the four groups' partial sums; group 0 writes (first chunk) or adds
+        const double uz = row(S::FU), x2 = uz * uz;
 #pragma unroll
-        for (int e = 0; e < EP; ++e)
+        for (int e = 0; e < E2; ++e) {
+          double Rv = R.cf[e][NC - 1];
+#pragma unroll
+          for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, R.cf[e][t2]);
+          const double Q = R.par[e] ? uz * Rv : Rv;
+          const double a = row(S::FW + R.l[e]) * Q;
+          const double a0 = a * row(S::FZ + 2 * R.m[e]), a1 = a * row(S::FZ + 2 * R.m[e] + 1);
 #pragma unroll
           for (int k = 0; k < NMAX; ++k) {
-            acc[e][0][k] = sum_rows(acc[e][0][k]);
-            acc[e][1][k] = sum_rows(acc[e][1][k]);
-          }
-        // c of species s: LL + 1 columns lm (the last one a sink) of NMAX channels
-        double* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
-        if (g == 0) {
-#pragma unroll
-          for (int e = 0; e < EP; ++e) {
-            double* __restrict__ dc = cs + R.lmc[e] * NMAX;
-            double* __restrict__ ds = cs + R.lms[e] * NMAX;
-            if (first) {
-              const bool central = R.lmc[e] == 0 && s == si;
-#pragma unroll
-              for (int k = 0; k < NMAX; ++k) {
-                dc[k] = acc[e][0][k] + (central ? bc[k] : 0.0);
-                ds[k] = acc[e][1][k];
-              }
-            } else {
-#pragma unroll
-              for (int k = 0; k < NMAX; ++k) {
-                dc[k] += acc[e][0][k];
-                ds[k] += acc[e][1][k];
-              }
-            }
+            acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
+            acc[e][1][k] = fma(a1, b[k], acc[e][1][k]);
           }
         }
       }
-      first = false;
-      w0 += 64;
-    } while (w0 < p1);
+    }
+    // c of species s: LL + 1 columns lm (the last one a sink, left zero) of NMAX channels
+    double* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
+#pragma unroll
+    for (int e = 0; e < E2; ++e) {
+      if (lane + 64 * e >= S::NREC || R.lmc[e] == LL) continue;
+      const bool central = R.lmc[e] == 0 && s == si;
+      double* __restrict__ dc = cs + R.lmc[e] * NMAX;
+#pragma unroll
+      for (int k = 0; k < NMAX; k += 2)
+        *reinterpret_cast<double2*>(dc + k) = double2{acc[e][0][k] + (central ? bc_in[k] : 0.0),
+                                                      acc[e][0][k + 1] + (central ? bc_in[k + 1] : 0.0)};
+      if (R.lms[e] != LL) {
+        double* __restrict__ ds = cs + R.lms[e] * NMAX;
+#pragma unroll
+        for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(ds + k) = double2{acc[e][1][k], acc[e][1][k + 1]};
+      }
+    }
+    if (lane < NMAX) cs[LL * NMAX + lane] = 0.0;
   }
   __threadfence_block();
   __syncthreads();
@@ -553,133 +409,144 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
   }
 }
 
+// LDS of the adjoint: the atom's cbar for every species ([species][lm][k]), then
+// the record coefficients [r][NC] and (parity, cos column, sin column) [r][4]
 template <int NMAX, int LMAX>
-__global__ __launch_bounds__(64, NMAX <= 8 ? 2 : 1) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T, int n_atoms,
-                                                       const int* __restrict__ offsets, int bound,
-                                                       const int* __restrict__ nj,
-                                                       const int* __restrict__ species,
-                                                       const double* __restrict__ rows,
-                                                       const double* __restrict__ cbar, double* __restrict__ gx,
-                                                       double* __restrict__ gy, double* __restrict__ gz) {
+struct AdjLds {
+  static constexpr int NC = Shape<NMAX, LMAX>::NC;
+  static size_t cb_doubles(const DevParams& P) { return (size_t)P.ns * (P.LL + 1) * NMAX; }
+  static size_t bytes(const DevParams& P) {
+    const size_t nrec = (size_t)(P.l + 1) * (P.l + 2) / 2;
+    return sizeof(double) * (cb_doubles(P) + nrec * NC) + sizeof(int) * 4 * nrec;
+  }
+};
+
+// the pair's contraction with the cbar of one species over every record (l, m),
+// l outer and m inner: S_r, S_x, S_y, S_z of the gradient
+template <int NMAX, int LMAX, typename FieldFn>
+__device__ inline void adjoint_records(int L, const double* __restrict__ cb, const double* __restrict__ rc,
+                                       const int* __restrict__ ri, FieldFn F, const double (&b)[NMAX],
+                                       const double (&db)[NMAX], double uz, double& sr, double& sx, double& sy,
+                                       double& sz) {
   using S = Shape<NMAX, LMAX>;
-  constexpr int E = S::E, EP = S::EP, NC = S::NC, LAR = S::LAR, ACH = S::ACH;
-  constexpr int XB = S::FR;  // derivative part of a staged row
+  constexpr int NC = S::NC;
+  const double x2 = uz * uz;
+  for (int l = 0; l <= L; ++l) {
+    const double we = F(S::FW + l), wd = F(S::FR + S::XW + l);
+#pragma unroll 2
+    for (int m = 0; m <= l; ++m) {
+      // the record of (l, m) in the tables: m outer, l = m..L inner
+      const int r = m * (L + 1) - m * (m - 1) / 2 + (l - m);
+      const double* __restrict__ cf = rc + r * NC;
+      const int par = ri[4 * r], lc = ri[4 * r + 1], ls = ri[4 * r + 2];
+      // Qbar_lm and its derivative: Q = x^par R(x^2)
+      double Rv = cf[NC - 1], Rd = 0.0;
+#pragma unroll
+      for (int t2 = NC - 2; t2 >= 0; --t2) {
+        Rd = fma(Rd, x2, Rv);
+        Rv = fma(Rv, x2, cf[t2]);
+      }
+      const double Q = par ? uz * Rv : Rv;
+      const double Qd = par ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
+      const int m1 = m > 0 ? m - 1 : 0;
+      const double zr = F(S::FZ + 2 * m), zi = F(S::FZ + 2 * m + 1);
+      const double zr1 = F(S::FZ + 2 * m1), zi1 = F(S::FZ + 2 * m1 + 1);
+      // the sin column of m = 0 is the sink column, which holds zeros
+      const double* __restrict__ c0 = cb + lc * NMAX;
+      const double* __restrict__ c1 = cb + ls * NMAX;
+      double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) {
+        U0 = fma(c0[k], db[k], U0);
+        V0 = fma(c0[k], b[k], V0);
+        U1 = fma(c1[k], db[k], U1);
+        V1 = fma(c1[k], b[k], V1);
+      }
+      const double fm = (double)m;
+      sr = fma(Q, fma(fma(U0, we, V0 * wd), zr, fma(U1, we, V1 * wd) * zi), sr);
+      const double W0 = V0 * we, W1 = V1 * we;
+      const double qm = Q * fm;
+      sx = fma(qm, fma(W0, zr1, W1 * zi1), sx);
+      sy = fma(qm, fma(W1, zr1, -W0 * zi1), sy);
+      sz = fma(Qd, fma(W0, zr, W1 * zi), sz);
+    }
+  }
+}
+
+// One wave per centre atom, one lane per pair (64 pairs per round): each lane
+// reads its pair's fields (coalesced across the lanes), contracts them with the
+// cbar of the neighbour's species over all records and writes the pair
+// gradient g = dE/dd, summed in the lane's registers.  The atom's cbar and the
+// record table are staged in LDS once and read as broadcasts.
+template <int NMAX, int LMAX>
+__global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
+                                                                       int n_atoms, const int* __restrict__ offsets,
+                                                                       int bound, const int* __restrict__ nj,
+                                                                       const int* __restrict__ species,
+                                                                       const double* __restrict__ rows,
+                                                                       const double* __restrict__ cbar,
+                                                                       double* __restrict__ gx,
+                                                                       double* __restrict__ gy,
+                                                                       double* __restrict__ gz) {
+  using S = Shape<NMAX, LMAX>;
+  constexpr int NC = S::NC;
   extern __shared__ __align__(16) double dyn[];
-  __shared__ int idx[64];
-  __shared__ RecTab<E, NC> rec;
   const int i = blockIdx.x;
   if (i >= n_atoms) return;
-  const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
-  const int LL = P.LL, LLP = LL + 1;
+  const int lane = threadIdx.x;
+  const int LLP = P.LL + 1, L = P.l, nrec = (L + 1) * (L + 2) / 2;
   const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
-  double* gacc = dyn + ACH * LAR;  // per-neighbour (S_r, S_x, S_y, S_z)
-  stage_records<E, NC>(T, rec, LL, lane);
-
-  if (P.ns > 1)  // a neighbour label outside 0..n_species-1 contributes nothing
-    for (int p = p0 + lane; p < p1; p += 64) {
-      const int sj = species[nj[p]];
-      if (sj < 0 || sj >= P.ns) gx[p] = gy[p] = gz[p] = 0.0;
+  if (p0 >= p1) return;
+  const int ncb = P.ns * LLP * NMAX;
+  double* cb = dyn;
+  double* rc = dyn + ncb;
+  int* ri = reinterpret_cast<int*>(rc + nrec * NC);
+  {
+    const double2* src = reinterpret_cast<const double2*>(cbar + (size_t)i * ncb);
+    for (int u = lane; u < ncb / 2; u += 64) reinterpret_cast<double2*>(cb)[u] = src[u];
+    for (int u = lane; u < nrec * NC; u += 64) {
+      const int r = u / NC, t = u - r * NC;
+      rc[u] = T->rec_coef[r % kRecLanes][r / kRecLanes][t];
     }
-
-  for (int s = 0; s < P.ns; ++s) {
-    const double* __restrict__ cbs = cbar + ((size_t)i * P.ns + s) * LLP * NMAX;
-    for (int w0 = p0; w0 < p1; w0 += ACH) {
-      const int pp = w0 + lane;
-      const bool take = lane < ACH && pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
-      const unsigned long long mask = __ballot(take);
-      __syncthreads();
-      if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
-      const int cnt = __popcll(mask);
-      __syncthreads();
-      if (cnt == 0) continue;
-      stage_rows<S::ROW, S::ROW>(rows, idx, cnt, dyn, LAR, lane);
-      __syncthreads();
-#pragma unroll 1
-      for (int pass = 0; pass < S::NPASS; ++pass) {
-        Records<EP, NC> R;
-        load_records<E, EP, NC>(rec, j, pass * EP, LL, R);
-        double cb[EP][2][NMAX];  // zero in the sink column and the channels k >= n_max
+    for (int r = lane; r < nrec; r += 64) {
+      const int jj = r % kRecLanes, slot = r / kRecLanes;
+      const int ls = T->rec_lm[jj][slot][1];
+      ri[4 * r] = T->rec_lmp[jj][slot] >> 16;
+      ri[4 * r + 1] = T->rec_lm[jj][slot][0];
+      ri[4 * r + 2] = ls < 0 ? P.LL : ls;
+    }
+  }
+  __syncthreads();
+  for (int pb = p0; pb < p1; pb += 64) {
+    const int p = pb + lane;
+    const bool live = p < p1;
+    const int pq = live ? p : p0;  // idle lanes read a valid row
+    const double* __restrict__ row = rows + (size_t)(pq >> 6) * (S::ROW * 64) + (pq & 63);
+    auto F = [&](int f) { return row[f * 64]; };
+    double b[NMAX], db[NMAX];
 #pragma unroll
-        for (int e = 0; e < EP; ++e)
-#pragma unroll
-          for (int k = 0; k < NMAX; ++k) {
-            cb[e][0][k] = cbs[R.lmc[e] * NMAX + k];
-            cb[e][1][k] = cbs[R.lms[e] * NMAX + k];
-          }
-        for (int t = g; t < cnt; t += 4) {
-          const double* __restrict__ row = dyn + t * LAR;
-          double b[NMAX], db[NMAX];
-#pragma unroll
-          for (int k = 0; k < NMAX; ++k) {
-            b[k] = row[S::FB + k];
-            db[k] = row[XB + S::XD + k];
-          }
-          const double uz = row[S::FU], x2 = uz * uz;
-          double sr = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-          for (int e = 0; e < EP; ++e) {
-            // Qbar_lm and its derivative: Q = x^par R(x^2)
-            double Rv = R.cf[e][NC - 1], Rd = 0.0;
-#pragma unroll
-            for (int t2 = NC - 2; t2 >= 0; --t2) {
-              Rd = fma(Rd, x2, Rv);
-              Rv = fma(Rv, x2, R.cf[e][t2]);
-            }
-            const double Q = R.par[e] ? uz * Rv : Rv;
-            const double Qd = R.par[e] ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
-            const int l = R.l[e], m = R.m[e], m1 = m > 0 ? m - 1 : 0;
-            const double we = row[S::FW + l], wd = row[XB + S::XW + l];
-            const double zr = row[S::FZ + 2 * m], zi = row[S::FZ + 2 * m + 1];
-            const double zr1 = row[S::FZ + 2 * m1], zi1 = row[S::FZ + 2 * m1 + 1];
-            double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
-#pragma unroll
-            for (int k = 0; k < NMAX; ++k) {
-              U0 = fma(cb[e][0][k], db[k], U0);
-              V0 = fma(cb[e][0][k], b[k], V0);
-              U1 = fma(cb[e][1][k], db[k], U1);
-              V1 = fma(cb[e][1][k], b[k], V1);
-            }
-            const double fm = (double)m;
-            sr = fma(Q, fma(fma(U0, we, V0 * wd), zr, fma(U1, we, V1 * wd) * zi), sr);
-            const double W0 = V0 * we, W1 = V1 * we;
-            const double qm = Q * fm;
-            sx = fma(qm, fma(W0, zr1, W1 * zi1), sx);
-            sy = fma(qm, fma(W1, zr1, -W0 * zi1), sy);
-            sz = fma(Qd, fma(W0, zr, W1 * zi), sz);
-          }
-          sr = row_sum(sr);
-          sx = row_sum(sx);
-          sy = row_sum(sy);
-          sz = row_sum(sz);
-          if (j == 0) {
-            double* ga = gacc + 4 * t;
-            if (pass == 0) {
-              ga[0] = sr;
-              ga[1] = sx;
-              ga[2] = sy;
-              ga[3] = sz;
-            } else {
-              ga[0] += sr;
-              ga[1] += sx;
-              ga[2] += sy;
-              ga[3] += sz;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      if (lane < cnt) {
-        const double* row = dyn + lane * LAR;
-        const double ux = row[XB + S::XU], uy = row[XB + S::XU + 1], uz = row[S::FU], ir = row[XB + S::XU + 2];
-        const double* ga = gacc + 4 * lane;
-        const double sr = ga[0], sx = ga[1], sy = ga[2], sz = ga[3];
-        // d u / d d = (I - u u^T) / r
-        const double ut = ux * sx + uy * sy + uz * sz;
-        const int p = idx[lane];
-        gx[p] = sr * ux + (sx - ux * ut) * ir;
-        gy[p] = sr * uy + (sy - uy * ut) * ir;
-        gz[p] = sr * uz + (sz - uz * ut) * ir;
-      }
+    for (int k = 0; k < NMAX; ++k) {
+      b[k] = F(S::FB + k);
+      db[k] = F(S::FR + S::XD + k);
+    }
+    const double uz = F(S::FU);
+    double sr = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    bool on = live;
+    int sj = 0;
+    if (P.ns > 1) {
+      // a neighbour label outside 0..n_species-1 contributes nothing
+      sj = species[nj[pq]];
+      on = on && sj >= 0 && sj < P.ns;
+      sj = on ? sj : 0;
+    }
+    adjoint_records<NMAX, LMAX>(L, cb + (size_t)sj * LLP * NMAX, rc, ri, F, b, db, uz, sr, sx, sy, sz);
+    if (live) {
+      const double ux = F(S::FR + S::XU), uy = F(S::FR + S::XU + 1), ir = F(S::FR + S::XU + 2);
+      // d u / d d = (I - u u^T) / r
+      const double ut = ux * sx + uy * sy + uz * sz;
+      gx[p] = on ? sr * ux + (sx - ux * ut) * ir : 0.0;
+      gy[p] = on ? sr * uy + (sy - uy * ut) * ir : 0.0;
+      gz[p] = on ? sr * uz + (sz - uz * ut) * ir : 0.0;
     }
   }
 }
@@ -757,21 +624,12 @@ size_t dispatch_size(int n, int l, F&& f) {
 size_t fwd_dyn_bytes(const DevParams& P) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
     using S = Shape<N, LM>;
-    const size_t rows = (size_t)S::CH * S::LFR, epi = (size_t)P.ns * N * (P.LL + 1) + P.K;
+    const size_t rows = (size_t)S::CH * S::FRP, epi = (size_t)P.ns * N * (P.LL + 1) + P.K;
     return sizeof(double) * (rows > epi ? rows : epi);
   });
 }
 size_t adj_dyn_bytes(const DevParams& P) {
-  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
-    using S = Shape<N, LM>;
-    return sizeof(double) * ((size_t)S::ACH * S::LAR + 4 * S::ACH);
-  });
-}
-size_t rec_bytes(const DevParams& P) {
-  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
-    using S = Shape<N, LM>;
-    return sizeof(RecTab<S::E, S::NC>);
-  });
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return AdjLds<N, LM>::bytes(P); });
 }
 size_t cbar_dyn_bytes(const DevParams& P) {
   const size_t m = (size_t)(P.l + 1) * P.nch * P.nch;
@@ -786,36 +644,32 @@ size_t c_doubles_per_atom(const DevParams& P) {
 size_t pair_row_doubles(const DevParams& P) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return (size_t)Shape<N, LM>::ROW; });
 }
+size_t pair_rows_bytes(const DevParams& P, long long n_pairs) {
+  const size_t blocks = (size_t)((n_pairs + 63) / 64);
+  return sizeof(double) * (blocks > 0 ? blocks : 1) * 64 * pair_row_doubles(P);
+}
 
 size_t descriptor_lds_bytes(const DevParams& P) {
-  return fwd_dyn_bytes(P) + rec_bytes(P) + 64 * sizeof(int) + kMaxN * sizeof(double);
+  return fwd_dyn_bytes(P) + 64 * sizeof(int);
 }
 size_t adjoint_lds_bytes(const DevParams& P) {
-  const size_t a = adj_dyn_bytes(P) + rec_bytes(P) + 64 * sizeof(int), b = cbar_dyn_bytes(P);
+  const size_t a = adj_dyn_bytes(P), b = cbar_dyn_bytes(P);
   return a > b ? a : b;
 }
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
-                            int block, bool staged, hipStream_t st) {
+                            int block, hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
-  if (staged && block > 128) block = 128;  // the staging buffer stays under 64 KB
   const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
   auto f = [&]<int N, int LM>() {
-    const size_t lds = staged ? sizeof(double) * (size_t)block * prep_stride<N, LM>() : 0;
     const int np = (int)n_pairs;
-    if (deriv && staged)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true>), dim3(blocks), dim3(block), lds, st, P, T, np, count, dx, dy,
-                         dz, rows, bc);
-    else if (deriv)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
-                         dz, rows, bc);
-    else if (staged)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true>), dim3(blocks), dim3(block), lds, st, P, T, np, count, dx,
-                         dy, dz, rows, bc);
+    if (deriv)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy, dz,
+                         rows, bc);
     else
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx,
-                         dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy, dz,
+                         rows, bc);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);

@@ -206,8 +206,8 @@ class Soap:
     def tuning(self) -> dict:
         return _lib.soap_get_tuning(self.ctx).as_dict()
 
-    def set_tuning(self, gap_fused: int = 0, gap_slices: int = 0, prep_block: int = 256, prep_staged: int = 0) -> None:
-        _lib.soap_set_tuning(self.ctx, _lib.soap_tuning(gap_fused, gap_slices, prep_block, prep_staged))
+    def set_tuning(self, gap_fused: int = 0, gap_slices: int = 0, prep_block: int = 256, cell_split: int = 2) -> None:
+        _lib.soap_set_tuning(self.ctx, _lib.soap_tuning(gap_fused, gap_slices, prep_block, cell_split))
 
     def autotune(self, nl: NeighbourList, species: torch.Tensor, q_sparse: torch.Tensor, alpha: torch.Tensor,
                  zeta: int, repeats: int = 3) -> dict:

@@ -1,9 +1,7 @@
 """Launch-shape tuning: every setting meets the bounds of its precision against
-the oracle; in FP64, settings that share the same kernels (they differ only in
-block size) agree bit for bit and the others agree to rounding (the staged and
-direct per-pair kernels are compiled separately and may contract operations
-differently); a repeated call with the same setting is bitwise identical; and
-the autotuner installs the setting it returns."""
+the oracle; in FP64, settings that differ only in block size agree bit for bit
+and the others (GAP order) to rounding; a repeated call with the same setting is
+bitwise identical; and the autotuner installs the setting it returns."""
 import numpy as np
 import pytest
 
@@ -16,10 +14,10 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 KW = dict(n_max=8, l_max=6, r_cut=4.5, sigma0_r=0.5, sigma0_perp=0.5)
 BOUNDS = {"fp64": 1e-10, "bf16": 5e-2}
-SETTINGS = [dict(gap_fused=0, gap_slices=0, prep_block=256, prep_staged=0),
-            dict(gap_fused=0, gap_slices=0, prep_block=64, prep_staged=1),
-            dict(gap_fused=1, gap_slices=256, prep_block=128, prep_staged=1),
-            dict(gap_fused=1, gap_slices=2048, prep_block=256, prep_staged=0)]
+SETTINGS = [dict(gap_fused=0, gap_slices=0, prep_block=256, cell_split=2),
+            dict(gap_fused=0, gap_slices=0, prep_block=64, cell_split=2),
+            dict(gap_fused=1, gap_slices=256, prep_block=128, cell_split=2),
+            dict(gap_fused=1, gap_slices=2048, prep_block=256, cell_split=2)]
 
 
 @pytest.fixture(scope="module")
@@ -58,9 +56,9 @@ def test_every_setting_within_bounds(case, prec):
         outs.append((e, F, ab))
     if prec == "fp64":
         for t, o in zip(SETTINGS[1:], outs[1:]):
-            same_kernels = t["prep_staged"] == SETTINGS[0]["prep_staged"]
+            same_order = t["gap_fused"] == SETTINGS[0]["gap_fused"]
             for x, y in zip(o, outs[0]):
-                if same_kernels:
+                if same_order:
                     assert np.array_equal(x, y), t
                 else:
                     assert np.abs(x - y).max() <= 1e-13 * np.abs(y).max(), t
@@ -77,6 +75,8 @@ def test_invalid_setting_rejected():
         soap.set_tuning(prep_block=100)
     with pytest.raises(_lib.SoapError):
         soap.set_tuning(gap_fused=2)
+    with pytest.raises(_lib.SoapError):
+        soap.set_tuning(cell_split=4)
 
 
 def test_autotune_installs_its_choice(case):
@@ -88,7 +88,46 @@ def test_autotune_installs_its_choice(case):
     chosen = soap.autotune(nl, _t(spec), _t(qs), _t(al), 3, repeats=2)
     print("autotune chose", chosen)
     assert soap.tuning == chosen
-    assert chosen["prep_block"] in (64, 128, 256) and chosen["gap_fused"] in (0, 1) and chosen["prep_staged"] in (0, 1)
+    assert chosen["prep_block"] in (64, 128, 256) and chosen["gap_fused"] in (0, 1)
+    assert chosen["cell_split"] == 2  # not searched: the autotuner times the GAP call on a built list
     e, F, _ = soap.energy_forces(nl, _t(spec), _t(qs), _t(al), 3)
     torch.cuda.synchronize()
     assert np.abs(F.cpu().numpy() - Fo).max() <= 5e-2 * np.abs(Fo).max()
+
+
+def test_cell_split_keeps_the_pair_set():
+    """Bins of r_cut, r_cut/2 and r_cut/3: the same pairs with bitwise-equal
+    vectors (only their order inside each atom's list changes), a consistent
+    reverse index, and energies and forces equal to rounding.  On this box the
+    coarse bins take the one-launch cell list and r_cut/3 bins (more than 8192)
+    the multi-launch one, so the two agree as well."""
+    from paper_1905_02142_amd import Soap, SoapParams
+
+    s = synth.rsa_box(3000, 40.0, 1.2, 1301)
+    spec = np.zeros(s.n_atoms, np.int32)
+    p = oracle.Params(**KW)
+    qs = synth.sparse_set(100, p.dim, 93)
+    al = synth.sparse_weights(100, 94)
+    soap = Soap(SoapParams(**KW))
+    pos = _t(s.positions)
+    ref = None
+    for split in (1, 2, 3):
+        soap.set_tuning(cell_split=split)
+        nl = soap.neighbors(pos, s.cell, s.pbc)
+        n = nl.n_pairs
+        c, j, img, rev = (getattr(nl, k)[:n].cpu().numpy() for k in ("center", "j", "img", "rev"))
+        d = np.stack([getattr(nl, k)[:n].cpu().numpy() for k in ("dx", "dy", "dz")], 1)
+        off = nl.offsets.cpu().numpy()
+        assert np.array_equal(c, np.repeat(np.arange(s.n_atoms), np.diff(off)))
+        assert np.array_equal(rev[rev], np.arange(n)) and np.array_equal(c[rev], j)
+        assert np.array_equal(d[rev], -d)
+        order = np.lexsort((img, j, c))
+        e, F, ab = (t.cpu().numpy() for t in soap.energy_forces(nl, _t(spec), _t(qs), _t(al), 3))
+        cur = dict(off=off, j=j[order], img=img[order], d=d[order], e=e, F=F, ab=ab)
+        if ref is None:
+            ref = cur
+            continue
+        for k in ("off", "j", "img", "d"):
+            assert np.array_equal(cur[k], ref[k]), (split, k)
+        for k in ("e", "F", "ab"):
+            assert np.abs(cur[k] - ref[k]).max() <= 1e-13 * np.abs(ref[k]).max(), (split, k)
