@@ -15,12 +15,14 @@
 //   FP64    v_mfma_f64_16x16x4_f64, FP64 accumulation, 64 x 64 tiles
 //   F32     v_mfma_f32_16x16x4_f32, FP32 accumulation, 64 x 64 tiles
 //   BF16    v_mfma_f32_16x16x32_bf16, FP32 accumulation, 128 x 128 tiles
+//           (scores) and 64 x 64 tiles (Qbar), both with 128-wide K-tiles
 //   BF16X3  a = a_hi + a_lo in BF16, a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
 // Row / column sums of the epilogue go to per-tile partial arrays that are
 // added in a fixed order, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gap.h"
 
@@ -50,7 +52,7 @@ struct PF32 {
 struct PBF16 {
   using T = __bf16;
   using Acc = f4;
-  static constexpr int BM = 128, BN = 128, KT = 32;
+  static constexpr int BM = 128, BN = 128, KT = 128;
   static constexpr bool kSplit = false;
   static constexpr bool kRowsInterleaved = false;
 };
@@ -66,12 +68,17 @@ template <typename P>
 struct QbarTile : P {
   static constexpr int BM = 64, BN = 64;
 };
+// BF16 Qbar: the contraction runs over all sparse points (Mp ~ 2000), 128 per K-tile
+template <>
+struct QbarTile<PBF16> : PBF16 {
+  static constexpr int BM = 64, BN = 64, KT = 128;
+};
 template <>
 struct QbarTile<PF64> : PF64 {};
 template <>
 struct QbarTile<PF32> : PF32 {};
 
-constexpr int kPad = 64;  // contraction dims are padded to a multiple of this (>= every KT)
+constexpr int kPad = 128;  // contraction dims are padded to a multiple of this (>= every KT)
 
 inline int padded(int x) { return (x + kPad - 1) / kPad * kPad; }
 
@@ -206,27 +213,30 @@ __device__ inline void mma_ktile(const Smem<P>& sm, int wm, int wn, int lane,
         }
     }
   } else {
-    b8 a[TM], b[TN], al[TM], bl[TN];
 #pragma unroll
-    for (int x = 0; x < TM; ++x) {
-      a[x] = *(const b8*)&sm.a[(ra + x * 16 + r16) * PITCH + 8 * kq];
-      if constexpr (P::kSplit) al[x] = *(const b8*)&sm.a_lo[(ra + x * 16 + r16) * PITCH + 8 * kq];
-    }
+    for (int ks = 0; ks < P::KT; ks += 32) {
+      b8 a[TM], b[TN], al[TM], bl[TN];
 #pragma unroll
-    for (int y = 0; y < TN; ++y) {
-      b[y] = *(const b8*)&sm.b[(rb + y * 16 + r16) * PITCH + 8 * kq];
-      if constexpr (P::kSplit) bl[y] = *(const b8*)&sm.b_lo[(rb + y * 16 + r16) * PITCH + 8 * kq];
-    }
-#pragma unroll
-    for (int x = 0; x < TM; ++x)
+      for (int x = 0; x < TM; ++x) {
+        a[x] = *(const b8*)&sm.a[(ra + x * 16 + r16) * PITCH + ks + 8 * kq];
+        if constexpr (P::kSplit) al[x] = *(const b8*)&sm.a_lo[(ra + x * 16 + r16) * PITCH + ks + 8 * kq];
+      }
 #pragma unroll
       for (int y = 0; y < TN; ++y) {
-        if constexpr (P::kSplit) {
-          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], b[y], acc[x][y], 0, 0, 0);
-          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bl[y], acc[x][y], 0, 0, 0);
-        }
-        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+        b[y] = *(const b8*)&sm.b[(rb + y * 16 + r16) * PITCH + ks + 8 * kq];
+        if constexpr (P::kSplit) bl[y] = *(const b8*)&sm.b_lo[(rb + y * 16 + r16) * PITCH + ks + 8 * kq];
       }
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y) {
+          if constexpr (P::kSplit) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], b[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bl[y], acc[x][y], 0, 0, 0);
+          }
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+    }
   }
 }
 
@@ -291,7 +301,8 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
                                                 double* __restrict__ e_part, double* __restrict__ ab_part) {
   using T = typename P::T;
   constexpr int TM = Frag<P>::TM, TN = Frag<P>::TN;
-  __shared__ Smem<P> sm;
+  extern __shared__ __align__(16) char dsm[];  // the operand tiles, sizeof(Smem<P>)
+  Smem<P>& sm = *reinterpret_cast<Smem<P>*>(dsm);
   __shared__ double rowsum[2][P::BM];
   __shared__ double colsum[2][P::BN];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
@@ -302,31 +313,50 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
 #pragma unroll
     for (int y = 0; y < TN; ++y) acc[x][y] = typename P::Acc{};
   gemm_tile<P>(sm, Qc, Qc_lo, Kp, N, Qsc, Qsc_lo, Kp, Mp, Kp, i0, s0, acc);
+  // G goes through LDS (the operand tiles are no longer needed) and out as
+  // whole 16-byte row pieces; the BF16X3 low part takes a second pass
+  constexpr int EPV = 16 / sizeof(T), GP = P::BN + EPV, VPR = P::BN / EPV;
+  static_assert(sizeof(T) * P::BM * GP <= sizeof(Smem<P>), "G tile must fit in the operand LDS");
+  T* gt = reinterpret_cast<T*>(&sm);
   double rows[TM][4] = {}, cols[TN] = {};
 #pragma unroll
-  for (int x = 0; x < TM; ++x)
+  for (int pass = 0; pass < (P::kSplit ? 2 : 1); ++pass) {
 #pragma unroll
-    for (int y = 0; y < TN; ++y)
+    for (int x = 0; x < TM; ++x)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = i0 + wm * (P::BM / 2) + acc_row<P>(x, r, lane);
-        const int gs = s0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
-        if (gi < N && gs < Mp) {
+      for (int y = 0; y < TN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int lr = wm * (P::BM / 2) + acc_row<P>(x, r, lane);
+          const int lc = wn * (P::BN / 2) + y * 16 + (lane & 15);
+          const int gi = i0 + lr, gs = s0 + lc;
           double g = 0.0;
-          if (gs < M) {
-            const double sv = (double)acc[x][y][r];
-            const double sz1 = ipow(sv, zeta - 1);
-            const double kv = sz1 * sv;
-            const double al = alpha[gs];
-            g = (double)zeta * al * sz1;
-            rows[x][r] = fma(al, kv, rows[x][r]);
-            cols[y] += kv;
+          if (gi < N && gs < M) {
+            // 16-bit operands: the zeta power in FP32 (its rounding is far below
+            // that of the operands); otherwise in FP64
+            using E = typename std::conditional<sizeof(T) == 2, float, double>::type;
+            const E sv = (E)acc[x][y][r];
+            E sz1 = (E)1;
+            for (int t = 1; t < zeta; ++t) sz1 *= sv;
+            const E al = (E)alpha[gs];
+            g = (double)((E)zeta * al * sz1);
+            if (pass == 0) {
+              const double kv = (double)(sz1 * sv);
+              rows[x][r] = fma((double)al, kv, rows[x][r]);
+              cols[y] += kv;
+            }
           }
           const T gh = cvt<T>(g);
-          G[(size_t)gi * Mp + gs] = gh;
-          if constexpr (P::kSplit) G_lo[(size_t)gi * Mp + gs] = cvt_lo(g, gh);
+          gt[lr * GP + lc] = pass == 0 ? gh : cvt_lo_any<T>(g, gh);
         }
-      }
+    __syncthreads();
+    T* __restrict__ dst = pass == 0 ? G : G_lo;
+    for (int u = tid; u < P::BM * VPR; u += 256) {
+      const int lr = u / VPR, c = (u % VPR) * EPV, gi = i0 + lr;
+      if (gi < N) *(u4*)(dst + (size_t)gi * Mp + s0 + c) = *(const u4*)(gt + lr * GP + c);
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
@@ -820,8 +850,15 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
   hipLaunchKernelGGL((k_convert3<T, P::kSplit>), blocks((long long)N * Kp + 2LL * Mp * Kp), dim3(256), 0, st, N, M,
                      K, Kp, Mp, Q, Qs, qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
   const int nst = (Mp + P::BN - 1) / P::BN, nit = (N + P::BM - 1) / P::BM;
-  hipLaunchKernelGGL(k_scores<P>, dim3(nst, nit), dim3(256), 0, st, N, M, Mp, Kp, qc, qc_lo, qsc, qsc_lo, alpha, zeta,
-                     G, G_lo, e_part, ab_part);
+  static bool attr = false;  // operand tiles above 64 KB of LDS need the opt-in
+  if (!attr && sizeof(Smem<P>) > 65536) {
+    const hipError_t a = hipFuncSetAttribute((const void*)k_scores<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)sizeof(Smem<P>));
+    if (a != hipSuccess) return a;
+  }
+  attr = true;
+  hipLaunchKernelGGL(k_scores<P>, dim3(nst, nit), dim3(256), sizeof(Smem<P>), st, N, M, Mp, Kp, qc, qc_lo, qsc,
+                     qsc_lo, alpha, zeta, G, G_lo, e_part, ab_part);
   hipLaunchKernelGGL(k_sum_parts2, dim3((N + M + 255) / 256), dim3(256), 0, st, N, nst, e_part, e, M, nit, ab_part,
                      alpha_bar);
   return hipGetLastError();
