@@ -50,7 +50,7 @@ def workload_setup(name, precision, dev):
 
 # stages that are exactly one kernel (the roofline is quoted for one kernel)
 SINGLE_KERNEL = {"descriptor": "k_descriptor", "pair_adjoint": "k_pair_adjoint", "pair_prep": "k_pair_prep",
-                 "cbar": "k_cbar", "gap_qbar": "k_qbar", "force_gather": "k_force_gather"}
+                 "gap_qbar": "k_qbar", "force_gather": "k_force_gather"}
 
 
 def algorithmic_work(stage, N, P, M, K, n, l_max, nch):
@@ -71,11 +71,10 @@ def algorithmic_work(stage, N, P, M, K, n, l_max, nch):
     if stage == "descriptor":
         # c accumulation (n L^2 FMA per pair, Eq. (08)) + power spectrum (L^2 FMA per channel pair, Eq. (09))
         return 2.0 * P * n * L2 + 2.0 * N * nab * L2, "flop"
-    if stage == "cbar":
-        return 2.0 * N * nch * nch * L2, "flop"
     if stage == "pair_adjoint":
-        # U and V contractions (2 n L^2 FMA per pair) and the gradient terms (~5 FMA per slot)
-        return 2.0 * P * (2 * n * L2 + 5 * L2), "flop"
+        # cbar = M c per atom (n_ch^2 L^2 FMA), then per pair the U and V contractions
+        # (2 n L^2 FMA) and the gradient terms (~5 FMA per slot)
+        return 2.0 * N * nch * nch * L2 + 2.0 * P * (2 * n * L2 + 5 * L2), "flop"
     if stage == "force_gather":
         return P * (4 + 2 * 24) + N * 24 + (N + 1) * 4, "byte"
     if stage == "neighbors":

@@ -226,7 +226,7 @@ typedef enum {
   SOAP_STAGE_FORCE_GATHER = 5,  /* per-atom force sums */
   SOAP_STAGE_GAP_FUSED = 6,     /* S, the zeta epilogue and Qbar = G Q_s in one pass (16/32-bit modes) */
   SOAP_STAGE_PAIR_PREP = 7,     /* per-pair radial, ilexp and azimuthal factors (one kernel) */
-  SOAP_STAGE_CBAR = 8,          /* vbar and cbar = M c, the power-spectrum adjoint (one kernel) */
+  SOAP_STAGE_CBAR = 8,          /* reserved: vbar and cbar = M c are now formed inside pair_adjoint (no launches) */
   SOAP_STAGE_COUNT = 9
 } soap_stage;
 soap_status soap_profile(soap_ctx* ctx, int enable);

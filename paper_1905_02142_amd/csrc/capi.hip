@@ -48,7 +48,7 @@ struct soap_ctx {
   Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_atoms, counts, scan_part,
       errflag;
   // descriptor / adjoint
-  Buf rows, bc, c, cbar, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
+  Buf rows, bc, c, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
   // stage timing
   struct Rec {
     int stage;
@@ -291,7 +291,7 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
 void soap_destroy(soap_ctx* ctx) {
   if (!ctx) return;
   Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
-                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c, &ctx->cbar,
+                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c,
                  &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp, &ctx->tune_out};
   for (Buf* b : bufs)
     if (b->p) hipFree(b->p);
@@ -552,17 +552,12 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
   SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
   SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
-  SOAP_ENSURE(ctx, ctx->cbar, sizeof(double) * N * soap::c_doubles_per_atom(P));
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, true, st)) != SOAP_OK) return s;
   {
-    {
-      StageTimer tm(ctx, SOAP_STAGE_CBAR, st);
-      SOAP_HIP(ctx, soap::launch_cbar(P, nl->n_atoms, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
-                                      (const double*)ctx->pnorm.p, q_bar, P.K, (double*)ctx->cbar.p, st));
-    }
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                            (const double*)ctx->rows.p, (const double*)ctx->cbar.p,
+                                            (const double*)ctx->rows.p, (const double*)ctx->c.p,
+                                            (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, q_bar, P.K,
                                             (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
@@ -619,16 +614,11 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
     SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
-    SOAP_ENSURE(ctx, ctx->cbar, sizeof(double) * N * soap::c_doubles_per_atom(P));
     {
-      {
-        StageTimer tm(ctx, SOAP_STAGE_CBAR, st);
-        SOAP_HIP(ctx, soap::launch_cbar(P, nl->n_atoms, (const double*)ctx->c.p, (const double*)ctx->q.p, P.K,
-                                        (const double*)ctx->pnorm.p, qbar, P.K, (double*)ctx->cbar.p, st));
-      }
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                              (const double*)ctx->rows.p, (const double*)ctx->cbar.p,
+                                              (const double*)ctx->rows.p, (const double*)ctx->c.p,
+                                              (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qbar, P.K,
                                               (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);

@@ -22,7 +22,8 @@
 // (the real form of Eq. (09)), packed a <= b then l with sqrt(2) off the
 // diagonal, and q = p / |p| follow from c staged in LDS.
 //
-// Adjoint: k_cbar forms vbar = (qbar - q (q.qbar)) / |p| and cbar = M c
+// Adjoint: each wave of k_pair_adjoint first forms, for its atom, vbar =
+// (qbar - q (q.qbar)) / |p| and cbar = M c
 // (M_aa = 2 vbar_aal, M_ab = sqrt(2) vbar_abl), the derivative of the power
 // spectrum and of the normalisation.  k_pair_adjoint takes one pair per lane:
 // the lane reads its pair's fields and runs over every record (l, m), with the
@@ -68,7 +69,6 @@ __device__ inline int isqrt_small(int v) {
 }
 
 constexpr int even(int w) { return w + (w & 1); }
-constexpr int kDenseM = 4096;  // cbar: largest (l_max + 1) n_ch^2 expanded densely in LDS
 template <int NMAX, int LMAX>
 struct Shape {
   static constexpr int NREC = (LMAX + 1) * (LMAX + 2) / 2;
@@ -324,22 +324,16 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   if (lane == 0 && pnorm_out) pnorm_out[i] = nrm;
 }
 
-// vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm}, written
-// in the padded layout of c ([species][lm < LL + 1][k < NMAX]) with zeros in the
-// sink column lm = LL and in the channels k >= n_max
+// vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm} of atom
+// i, written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
+// NMAX]) with zeros in the sink column lm = LL and in the channels k >= n_max.
+// vb: K doubles of LDS scratch.  Ends with a block barrier.
 template <int NMAX>
-__global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const double* __restrict__ c,
-                                             const double* __restrict__ q, int q_pitch,
-                                             const double* __restrict__ pnorm, const double* __restrict__ qbar,
-                                             int qbar_pitch, double* __restrict__ cbar) {
-  extern __shared__ __align__(16) double dyn[];
-  const int i = blockIdx.x;
-  if (i >= n_atoms) return;
-  const int lane = threadIdx.x;
+__device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
+                                 const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
+                                 const double* __restrict__ qbar, int qbar_pitch, double* cb, double* vb, int lane) {
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
-  const int per_atom = ns * NMAX * LLP;
-  double* vb = dyn;
-  const double* __restrict__ csh = c + (size_t)i * per_atom;  // c of atom i, [species][lm][k], read in place
+  const double* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
   const double* qb = qbar + (size_t)i * qbar_pitch;
   double dot = 0.0;
@@ -349,24 +343,9 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int k = lane; k < K; k += 64) vb[k] = (qb[k] - qi[k] * dot) * inv;
   __syncthreads();
-  // cbar_{(s,k), lm} = sum_{(sb,kb)} M_{(s,k),(sb,kb)}(l) c_{(sb,kb), lm}; with few channels
-  // the matrices M(l) are expanded densely in LDS first, so the products read rows
-  // of M without index arithmetic
-  const bool dense = L1 * nch * nch <= kDenseM;
-  double* Ml = vb + K;  // [l][a][b]
-  if (dense) {
-    for (int r = lane; r < nch * nch; r += 64) {  // one division per (a, b), all l
-      const int a = r / nch, b = r - a * nch;
-      const int lo = a < b ? a : b, hi = a < b ? b : a;
-      const double w = a == b ? 2.0 : kSqrt2;
-      const double* src = vb + ab_index(lo, hi, nch) * L1;
-      for (int l = 0; l < L1; ++l) Ml[l * nch * nch + r] = w * src[l];
-    }
-    __syncthreads();
-  }
-  // task = (column (s, lm), half of the NMAX channels)
+  // task = (column (s, lm), half of the NMAX channels);
+  // M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b), vbar packed a <= b then l
   constexpr int KH = NMAX / 2;
-  double* co = cbar + (size_t)i * per_atom;
   const double inv_llp = 1.0 / (double)LLP;
   for (int task = lane; task < 2 * ns * LLP; task += 64) {
     const int col = task >> 1, h = task & 1;
@@ -384,40 +363,35 @@ __global__ __launch_bounds__(64) void k_cbar(DevParams P, int n_atoms, const dou
         for (int kk = 0; kk < KH; ++kk) {
           const int k = h * KH + kk, a = s * n + k;
           if (k < n) {
-            if (dense) {
-              const double* mrow = Ml + (l * nch + a) * nch + sb * n;
 #pragma unroll
-              for (int kb = 0; kb < NMAX; ++kb)
-                if (kb < n) acc[kk] = fma(mrow[kb], cv[kb], acc[kk]);
-            } else {
-#pragma unroll
-              for (int kb = 0; kb < NMAX; ++kb) {
-                const int b = sb * n + kb;
-                if (kb < n) {
-                  const int lo = a < b ? a : b, hi = a < b ? b : a;
-                  acc[kk] = fma((a == b ? 2.0 : kSqrt2) * vb[ab_index(lo, hi, nch) * L1 + l], cv[kb], acc[kk]);
-                }
+            for (int kb = 0; kb < NMAX; ++kb) {
+              const int b = sb * n + kb;
+              if (kb < n) {
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                acc[kk] = fma((a == b ? 2.0 : kSqrt2) * vb[ab_index(lo, hi, nch) * L1 + l], cv[kb], acc[kk]);
               }
             }
           }
         }
       }
     }
-    double* dst = co + (size_t)col * NMAX + h * KH;
+    double* dst = cb + (size_t)col * NMAX + h * KH;
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) dst[kk] = acc[kk];
   }
+  __syncthreads();
 }
 
 // LDS of the adjoint: the atom's cbar for every species ([species][lm][k]), then
-// the record coefficients [r][NC] and (parity, cos column, sin column) [r][4]
+// a region that first holds vbar (K doubles) and then the record coefficients
+// [r][NC] and (parity, cos column, sin column) [r][4]
 template <int NMAX, int LMAX>
 struct AdjLds {
   static constexpr int NC = Shape<NMAX, LMAX>::NC;
   static size_t cb_doubles(const DevParams& P) { return (size_t)P.ns * (P.LL + 1) * NMAX; }
   static size_t bytes(const DevParams& P) {
-    const size_t nrec = (size_t)(P.l + 1) * (P.l + 2) / 2;
-    return sizeof(double) * (cb_doubles(P) + nrec * NC) + sizeof(int) * 4 * nrec;
+    const size_t nrec = (size_t)(P.l + 1) * (P.l + 2) / 2, rec = nrec * NC + 2 * nrec;
+    return sizeof(double) * (cb_doubles(P) + (rec > (size_t)P.K ? rec : (size_t)P.K));
   }
 };
 
@@ -476,16 +450,20 @@ __device__ inline void adjoint_records(int L, const double* __restrict__ cb, con
 // One wave per centre atom, one lane per pair (64 pairs per round): each lane
 // reads its pair's fields (coalesced across the lanes), contracts them with the
 // cbar of the neighbour's species over all records and writes the pair
-// gradient g = dE/dd, summed in the lane's registers.  The atom's cbar and the
-// record table are staged in LDS once and read as broadcasts.
+// gradient g = dE/dd, summed in the lane's registers.  The wave first forms the
+// atom's cbar in LDS (form_cbar), then stages the record table; both are read
+// as broadcasts.
 template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
                                                                        int n_atoms, const int* __restrict__ offsets,
                                                                        int bound, const int* __restrict__ nj,
                                                                        const int* __restrict__ species,
                                                                        const double* __restrict__ rows,
-                                                                       const double* __restrict__ cbar,
-                                                                       double* __restrict__ gx,
+                                                                       const double* __restrict__ c,
+                                                                       const double* __restrict__ q, int q_pitch,
+                                                                       const double* __restrict__ pnorm,
+                                                                       const double* __restrict__ qbar,
+                                                                       int qbar_pitch, double* __restrict__ gx,
                                                                        double* __restrict__ gy,
                                                                        double* __restrict__ gz) {
   using S = Shape<NMAX, LMAX>;
@@ -501,9 +479,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
   double* cb = dyn;
   double* rc = dyn + ncb;
   int* ri = reinterpret_cast<int*>(rc + nrec * NC);
+  form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar_pitch, cb, rc, lane);  // vbar in the record region
   {
-    const double2* src = reinterpret_cast<const double2*>(cbar + (size_t)i * ncb);
-    for (int u = lane; u < ncb / 2; u += 64) reinterpret_cast<double2*>(cb)[u] = src[u];
     for (int u = lane; u < nrec * NC; u += 64) {
       const int r = u / NC, t = u - r * NC;
       rc[u] = T->rec_coef[r % kRecLanes][r / kRecLanes][t];
@@ -631,10 +608,6 @@ size_t fwd_dyn_bytes(const DevParams& P) {
 size_t adj_dyn_bytes(const DevParams& P) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return AdjLds<N, LM>::bytes(P); });
 }
-size_t cbar_dyn_bytes(const DevParams& P) {
-  const size_t m = (size_t)(P.l + 1) * P.nch * P.nch;
-  return sizeof(double) * (P.K + (m <= (size_t)kDenseM ? m : 0));
-}
 
 }  // namespace
 
@@ -652,10 +625,7 @@ size_t pair_rows_bytes(const DevParams& P, long long n_pairs) {
 size_t descriptor_lds_bytes(const DevParams& P) {
   return fwd_dyn_bytes(P) + 64 * sizeof(int);
 }
-size_t adjoint_lds_bytes(const DevParams& P) {
-  const size_t a = adj_dyn_bytes(P), b = cbar_dyn_bytes(P);
-  return a > b ? a : b;
-}
+size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P); }
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
@@ -689,25 +659,15 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
   return dispatch(P.n, P.l, f);
 }
 
-hipError_t launch_cbar(const DevParams& P, int n_atoms, const double* c, const double* q, int q_pitch,
-                       const double* pnorm, const double* qbar, int qbar_pitch, double* cbar, hipStream_t st) {
-  if (n_atoms == 0) return hipSuccess;
-  auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_cbar<N>), dim3(n_atoms), dim3(64), cbar_dyn_bytes(P), st, P, n_atoms, c, q, q_pitch, pnorm,
-                       qbar, qbar_pitch, cbar);
-    return hipGetLastError();
-  };
-  return dispatch(P.n, P.l, f);
-}
-
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
-                               const int* nj, const int* species, const double* rows, const double* cbar, double* gx,
-                               double* gy, double* gz, hipStream_t st) {
+                               const int* nj, const int* species, const double* rows, const double* c,
+                               const double* q, int q_pitch, const double* pnorm, const double* qbar, int qbar_pitch,
+                               double* gx, double* gy, double* gz, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
     hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
-                       rows, cbar, gx, gy, gz);
+                       rows, c, q, q_pitch, pnorm, qbar, qbar_pitch, gx, gy, gz);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
