@@ -82,6 +82,32 @@ def algorithmic_work(stage, N, P, M, K, n, l_max, nch):
     return 0.0, "flop"
 
 
+# HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE counter
+# runs (scaled by what the counters read for a plain device copy), kept with the
+# profiles; used only while the kernel's source file is unchanged since the runs
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel, workload, precision):
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for t in rec.get("kernels", []):
+        if t.get("kernel") != kernel or t.get("workload") != workload or t.get("precision") != precision:
+            continue
+        try:
+            with open(os.path.join(ROOT, t["source"]), "rb") as f:
+                sha = hashlib.sha256(f.read()).hexdigest()
+        except OSError:
+            return None
+        return t["bytes_per_launch"] if sha == t.get("source_sha256") else None
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,8 +238,17 @@ def main():
     dom = main_run["dominant"]
     bound, peak, u, achieved = rate(dom, main_run["dominant_ms"])
     roofline = {"kernel": SINGLE_KERNEL[dom], "bound": bound, "achieved": round(achieved, 3), "peak": peak,
-                "unit": u, "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": u, "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(SINGLE_KERNEL[dom], args.workload, args.precision),
                 "avg_launch_ms": round(main_run["dominant_ms"], 5)}
+
+    if args.calibrate_copy:  # the reference copy for the HBM byte counters, after everything else
+        src = torch.ones(1 << 26, dtype=torch.float64, device=dev)  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

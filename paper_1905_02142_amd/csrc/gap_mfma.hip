@@ -277,6 +277,24 @@ __device__ inline void gemm_tile(Smem<P>& sm, const typename P::T* __restrict__ 
   }
 }
 
+// (column tile, row tile) of this workgroup.  Workgroups are handed to the eight
+// XCDs round-robin by linear index; tiles are numbered so that each XCD takes
+// one rectangle of the tile grid (the grid cut into xr x xc rectangles, xr xc =
+// 8), which its L2 serves: every row and column operand tile is then fetched
+// from HBM by one or a few XCDs instead of by all eight.
+__device__ inline void xcd_tile(int& tc, int& tr, int xr, int xc) {
+  const int nc = gridDim.x, nr = gridDim.y;
+  const int b = blockIdx.y * nc + blockIdx.x;
+  if (nr % xr == 0 && nc % xc == 0) {
+    const int x = b % 8, slot = b / 8, cc = nc / xc;
+    tr = (x / xc) * (nr / xr) + slot / cc;
+    tc = (x % xc) * cc + slot % cc;
+  } else {
+    tc = b % nc;
+    tr = b / nc;
+  }
+}
+
 // row of element r of acc[x][.] within the wave's block
 template <typename P>
 __device__ inline int acc_row(int x, int r, int lane) {
@@ -306,7 +324,9 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
   __shared__ double rowsum[2][P::BM];
   __shared__ double colsum[2][P::BN];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
-  const int i0 = blockIdx.y * P::BM, s0 = blockIdx.x * P::BN;
+  int tc, tr;
+  xcd_tile(tc, tr, 4, 2);  // both operands are reused across the grid
+  const int i0 = tr * P::BM, s0 = tc * P::BN;
   typename P::Acc acc[TM][TN];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -377,10 +397,10 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
   for (int t = tid; t < P::BM + P::BN; t += 256) {
     if (t < P::BM) {
       const int gi = i0 + t;
-      if (gi < N) e_part[(size_t)blockIdx.x * N + gi] = rowsum[0][t] + rowsum[1][t];
+      if (gi < N) e_part[(size_t)tc * N + gi] = rowsum[0][t] + rowsum[1][t];
     } else {
       const int c = t - P::BM, gs = s0 + c;
-      if (gs < M) ab_part[(size_t)blockIdx.y * M + gs] = colsum[0][c] + colsum[1][c];
+      if (gs < M) ab_part[(size_t)tr * M + gs] = colsum[0][c] + colsum[1][c];
     }
   }
 }
@@ -394,7 +414,9 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, cons
   constexpr int TM = Frag<P>::TM, TN = Frag<P>::TN;
   __shared__ Smem<P> sm;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
-  const int i0 = blockIdx.y * P::BM, c0 = blockIdx.x * P::BN;
+  int tc, tr;
+  xcd_tile(tc, tr, 8, 1);  // few column tiles: an XCD takes whole rows of tiles
+  const int i0 = tr * P::BM, c0 = tc * P::BN;
   typename P::Acc acc[TM][TN];
 #pragma unroll
   for (int x = 0; x < TM; ++x)

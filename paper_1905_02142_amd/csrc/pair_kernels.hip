@@ -116,6 +116,14 @@ __device__ inline void lane_records(const DevTables* __restrict__ T, int lane, i
   }
 }
 
+// (c_r + i c_i) <- (c_r + i c_i)(u_x + i u_y) with explicit FMAs, so that every
+// kernel forming the powers (u_x + i u_y)^m gets the same bits
+__device__ inline void azimuthal_step(double& cr, double& ci, double ux, double uy) {
+  const double nr = fma(cr, ux, -(ci * uy));
+  ci = fma(cr, uy, ci * ux);
+  cr = nr;
+}
+
 template <int NMAX, int LMAX, bool DERIV>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
                                                      const int* __restrict__ count, const double* __restrict__ dx,
@@ -168,9 +176,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   for (int m = 0; m <= LMAX; ++m) {
     st(S::FZ + 2 * m, cr);
     st(S::FZ + 2 * m + 1, ci);
-    const double nr = cr * ux - ci * uy;
-    ci = cr * uy + ci * ux;
-    cr = nr;
+    azimuthal_step(cr, ci, ux, uy);
   }
   if (DERIV) {
 #pragma unroll
@@ -400,13 +406,15 @@ struct AdjLds {
 template <int NMAX, int LMAX, typename FieldFn>
 __device__ inline void adjoint_records(int L, const double* __restrict__ cb, const double* __restrict__ rc,
                                        const int* __restrict__ ri, FieldFn F, const double (&b)[NMAX],
-                                       const double (&db)[NMAX], double uz, double& sr, double& sx, double& sy,
-                                       double& sz) {
+                                       const double (&db)[NMAX], double uz, double ux, double uy, double& sr,
+                                       double& sx, double& sy, double& sz) {
   using S = Shape<NMAX, LMAX>;
   constexpr int NC = S::NC;
   const double x2 = uz * uz;
   for (int l = 0; l <= L; ++l) {
     const double we = F(S::FW + l), wd = F(S::FR + S::XW + l);
+    // (u_x + i u_y)^m and ^(m-1) by the recurrence of the per-pair kernel (the same bits)
+    double zr = 1.0, zi = 0.0, zr1 = 1.0, zi1 = 0.0;
 #pragma unroll 2
     for (int m = 0; m <= l; ++m) {
       // the record of (l, m) in the tables: m outer, l = m..L inner
@@ -422,9 +430,11 @@ __device__ inline void adjoint_records(int L, const double* __restrict__ cb, con
       }
       const double Q = par ? uz * Rv : Rv;
       const double Qd = par ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
-      const int m1 = m > 0 ? m - 1 : 0;
-      const double zr = F(S::FZ + 2 * m), zi = F(S::FZ + 2 * m + 1);
-      const double zr1 = F(S::FZ + 2 * m1), zi1 = F(S::FZ + 2 * m1 + 1);
+      if (m > 0) {
+        zr1 = zr;
+        zi1 = zi;
+        azimuthal_step(zr, zi, ux, uy);
+      }
       // the sin column of m = 0 is the sink column, which holds zeros
       const double* __restrict__ c0 = cb + lc * NMAX;
       const double* __restrict__ c1 = cb + ls * NMAX;
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       b[k] = F(S::FB + k);
       db[k] = F(S::FR + S::XD + k);
     }
-    const double uz = F(S::FU);
+    const double uz = F(S::FU), ux = F(S::FR + S::XU), uy = F(S::FR + S::XU + 1);
     double sr = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     bool on = live;
     int sj = 0;
@@ -516,9 +526,9 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       on = on && sj >= 0 && sj < P.ns;
       sj = on ? sj : 0;
     }
-    adjoint_records<NMAX, LMAX>(L, cb + (size_t)sj * LLP * NMAX, rc, ri, F, b, db, uz, sr, sx, sy, sz);
+    adjoint_records<NMAX, LMAX>(L, cb + (size_t)sj * LLP * NMAX, rc, ri, F, b, db, uz, ux, uy, sr, sx, sy, sz);
     if (live) {
-      const double ux = F(S::FR + S::XU), uy = F(S::FR + S::XU + 1), ir = F(S::FR + S::XU + 2);
+      const double ir = F(S::FR + S::XU + 2);
       // d u / d d = (I - u u^T) / r
       const double ut = ux * sx + uy * sy + uz * sz;
       gx[p] = on ? sr * ux + (sx - ux * ut) * ir : 0.0;
