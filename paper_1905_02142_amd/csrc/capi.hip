@@ -602,12 +602,13 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
     {
       StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
+      // with forces the Qbar pass also finishes the energy and dE/dalpha sums
       SOAP_HIP(ctx, soap::launch_gap_scores(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta,
-                                            e_atom, alpha_grad, ctx->gapw.p, st));
+                                            e_atom, alpha_grad, qbar == nullptr, ctx->gapw.p, st));
     }
     if (qbar) {
       StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
-      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, ctx->gapw.p, st));
+      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, e_atom, alpha_grad, ctx->gapw.p, st));
     }
   }
   if (forces) {

@@ -9,11 +9,15 @@ namespace soap {
 // The workspace holds the converted, zero-padded operands, G and the per-tile
 // partial sums.
 size_t gap_workspace_bytes(int N, int M, int K, int prec);
-// e (N) and alpha_bar (M, nullable); G stays in work for the qbar pass
+// e (N) and alpha_bar (M, nullable); G stays in work for the qbar pass.  With
+// sums false the per-tile partial sums are left in work for launch_gap_qbar to
+// finish (e and alpha_bar are then written by that call)
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                             int zeta, double* e, double* alpha_bar, void* work, hipStream_t st);
-// Qbar (N x K) = G Q_s, from the operands the scores pass left in work
-hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, const void* work, hipStream_t st);
+                             int zeta, double* e, double* alpha_bar, bool sums, void* work, hipStream_t st);
+// Qbar (N x K) = G Q_s, from the operands the scores pass left in work; with e
+// non-null it also finishes e and alpha_bar (nullable) from the partial sums
+hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar,
+                           const void* work, hipStream_t st);
 
 // Fused scores + Qbar (prec 1..3, padded K <= 352): e, alpha_bar (nullable) and
 // Qbar in one pass with no N x M intermediate in HBM

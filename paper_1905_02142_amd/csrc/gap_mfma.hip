@@ -405,12 +405,31 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
   }
 }
 
+// e[i] = sum_t e_part[t][i] (t < nte) and, if ab, ab[j] = sum_t ab_part[t][j] (t < nta),
+// each in a fixed order; the loads of eight terms are issued together
+__device__ inline double ordered_sum(const double* __restrict__ part, int n, int nt, int j) {
+  double s = 0.0;
+  int t = 0;
+  for (; t + 8 <= nt; t += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(t + u) * n + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; t < nt; ++t) s += part[(size_t)t * n + j];
+  return s;
+}
+
 // Qbar tile = G (N x Mp) Q_s^T-converted (Kp x Mp)^T, written for descriptor columns < K
 template <typename P>
 __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, const typename P::T* __restrict__ G,
                                               const typename P::T* __restrict__ G_lo,
                                               const typename P::T* __restrict__ QsT,
-                                              const typename P::T* __restrict__ QsT_lo, double* __restrict__ Qbar) {
+                                              const typename P::T* __restrict__ QsT_lo, double* __restrict__ Qbar,
+                                              int M, int nte, const double* __restrict__ e_part,
+                                              double* __restrict__ e, int nta, const double* __restrict__ ab_part,
+                                              double* __restrict__ ab) {
   constexpr int TM = Frag<P>::TM, TN = Frag<P>::TN;
   __shared__ Smem<P> sm;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
@@ -433,22 +452,16 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, cons
         const int gc = c0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
         if (gi < N && gc < K) Qbar[(size_t)gi * K + gc] = (double)acc[x][y][r];
       }
-}
-
-// e[i] = sum_t e_part[t][i] (t < nte) and, if ab, ab[j] = sum_t ab_part[t][j] (t < nta),
-// each in a fixed order; the loads of eight terms are issued together
-__device__ inline double ordered_sum(const double* __restrict__ part, int n, int nt, int j) {
-  double s = 0.0;
-  int t = 0;
-  for (; t + 8 <= nt; t += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(t + u) * n + j];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+  // the scores pass's per-tile partial sums, finished here (e non-null): each
+  // workgroup takes one slice of the N + M outputs, each output a fixed-order sum
+  if (e) {
+    const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int per = (N + M + nb - 1) / nb, j1 = min((b + 1) * per, N + M);
+    for (int j = b * per + tid; j < j1; j += 256) {
+      if (j < N) e[j] = ordered_sum(e_part, N, nte, j);
+      else if (ab) ab[j - N] = ordered_sum(ab_part, M, nta, j - N);
+    }
   }
-  for (; t < nt; ++t) s += part[(size_t)t * n + j];
-  return s;
 }
 
 __global__ void k_sum_parts2(int N, int nte, const double* __restrict__ e_part, double* __restrict__ e, int M, int nta,
@@ -860,7 +873,7 @@ Layout layout(int N, int M, int K) {
 
 template <typename P>
 hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta,
-                       double* e, double* alpha_bar, void* work, hipStream_t st) {
+                       double* e, double* alpha_bar, bool sums, void* work, hipStream_t st) {
   using T = typename P::T;
   const Layout L = layout<P>(N, M, K);
   char* w = (char*)work;
@@ -881,13 +894,15 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
   attr = true;
   hipLaunchKernelGGL(k_scores<P>, dim3(nst, nit), dim3(256), sizeof(Smem<P>), st, N, M, Mp, Kp, qc, qc_lo, qsc,
                      qsc_lo, alpha, zeta, G, G_lo, e_part, ab_part);
-  hipLaunchKernelGGL(k_sum_parts2, dim3((N + M + 255) / 256), dim3(256), 0, st, N, nst, e_part, e, M, nit, ab_part,
-                     alpha_bar);
+  if (sums)
+    hipLaunchKernelGGL(k_sum_parts2, dim3((N + M + 255) / 256), dim3(256), 0, st, N, nst, e_part, e, M, nit, ab_part,
+                       alpha_bar);
   return hipGetLastError();
 }
 
 template <typename P>
-hipError_t qbar_impl(int N, int M, int K, double* Qbar, const void* work, hipStream_t st) {
+hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work,
+                     hipStream_t st) {
   using T = typename P::T;
   const Layout L = layout<P>(N, M, K);
   const char* w = (const char*)work;
@@ -896,7 +911,11 @@ hipError_t qbar_impl(int N, int M, int K, double* Qbar, const void* work, hipStr
   const T *G = (const T*)(w + L.g), *G_lo = (const T*)(w + L.g_lo);
   using Q = QbarTile<P>;
   const int nit = (N + Q::BM - 1) / Q::BM, nct = (Kp + Q::BN - 1) / Q::BN;
-  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit), dim3(256), 0, st, N, K, Mp, Kp, G, G_lo, qst, qst_lo, Qbar);
+  const double* e_part = (const double*)(w + L.e_part);
+  const double* ab_part = (const double*)(w + L.ab_part);
+  const int nst = Mp / P::BN, nsi = (N + P::BM - 1) / P::BM;  // the scores pass's tile counts
+  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit), dim3(256), 0, st, N, K, Mp, Kp, G, G_lo, qst, qst_lo, Qbar, M, nst,
+                     e_part, e, nsi, ab_part, alpha_bar);
   return hipGetLastError();
 }
 
@@ -912,13 +931,13 @@ size_t gap_workspace_bytes(int N, int M, int K, int prec) {
 }
 
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                             int zeta, double* e, double* alpha_bar, void* work, hipStream_t st) {
+                             int zeta, double* e, double* alpha_bar, bool sums, void* work, hipStream_t st) {
   if (N == 0) return hipSuccess;
   switch (prec) {
-    case 0: return scores_impl<PF64>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
-    case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
-    case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
-    default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, work, st);
+    case 0: return scores_impl<PF64>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
+    case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
+    case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
+    default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
   }
 }
 
@@ -953,13 +972,14 @@ hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, cons
   }
 }
 
-hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, const void* work, hipStream_t st) {
+hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work,
+                           hipStream_t st) {
   if (N == 0) return hipSuccess;
   switch (prec) {
-    case 0: return qbar_impl<PF64>(N, M, K, Qbar, work, st);
-    case 1: return qbar_impl<PF32>(N, M, K, Qbar, work, st);
-    case 2: return qbar_impl<PBF16>(N, M, K, Qbar, work, st);
-    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, work, st);
+    case 0: return qbar_impl<PF64>(N, M, K, Qbar, e, alpha_bar, work, st);
+    case 1: return qbar_impl<PF32>(N, M, K, Qbar, e, alpha_bar, work, st);
+    case 2: return qbar_impl<PBF16>(N, M, K, Qbar, e, alpha_bar, work, st);
+    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, e, alpha_bar, work, st);
   }
 }
 

@@ -207,6 +207,28 @@ def test_deterministic_bitwise():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_energies_alone_equal_energies_with_forces(precision):
+    """Without forces the scores pass finishes the energy and dE/dalpha sums
+    itself; with forces the Qbar pass does, in the same order.  The forward
+    pass without forces runs the per-pair kernel compiled without derivatives,
+    which may round differently in the last bit, so the two agree to rounding."""
+    kw, n, L, ns, seed = DESC_CASES["box300_n8l8"]
+    s = synth.rsa_box(n, L, 1.2, seed)
+    soap = _soap(precision=precision, **kw)
+    qs = _t(synth.sparse_set(64, soap.dim, 7))
+    al = _t(synth.sparse_weights(64, 8))
+    spec = _t(np.zeros(n, np.int32))
+    nl, _ = _gpu_nl(soap, [s])
+    e1, F1, ab1 = soap.energy_forces(nl, spec, qs, al, 4)
+    e0, F0, ab0 = soap.energy_forces(nl, spec, qs, al, 4, forces=False)
+    torch.cuda.synchronize()
+    assert F0 is None
+    for a, b in ((e0, e1), (ab0, ab1)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
 def test_zero_neighbour_atoms():
     # isolated atoms far apart, no central Gaussian: p = 0 -> q = 0, e = 0, F = 0
     pos = np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0], [1.0, 1.0, 2.5]])
