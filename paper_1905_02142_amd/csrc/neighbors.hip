@@ -32,12 +32,11 @@ __device__ inline int find_structure(const int* __restrict__ so, int ns, int a) 
   return lo;
 }
 
-// bin of atom a (global bin index) and the lattice wrap that brings it into its cell
-__device__ inline void locate_atom(int a, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
-                                   const int* __restrict__ so, int n_struct, int* __restrict__ err, int& bin_out,
-                                   int& wrap_out) {
-  const StructMeta& M = meta[find_structure(so, n_struct, a)];
-  double p[3] = {pos[3 * a], pos[3 * a + 1], pos[3 * a + 2]};
+// bin (global bin index) of a position in structure M and the lattice wrap that
+// brings it into its cell
+__device__ inline void locate_pos(const StructMeta& M, double p0, double p1, double p2, int* __restrict__ err,
+                                  int& bin_out, int& wrap_out) {
+  double p[3] = {p0, p1, p2};
   if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
     atomicOr(err, kErrNonFinite);
     p[0] = p[1] = p[2] = 0.0;
@@ -67,6 +66,14 @@ __device__ inline void locate_atom(int a, const double* __restrict__ pos, const 
   }
   bin_out = M.bin0 + (b[2] * M.nbin[1] + b[1]) * M.nbin[0] + b[0];
   wrap_out = pack_img(w[0], w[1], w[2]);
+}
+
+// the same for atom a of the batch
+__device__ inline void locate_atom(int a, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
+                                   const int* __restrict__ so, int n_struct, int* __restrict__ err, int& bin_out,
+                                   int& wrap_out) {
+  locate_pos(meta[find_structure(so, n_struct, a)], pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], err, bin_out,
+             wrap_out);
 }
 
 __global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const StructMeta* __restrict__ meta,
@@ -104,16 +111,31 @@ __global__ __launch_bounds__(kSmallBinThreads) void k_bin_small(int n_atoms, con
   if (t < 4) err[t] = 0;
   __syncthreads();
   int mybin[PER];
+  // positions of eight atoms loaded together, then binned
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int a = t + k * kSmallBinThreads;
-    mybin[k] = -1;
-    if (a < n_atoms) {
-      int wrap;
-      locate_atom(a, pos, meta, so, n_struct, err, mybin[k], wrap);
-      atom_bin[a] = mybin[k];
-      atom_wrap[a] = wrap;
-      atomicAdd(&cnt[mybin[k]], 1);
+  for (int k0 = 0; k0 < PER; k0 += 8) {
+    double px[8], py[8], pz[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = t + (k0 + k) * kSmallBinThreads;
+      const bool ok = a < n_atoms;
+      px[k] = ok ? pos[3 * a] : 0.0;
+      py[k] = ok ? pos[3 * a + 1] : 0.0;
+      pz[k] = ok ? pos[3 * a + 2] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = t + (k0 + k) * kSmallBinThreads;
+      mybin[k0 + k] = -1;
+      if (a < n_atoms) {
+        int wrap;
+        // one structure: its geometry is the same for every lane
+        const StructMeta& M = meta[n_struct == 1 ? 0 : find_structure(so, n_struct, a)];
+        locate_pos(M, px[k], py[k], pz[k], err, mybin[k0 + k], wrap);
+        atom_bin[a] = mybin[k0 + k];
+        atom_wrap[a] = wrap;
+        atomicAdd(&cnt[mybin[k0 + k]], 1);
+      }
     }
   }
   __syncthreads();
