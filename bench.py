@@ -36,16 +36,59 @@ def workload_setup(name, precision, dev):
     from paper_1905_02142_amd import Soap, SoapParams
 
     w = synth.workload(name)
-    if len(w["structures"]) != 1:
-        raise SystemExit("bench.py times single-structure workloads")
-    s = w["structures"][0]
+    ss = w["structures"]
+    pos = np.concatenate([x.positions for x in ss])
+    cells = np.stack([x.cell for x in ss])
+    pbc = np.stack([x.pbc for x in ss]).astype(np.int32)
+    so = np.cumsum([0] + [x.n_atoms for x in ss]).astype(np.int32) if len(ss) > 1 else None
     kw = dict(n_max=w["n_max"], l_max=w["l_max"], r_cut=w["r_cut"], sigma0_r=w["sigma"], sigma0_perp=w["sigma"],
               n_species=w["n_species"])
     soap = Soap(SoapParams(precision=precision, **kw))
     t = lambda a, dt=None: torch.tensor(np.ascontiguousarray(a), device=dev, dtype=dt)
-    st = dict(w=w, s=s, kw=kw, soap=soap, pos=t(s.positions), spec=t(w["species"], torch.int32),
-              qs=t(w["q_sparse"]), al=t(w["alpha"]))
+    gap = bool(w["M"])
+    st = dict(w=w, structures=ss, n_atoms=len(pos), cells=cells, pbc=pbc, so=so, kw=kw, soap=soap, pos=t(pos),
+              spec=t(w["species"], torch.int32), gap=gap, qs=t(w["q_sparse"]) if gap else None,
+              al=t(w["alpha"]) if gap else None)
     return st
+
+
+def cpu_oracle_rate(st, budget_s=15.0):
+    """The oracle's atoms/s on a bounded sample of centres spread evenly over the
+    workload (neighbour list, descriptor and, with a sparse set, GAP energies and
+    the pair gradients of those centres), sized from a pilot to take ~budget_s."""
+    import numpy as np
+
+    import oracle
+
+    w, ss = st["w"], st["structures"]
+    p = oracle.Params(**st["kw"])
+    offs = np.cumsum([0] + [x.n_atoms for x in ss])
+
+    def run(k):
+        # centres: every (N/k)-th atom of the concatenated workload
+        picks = np.unique(np.linspace(0, offs[-1] - 1, k).astype(np.int64))
+        t0 = time.perf_counter()
+        for b, x in enumerate(ss):
+            c = picks[(picks >= offs[b]) & (picks < offs[b + 1])] - offs[b]
+            if len(c) == 0:
+                continue
+            nl = oracle.neighbors(x.positions, x.cell, x.pbc, p.r_cut, centres=c)
+            spec = w["species"][offs[b]:offs[b + 1]]
+            q, _ = oracle.descriptor(p, nl, spec)
+            if st["gap"]:
+                e, qbar, _ = oracle.gap(q, w["q_sparse"], w["alpha"], w["zeta"])
+                oracle.descriptor_vjp(p, nl, spec, qbar)
+        return len(picks), time.perf_counter() - t0
+
+    run(min(offs[-1], 8))  # one-time set-up (tables, library) outside the timing
+    k, t = run(min(offs[-1], 32))
+    for _ in range(3):  # grow the sample until it takes about the budget
+        if t >= 0.5 * budget_s or k >= offs[-1]:
+            break
+        k, t = run(int(min(offs[-1], max(k + 1, k * budget_s / max(t, 1e-3)))))
+    return {"value": round(k / t, 2), "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} of {offs[-1]} centres evenly spread over the workload (their neighbour lists, "
+                      f"descriptors" + (", GAP energies and pair gradients" if st["gap"] else "") + f"), {t:.1f} s"}
 
 
 # stages that are exactly one kernel (the roofline is quoted for one kernel)
@@ -142,27 +185,36 @@ def main():
 
     def run_mode(precision, steps, warmup):
         st = workload_setup(args.workload, precision, dev)
-        soap, w, s = st["soap"], st["w"], st["s"]
-        N = s.n_atoms
-        nl = soap.neighbors(st["pos"], s.cell, s.pbc)
+        soap, w = st["soap"], st["w"]
+        N = st["n_atoms"]
+        geo = (st["cells"], st["pbc"])
+        nl = soap.neighbors(st["pos"], *geo, struct_offsets=st["so"])
         n_pairs = nl.n_pairs
         if not args.sync_neighbors:
             # a list with a 25 % reserve over the current count, as a dynamics run would keep
             nl = NeighbourList(N, n_pairs + n_pairs // 4 + 256, dev)
-            soap.neighbors(st["pos"], s.cell, s.pbc, nl=nl)
+            soap.neighbors(st["pos"], *geo, struct_offsets=st["so"], nl=nl)
         M = w["M"]
         e = torch.empty(N, dtype=torch.float64, device=dev)
         F = torch.empty(N, 3, dtype=torch.float64, device=dev)
-        ab = torch.empty(M, dtype=torch.float64, device=dev)
+        ab = torch.empty(max(M, 1), dtype=torch.float64, device=dev)
+        q = None
 
         def step():
+            nonlocal q
             if args.sync_neighbors:
-                soap.neighbors(st["pos"], s.cell, s.pbc, nl=nl)
+                soap.neighbors(st["pos"], *geo, struct_offsets=st["so"], nl=nl)
             else:
-                soap.neighbors_async(st["pos"], s.cell, s.pbc, nl)
-            soap.energy_forces(nl, st["spec"], st["qs"], st["al"], w["zeta"], out=(e, F, ab))
+                soap.neighbors_async(st["pos"], *geo, nl, struct_offsets=st["so"])
+            if st["gap"]:
+                soap.energy_forces(nl, st["spec"], st["qs"], st["al"], w["zeta"], out=(e, F, ab))
+            else:  # a workload without a sparse set times the descriptor alone
+                q = soap.descriptor(nl, st["spec"])
 
-        tuning = soap.tuning if args.no_autotune else soap.autotune(nl, st["spec"], st["qs"], st["al"], w["zeta"])
+        if args.no_autotune or not st["gap"]:
+            tuning = soap.tuning
+        else:
+            tuning = soap.autotune(nl, st["spec"], st["qs"], st["al"], w["zeta"])
 
         for _ in range(warmup):
             step()
@@ -189,17 +241,17 @@ def main():
             assert soap.check_neighbors(nl) == n_pairs
         _lib.soap_profile(soap.ctx, False)
         timed = _lib.soap_profile_read(soap.ctx)[dominant]
-        res = dict(st=st, soap=soap, w=w, s=s, N=N, nl=nl, M=M, stages=stages, tuning=tuning, dominant=dominant,
+        res = dict(st=st, soap=soap, w=w, N=N, nl=nl, M=M, stages=stages, tuning=tuning, dominant=dominant,
                    dominant_ms=timed[0] / timed[1],
                    ms=(t1 - t0) * 1e3 / steps, value=N * steps / (t1 - t0),
                    e=e.cpu().numpy(), F=F.cpu().numpy(), ab=ab.cpu().numpy())
         return res
 
     main_run = run_mode(args.precision, args.steps, args.warmup)
-    st, soap, w, s, N, nl, M = (main_run[k] for k in ("st", "soap", "w", "s", "N", "nl", "M"))
+    st, soap, w, N, nl, M = (main_run[k] for k in ("st", "soap", "w", "N", "nl", "M"))
     stages, ms, value = main_run["stages"], main_run["ms"], main_run["value"]
     fp64_path = None
-    if args.precision != "fp64":
+    if args.precision != "fp64" and st["gap"]:
         ref = run_mode("fp64", args.steps, args.warmup)
         dF = main_run["F"] - ref["F"]
         fp64_path = {"value": round(ref["value"], 1), "ms_per_step": round(ref["ms"], 4),
@@ -250,18 +302,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        okw = dict(st["kw"])
-        p = oracle.Params(**okw)
-        t2 = time.perf_counter()
-        oracle.energy_forces(p, s.positions, s.cell, s.pbc, w["species"], w["q_sparse"], w["alpha"], w["zeta"])
-        t3 = time.perf_counter()
-        cpu = {"value": round(N / (t3 - t2), 2), "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"the full workload once ({N} atoms: brute-force neighbour list, descriptor, GAP "
-                         f"energies and forces), {t3 - t2:.1f} s"}
+    cpu = None if args.no_cpu_baseline else cpu_oracle_rate(st)
 
     out = {
         "metric": "atomic environments/s (descriptor+forces+GAP kernel)",
@@ -276,7 +317,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else f"f64 (GAP contraction {args.precision})",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_atoms": N, "n_pairs": P, "r_cut": w["r_cut"], "n_max": n,
+        "config": {"workload": args.workload, "structures": len(st["structures"]), "n_atoms": N, "n_pairs": P,
+                   "path": "descriptor, GAP energies and forces" if st["gap"] else "descriptor only (no sparse set)",
+                   "r_cut": w["r_cut"], "n_max": n,
                    "l_max": w["l_max"], "n_species": w["n_species"], "M": M, "zeta": w["zeta"], "K": K,
                    "precision": args.precision, "tuning": main_run["tuning"],
                    "neighbour_build": "sync" if args.sync_neighbors else "async, count checked after the timed steps"},
