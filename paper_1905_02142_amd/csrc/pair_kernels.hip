@@ -206,6 +206,15 @@ __device__ inline void stage_fields(const double* __restrict__ rows, const int* 
   }
 }
 
+// the forward keeps the power spectrum in LDS when c and p of one atom together
+// stay within the row staging area or within 16 KB
+template <int NMAX, int LMAX>
+__host__ __device__ inline bool fwd_p_in_lds(const DevParams& P) {
+  using S = Shape<NMAX, LMAX>;
+  const int need = P.ns * NMAX * (P.LL + 1) + P.K;
+  return need <= S::CH * S::FRP || need * (int)sizeof(double) <= 16384;
+}
+
 template <int NMAX, int LMAX>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams P, const DevTables* __restrict__ T,
                                                                      int n_atoms, const int* __restrict__ offsets,
@@ -297,10 +306,14 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   __threadfence_block();
   __syncthreads();
   // power spectrum from c staged in LDS in its HBM layout [species][lm][k]: lane per
-  // channel pair (a, b), a <= b, all l; p in vsh
+  // channel pair (a, b), a <= b, all l.  p is kept in LDS when it fits
+  // (fwd_p_in_lds); otherwise it goes straight to the q row and is rescaled there
+  // by the lane that wrote it, so that several species do not cut the number of
+  // wavefronts per CU
   const int per_atom = P.ns * NMAX * LLP;
   double* csh = dyn;
-  double* vsh = dyn + per_atom;
+  double* __restrict__ qi = q_out + (size_t)i * q_pitch;
+  double* __restrict__ pv = fwd_p_in_lds<NMAX, LMAX>(P) ? dyn + per_atom : qi;
   for (int t = lane; t < per_atom / 2; t += 64)
     reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci_out)[t];
   __syncthreads();
@@ -317,16 +330,21 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       double v = 0.0;
       for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) v = fma(ca[lm * NMAX], cb[lm * NMAX], v);
       v *= scale;
-      vsh[ab * L1 + l] = v;
+      pv[ab * L1 + l] = v;
       ss = fma(v, v, ss);
     }
   }
   ss = wave_sum(ss);
-  __syncthreads();
   const double nrm = sqrt(ss);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  double* __restrict__ qi = q_out + (size_t)i * q_pitch;
-  for (int k = lane; k < q_pitch; k += 64) qi[k] = k < P.K ? vsh[k] * inv : 0.0;
+  if (pv != qi) {  // p in LDS: every lane writes a contiguous part of q
+    __syncthreads();
+    for (int k = lane; k < q_pitch; k += 64) qi[k] = k < P.K ? pv[k] * inv : 0.0;
+  } else {
+    for (int ab = lane; ab < nab; ab += 64)
+      for (int l = 0; l < L1; ++l) qi[ab * L1 + l] *= inv;
+    for (int k = P.K + lane; k < q_pitch; k += 64) qi[k] = 0.0;
+  }
   if (lane == 0 && pnorm_out) pnorm_out[i] = nrm;
 }
 
@@ -611,7 +629,8 @@ size_t dispatch_size(int n, int l, F&& f) {
 size_t fwd_dyn_bytes(const DevParams& P) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
     using S = Shape<N, LM>;
-    const size_t rows = (size_t)S::CH * S::FRP, epi = (size_t)P.ns * N * (P.LL + 1) + P.K;
+    const size_t rows = (size_t)S::CH * S::FRP,
+                 epi = (size_t)P.ns * N * (P.LL + 1) + (fwd_p_in_lds<N, LM>(P) ? (size_t)P.K : 0);
     return sizeof(double) * (rows > epi ? rows : epi);
   });
 }
