@@ -351,11 +351,13 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
 // vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm} of atom
 // i, written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
 // NMAX]) with zeros in the sink column lm = LL and in the channels k >= n_max.
-// vb: K doubles of LDS scratch.  Ends with a block barrier.
+// vb: K doubles of LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a
+// block barrier.
 template <int NMAX>
 __device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
-                                 const double* __restrict__ qbar, int qbar_pitch, double* cb, double* vb, int lane) {
+                                 const double* __restrict__ qbar, int qbar_pitch, double* cb, double* vb, int* abx,
+                                 int lane) {
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const double* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
@@ -366,6 +368,11 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
   const double nrm = pnorm[i];
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int k = lane; k < K; k += 64) vb[k] = (qb[k] - qi[k] * dot) * inv;
+  // abx[a][b] = (packed index of the pair {a, b}) * (l_max + 1), the row of vbar
+  for (int r = lane; r < nch * nch; r += 64) {
+    const int a = r / nch, b = r - a * nch;
+    abx[r] = ab_index(a < b ? a : b, a < b ? b : a, nch) * L1;
+  }
   __syncthreads();
   // task = (column (s, lm), half of the NMAX channels);
   // M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b), vbar packed a <= b then l
@@ -387,14 +394,11 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
         for (int kk = 0; kk < KH; ++kk) {
           const int k = h * KH + kk, a = s * n + k;
           if (k < n) {
+            const int* __restrict__ row = abx + a * nch + sb * n;
 #pragma unroll
-            for (int kb = 0; kb < NMAX; ++kb) {
-              const int b = sb * n + kb;
-              if (kb < n) {
-                const int lo = a < b ? a : b, hi = a < b ? b : a;
-                acc[kk] = fma((a == b ? 2.0 : kSqrt2) * vb[ab_index(lo, hi, nch) * L1 + l], cv[kb], acc[kk]);
-              }
-            }
+            for (int kb = 0; kb < NMAX; ++kb)
+              if (kb < n)
+                acc[kk] = fma((sb * n + kb == a ? 2.0 : kSqrt2) * vb[row[kb] + l], cv[kb], acc[kk]);
           }
         }
       }
@@ -408,14 +412,16 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
 
 // LDS of the adjoint: the atom's cbar for every species ([species][lm][k]), then
 // a region that first holds vbar (K doubles) and then the record coefficients
-// [r][NC] and (parity, cos column, sin column) [r][4]
+// [r][NC] and (parity, cos column, sin column) [r][4], then the channel-pair
+// index table of form_cbar (n_ch^2 ints)
 template <int NMAX, int LMAX>
 struct AdjLds {
   static constexpr int NC = Shape<NMAX, LMAX>::NC;
   static size_t cb_doubles(const DevParams& P) { return (size_t)P.ns * (P.LL + 1) * NMAX; }
   static size_t bytes(const DevParams& P) {
     const size_t nrec = (size_t)(P.l + 1) * (P.l + 2) / 2, rec = nrec * NC + 2 * nrec;
-    return sizeof(double) * (cb_doubles(P) + (rec > (size_t)P.K ? rec : (size_t)P.K));
+    return sizeof(double) * (cb_doubles(P) + (rec > (size_t)P.K ? rec : (size_t)P.K)) +
+           sizeof(int) * (size_t)P.nch * P.nch;
   }
 };
 
@@ -507,7 +513,11 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
   double* cb = dyn;
   double* rc = dyn + ncb;
   int* ri = reinterpret_cast<int*>(rc + nrec * NC);
-  form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar_pitch, cb, rc, lane);  // vbar in the record region
+  {
+    const int nrec_d = nrec * NC + 2 * nrec;
+    int* abx = reinterpret_cast<int*>(rc + (nrec_d > P.K ? nrec_d : P.K));
+    form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar_pitch, cb, rc, abx, lane);  // vbar in the record region
+  }
   {
     for (int u = lane; u < nrec * NC; u += 64) {
       const int r = u / NC, t = u - r * NC;
