@@ -192,6 +192,22 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
                                  const double* q_bar, double* pos_grad, hipStream_t stream);
 
 /*
+ * Descriptor Jacobian in tiles, for fitting with forces (the kernel derivatives
+ * that Sec. IV.A reports the new SOAP code lacked): for the descriptor components
+ * k0 <= k < k1,
+ *   jac[((k - k0) * 3 + x) * B + p] = d q_{i,k} / d (d_p)_x
+ * for every pair p of centre i, d_p = r_j + T - r_i, x = 0, 1, 2, where B is
+ * nl->n_pairs (or nl->capacity for a list whose count is still on the device).
+ * The derivative of q_i with respect to a position follows by the chain rule:
+ * d/dr_j gains +jac_p, d/dr_i gains -jac_p.  jac: (k1 - k0) x 3 x B doubles
+ * (device, caller-owned).  One forward pass, then one adjoint pass per
+ * component (with qbar = the unit vector e_k on every atom).  SOAP_EINVAL unless
+ * 0 <= k0 < k1 <= K.
+ */
+soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, int k0, int k1,
+                                     double* jac, hipStream_t stream);
+
+/*
  * GAP energies and forces.  q_sparse: M x K sparse descriptors (FP64; cast by
  * the library to the context's precision), alpha: M weights, zeta >= 1 integer.
  * Outputs: e_atom (n_atoms) local energies; forces (n_atoms x 3, nullable =>

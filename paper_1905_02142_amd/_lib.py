@@ -22,7 +22,7 @@ EXPORTED = (
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
     "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
-    "soap_build_neighbors_async", "soap_neighbors_check",
+    "soap_build_neighbors_async", "soap_neighbors_check", "soap_descriptor_jacobian",
 )
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
           "pair_prep", "cbar")
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.soap_descriptor.restype = i
     lib.soap_descriptor_grad.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
     lib.soap_descriptor_grad.restype = i
+    lib.soap_descriptor_jacobian.argtypes = [vp, P(soap_nlist), vp, i, i, vp, vp]
+    lib.soap_descriptor_jacobian.restype = i
     lib.gap_energy_forces.argtypes = [vp, P(soap_nlist), vp, vp, vp, i, i, vp, vp, vp, vp]
     lib.gap_energy_forces.restype = i
     lib.soap_radial_basis_table.argtypes = [i, d, d, vp, vp]
@@ -187,6 +189,10 @@ def soap_descriptor(ctx, nl: soap_nlist, species, q, p_norm, stream) -> None:
 
 def soap_descriptor_grad(ctx, nl: soap_nlist, species, q_bar, pos_grad, stream) -> None:
     check(load().soap_descriptor_grad(ctx, ctypes.byref(nl), species, q_bar, pos_grad, stream), ctx)
+
+
+def soap_descriptor_jacobian(ctx, nl: soap_nlist, species, k0, k1, jac, stream) -> None:
+    check(load().soap_descriptor_jacobian(ctx, ctypes.byref(nl), species, k0, k1, jac, stream), ctx)
 
 
 def gap_energy_forces(ctx, nl: soap_nlist, species, q_sparse, alpha, M, zeta, e_atom, forces, alpha_grad,

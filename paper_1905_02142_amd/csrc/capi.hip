@@ -566,6 +566,36 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   return SOAP_OK;
 }
 
+soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, int k0, int k1,
+                                     double* jac, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = check_nlist(ctx, nl);
+  if (s != SOAP_OK) return s;
+  if ((s = check_lds(ctx)) != SOAP_OK) return s;
+  const soap::DevParams& P = ctx->dp;
+  if (k0 < 0 || k1 > P.K || k0 >= k1) return fail(ctx, SOAP_EINVAL, "need 0 <= k0 < k1 <= K");
+  if (nl->n_atoms == 0) return SOAP_OK;
+  if (!species || !jac) return fail(ctx, SOAP_EINVAL, "null species or Jacobian");
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
+  SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
+  SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
+  SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * N * P.K);
+  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, true, st)) != SOAP_OK) return s;
+  // column k of every atom's Jacobian: the pair adjoint with qbar = e_k on every
+  // row (each q_i depends on the pairs of centre i only)
+  double* qb = (double*)ctx->qbar.p;
+  for (int k = k0; k < k1; ++k) {
+    SOAP_HIP(ctx, soap::launch_unit_rows((int)N, P.K, k, k == k0 ? -1 : k - 1, qb, st));
+    double* tile = jac + (size_t)(k - k0) * 3 * NP;
+    StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
+    SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
+                                            (const double*)ctx->rows.p, (const double*)ctx->c.p,
+                                            (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qb, P.K, tile,
+                                            tile + NP, tile + 2 * NP, st));
+  }
+  return SOAP_OK;
+}
+
 soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_sparse,
                               const double* alpha, int M, int zeta, double* e_atom, double* forces,
                               double* alpha_grad, hipStream_t st) {

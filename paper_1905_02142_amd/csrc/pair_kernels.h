@@ -47,6 +47,10 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
 // angular records (Qbar_lm polynomials) and ilexp series tables for these parameters
 void build_angular_tables(const DevParams& P, DevTables& T);
 
+// qbar (n_rows x K) = e_kset on every row; with kclear >= 0 only columns kset
+// and kclear (the previous kset, set to zero) are written
+hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qbar, hipStream_t st);
+
 // out = F (overwrite) or pos_grad -= F (accumulate_grad)
 hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
                                const double* gz, double* out, bool accumulate_grad, hipStream_t st);

@@ -712,6 +712,25 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
   return dispatch(P.n, P.l, f);
 }
 
+// qbar (n_rows x K) set to the unit vector e_kset on every row; column kclear
+// (a previous kset) is cleared, or, with kclear < 0, the whole matrix
+__global__ void k_unit_rows(int n_rows, int K, int kset, int kclear, double* __restrict__ qbar) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kclear < 0) {
+    if (t < (long long)n_rows * K) qbar[t] = (int)(t % K) == kset ? 1.0 : 0.0;
+  } else if (t < n_rows) {
+    qbar[t * K + kclear] = 0.0;
+    qbar[t * K + kset] = 1.0;
+  }
+}
+
+hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qbar, hipStream_t st) {
+  const long long n = kclear < 0 ? (long long)n_rows * K : n_rows;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_rows, K, kset, kclear, qbar);
+  return hipGetLastError();
+}
+
 hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
                                const double* gz, double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;

@@ -182,6 +182,16 @@ class Soap:
                                   _stream())
         return pos_grad
 
+    def descriptor_jacobian(self, nl: NeighbourList, species: torch.Tensor, k0: int = 0, k1: int | None = None):
+        """soap_descriptor_jacobian: (k1 - k0, 3, n_pairs) with [k, x, p] = d q_{i,k} / d (d_p)_x
+        for pair p of centre i (d_p = r_j + T - r_i)."""
+        k1 = self.dim if k1 is None else k1
+        bound = nl.capacity if nl.deferred else max(nl.n_pairs, 1)
+        jac = torch.empty(max(k1 - k0, 0), 3, bound, dtype=torch.float64, device=nl.device)
+        sp = species.to(torch.int32).contiguous()
+        _lib.soap_descriptor_jacobian(self.ctx, nl.c_struct(), sp.data_ptr(), int(k0), int(k1), jac.data_ptr(), _stream())
+        return jac if nl.deferred else jac[:, :, : nl.n_pairs]
+
     def energy_forces(self, nl: NeighbourList, species: torch.Tensor, q_sparse: torch.Tensor,
                       alpha: torch.Tensor, zeta: int, forces: bool = True, alpha_grad: bool = True,
                       out=None):
