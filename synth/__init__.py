@@ -188,6 +188,11 @@ WORKLOADS = {
                           seed=5004),
     "box262144_n10l10": dict(n_atoms=262144, box=138.0, d_min=1.2, r_cut=5.5, sigma=0.5, n_max=10,
                              l_max=10, n_species=1, M=4000, zeta=4, seed=1005),
+    # the paper's speed-test structure (Sec. III.D): 10000 random atoms in a 46.371 A
+    # cube, no two closer than 0.7 A; descriptor only.  r_cut and sigma are not given
+    # there: 5 A and 0.5 A as in the 4096-atom workload; n_max, l_max are swept 3..12
+    "speed10000_n10l10": dict(n_atoms=10000, box=46.371, d_min=0.7, r_cut=5.0, sigma=0.5, n_max=10,
+                              l_max=10, n_species=1, M=0, zeta=0, seed=1006),
 }
 
 
