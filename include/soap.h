@@ -253,6 +253,27 @@ const char* soap_stage_name(int stage);
 /* Bytes of device workspace the context currently holds. */
 long long soap_workspace_bytes(const soap_ctx* ctx);
 
+/*
+ * Verlet skin: later neighbour builds on ctx list every pair closer than
+ * r_cut + skin (0 <= skin <= r_cut; default 0).  The descriptor kernels give the
+ * pairs at r >= r_cut exactly zero weight, so every result equals that of a list
+ * built to r_cut (up to the order of the per-atom sums); the list stays valid
+ * while no atom has moved more than skin / 2 since the build.  SOAP_EINVAL
+ * outside that range.
+ */
+soap_status soap_set_neighbor_skin(soap_ctx* ctx, double skin);
+
+/*
+ * Pair vectors of a reused list: (dx, dy, dz)[p] = r_j + T - r_i for every listed
+ * pair, from the current positions pos (n_atoms x 3, device; positions are not
+ * re-wrapped into the cell, so the stored images T stay valid).  The lattice and
+ * structure layout are those of the last build on ctx, which must be the build of
+ * nl.  A list built with a skin is reused this way, step after step, until some
+ * atom has moved more than skin / 2 since the build.  For unmoved atoms the
+ * result is bitwise that of the build.  No host synchronisation.
+ */
+soap_status soap_update_pair_vectors(soap_ctx* ctx, const soap_nlist* nl, const double* pos, hipStream_t stream);
+
 /* ------------------------------------------------------------------ tuning
  * Launch-shape choices that change speed, not the method.  Every setting
  * computes the same quantities and meets the same bounds; settings that change

@@ -22,7 +22,8 @@ EXPORTED = (
     "soap_build_neighbors", "soap_descriptor", "soap_descriptor_grad", "gap_energy_forces",
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
     "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
-    "soap_build_neighbors_async", "soap_neighbors_check", "soap_descriptor_jacobian",
+    "soap_build_neighbors_async", "soap_neighbors_check", "soap_descriptor_jacobian", "soap_set_neighbor_skin",
+    "soap_update_pair_vectors",
 )
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
           "pair_prep", "cbar")
@@ -98,6 +99,10 @@ def load(path: str = LIB_PATH):
     lib.soap_descriptor.restype = i
     lib.soap_descriptor_grad.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
     lib.soap_descriptor_grad.restype = i
+    lib.soap_update_pair_vectors.argtypes = [vp, P(soap_nlist), vp, vp]
+    lib.soap_update_pair_vectors.restype = i
+    lib.soap_set_neighbor_skin.argtypes = [vp, d]
+    lib.soap_set_neighbor_skin.restype = i
     lib.soap_descriptor_jacobian.argtypes = [vp, P(soap_nlist), vp, i, i, vp, vp]
     lib.soap_descriptor_jacobian.restype = i
     lib.gap_energy_forces.argtypes = [vp, P(soap_nlist), vp, vp, vp, i, i, vp, vp, vp, vp]
@@ -189,6 +194,14 @@ def soap_descriptor(ctx, nl: soap_nlist, species, q, p_norm, stream) -> None:
 
 def soap_descriptor_grad(ctx, nl: soap_nlist, species, q_bar, pos_grad, stream) -> None:
     check(load().soap_descriptor_grad(ctx, ctypes.byref(nl), species, q_bar, pos_grad, stream), ctx)
+
+
+def soap_update_pair_vectors(ctx, nl: soap_nlist, pos, stream) -> None:
+    check(load().soap_update_pair_vectors(ctx, ctypes.byref(nl), pos, stream), ctx)
+
+
+def soap_set_neighbor_skin(ctx, skin: float) -> None:
+    check(load().soap_set_neighbor_skin(ctx, float(skin)), ctx)
 
 
 def soap_descriptor_jacobian(ctx, nl: soap_nlist, species, k0, k1, jac, stream) -> None:

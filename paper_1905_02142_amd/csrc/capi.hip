@@ -42,6 +42,8 @@ struct soap_ctx {
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
   soap_tuning tune{0, 0, 256, 2};
+  double skin = 0.0;  // neighbour lists are built to r_cut + skin
+  int built_atoms = -1, built_structures = 0;  // the geometry of the last build (meta on the device)
   Buf tune_out;  // scratch outputs of the autotuner
   size_t pinned_bytes = 0;
   // neighbour build
@@ -328,7 +330,7 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
   if (nl->capacity > 2147483647LL) return fail(ctx, SOAP_ENOTSUP, "capacity above 2^31-1 pairs");
   if (nl->capacity > 0 && (!nl->j || !nl->img || !nl->rev || !nl->center || !nl->dx || !nl->dy || !nl->dz))
     return fail(ctx, SOAP_EINVAL, "null per-pair arrays");
-  const double rc = ctx->dp.rc;
+  const double rc = ctx->dp.rc + ctx->skin;  // the list's cutoff
   // per-structure cell-list geometry
   std::vector<soap::StructMeta> meta(n_structures);
   std::vector<int> so(n_structures + 1);
@@ -458,6 +460,8 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
   nl->n_atoms = n_atoms;
   nl->n_structures = n_structures;
   nl->n_pairs = SOAP_PAIRS_DEFERRED;
+  ctx->built_atoms = n_atoms;
+  ctx->built_structures = n_structures;
   return SOAP_OK;
 }
 
@@ -656,6 +660,28 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
                                             (const double*)ctx->gy.p, (const double*)ctx->gz.p, forces, false, st));
   }
+  return SOAP_OK;
+}
+
+soap_status soap_update_pair_vectors(soap_ctx* ctx, const soap_nlist* nl, const double* pos, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = check_nlist(ctx, nl);
+  if (s != SOAP_OK) return s;
+  if (nl->n_atoms != ctx->built_atoms || nl->n_structures != ctx->built_structures || !ctx->meta.p)
+    return fail(ctx, SOAP_EINVAL, "the list does not match the last build on this context");
+  if (nl->n_atoms > 0 && !pos) return fail(ctx, SOAP_EINVAL, "null positions");
+  const int ns = nl->n_structures;
+  const soap::StructMeta* dmeta = (const soap::StructMeta*)ctx->meta.p;
+  const int* dso = (const int*)((const char*)ctx->meta.p + sizeof(soap::StructMeta) * ns);
+  SOAP_HIP(ctx, soap::launch_pair_vectors(pair_bound(nl), pair_count(nl), pos, dmeta, dso, ns, nl->center, nl->j,
+                                          nl->img, nl->dx, nl->dy, nl->dz, st));
+  return SOAP_OK;
+}
+
+soap_status soap_set_neighbor_skin(soap_ctx* ctx, double skin) {
+  if (!ctx) return SOAP_EINVAL;
+  if (!(skin >= 0.0) || !(skin <= ctx->dp.rc)) return fail(ctx, SOAP_EINVAL, "skin must be in [0, r_cut]");
+  ctx->skin = skin;
   return SOAP_OK;
 }
 

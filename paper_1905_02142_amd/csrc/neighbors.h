@@ -60,6 +60,11 @@ hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructM
 // pairs 0..min(*count, bound) (count nullptr: 0..bound); list ranges are cut at bound
 hipError_t launch_reverse(long long bound, const int* count, const int* offsets, const int* nj, const int* nimg,
                           const int* ncenter, int* rev, int* err, hipStream_t st);
+// pair vectors d_p = r_j + T cell - r_i of listed pairs 0..min(*count, bound) (count
+// nullptr: 0..bound) from positions pos
+hipError_t launch_pair_vectors(long long bound, const int* count, const double* pos, const StructMeta* meta,
+                               const int* so, int n_struct, const int* ncenter, const int* nj, const int* nimg,
+                               double* ndx, double* ndy, double* ndz, hipStream_t st);
 // out[0] = *total, out[1] = *err, written by one kernel (out may be mapped host memory)
 hipError_t launch_report(const int* total, const int* err, int* out, hipStream_t st);
 

@@ -484,6 +484,31 @@ __global__ void k_init_build(int n_bins, int* __restrict__ bin_count, int* __res
   if (t < 4) err[t] = 0;
 }
 
+// d_p = (r_j - r_i) + T cell for every listed pair from the current positions,
+// with the expression and operation order of k_pairs, so unmoved atoms give the
+// bits of a fresh build (a list reused under a Verlet skin)
+__global__ __launch_bounds__(256) void k_pair_vectors(long long bound, const int* __restrict__ count,
+                                                      const double* __restrict__ pos,
+                                                      const StructMeta* __restrict__ meta,
+                                                      const int* __restrict__ so, int n_struct,
+                                                      const int* __restrict__ ncenter, const int* __restrict__ nj,
+                                                      const int* __restrict__ nimg, double* __restrict__ ndx,
+                                                      double* __restrict__ ndy, double* __restrict__ ndz) {
+  const long long n_pairs = count ? min(bound, (long long)max(*count, 0)) : bound;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const int i = ncenter[p], j = nj[p];
+  const StructMeta& M = meta[find_structure(so, n_struct, i)];
+  int T[3];
+  unpack_img(nimg[p], T);
+  const double tx = T[0] * M.cell[0] + T[1] * M.cell[3] + T[2] * M.cell[6];
+  const double ty = T[0] * M.cell[1] + T[1] * M.cell[4] + T[2] * M.cell[7];
+  const double tz = T[0] * M.cell[2] + T[1] * M.cell[5] + T[2] * M.cell[8];
+  ndx[p] = (pos[3 * j] - pos[3 * i]) + tx;
+  ndy[p] = (pos[3 * j + 1] - pos[3 * i + 1]) + ty;
+  ndz[p] = (pos[3 * j + 2] - pos[3 * i + 2]) + tz;
+}
+
 // out[0] = pair count, out[1] = error bits of the last build (out may be host-pinned memory)
 __global__ void k_report(const int* __restrict__ total, const int* __restrict__ err, int* __restrict__ out) {
   if (threadIdx.x == 0) {
@@ -493,6 +518,15 @@ __global__ void k_report(const int* __restrict__ total, const int* __restrict__ 
 }
 
 }  // namespace
+
+hipError_t launch_pair_vectors(long long bound, const int* count, const double* pos, const StructMeta* meta,
+                               const int* so, int n_struct, const int* ncenter, const int* nj, const int* nimg,
+                               double* ndx, double* ndy, double* ndz, hipStream_t st) {
+  if (bound == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_vectors, dim3((unsigned)((bound + 255) / 256)), dim3(256), 0, st, bound, count, pos, meta,
+                     so, n_struct, ncenter, nj, nimg, ndx, ndy, ndz);
+  return hipGetLastError();
+}
 
 hipError_t launch_report(const int* total, const int* err, int* out, hipStream_t st) {
   hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, st, total, err, out);

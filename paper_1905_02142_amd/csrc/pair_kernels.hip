@@ -153,6 +153,10 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
   radial<NMAX, DERIV>(P, tab, r, B, dB);
+  if (!(r < P.rc)) {  // a pair of a list built with a skin beyond r_cut: no density, no gradient
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;
+  }
   const double sp = P.s0p + P.ap * r;
   const double zz = r * r / (sp * sp);
   constexpr int LE = DERIV ? LMAX + 1 : LMAX;

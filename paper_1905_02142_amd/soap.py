@@ -211,6 +211,16 @@ class Soap:
                                e.data_ptr(), _ptr(F), _ptr(ab), _stream())
         return e, F, ab
 
+    def update_pair_vectors(self, nl: NeighbourList, positions: torch.Tensor) -> None:
+        """soap_update_pair_vectors: the list's d_p from the current positions (a reused skin list)."""
+        pos = positions.contiguous()
+        assert pos.dtype == torch.float64 and pos.is_cuda
+        _lib.soap_update_pair_vectors(self.ctx, nl.c_struct(), pos.data_ptr(), _stream())
+
+    def set_neighbor_skin(self, skin: float) -> None:
+        """soap_set_neighbor_skin: later lists reach r_cut + skin (pairs beyond r_cut weigh zero)."""
+        _lib.soap_set_neighbor_skin(self.ctx, skin)
+
     # ---------------------------------------------------------------- tuning
     @property
     def tuning(self) -> dict:
