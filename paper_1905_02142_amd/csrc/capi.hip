@@ -47,8 +47,8 @@ struct soap_ctx {
   Buf tune_out;  // scratch outputs of the autotuner
   size_t pinned_bytes = 0;
   // neighbour build
-  Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_atoms, counts, scan_part,
-      errflag;
+  Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_cand, counts, opre,
+      scan_part, errflag;
   // descriptor / adjoint
   Buf rows, bc, c, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
   // stage timing
@@ -293,7 +293,7 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
 void soap_destroy(soap_ctx* ctx) {
   if (!ctx) return;
   Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
-                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_atoms, &ctx->counts, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c,
+                 &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_cand, &ctx->counts, &ctx->opre, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c,
                  &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp, &ctx->tune_out};
   for (Buf* b : bufs)
     if (b->p) hipFree(b->p);
@@ -318,7 +318,7 @@ namespace {
 
 // Everything of a neighbour build up to the filled list, enqueued on st with no
 // host synchronisation.  The pair count stays on the device (offsets[n_atoms]);
-// the fill and the reverse search write only below the capacity, so a list that
+// the fill writes only below the capacity, so a list that
 // overflows is detected afterwards, from the count, without any access beyond it.
 soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells, const int32_t* pbc,
                           const int32_t* struct_offsets, int n_structures, soap_nlist* nl, hipStream_t st) {
@@ -335,6 +335,7 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
   std::vector<soap::StructMeta> meta(n_structures);
   std::vector<int> so(n_structures + 1);
   int n_bins = 0;
+  long long n_opre = 0;  // per-(centre, slab offset) hit prefixes of the count pass
   for (int s = 0; s <= n_structures; ++s) {
     so[s] = struct_offsets ? struct_offsets[s] : (s == 0 ? 0 : n_atoms);
     if (s > 0 && so[s] < so[s - 1]) return fail(ctx, SOAP_EINVAL, "structure offsets must be non-decreasing");
@@ -384,6 +385,11 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
     M.bin0 = n_bins;
     M.atom0 = so[s];
     M.atom1 = so[s + 1];
+    M.n_off = (2 * M.R[0] + 1) * (2 * M.R[1] + 1) * (2 * M.R[2] + 1);
+    M.pad_ = 0;
+    M.obase = n_opre;
+    n_opre += (long long)M.n_off * (so[s + 1] - so[s]);
+    if (nb_total > (1 << 30) - n_bins) return fail(ctx, SOAP_ENOTSUP, "too many cell-list bins");
     n_bins += nb_total;
   }
   const size_t up = sizeof(soap::StructMeta) * n_structures + sizeof(int) * (n_structures + 1);
@@ -398,7 +404,8 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
   SOAP_ENSURE(ctx, ctx->bin_count, sizeof(int) * n_bins);
   SOAP_ENSURE(ctx, ctx->bin_start, sizeof(int) * (n_bins + 1));
   SOAP_ENSURE(ctx, ctx->bin_cursor, sizeof(int) * n_bins);
-  SOAP_ENSURE(ctx, ctx->bin_atoms, sizeof(int) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->bin_cand, sizeof(soap::Cand) * n_atoms);
+  SOAP_ENSURE(ctx, ctx->opre, sizeof(int) * (size_t)std::max(n_opre, 1LL));
   SOAP_ENSURE(ctx, ctx->bin_unsorted, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->counts, sizeof(int) * n_atoms);
   SOAP_ENSURE(ctx, ctx->scan_part,
@@ -426,8 +433,8 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
   if (soap::bin_small_fits(n_atoms, n_bins)) {
     // the cell list of a small system in one launch
     SOAP_HIP(ctx, soap::launch_bin_small(n_atoms, pos, dmeta, dso, n_structures, n_bins, (int*)ctx->atom_bin.p,
-                                         (int*)ctx->atom_wrap.p, (int*)ctx->bin_start.p, (int*)ctx->bin_atoms.p, err,
-                                         st));
+                                         (int*)ctx->atom_wrap.p, (int*)ctx->bin_start.p, (soap::Cand*)ctx->bin_cand.p,
+                                         err, st));
   } else {
     SOAP_HIP(ctx, soap::launch_init_build(n_bins, (int*)ctx->bin_count.p, (int*)ctx->bin_cursor.p, err, st));
     if (n_atoms > 0) {
@@ -437,25 +444,25 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
     SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->bin_count.p, n_bins, (int*)ctx->bin_start.p,
                                        (int*)ctx->scan_part.p, st));
     if (n_atoms > 0) {
-      SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, (const int*)ctx->atom_bin.p, (const int*)ctx->bin_start.p,
-                                           (int*)ctx->bin_cursor.p, (int*)ctx->bin_unsorted.p,
-                                           (int*)ctx->bin_atoms.p, st));
+      SOAP_HIP(ctx, soap::launch_fill_bins(n_atoms, pos, (const int*)ctx->atom_bin.p, (const int*)ctx->atom_wrap.p,
+                                           (const int*)ctx->bin_start.p, (int*)ctx->bin_cursor.p,
+                                           (int*)ctx->bin_unsorted.p, (soap::Cand*)ctx->bin_cand.p, st));
     }
   }
   if (n_atoms > 0) {
     SOAP_HIP(ctx, soap::launch_pairs(false, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
-                                     (const int*)ctx->bin_atoms.p, (int*)ctx->counts.p, nullptr, 0, nullptr, nullptr,
-                                     nullptr, nullptr, nullptr, nullptr, nullptr, err, st));
+                                     (const soap::Cand*)ctx->bin_cand.p, (int*)ctx->counts.p, (int*)ctx->opre.p,
+                                     nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, err,
+                                     st));
   }
   SOAP_HIP(ctx, soap::scan_exclusive((const int*)ctx->counts.p, n_atoms, nl->offsets, (int*)ctx->scan_part.p, st));
   if (n_atoms > 0 && nl->capacity > 0) {
     SOAP_HIP(ctx, soap::launch_pairs(true, n_atoms, pos, dmeta, dso, n_structures, rc, (const int*)ctx->atom_bin.p,
                                      (const int*)ctx->atom_wrap.p, (const int*)ctx->bin_start.p,
-                                     (const int*)ctx->bin_atoms.p, nullptr, nl->offsets, nl->capacity, nl->j, nl->img,
-                                     nl->center, nl->dx, nl->dy, nl->dz, nl->rev, err, st));
-    SOAP_HIP(ctx, soap::launch_reverse(nl->capacity, nl->offsets + n_atoms, nl->offsets, nl->j, nl->img, nl->center,
-                                       nl->rev, err, st));
+                                     (const soap::Cand*)ctx->bin_cand.p, nullptr, (int*)ctx->opre.p, nl->offsets,
+                                     nl->capacity, nl->j, nl->img, nl->center, nl->dx, nl->dy, nl->dz, nl->rev, err,
+                                     st));
   }
   nl->n_atoms = n_atoms;
   nl->n_structures = n_structures;
@@ -467,8 +474,7 @@ soap_status enqueue_build(soap_ctx* ctx, int n_atoms, const double* pos, const d
 
 // Waits for the last build on st and reads its pair count and error bits (one
 // kernel writes both into pinned host memory).  Input errors come first, then
-// capacity overflow (required_pairs holds the count needed), then the
-// reverse-pair consistency check.
+// capacity overflow (required_pairs holds the count needed).
 soap_status read_report(soap_ctx* ctx, const soap_nlist* nl, long long* total_out, hipStream_t st) {
   if (!ctx->report) {
     if (hipHostMalloc((void**)&ctx->report, 64, hipHostMallocDefault) != hipSuccess) {
@@ -492,7 +498,6 @@ soap_status read_report(soap_ctx* ctx, const soap_nlist* nl, long long* total_ou
   if (eb & soap::kErrFarOutside) return fail(ctx, SOAP_EINVAL, "atom more than 500 cells outside its cell");
   if (total < 0) return fail(ctx, SOAP_ENOTSUP, "pair count overflows 32-bit offsets");
   if (total > nl->capacity) return fail(ctx, SOAP_EOVERFLOW, "neighbour list capacity too small");
-  if (eb & soap::kErrNoReverse) return fail(ctx, SOAP_EHIP, "a pair without its reverse (internal error)");
   return SOAP_OK;
 }
 

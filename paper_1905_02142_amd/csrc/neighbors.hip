@@ -9,7 +9,13 @@
 // narrower than 2 r_cut work unchanged.  Non-periodic axes use one slab.
 //
 // Order: each centre's pairs follow the fixed slab-offset loop and, within a
-// bin, ascending atom index, so the list is identical on every run.
+// bin, ascending atom index, so the list is identical on every run.  That order
+// also places every reverse pair without a search: if centre i meets j at slab
+// offset o with bin shift g, centre j meets i at offset -o with shift -g, after
+// its hits of the offsets before -o (recorded per centre and offset by the count
+// pass) and after the atoms of i's bin with a smaller index that j also reaches.
+#include <hip/hip_runtime.h>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -88,6 +94,38 @@ __global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const S
   atomicAdd(&bin_count[bin], 1);
 }
 
+// the bins of up to PER atoms per thread (t + k * kSmallBinThreads) of one
+// structure's geometry M, counted into the LDS bin counters; mybin[k] stays -1
+// for k beyond the atoms
+template <int PER>
+__device__ inline void bin_block(int n_atoms, const double* __restrict__ pos, const StructMeta& M, int t,
+                                 int* __restrict__ atom_bin, int* __restrict__ atom_wrap, int* __restrict__ cnt,
+                                 int* __restrict__ err, int (&mybin)[PER], int (&mywrap)[PER]) {
+#pragma unroll
+  for (int k0 = 0; k0 < PER; k0 += 4) {
+    if (k0 * kSmallBinThreads >= n_atoms) break;  // the same for every thread
+    // four positions requested before any is used; out-of-range atoms read the last one
+    double px[4], py[4], pz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = min(t + (k0 + k) * kSmallBinThreads, n_atoms - 1);
+      px[k] = pos[3 * a];
+      py[k] = pos[3 * a + 1];
+      pz[k] = pos[3 * a + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = t + (k0 + k) * kSmallBinThreads;
+      if (a < n_atoms) {
+        locate_pos(M, px[k], py[k], pz[k], err, mybin[k0 + k], mywrap[k0 + k]);
+        atom_bin[a] = mybin[k0 + k];
+        atom_wrap[a] = mywrap[k0 + k];
+        atomicAdd(&cnt[mybin[k0 + k]], 1);
+      }
+    }
+  }
+}
+
 // The whole cell list of a small system in one workgroup: error word cleared,
 // atoms binned, bin counts scanned into bin_start, atoms placed by LDS cursors
 // and then ranked by index inside each bin; the same result as k_init_build ..
@@ -98,64 +136,60 @@ __global__ __launch_bounds__(kSmallBinThreads) void k_bin_small(int n_atoms, con
                                                                 const StructMeta* __restrict__ meta,
                                                                 const int* __restrict__ so, int n_struct, int n_bins,
                                                                 int* __restrict__ atom_bin, int* __restrict__ atom_wrap,
-                                                                int* __restrict__ bin_start,
-                                                                int* __restrict__ bin_atoms, int* __restrict__ err) {
+                                                                int* __restrict__ bin_start, Cand* __restrict__ cand,
+                                                                int* __restrict__ err) {
   constexpr int PER = kSmallAtoms / kSmallBinThreads;  // atoms per thread at most
   extern __shared__ int lds[];
   int* cnt = lds;               // n_bins: counts, then cursors
   int* start = lds + n_bins;    // n_bins
-  int* unsorted = lds + 2 * n_bins;  // n_atoms; its first kSmallBinThreads words serve the scan first
-  int* part = unsorted;
+  int* unsorted = lds + 2 * n_bins;  // n_atoms
   const int t = threadIdx.x;
   for (int b = t; b < n_bins; b += kSmallBinThreads) cnt[b] = 0;
   if (t < 4) err[t] = 0;
   __syncthreads();
-  int mybin[PER];
-  // positions of eight atoms loaded together, then binned
+  int mybin[PER], mywrap[PER];
 #pragma unroll
-  for (int k0 = 0; k0 < PER; k0 += 8) {
-    double px[8], py[8], pz[8];
+  for (int k = 0; k < PER; ++k) mybin[k] = mywrap[k] = -1;
+  if (n_struct == 1) {
+    // one structure: its geometry sits in scalar registers for every atom
+    const StructMeta M = meta[0];
+    bin_block<PER>(n_atoms, pos, M, t, atom_bin, atom_wrap, cnt, err, mybin, mywrap);
+  } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = t + (k0 + k) * kSmallBinThreads;
-      const bool ok = a < n_atoms;
-      px[k] = ok ? pos[3 * a] : 0.0;
-      py[k] = ok ? pos[3 * a + 1] : 0.0;
-      pz[k] = ok ? pos[3 * a + 2] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = t + (k0 + k) * kSmallBinThreads;
-      mybin[k0 + k] = -1;
+    for (int k = 0; k < PER; ++k) {
+      const int a = t + k * kSmallBinThreads;
       if (a < n_atoms) {
-        int wrap;
-        // one structure: its geometry is the same for every lane
-        const StructMeta& M = meta[n_struct == 1 ? 0 : find_structure(so, n_struct, a)];
-        locate_pos(M, px[k], py[k], pz[k], err, mybin[k0 + k], wrap);
-        atom_bin[a] = mybin[k0 + k];
-        atom_wrap[a] = wrap;
-        atomicAdd(&cnt[mybin[k0 + k]], 1);
+        locate_atom(a, pos, meta, so, n_struct, err, mybin[k], mywrap[k]);
+        atom_bin[a] = mybin[k];
+        atom_wrap[a] = mywrap[k];
+        atomicAdd(&cnt[mybin[k]], 1);
       }
     }
   }
   __syncthreads();
-  // exclusive scan: thread t owns bins t*per .. t*per+per-1
+  // exclusive scan of the bin counts: thread t owns bins t*per .. t*per+per-1;
+  // a scan inside each wavefront, then over the wavefront totals
+  __shared__ int wsum[kSmallBinThreads / 64];
   const int per = (n_bins + kSmallBinThreads - 1) / kSmallBinThreads;
   int sum = 0;
   for (int k = 0; k < per; ++k) {
     const int b = t * per + k;
     if (b < n_bins) sum += cnt[b];
   }
-  part[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < kSmallBinThreads; o <<= 1) {
-    const int x = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += x;
-    __syncthreads();
+  const int lane = t & 63, w = t >> 6;
+  int incl = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += v;
   }
-  int run = part[t] - sum;
-  const int total = part[kSmallBinThreads - 1];
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int run = incl - sum, total = 0;
+  for (int k = 0; k < kSmallBinThreads / 64; ++k) {
+    const int v = wsum[k];
+    run += k < w ? v : 0;
+    total += v;
+  }
   for (int k = 0; k < per; ++k) {
     const int b = t * per + k;
     if (b < n_bins) {
@@ -167,43 +201,75 @@ __global__ __launch_bounds__(kSmallBinThreads) void k_bin_small(int n_atoms, con
     }
   }
   if (t == 0) bin_start[n_bins] = total;
-  __syncthreads();  // the scan is done with `part` before `unsorted` is written
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; ++k)
     if (mybin[k] >= 0) unsorted[atomicAdd(&cnt[mybin[k]], 1)] = t + k * kSmallBinThreads;
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    if (mybin[k] >= 0) {
-      const int a = t + k * kSmallBinThreads;
-      const int s0 = start[mybin[k]], e0 = cnt[mybin[k]];  // the cursor ends at the bin's end
-      int rank = 0;
-      for (int q = s0; q < e0; ++q) rank += unsorted[q] < a;
-      bin_atoms[s0 + rank] = a;
+  for (int k0 = 0; k0 < PER; k0 += 4) {
+    if (k0 * kSmallBinThreads >= n_atoms) break;
+    double px[4], py[4], pz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = min(t + (k0 + k) * kSmallBinThreads, n_atoms - 1);
+      px[k] = pos[3 * a];
+      py[k] = pos[3 * a + 1];
+      pz[k] = pos[3 * a + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (mybin[k0 + k] >= 0) {
+        const int a = t + (k0 + k) * kSmallBinThreads;
+        const int s0 = start[mybin[k0 + k]], e0 = cnt[mybin[k0 + k]];  // the cursor ends at the bin's end
+        int rank = 0;
+        for (int q = s0; q < e0; ++q) rank += unsorted[q] < a;
+        Cand c;
+        c.x = px[k];
+        c.y = py[k];
+        c.z = pz[k];
+        c.j = a;
+        c.wrap = mywrap[k0 + k];
+        cand[s0 + rank] = c;
+      }
     }
   }
 }
 
 __global__ void k_fill_bins(int n_atoms, const int* __restrict__ atom_bin, const int* __restrict__ bin_start,
-                            int* __restrict__ bin_cursor, int* __restrict__ bin_atoms) {
+                            int* __restrict__ bin_cursor, int* __restrict__ unsorted) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n_atoms) return;
   int bin = atom_bin[a];
   int slot = atomicAdd(&bin_cursor[bin], 1);
-  bin_atoms[bin_start[bin] + slot] = a;
+  unsorted[bin_start[bin] + slot] = a;
 }
 
 // place atom a at its rank (by index) among the atoms of its bin; `unsorted`
 // holds each bin's atoms in the arbitrary order the atomics produced
-__global__ void k_rank_bins(int n_atoms, const int* __restrict__ atom_bin, const int* __restrict__ bin_start,
-                            const int* __restrict__ unsorted, int* __restrict__ bin_atoms) {
+__global__ void k_rank_bins(int n_atoms, const double* __restrict__ pos, const int* __restrict__ atom_bin,
+                            const int* __restrict__ atom_wrap, const int* __restrict__ bin_start,
+                            const int* __restrict__ unsorted, Cand* __restrict__ cand) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n_atoms) return;
   const int bin = atom_bin[a];
   const int s = bin_start[bin], e = bin_start[bin + 1];
   int rank = 0;
   for (int t = s; t < e; ++t) rank += unsorted[t] < a;
-  bin_atoms[s + rank] = a;
+  Cand c;
+  c.x = pos[3 * a];
+  c.y = pos[3 * a + 1];
+  c.z = pos[3 * a + 2];
+  c.j = a;
+  c.wrap = atom_wrap[a];
+  cand[s + rank] = c;
+}
+
+// bits lo..hi-1 of a 64-bit mask (0 <= lo <= hi <= 64)
+__device__ inline unsigned long long bit_range(int lo, int hi) {
+  const unsigned long long below_hi = hi >= 64 ? ~0ull : (1ull << hi) - 1ull;
+  const unsigned long long below_lo = lo >= 64 ? ~0ull : (1ull << lo) - 1ull;
+  return below_hi & ~below_lo;
 }
 
 // One wavefront per centre atom.  The (2R+1)^3 slab offsets are taken 64 at a
@@ -211,44 +277,69 @@ __global__ void k_rank_bins(int n_atoms, const int* __restrict__ atom_bin, const
 // turns the counts into a flat candidate range, and the lanes then sweep the
 // candidates 64 at a time.  Hits are compacted with a ballot, so the pair order
 // (offset order, then ascending atom index within a bin) is fixed.
+//
+// Count pass: count[i], and opre[i][o] = the hits of i before offset o.
+// Fill pass: the pairs, and rev of each.  For the pair (i -> j, T) found at
+// offset o with bin shift g, centre j meets i's bin at offset n_off - 1 - o
+// with shift -g; among that bin's atoms (ascending index) the ones before i that
+// j reaches precede (j -> i, -T) in j's list, so
+//   rev = offsets[j] + opre[j][n_off - 1 - o] + #{a in bin(i), a < i, j reaches a},
+// where "j reaches a" is evaluated with exactly the arithmetic of j's own scan.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __restrict__ pos,
                                                const StructMeta* __restrict__ meta, const int* __restrict__ so,
                                                int n_struct, double rc2, const int* __restrict__ atom_bin,
                                                const int* __restrict__ atom_wrap, const int* __restrict__ bin_start,
-                                               const int* __restrict__ bin_atoms, int* __restrict__ count,
-                                               const int* __restrict__ offsets, long long capacity,
-                                               int* __restrict__ nj, int* __restrict__ nimg,
+                                               const Cand* __restrict__ cand, int* __restrict__ count,
+                                               int* __restrict__ opre, const int* __restrict__ offsets,
+                                               long long capacity, int* __restrict__ nj, int* __restrict__ nimg,
                                                int* __restrict__ ncenter, double* __restrict__ ndx,
                                                double* __restrict__ ndy, double* __restrict__ ndz,
                                                int* __restrict__ nrev, int* __restrict__ err) {
   __shared__ int s_pref[4][65];   // inclusive scan of candidate counts
-  __shared__ int s_start[4][64];  // first bin_atoms slot of each offset
+  __shared__ int s_start[4][64];  // first cand slot of each offset
   __shared__ int s_shift[4][64];  // lattice shift of each offset (packed)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wv;
+  // the centre is uniform over the wavefront: its data and its structure's
+  // geometry are read once into scalar registers
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
   if (i >= n_atoms) return;
-  const StructMeta& M = meta[find_structure(so, n_struct, i)];
+  const StructMeta& M = meta[n_struct == 1 ? 0 : find_structure(so, n_struct, i)];
+  double cell[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cell[k] = M.cell[k];
+  const int nb0 = M.nbin[0], nb1 = M.nbin[1], nb2 = M.nbin[2];
+  const int R0 = M.R[0], R1 = M.R[1], R2 = M.R[2];
+  const int p0 = M.pbc[0], p1 = M.pbc[1], p2 = M.pbc[2];
+  const int bin0 = M.bin0;
   const double pix = pos[3 * i], piy = pos[3 * i + 1], piz = pos[3 * i + 2];
-  const int local = atom_bin[i] - M.bin0;
-  const int b0 = local % M.nbin[0], b1 = (local / M.nbin[0]) % M.nbin[1], b2 = local / (M.nbin[0] * M.nbin[1]);
+  const int bi = atom_bin[i];
+  const int local = bi - bin0;
+  const int b0 = local % nb0, b1 = (local / nb0) % nb1, b2 = local / (nb0 * nb1);
   int wi[3];
   unpack_img(atom_wrap[i], wi);
-  const int n0 = 2 * M.R[0] + 1, n1 = 2 * M.R[1] + 1, n2 = 2 * M.R[2] + 1;
+  const int n0 = 2 * R0 + 1, n1 = 2 * R1 + 1, n2 = 2 * R2 + 1;
   const int n_off = n0 * n1 * n2;
+  // opre of centre a of this structure: opre + obase_a + a * n_off
+  int* const opre_s = opre + (M.obase - (long long)M.atom0 * n_off);
   long long out = FILL ? offsets[i] : 0;
+  // fill: the slots of i's bin holding atoms with a smaller index than i
+  const int m0 = FILL ? bin_start[bi] : 0;
+  int m1 = m0;
+  if (FILL)
+    while (cand[m1].j < i) ++m1;  // i itself is in the bin, so this stops
   int cnt = 0;
   for (int g0 = 0; g0 < n_off; g0 += 64) {
     const int o = g0 + lane;
     int len = 0, start = 0, shift = 0;
     if (o < n_off) {
-      const int ox = o % n0 - M.R[0], oy = (o / n0) % n1 - M.R[1], oz = o / (n0 * n1) - M.R[2];
+      const int ox = o % n0 - R0, oy = (o / n0) % n1 - R1, oz = o / (n0 * n1) - R2;
       const int ux = b0 + ox, uy = b1 + oy, uz = b2 + oz;
-      const int gx = M.pbc[0] ? floordiv(ux, M.nbin[0]) : 0;
-      const int gy = M.pbc[1] ? floordiv(uy, M.nbin[1]) : 0;
-      const int gz = M.pbc[2] ? floordiv(uz, M.nbin[2]) : 0;
-      const int cx = ux - gx * M.nbin[0], cy = uy - gy * M.nbin[1], cz = uz - gz * M.nbin[2];
-      const int bin = M.bin0 + (cz * M.nbin[1] + cy) * M.nbin[0] + cx;
+      const int gx = p0 ? floordiv(ux, nb0) : 0;
+      const int gy = p1 ? floordiv(uy, nb1) : 0;
+      const int gz = p2 ? floordiv(uz, nb2) : 0;
+      const int cx = ux - gx * nb0, cy = uy - gy * nb1, cz = uz - gz * nb2;
+      const int bin = bin0 + (cz * nb1 + cy) * nb0 + cx;
       start = bin_start[bin];
       len = bin_start[bin + 1] - start;
       shift = pack_img(gx, gy, gz);
@@ -259,6 +350,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
       const int v = __shfl_up(incl, d, 64);
       if (lane >= d) incl += v;
     }
+    const int excl = incl - len;
     s_pref[wv][lane + 1] = incl;
     if (lane == 0) s_pref[wv][0] = 0;
     s_start[wv][lane] = start;
@@ -266,47 +358,76 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS writes visible to the wave
     const int total = __shfl(incl, 63, 64);
+    int my_hits = 0;  // count pass: hits of offset o (this lane's)
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
       bool hit = false;
-      int j = 0, T0 = 0, T1 = 0, T2 = 0;
+      int lo = 0, j = 0, T0 = 0, T1 = 0, T2 = 0;
+      Cand a;
+      a.x = a.y = a.z = 0.0;
+      a.j = a.wrap = 0;
       double ddx = 0.0, ddy = 0.0, ddz = 0.0;
       if (c < total) {
         // offset b with s_pref[b] <= c < s_pref[b + 1]
-        int lo = 0, hi = 64;
+        int hi = 64;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
           if (s_pref[wv][mid] <= c) lo = mid;
           else hi = mid;
         }
-        j = bin_atoms[s_start[wv][lo] + (c - s_pref[wv][lo])];
+        a = cand[s_start[wv][lo] + (c - s_pref[wv][lo])];
+        j = a.j;
         int gsh[3], wj[3];
         unpack_img(s_shift[wv][lo], gsh);
-        unpack_img(atom_wrap[j], wj);
+        unpack_img(a.wrap, wj);
         T0 = gsh[0] - wj[0] + wi[0];
         T1 = gsh[1] - wj[1] + wi[1];
         T2 = gsh[2] - wj[2] + wi[2];
         if (!(j == i && T0 == 0 && T1 == 0 && T2 == 0)) {
           // d = (r_j - r_i) + T cell, the same operation order for a pair and its reverse
-          const double tx = T0 * M.cell[0] + T1 * M.cell[3] + T2 * M.cell[6];
-          const double ty = T0 * M.cell[1] + T1 * M.cell[4] + T2 * M.cell[7];
-          const double tz = T0 * M.cell[2] + T1 * M.cell[5] + T2 * M.cell[8];
-          ddx = (pos[3 * j] - pix) + tx;
-          ddy = (pos[3 * j + 1] - piy) + ty;
-          ddz = (pos[3 * j + 2] - piz) + tz;
-          const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          double tx, ty, tz;
+          lattice_shift(T0, T1, T2, cell, tx, ty, tz);
+          ddx = (a.x - pix) + tx;
+          ddy = (a.y - piy) + ty;
+          ddz = (a.z - piz) + tz;
+          const double r2 = __fma_rn(ddz, ddz, __fma_rn(ddy, ddy, ddx * ddx));
           hit = r2 < rc2;
           if (hit && r2 < 1e-16) atomicOr(err, kErrCoincident);
         }
       }
       const unsigned long long mask = __ballot(hit);
+      if (!FILL) {
+        // this lane's offset owns candidates excl..incl-1
+        const int lo_b = min(max(excl - c0, 0), 64), hi_b = min(max(incl - c0, 0), 64);
+        my_hits += __popcll(mask & bit_range(lo_b, hi_b));
+      }
       if (FILL && hit) {
         const long long q = out + __popcll(mask & ((1ull << lane) - 1ull));
         if (q < capacity) {
+          // the reverse pair: j's hits before the opposite offset, then the
+          // atoms of i's bin below i that j reaches with the shift -g
+          int gsh[3];
+          unpack_img(s_shift[wv][lo], gsh);
+          int wj[3];
+          unpack_img(a.wrap, wj);
+          int rank = 0;
+          for (int m = m0; m < m1; ++m) {
+            const Cand b = cand[m];
+            int wb[3];
+            unpack_img(b.wrap, wb);
+            const int U0 = -gsh[0] - wb[0] + wj[0], U1 = -gsh[1] - wb[1] + wj[1], U2 = -gsh[2] - wb[2] + wj[2];
+            if (!(b.j == j && U0 == 0 && U1 == 0 && U2 == 0)) {
+              double ux, uy, uz;
+              lattice_shift(U0, U1, U2, cell, ux, uy, uz);
+              const double ex = (b.x - a.x) + ux, ey = (b.y - a.y) + uy, ez = (b.z - a.z) + uz;
+              rank += __fma_rn(ez, ez, __fma_rn(ey, ey, ex * ex)) < rc2;
+            }
+          }
+          const long long rq = (long long)offsets[j] + opre_s[(long long)j * n_off + (n_off - 1 - (g0 + lo))] + rank;
           nj[q] = j;
           nimg[q] = pack_img(T0, T1, T2);
           ncenter[q] = i;
-          nrev[q] = (int)q;  // until the reverse search sets it
+          nrev[q] = rq < capacity ? (int)rq : (int)q;  // an overflowed list holds no valid reverse
           ndx[q] = ddx;
           ndy[q] = ddy;
           ndz[q] = ddz;
@@ -315,64 +436,19 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
       out += __popcll(mask);
       cnt += __popcll(mask);
     }
+    if (!FILL) {
+      // hits before each offset of this group: the centre's running count plus a wave scan
+      int h = my_hits;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(h, d, 64);
+        if (lane >= d) h += v;
+      }
+      const int group_hits = __shfl(h, 63, 64);  // read by every lane, outside the branch below
+      if (o < n_off) opre_s[(long long)i * n_off + o] = cnt - group_hits + (h - my_hits);
+    }
     __builtin_amdgcn_wave_barrier();
   }
   if (!FILL && lane == 0) count[i] = cnt;
-}
-
-// rev[p]: the pair (j -> i, -T) in j's list.  Only pairs with i < j search (16
-// lanes probe j's list with coalesced loads; the match is unique, so the
-// minimum over the probes is it) and set both directions; pairs with i == j (a
-// periodic image of the centre) search their own list; pairs with i > j are
-// set by their partner.  Every rev entry starts as the pair itself.
-// With a device-side count (count != nullptr) the pairs are the first
-// min(*count, bound) entries and every list range is cut at bound, so a list
-// that overflowed its capacity is searched only where it was written.
-__global__ __launch_bounds__(256) void k_reverse(long long bound, const int* __restrict__ count,
-                                                 const int* __restrict__ offsets, const int* __restrict__ nj,
-                                                 const int* __restrict__ nimg, const int* __restrict__ ncenter,
-                                                 int* __restrict__ rev, int* __restrict__ err) {
-  const long long n_pairs = count ? min(bound, (long long)max(*count, 0)) : bound;
-  const int cap = (int)min(bound, 2147483647LL);
-  const long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  const int sub = threadIdx.x & 15;
-  int found = 0x7fffffff;
-  bool searched = false;
-  int i = 0, j = 0;
-  if (p < n_pairs) {
-    i = ncenter[p];
-    j = nj[p];
-    if (i <= j) {
-      searched = true;
-      int T[3];
-      unpack_img(nimg[p], T);
-      const int want = pack_img(-T[0], -T[1], -T[2]);
-      // four probes per lane in flight: the list is swept 64 entries per round
-      const int q1 = min(offsets[j + 1], cap);
-      for (int q0 = min(offsets[j], cap) + sub; q0 < q1; q0 += 64) {
-        int cj[4], ci[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = q0 + 16 * u;
-          cj[u] = q < q1 ? nj[q] : -1;
-          ci[u] = q < q1 ? nimg[q] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (cj[u] == i && ci[u] == want) found = min(found, q0 + 16 * u);
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) found = min(found, __shfl_xor(found, o, 16));
-  if (searched && sub == 0) {
-    if (found == 0x7fffffff) {
-      atomicOr(err, kErrNoReverse);
-    } else {
-      rev[p] = found;
-      if (i < j) rev[found] = (int)p;
-    }
-  }
 }
 
 // ---------------------------------------------------------------- scan
@@ -501,9 +577,8 @@ __global__ __launch_bounds__(256) void k_pair_vectors(long long bound, const int
   const StructMeta& M = meta[find_structure(so, n_struct, i)];
   int T[3];
   unpack_img(nimg[p], T);
-  const double tx = T[0] * M.cell[0] + T[1] * M.cell[3] + T[2] * M.cell[6];
-  const double ty = T[0] * M.cell[1] + T[1] * M.cell[4] + T[2] * M.cell[7];
-  const double tz = T[0] * M.cell[2] + T[1] * M.cell[5] + T[2] * M.cell[8];
+  double tx, ty, tz;
+  lattice_shift(T[0], T[1], T[2], M.cell, tx, ty, tz);
   ndx[p] = (pos[3 * j] - pos[3 * i]) + tx;
   ndy[p] = (pos[3 * j + 1] - pos[3 * i + 1]) + ty;
   ndz[p] = (pos[3 * j + 2] - pos[3 * i + 2]) + tz;
@@ -553,10 +628,7 @@ hipError_t scan_exclusive(const int* in, int n, int* out, int* part, hipStream_t
 
 int scan_partials_needed(int n) { return (n + kScanTile) / kScanTile; }
 
-size_t bin_small_lds_bytes(int n_atoms, int n_bins) {
-  const int a = n_atoms > kSmallBinThreads ? n_atoms : kSmallBinThreads;
-  return sizeof(int) * ((size_t)a + 2 * (size_t)n_bins);
-}
+size_t bin_small_lds_bytes(int n_atoms, int n_bins) { return sizeof(int) * ((size_t)n_atoms + 2 * (size_t)n_bins); }
 
 bool bin_small_fits(int n_atoms, int n_bins) {
   return n_atoms > 0 && n_atoms <= kSmallAtoms && n_bins <= kSmallBins &&
@@ -564,7 +636,7 @@ bool bin_small_fits(int n_atoms, int n_bins) {
 }
 
 hipError_t launch_bin_small(int n_atoms, const double* pos, const StructMeta* meta, const int* so, int n_struct,
-                            int n_bins, int* atom_bin, int* atom_wrap, int* bin_start, int* bin_atoms, int* err,
+                            int n_bins, int* atom_bin, int* atom_wrap, int* bin_start, Cand* cand, int* err,
                             hipStream_t st) {
   if (!bin_small_fits(n_atoms, n_bins)) return hipErrorInvalidValue;
   static bool attr = false;  // LDS beyond 64 KB needs the opt-in once per process
@@ -575,7 +647,7 @@ hipError_t launch_bin_small(int n_atoms, const double* pos, const StructMeta* me
     attr = true;
   }
   hipLaunchKernelGGL(k_bin_small, dim3(1), dim3(kSmallBinThreads), bin_small_lds_bytes(n_atoms, n_bins), st, n_atoms,
-                     pos, meta, so, n_struct, n_bins, atom_bin, atom_wrap, bin_start, bin_atoms, err);
+                     pos, meta, so, n_struct, n_bins, atom_bin, atom_wrap, bin_start, cand, err);
   return hipGetLastError();
 }
 
@@ -586,34 +658,27 @@ hipError_t launch_bin_atoms(int n_atoms, const double* pos, const StructMeta* me
   return hipGetLastError();
 }
 
-hipError_t launch_fill_bins(int n_atoms, const int* atom_bin, const int* bin_start, int* bin_cursor, int* unsorted,
-                            int* bin_atoms, hipStream_t st) {
+hipError_t launch_fill_bins(int n_atoms, const double* pos, const int* atom_bin, const int* atom_wrap,
+                            const int* bin_start, int* bin_cursor, int* unsorted, Cand* cand, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_bins, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, atom_bin, bin_start,
                      bin_cursor, unsorted);
-  hipLaunchKernelGGL(k_rank_bins, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, atom_bin, bin_start,
-                     unsorted, bin_atoms);
+  hipLaunchKernelGGL(k_rank_bins, dim3((n_atoms + 255) / 256), dim3(256), 0, st, n_atoms, pos, atom_bin, atom_wrap,
+                     bin_start, unsorted, cand);
   return hipGetLastError();
 }
 
 hipError_t launch_pairs(bool fill, int n_atoms, const double* pos, const StructMeta* meta, const int* so,
                         int n_struct, double rc, const int* atom_bin, const int* atom_wrap, const int* bin_start,
-                        const int* bin_atoms, int* count, const int* offsets, long long capacity, int* nj, int* nimg,
-                        int* ncenter, double* ndx, double* ndy, double* ndz, int* nrev, int* err, hipStream_t st) {
+                        const Cand* cand, int* count, int* opre, const int* offsets, long long capacity, int* nj,
+                        int* nimg, int* ncenter, double* ndx, double* ndy, double* ndz, int* nrev, int* err,
+                        hipStream_t st) {
   dim3 g((n_atoms + 3) / 4), b(256);
   if (fill)
     hipLaunchKernelGGL(k_pairs<true>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
-                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, nrev, err);
+                       bin_start, cand, count, opre, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, nrev, err);
   else
     hipLaunchKernelGGL(k_pairs<false>, g, b, 0, st, n_atoms, pos, meta, so, n_struct, rc * rc, atom_bin, atom_wrap,
-                       bin_start, bin_atoms, count, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, nrev, err);
-  return hipGetLastError();
-}
-
-hipError_t launch_reverse(long long bound, const int* count, const int* offsets, const int* nj, const int* nimg,
-                          const int* ncenter, int* rev, int* err, hipStream_t st) {
-  if (bound == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reverse, dim3((unsigned)((bound + 15) / 16)), dim3(256), 0, st, bound, count, offsets, nj,
-                     nimg, ncenter, rev, err);
+                       bin_start, cand, count, opre, offsets, capacity, nj, nimg, ncenter, ndx, ndy, ndz, nrev, err);
   return hipGetLastError();
 }
 
