@@ -197,15 +197,29 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
 
 // fields 0..WIDTH-1 of the compacted pairs idx[0..cnt) copied into LDS rows,
 // dst[t * STRIDE + f]; for consecutive pairs each field is one or two
-// contiguous runs in HBM
-template <int WIDTH, int ROW, int CH, int STRIDE>
+// contiguous runs in HBM.  BATCH loads per lane are issued before the first is
+// stored, so the wave waits for memory ceil(WIDTH CH / (64 BATCH)) times instead
+// of once per load; out-of-range slots read the first field of the first block.
+template <int WIDTH, int ROW, int CH, int STRIDE, int BATCH>
 __device__ inline void stage_fields(const double* __restrict__ rows, const int* idx, int cnt,
                                     double* __restrict__ dst, int lane) {
-  for (int u = lane; u < WIDTH * CH; u += 64) {
-    const int f = u / CH, t = u % CH;
-    if (t < cnt) {
-      const int p = idx[t];
-      dst[t * STRIDE + f] = rows[(size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63)];
+  constexpr int ITER = (WIDTH * CH + 63) / 64;
+#pragma unroll 1
+  for (int k0 = 0; k0 < ITER; k0 += BATCH) {
+    double v[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int u = lane + 64 * (k0 + k);
+      const int f = u / CH, t = u % CH;
+      const bool ok = k0 + k < ITER && u < WIDTH * CH && t < cnt;
+      const int p = ok ? idx[t] : 0;
+      v[k] = rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int u = lane + 64 * (k0 + k);
+      const int f = u / CH, t = u % CH;
+      if (k0 + k < ITER && u < WIDTH * CH && t < cnt) dst[t * STRIDE + f] = v[k];
     }
   }
 }
@@ -258,7 +272,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      stage_fields<S::FR, S::ROW, CH, FRP>(rows, idx, cnt, dyn, lane);
+      stage_fields<S::FR, S::ROW, CH, FRP, 6>(rows, idx, cnt, dyn, lane);
       __syncthreads();
 #pragma unroll 2
       for (int t = 0; t < cnt; ++t) {
@@ -288,24 +302,37 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
         }
       }
     }
-    // c of species s: LL + 1 columns lm (the last one a sink, left zero) of NMAX channels
+    // c of species s: LL + 1 columns lm (the last one a sink, left zero) of NMAX
+    // channels; with one species it also goes to LDS, where the power spectrum
+    // reads it, once the wave is done with the staged rows
     double* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
+    const bool c_lds = P.ns == 1;
+    if (c_lds) __syncthreads();
 #pragma unroll
     for (int e = 0; e < E2; ++e) {
       if (lane + 64 * e >= S::NREC || R.lmc[e] == LL) continue;
       const bool central = R.lmc[e] == 0 && s == si;
       double* __restrict__ dc = cs + R.lmc[e] * NMAX;
 #pragma unroll
-      for (int k = 0; k < NMAX; k += 2)
-        *reinterpret_cast<double2*>(dc + k) = double2{acc[e][0][k] + (central ? bc_in[k] : 0.0),
-                                                      acc[e][0][k + 1] + (central ? bc_in[k + 1] : 0.0)};
+      for (int k = 0; k < NMAX; k += 2) {
+        const double2 v{acc[e][0][k] + (central ? bc_in[k] : 0.0), acc[e][0][k + 1] + (central ? bc_in[k + 1] : 0.0)};
+        *reinterpret_cast<double2*>(dc + k) = v;
+        if (c_lds) *reinterpret_cast<double2*>(dyn + R.lmc[e] * NMAX + k) = v;
+      }
       if (R.lms[e] != LL) {
         double* __restrict__ ds = cs + R.lms[e] * NMAX;
 #pragma unroll
-        for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(ds + k) = double2{acc[e][1][k], acc[e][1][k + 1]};
+        for (int k = 0; k < NMAX; k += 2) {
+          const double2 v{acc[e][1][k], acc[e][1][k + 1]};
+          *reinterpret_cast<double2*>(ds + k) = v;
+          if (c_lds) *reinterpret_cast<double2*>(dyn + R.lms[e] * NMAX + k) = v;
+        }
       }
     }
-    if (lane < NMAX) cs[LL * NMAX + lane] = 0.0;
+    if (lane < NMAX) {
+      cs[LL * NMAX + lane] = 0.0;
+      if (c_lds) dyn[LL * NMAX + lane] = 0.0;
+    }
   }
   __threadfence_block();
   __syncthreads();
@@ -318,9 +345,11 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   double* csh = dyn;
   double* __restrict__ qi = q_out + (size_t)i * q_pitch;
   double* __restrict__ pv = fwd_p_in_lds<NMAX, LMAX>(P) ? dyn + per_atom : qi;
-  for (int t = lane; t < per_atom / 2; t += 64)
-    reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci_out)[t];
-  __syncthreads();
+  if (P.ns > 1) {
+    for (int t = lane; t < per_atom / 2; t += 64)
+      reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci_out)[t];
+    __syncthreads();
+  }
   const int L1 = P.l + 1, nab = nch * (nch + 1) / 2;
   double ss = 0.0;
   for (int ab = lane; ab < nab; ab += 64) {
