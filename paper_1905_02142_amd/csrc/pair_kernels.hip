@@ -385,30 +385,102 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
 // i, written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
 // NMAX]) with zeros in the sink column lm = LL and in the channels k >= n_max.
 // vb: K doubles of LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a
-// block barrier.
+// block barrier.  The global reads are issued eight per lane at a time; with
+// one species the atom's c is first copied into cb, where each lane transforms
+// whole columns in place (a column of cbar needs only the same column of c).
 template <int NMAX>
 __device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
                                  const double* __restrict__ qbar, int qbar_pitch, double* cb, double* vb, int* abx,
                                  int lane) {
+  constexpr int B = 8;  // loads per lane in flight
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const double* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
   const double* qb = qbar + (size_t)i * qbar_pitch;
+  if (ns == 1) {
+    const int nc = NMAX * LLP;
+    for (int t0 = 0; t0 < nc; t0 += 64 * B) {
+      double v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) v[u] = csh[min(t0 + lane + 64 * u, nc - 1)];
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (t0 + lane + 64 * u < nc) cb[t0 + lane + 64 * u] = v[u];
+    }
+  }
   double dot = 0.0;
-  for (int k = lane; k < K; k += 64) dot = fma(qi[k], qb[k], dot);
+  for (int k0 = 0; k0 < K; k0 += 64 * B) {
+    double a[B], g[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int k = min(k0 + lane + 64 * u, K - 1);
+      a[u] = qi[k];
+      g[u] = qb[k];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + lane + 64 * u < K) dot = fma(a[u], g[u], dot);
+  }
   dot = wave_sum(dot);
   const double nrm = pnorm[i];
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int k = lane; k < K; k += 64) vb[k] = (qb[k] - qi[k] * dot) * inv;
+  for (int k0 = 0; k0 < K; k0 += 64 * B) {
+    double a[B], g[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int k = min(k0 + lane + 64 * u, K - 1);
+      a[u] = qi[k];
+      g[u] = qb[k];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + lane + 64 * u < K) vb[k0 + lane + 64 * u] = (g[u] - a[u] * dot) * inv;
+  }
   // abx[a][b] = (packed index of the pair {a, b}) * (l_max + 1), the row of vbar
-  for (int r = lane; r < nch * nch; r += 64) {
+  for (int r = lane; r < (ns > 1 ? nch * nch : 0); r += 64) {
     const int a = r / nch, b = r - a * nch;
     abx[r] = ab_index(a < b ? a : b, a < b ? b : a, nch) * L1;
   }
   __syncthreads();
-  // task = (column (s, lm), half of the NMAX channels);
   // M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b), vbar packed a <= b then l
+  if (ns == 1) {
+    for (int lm = lane; lm < LL; lm += 64) {
+      const int l = isqrt_small(lm);
+      double* col = cb + (size_t)lm * NMAX;
+      double cv[NMAX];
+#pragma unroll
+      for (int kb = 0; kb < NMAX; kb += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(col + kb);
+        cv[kb] = v.x;
+        cv[kb + 1] = v.y;
+      }
+      // each vbar entry of the symmetric M(l) is read once; every acc[k] still
+      // takes its terms in the order kb = 0, 1, ...
+      double acc[NMAX];
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int a = 0; a < NMAX; ++a)
+#pragma unroll
+        for (int b = a; b < NMAX; ++b)
+          if (b < n) {
+            const double v = vb[(a * nch - a * (a - 1) / 2 + (b - a)) * L1 + l];
+            if (a == b) {
+              acc[a] = fma(2.0 * v, cv[a], acc[a]);
+            } else {
+              const double w = kSqrt2 * v;
+              acc[a] = fma(w, cv[b], acc[a]);
+              acc[b] = fma(w, cv[a], acc[b]);
+            }
+          }
+#pragma unroll
+      for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(col + k) = double2{acc[k], acc[k + 1]};
+    }
+    __syncthreads();
+    return;
+  }
+  // several species: task = (column (s, lm), half of the NMAX channels), c read from HBM
   constexpr int KH = NMAX / 2;
   const double inv_llp = 1.0 / (double)LLP;
   for (int task = lane; task < 2 * ns * LLP; task += 64) {
