@@ -1,6 +1,6 @@
 // Descriptor forward and adjoint kernels (FP64 VALU).
 //
-// k_pair_prep, one thread per neighbour pair i -> j (d = r_j + T - r_i, r = |d|,
+// k_pair_prep, per neighbour pair i -> j (d = r_j + T - r_i, r = |d|,
 // u = d / r): everything of Eq. (08) that depends on the pair alone, written as
 // the pair's fields in HBM (blocks of 64 pairs, field-major, so every store and
 // every per-lane load of a field is one contiguous run) that the forward and the
@@ -124,6 +124,10 @@ __device__ inline void azimuthal_step(double& cr, double& ci, double ux, double 
   cr = nr;
 }
 
+// Two workgroups per block of pairs: even blocks write the radial fields (B_k,
+// dB_k/dr) and odd blocks the angular ones (w_l e_l, its derivative, the
+// azimuthal powers, u and 1/r), so each pair's serial FP64 chain is split in
+// two and twice as many wavefronts share the latency.
 template <int NMAX, int LMAX, bool DERIV>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
                                                      const int* __restrict__ count, const double* __restrict__ dx,
@@ -133,7 +137,16 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   __shared__ PairTab<NMAX, LMAX> tab;
   // pairs 0..n_pairs: the bound, or the device-side count cut at the bound
   const int n_pairs = count ? min(bound, max(*count, 0)) : bound;
-  if (blockIdx.x > 0 && (int)(blockIdx.x * blockDim.x) >= n_pairs) return;  // block 0 also writes bc
+  const int pblock = blockIdx.x >> 1;
+  const bool angular = blockIdx.x & 1;
+  if (pblock > 0 && (int)(pblock * blockDim.x) >= n_pairs) return;  // block 0 also writes bc
+  const int p = pblock * blockDim.x + threadIdx.x;
+  double x = 0.0, y = 0.0, z = 0.0;
+  if (p < n_pairs) {  // in flight while the tables are staged
+    x = dx[p];
+    y = dy[p];
+    z = dz[p];
+  }
   stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, blockDim.x);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -145,18 +158,29 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * tab.lw[0] * 0.28209479177387814;
   }
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
-  const double x = dx[p], y = dy[p], z = dz[p];
-  const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
-  double B[NMAX], dB[NMAX];
+  const double r = sqrt(x * x + y * y + z * z);
+  // field f of this pair: one coalesced 512-byte segment per field for each 64 pairs
+  double* __restrict__ row = rows + (size_t)(p >> 6) * (S::ROW * 64) + (p & 63);
+  auto st = [&](int f, double v) { row[f * 64] = v; };
+  if (!angular) {
+    double B[NMAX], dB[NMAX];
 #pragma unroll
-  for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
-  radial<NMAX, DERIV>(P, tab, r, B, dB);
-  if (!(r < P.rc)) {  // a pair of a list built with a skin beyond r_cut: no density, no gradient
+    for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
+    radial<NMAX, DERIV>(P, tab, r, B, dB);
+    if (!(r < P.rc)) {  // a pair of a list built with a skin beyond r_cut: no density, no gradient
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;
+      for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) st(S::FB + k, B[k]);
+    if (DERIV) {
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) st(S::FR + S::XD + k, dB[k]);
+    }
+    return;
   }
+  const double ir = 1.0 / r;
   const double sp = P.s0p + P.ap * r;
   const double zz = r * r / (sp * sp);
   constexpr int LE = DERIV ? LMAX + 1 : LMAX;
@@ -167,11 +191,6 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   const double izz = 1.0 / zz;
   const double dzdr = 2.0 * r / (sp * sp) - 2.0 * r * r * P.ap / (sp * sp * sp);
   const double ux = x * ir, uy = y * ir, uz = z * ir;
-  // field f of this pair: one coalesced 512-byte segment per field for each 64 pairs
-  double* __restrict__ row = rows + (size_t)(p >> 6) * (S::ROW * 64) + (p & 63);
-  auto st = [&](int f, double v) { row[f * 64] = v; };
-#pragma unroll
-  for (int k = 0; k < NMAX; ++k) st(S::FB + k, B[k]);
 #pragma unroll
   for (int l = 0; l <= LMAX; ++l) st(S::FW + l, tab.lw[l] * e[l]);
   st(S::FU, uz);
@@ -183,8 +202,6 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
     azimuthal_step(cr, ci, ux, uy);
   }
   if (DERIV) {
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k) st(S::FR + S::XD + k, dB[k]);
     // d e_l / dz = e_{l+1} + (l/z - 1) e_l
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l)
@@ -624,16 +641,34 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
     form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar_pitch, cb, rc, abx, lane);  // vbar in the record region
   }
   {
-    for (int u = lane; u < nrec * NC; u += 64) {
-      const int r = u / NC, t = u - r * NC;
-      rc[u] = T->rec_coef[r % kRecLanes][r / kRecLanes][t];
+    // the record table, every global read of a lane issued before its stores
+    constexpr int RPL = (S::NREC * NC + 63) / 64;
+    double v[RPL];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const int u = min(lane + 64 * k, nrec * NC - 1), r = u / NC, t = u - r * NC;
+      v[k] = T->rec_coef[r % kRecLanes][r / kRecLanes][t];
     }
-    for (int r = lane; r < nrec; r += 64) {
-      const int jj = r % kRecLanes, slot = r / kRecLanes;
-      const int ls = T->rec_lm[jj][slot][1];
-      ri[4 * r] = T->rec_lmp[jj][slot] >> 16;
-      ri[4 * r + 1] = T->rec_lm[jj][slot][0];
-      ri[4 * r + 2] = ls < 0 ? P.LL : ls;
+    constexpr int IPL = (S::NREC + 63) / 64;
+    int lmp[IPL], lc[IPL], ls[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const int r = min(lane + 64 * k, nrec - 1), jj = r % kRecLanes, slot = r / kRecLanes;
+      lmp[k] = T->rec_lmp[jj][slot];
+      lc[k] = T->rec_lm[jj][slot][0];
+      ls[k] = T->rec_lm[jj][slot][1];
+    }
+#pragma unroll
+    for (int k = 0; k < RPL; ++k)
+      if (lane + 64 * k < nrec * NC) rc[lane + 64 * k] = v[k];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const int r = lane + 64 * k;
+      if (r < nrec) {
+        ri[4 * r] = lmp[k] >> 16;
+        ri[4 * r + 1] = lc[k];
+        ri[4 * r + 2] = ls[k] < 0 ? P.LL : ls[k];
+      }
     }
   }
   __syncthreads();
@@ -775,7 +810,8 @@ hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_
                             const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
                             int block, hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
-  const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);  // block 0 also writes bc
+  // two workgroups (radial, angular) per block of pairs; block 0 also writes bc
+  const int blocks = 2 * ((int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0));
   auto f = [&]<int N, int LM>() {
     const int np = (int)n_pairs;
     if (deriv)

@@ -73,14 +73,32 @@ struct PairTab {
   double idf[LMAX + 3];
 };
 
+// every entry of the tables requested before any is stored, so a workgroup
+// waits for memory once; the struct is read as one array of doubles
+// (nthreads >= 64)
 template <int NMAX, int LMAX>
 __device__ inline void stage_pair_tables(const DevTables* __restrict__ T, PairTab<NMAX, LMAX>& t, int lane,
                                          int nthreads) {
-  for (int x = lane; x < NMAX * NMAX; x += nthreads) t.W[x / NMAX][x % NMAX] = T->W[(x / NMAX) * kMaxN + x % NMAX];
-  for (int x = lane; x < NMAX; x += nthreads) t.invN[x] = T->invN[x];
-  for (int x = lane; x < LMAX + 2; x += nthreads) t.lw[x] = T->lw[x];
-  for (int x = lane; x < 3 * kIlexpTerms; x += nthreads) t.rec[x / kIlexpTerms][x % kIlexpTerms] = T->ilx_rec[x / kIlexpTerms][x % kIlexpTerms];
-  for (int x = lane; x < LMAX + 3; x += nthreads) t.idf[x] = T->ilx_idf[x];
+  constexpr int nW = NMAX * NMAX, nI = NMAX, nL = LMAX + 2, nR = 3 * kIlexpTerms, nD = LMAX + 3;
+  constexpr int total = nW + nI + nL + nR + nD;
+  static_assert(sizeof(PairTab<NMAX, LMAX>) == total * sizeof(double), "PairTab is a plain array of doubles");
+  constexpr int PER = (total + 63) / 64;
+  double v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    int y = lane + k * nthreads;
+    const double* src = T->W;  // past the end: any valid address
+    if (y < nW) src = T->W + (y / NMAX) * kMaxN + y % NMAX;
+    else if ((y -= nW) < nI) src = T->invN + y;
+    else if ((y -= nI) < nL) src = T->lw + y;
+    else if ((y -= nL) < nR) src = &T->ilx_rec[0][0] + y;
+    else if ((y -= nR) < nD) src = T->ilx_idf + y;
+    v[k] = *src;
+  }
+  double* dst = reinterpret_cast<double*>(&t);
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (lane + k * nthreads < total) dst[lane + k * nthreads] = v[k];
 }
 
 constexpr double kPi = 3.14159265358979323846;
