@@ -376,12 +376,17 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
     const double* ca = csh + sa * LLP * NMAX + (a - sa * n);
     const double* cb = csh + sb * LLP * NMAX + (b - sb * n);
     const double scale = a != b ? kSqrt2 : 1.0;
-    for (int l = 0; l < L1; ++l) {
-      double v = 0.0;
-      for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) v = fma(ca[lm * NMAX], cb[lm * NMAX], v);
-      v *= scale;
-      pv[ab * L1 + l] = v;
-      ss = fma(v, v, ss);
+    // unrolled over l and m, so that the LDS reads of each l are issued together
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      if (l < L1) {
+        double v = 0.0;
+#pragma unroll
+        for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) v = fma(ca[lm * NMAX], cb[lm * NMAX], v);
+        v *= scale;
+        pv[ab * L1 + l] = v;
+        ss = fma(v, v, ss);
+      }
     }
   }
   ss = wave_sum(ss);
