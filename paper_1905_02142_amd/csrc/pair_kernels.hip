@@ -712,31 +712,32 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
 }
 
 // F_k = sum over k's pairs q of (g_q - g_rev(q)) (= -dE/dr_k); mode 1 adds -F_k into
-// pos_grad.  16 lanes per atom stride over its pairs; the partial sums are
-// combined by a fixed butterfly, so the result is the same on every run.
+// pos_grad.  One wavefront per atom, one pair per lane (an atom's list is
+// usually shorter than 64, so its reverse indices and both gradients are read
+// in one round); the lane sums are combined by a fixed butterfly, so the result
+// is the same on every run.
 __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets, int bound,
                                                       const int* __restrict__ rev, const double* __restrict__ gx,
                                                       const double* __restrict__ gy, const double* __restrict__ gz,
                                                       double* __restrict__ out, int accumulate_grad) {
-  const int k = blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int sub = threadIdx.x & 15;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= n_atoms) return;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  if (k < n_atoms) {
-    const int q1 = min(offsets[k + 1], bound);
-    for (int q = min(offsets[k], bound) + sub; q < q1; q += 16) {
-      const int r = rev[q];
-      fx += gx[q] - gx[r];
-      fy += gy[q] - gy[r];
-      fz += gz[q] - gz[r];
-    }
+  const int q1 = min(offsets[k + 1], bound);
+  for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
+    const int r = rev[q];
+    fx += gx[q] - gx[r];
+    fy += gy[q] - gy[r];
+    fz += gz[q] - gz[r];
   }
 #pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) {
-    fx += __shfl_xor(fx, o, 16);
-    fy += __shfl_xor(fy, o, 16);
-    fz += __shfl_xor(fz, o, 16);
+  for (int o = 32; o >= 1; o >>= 1) {
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
   }
-  if (k < n_atoms && sub == 0) {
+  if (lane == 0) {
     if (accumulate_grad) {
       out[3 * k] -= fx;
       out[3 * k + 1] -= fy;
@@ -880,7 +881,7 @@ hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qba
 hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
                                const double* gz, double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 15) / 16), dim3(256), 0, st, n_atoms, offsets, bound, rev, gx, gy, gz,
+  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 3) / 4), dim3(256), 0, st, n_atoms, offsets, bound, rev, gx, gy, gz,
                      out, accumulate_grad ? 1 : 0);
   return hipGetLastError();
 }
