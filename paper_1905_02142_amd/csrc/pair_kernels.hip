@@ -564,29 +564,47 @@ __device__ inline void adjoint_records(int L, const double* __restrict__ cb, con
   const double x2 = uz * uz;
   for (int l = 0; l <= L; ++l) {
     const double we = F(S::FW + l), wd = F(S::FR + S::XW + l);
-    // (u_x + i u_y)^m and ^(m-1) by the recurrence of the per-pair kernel (the same bits)
-    double zr = 1.0, zi = 0.0, zr1 = 1.0, zi1 = 0.0;
-#pragma unroll 2
-    for (int m = 0; m <= l; ++m) {
-      // the record of (l, m) in the tables: m outer, l = m..L inner
-      const int r = m * (L + 1) - m * (m - 1) / 2 + (l - m);
+    // Qbar_lm = x^par R(x^2), R of degree (l - m) / 2: the higher table
+    // coefficients are zero, so Horner starts at the top non-zero one (the same
+    // bits as running over all NC)
+    auto qbar = [&](int r, int m, double& Q, double& Qd) {
       const double* __restrict__ cf = rc + r * NC;
-      const int par = ri[4 * r], lc = ri[4 * r + 1], ls = ri[4 * r + 2];
-      // Qbar_lm and its derivative: Q = x^par R(x^2)
-      double Rv = cf[NC - 1], Rd = 0.0;
-#pragma unroll
-      for (int t2 = NC - 2; t2 >= 0; --t2) {
+      const int par = ri[4 * r], d = (l - m) >> 1;
+      double Rv = cf[d], Rd = 0.0;
+      for (int t2 = d - 1; t2 >= 0; --t2) {
         Rd = fma(Rd, x2, Rv);
         Rv = fma(Rv, x2, cf[t2]);
       }
-      const double Q = par ? uz * Rv : Rv;
-      const double Qd = par ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
-      if (m > 0) {
-        zr1 = zr;
-        zi1 = zi;
-        azimuthal_step(zr, zi, ux, uy);
+      Q = par ? uz * Rv : Rv;
+      Qd = par ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
+    };
+    {
+      // m = 0 (record r = l): only the cos column (the sin column is the sink, all
+      // zeros), no azimuthal factor and no contribution to S_x, S_y
+      double Q, Qd;
+      qbar(l, 0, Q, Qd);
+      const double* __restrict__ c0 = cb + ri[4 * l + 1] * NMAX;
+      double U0 = 0.0, V0 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) {
+        U0 = fma(c0[k], db[k], U0);
+        V0 = fma(c0[k], b[k], V0);
       }
-      // the sin column of m = 0 is the sink column, which holds zeros
+      sr = fma(Q, fma(U0, we, V0 * wd), sr);
+      sz = fma(Qd, V0 * we, sz);
+    }
+    // (u_x + i u_y)^m and ^(m-1) by the recurrence of the per-pair kernel (the same bits)
+    double zr = 1.0, zi = 0.0, zr1 = 1.0, zi1 = 0.0;
+#pragma unroll 2
+    for (int m = 1; m <= l; ++m) {
+      // the record of (l, m) in the tables: m outer, l = m..L inner
+      const int r = m * (L + 1) - m * (m - 1) / 2 + (l - m);
+      const int lc = ri[4 * r + 1], ls = ri[4 * r + 2];
+      double Q, Qd;
+      qbar(r, m, Q, Qd);
+      zr1 = zr;
+      zi1 = zi;
+      azimuthal_step(zr, zi, ux, uy);
       const double* __restrict__ c0 = cb + lc * NMAX;
       const double* __restrict__ c1 = cb + ls * NMAX;
       double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
