@@ -47,7 +47,8 @@ def _gpu_nl(soap, s_list):
     return nl, pos
 
 
-@pytest.mark.parametrize("case", ["box64", "small_box_images", "triclinic", "batch3", "cluster"])
+@pytest.mark.parametrize("case", ["box64", "small_box_images", "tiny_cell", "thin_slab", "triclinic", "batch3",
+                                  "cluster"])
 def test_neighbour_list_matches_oracle(case):
     rc = 3.7
     if case == "box64":
@@ -55,6 +56,17 @@ def test_neighbour_list_matches_oracle(case):
     elif case == "small_box_images":
         rc = 5.5
         ss = [synth.rsa_box(6, 5.2, 1.2, 12)]
+    elif case == "tiny_cell":
+        # 2.4 A cell, r_cut 5: 7 slab offsets per axis (343, six groups of 64)
+        rc = 5.0
+        cell = np.eye(3) * 2.4
+        ss = [synth.Structure(np.array([[0.3, 0.4, 0.5], [1.5, 1.7, 1.2]]), cell, np.ones(3, np.int32))]
+    elif case == "thin_slab":
+        # one axis far thinner than r_cut: 5 x 5 x 7 offsets
+        rc = 5.0
+        cell = np.diag([11.0, 10.5, 2.3])
+        frac = np.random.default_rng(6).random((18, 3))
+        ss = [synth.Structure(frac @ cell, cell, np.ones(3, np.int32))]
     elif case == "triclinic":
         cell = np.array([[6.0, 0.0, 0.0], [2.5, 5.5, 0.0], [1.0, -1.5, 6.2]])
         frac = np.random.default_rng(4).random((8, 3))
