@@ -172,7 +172,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              f"the multi-GPU decomposition is described in DESIGN.md and not run here", file=sys.stderr)
+              f"the multi-GPU decomposition is not run here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

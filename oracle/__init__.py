@@ -16,7 +16,7 @@ Paper: M. A. Caro, "Optimizing many-body atomic descriptors for enhanced
 computational performance of machine learning based interatomic potentials",
 arXiv:1905.02142.  Section / equation references are to that paper.
 
-Readings of points the paper leaves open (each is also listed in the design doc):
+Readings of points the paper leaves open:
   * W = S^{-1/2} is formed in 50-digit arithmetic from S by direct quadrature of
     the basis definitions; S over [0, r_cut] for every pair of basis functions,
     the Gaussian basis overlap with a neighbour integrated to infinity as printed.
