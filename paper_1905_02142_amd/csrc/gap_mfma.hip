@@ -339,6 +339,19 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
   static_assert(sizeof(T) * P::BM * GP <= sizeof(Smem<P>), "G tile must fit in the operand LDS");
   T* gt = reinterpret_cast<T*>(&sm);
   double rows[TM][4] = {}, cols[TN] = {};
+  // 16-bit operands: the zeta power in FP32 (its rounding is far below that of
+  // the operands); otherwise in FP64
+  using E = typename std::conditional<sizeof(T) == 2, float, double>::type;
+  // the weights of this lane's columns, read once; a padding column (gs >= M)
+  // has weight 0, and its scores, like those of padding rows, are exactly 0
+  // (zero operand rows), so the tile needs no per-element bounds test: padding
+  // contributes nothing to the sums, and its G entries are 0 or never stored
+  E al_y[TN];
+#pragma unroll
+  for (int y = 0; y < TN; ++y) {
+    const int gs = s0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
+    al_y[y] = gs < M ? (E)alpha[gs] : (E)0;
+  }
 #pragma unroll
   for (int pass = 0; pass < (P::kSplit ? 2 : 1); ++pass) {
 #pragma unroll
@@ -349,22 +362,15 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
         for (int r = 0; r < 4; ++r) {
           const int lr = wm * (P::BM / 2) + acc_row<P>(x, r, lane);
           const int lc = wn * (P::BN / 2) + y * 16 + (lane & 15);
-          const int gi = i0 + lr, gs = s0 + lc;
-          double g = 0.0;
-          if (gi < N && gs < M) {
-            // 16-bit operands: the zeta power in FP32 (its rounding is far below
-            // that of the operands); otherwise in FP64
-            using E = typename std::conditional<sizeof(T) == 2, float, double>::type;
-            const E sv = (E)acc[x][y][r];
-            E sz1 = (E)1;
-            for (int t = 1; t < zeta; ++t) sz1 *= sv;
-            const E al = (E)alpha[gs];
-            g = (double)((E)zeta * al * sz1);
-            if (pass == 0) {
-              const double kv = (double)(sz1 * sv);
-              rows[x][r] = fma((double)al, kv, rows[x][r]);
-              cols[y] += kv;
-            }
+          const E sv = (E)acc[x][y][r];
+          E sz1 = (E)1;
+          for (int t = 1; t < zeta; ++t) sz1 *= sv;
+          const E al = al_y[y];
+          const double g = (double)((E)zeta * al * sz1);
+          if (pass == 0) {
+            const double kv = (double)(sz1 * sv);
+            rows[x][r] = fma((double)al, kv, rows[x][r]);
+            cols[y] += kv;
           }
           const T gh = cvt<T>(g);
           gt[lr * GP + lc] = pass == 0 ? gh : cvt_lo_any<T>(g, gh);
