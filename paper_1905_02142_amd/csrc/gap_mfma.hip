@@ -115,27 +115,29 @@ __global__ void k_convert(int rows, int cols, int rows_p, int cols_p, const doub
 
 // the three operand conversions of one GAP call in one launch: Q (N x Kp), Q_s
 // (Mp x Kp) and Q_s^T (Kp x Mp), zero padded
-template <typename T, bool SPLIT>
+// I: the element index type, int when N Kp + 2 Mp Kp fits (its divisions are
+// much cheaper than 64-bit ones), else long long
+template <typename T, bool SPLIT, typename I>
 __global__ void k_convert3(int N, int M, int K, int Kp, int Mp, const double* __restrict__ Q,
                            const double* __restrict__ Qs, T* __restrict__ qc, T* __restrict__ qc_lo,
                            T* __restrict__ qsc, T* __restrict__ qsc_lo, T* __restrict__ qst, T* __restrict__ qst_lo) {
-  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long n1 = (long long)N * Kp, n2 = (long long)Mp * Kp;
+  I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  const I n1 = (I)N * Kp, n2 = (I)Mp * Kp;
   double x;
   T* dst;
   T* dlo;
   if (e < n1) {
-    const int r = (int)(e / Kp), c = (int)(e - (long long)r * Kp);
+    const int r = (int)(e / Kp), c = (int)(e - (I)r * Kp);
     x = c < K ? Q[(size_t)r * K + c] : 0.0;
     dst = qc;
     dlo = qc_lo;
   } else if ((e -= n1) < n2) {
-    const int r = (int)(e / Kp), c = (int)(e - (long long)r * Kp);
+    const int r = (int)(e / Kp), c = (int)(e - (I)r * Kp);
     x = (r < M && c < K) ? Qs[(size_t)r * K + c] : 0.0;
     dst = qsc;
     dlo = qsc_lo;
   } else if ((e -= n2) < n2) {
-    const int r = (int)(e / Mp), c = (int)(e - (long long)r * Mp);  // dst[r][c] = Qs[c][r]
+    const int r = (int)(e / Mp), c = (int)(e - (I)r * Mp);  // dst[r][c] = Qs[c][r]
     x = (c < M && r < K) ? Qs[(size_t)c * K + r] : 0.0;
     dst = qst;
     dlo = qst_lo;
@@ -888,8 +890,13 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
   T *qst = (T*)(w + L.qst), *qst_lo = (T*)(w + L.qst_lo), *G = (T*)(w + L.g), *G_lo = (T*)(w + L.g_lo);
   double *e_part = (double*)(w + L.e_part), *ab_part = (double*)(w + L.ab_part);
   auto blocks = [](long long n) { return dim3((unsigned)((n + 255) / 256)); };
-  hipLaunchKernelGGL((k_convert3<T, P::kSplit>), blocks((long long)N * Kp + 2LL * Mp * Kp), dim3(256), 0, st, N, M,
-                     K, Kp, Mp, Q, Qs, qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
+  const long long nconv = (long long)N * Kp + 2LL * Mp * Kp;
+  if (nconv < 2147483647LL - 256)
+    hipLaunchKernelGGL((k_convert3<T, P::kSplit, int>), blocks(nconv), dim3(256), 0, st, N, M, K, Kp, Mp, Q, Qs, qc,
+                       qc_lo, qsc, qsc_lo, qst, qst_lo);
+  else
+    hipLaunchKernelGGL((k_convert3<T, P::kSplit, long long>), blocks(nconv), dim3(256), 0, st, N, M, K, Kp, Mp, Q, Qs,
+                       qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
   const int nst = (Mp + P::BN - 1) / P::BN, nit = (N + P::BM - 1) / P::BM;
   static bool attr = false;  // operand tiles above 64 KB of LDS need the opt-in
   if (!attr && sizeof(Smem<P>) > 65536) {
