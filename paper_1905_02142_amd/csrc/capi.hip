@@ -566,8 +566,8 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                             (const double*)ctx->rows.p, (const double*)ctx->c.p,
-                                            (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, q_bar, P.K,
-                                            (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+                                            (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, q_bar, nullptr,
+                                            P.K, (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
   SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
@@ -599,8 +599,8 @@ soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const 
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                             (const double*)ctx->rows.p, (const double*)ctx->c.p,
-                                            (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qb, P.K, tile,
-                                            tile + NP, tile + 2 * NP, st));
+                                            (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qb, nullptr, P.K,
+                                            tile, tile + NP, tile + 2 * NP, st));
   }
   return SOAP_OK;
 }
@@ -625,13 +625,17 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, forces != nullptr, st)) != SOAP_OK)
     return s;
+  const int prec = (int)ctx->prm.precision;
+  const bool fused = forces && ctx->tune.gap_fused && soap::gap_fused_supported(P.K, prec);
+  // the unfused Qbar pass splits its contraction over the sparse points into
+  // parts that the adjoint adds
+  const int slices = fused ? 1 : soap::gap_qbar_slices(M, prec);
   double* qbar = nullptr;
   if (forces) {
-    SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * N * P.K);
+    SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * slices * N * P.K);
     qbar = (double*)ctx->qbar.p;
   }
-  const int prec = (int)ctx->prm.precision;
-  if (qbar && ctx->tune.gap_fused && soap::gap_fused_supported(P.K, prec)) {
+  if (fused) {
     const int target = ctx->tune.gap_slices > 0 ? ctx->tune.gap_slices : 512;
     SOAP_ENSURE(ctx, ctx->gapw, soap::gap_fused_workspace_bytes((int)N, M, P.K, prec, target));
     StageTimer tm(ctx, SOAP_STAGE_GAP_FUSED, st);
@@ -647,7 +651,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     }
     if (qbar) {
       StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
-      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, e_atom, alpha_grad, ctx->gapw.p, st));
+      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, e_atom, alpha_grad, ctx->gapw.p, slices, st));
     }
   }
   if (forces) {
@@ -658,8 +662,9 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                               (const double*)ctx->rows.p, (const double*)ctx->c.p,
-                                              (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qbar, P.K,
-                                              (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+                                              (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qbar,
+                                              slices == 2 ? qbar + N * P.K : nullptr, P.K, (double*)ctx->gx.p,
+                                              (double*)ctx->gy.p, (double*)ctx->gz.p, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,

@@ -14,10 +14,15 @@ size_t gap_workspace_bytes(int N, int M, int K, int prec);
 // finish (e and alpha_bar are then written by that call)
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
                              int zeta, double* e, double* alpha_bar, bool sums, void* work, hipStream_t st);
-// Qbar (N x K) = G Q_s, from the operands the scores pass left in work; with e
-// non-null it also finishes e and alpha_bar (nullable) from the partial sums
+// Qbar = G Q_s, from the operands the scores pass left in work, as `slices`
+// parts (Qbar + s N K, s < slices, each N x K) that sum to it: part s contracts
+// over the sparse points s Mp / slices .. (s + 1) Mp / slices - 1, which
+// multiplies the workgroups of this long contraction.  With e non-null it also
+// finishes e and alpha_bar (nullable) from the partial sums
 hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar,
-                           const void* work, hipStream_t st);
+                           const void* work, int slices, hipStream_t st);
+// the slice count launch_gap_qbar accepts and that pays off for M sparse points: 1 or 2
+int gap_qbar_slices(int M, int prec);
 
 // Fused scores + Qbar (prec 1..3, padded K <= 352): e, alpha_bar (nullable) and
 // Qbar in one pass with no N x M intermediate in HBM

@@ -431,7 +431,8 @@ __device__ inline double ordered_sum(const double* __restrict__ part, int n, int
 
 // Qbar tile = G (N x Mp) Q_s^T-converted (Kp x Mp)^T, written for descriptor columns < K
 template <typename P>
-__global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, const typename P::T* __restrict__ G,
+__global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, int kslice,
+                                              const typename P::T* __restrict__ G,
                                               const typename P::T* __restrict__ G_lo,
                                               const typename P::T* __restrict__ QsT,
                                               const typename P::T* __restrict__ QsT_lo, double* __restrict__ Qbar,
@@ -449,7 +450,11 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, cons
   for (int x = 0; x < TM; ++x)
 #pragma unroll
     for (int y = 0; y < TN; ++y) acc[x][y] = typename P::Acc{};
-  gemm_tile<P>(sm, G, G_lo, Mp, N, QsT, QsT_lo, Mp, Kp, Mp, i0, c0, acc);
+  // slice z of the contraction over the sparse points: points z kslice ..
+  // (z + 1) kslice - 1, into its own N x K part of Qbar
+  const int z = blockIdx.z, k0 = z * kslice;
+  gemm_tile<P>(sm, G + k0, G_lo + k0, Mp, N, QsT + k0, QsT_lo + k0, Mp, Kp, kslice, i0, c0, acc);
+  double* __restrict__ Qz = Qbar + (size_t)z * N * K;
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
@@ -458,11 +463,12 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, cons
       for (int r = 0; r < 4; ++r) {
         const int gi = i0 + wm * (P::BM / 2) + acc_row<P>(x, r, lane);
         const int gc = c0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
-        if (gi < N && gc < K) Qbar[(size_t)gi * K + gc] = (double)acc[x][y][r];
+        if (gi < N && gc < K) Qz[(size_t)gi * K + gc] = (double)acc[x][y][r];
       }
-  // the scores pass's per-tile partial sums, finished here (e non-null): each
-  // workgroup takes one slice of the N + M outputs, each output a fixed-order sum
-  if (e) {
+  // the scores pass's per-tile partial sums, finished here (e non-null) by the
+  // first slice: each workgroup takes one part of the N + M outputs, each
+  // output a fixed-order sum
+  if (e && z == 0) {
     const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
     const int per = (N + M + nb - 1) / nb, j1 = min((b + 1) * per, N + M);
     for (int j = b * per + tid; j < j1; j += 256) {
@@ -914,7 +920,7 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
 }
 
 template <typename P>
-hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work,
+hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work, int slices,
                      hipStream_t st) {
   using T = typename P::T;
   const Layout L = layout<P>(N, M, K);
@@ -927,8 +933,9 @@ hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha
   const double* e_part = (const double*)(w + L.e_part);
   const double* ab_part = (const double*)(w + L.ab_part);
   const int nst = Mp / P::BN, nsi = (N + P::BM - 1) / P::BM;  // the scores pass's tile counts
-  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit), dim3(256), 0, st, N, K, Mp, Kp, G, G_lo, qst, qst_lo, Qbar, M, nst,
-                     e_part, e, nsi, ab_part, alpha_bar);
+  if (slices < 1 || Mp % (slices * Q::KT) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit, slices), dim3(256), 0, st, N, K, Mp, Kp, Mp / slices, G, G_lo, qst,
+                     qst_lo, Qbar, M, nst, e_part, e, nsi, ab_part, alpha_bar);
   return hipGetLastError();
 }
 
@@ -985,14 +992,27 @@ hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, cons
   }
 }
 
+int gap_qbar_slices(int M, int prec) {
+  const int Mp = padded(M);
+  int kt;
+  switch (prec) {
+    case 0: kt = QbarTile<PF64>::KT; break;
+    case 1: kt = QbarTile<PF32>::KT; break;
+    case 2: kt = QbarTile<PBF16>::KT; break;
+    default: kt = QbarTile<PBF16X3>::KT; break;
+  }
+  // two slices once each keeps at least four K-steps
+  return (Mp % (2 * kt) == 0 && Mp / 2 >= 4 * kt) ? 2 : 1;
+}
+
 hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work,
-                           hipStream_t st) {
+                           int slices, hipStream_t st) {
   if (N == 0) return hipSuccess;
   switch (prec) {
-    case 0: return qbar_impl<PF64>(N, M, K, Qbar, e, alpha_bar, work, st);
-    case 1: return qbar_impl<PF32>(N, M, K, Qbar, e, alpha_bar, work, st);
-    case 2: return qbar_impl<PBF16>(N, M, K, Qbar, e, alpha_bar, work, st);
-    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, e, alpha_bar, work, st);
+    case 0: return qbar_impl<PF64>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+    case 1: return qbar_impl<PF32>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+    case 2: return qbar_impl<PBF16>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
   }
 }
 

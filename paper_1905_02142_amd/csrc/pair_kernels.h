@@ -37,12 +37,14 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
                              int q_pitch, double* pnorm, hipStream_t st);
 
 // pair gradients g_p = dE/dd_p (SoA) from qbar = dE/dq (n_atoms rows of
-// qbar_pitch), the forward c, q, |p| and the pair rows with derivatives; cbar is
-// formed per atom inside the kernel
+// qbar_pitch; with qbar2 non-null, qbar + qbar2, the two parts of a sliced GAP
+// contraction), the forward c, q, |p| and the pair rows with derivatives; cbar
+// is formed per atom inside the kernel
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                                const int* nj, const int* species, const double* rows, const double* c,
-                               const double* q, int q_pitch, const double* pnorm, const double* qbar, int qbar_pitch,
-                               double* gx, double* gy, double* gz, hipStream_t st);
+                               const double* q, int q_pitch, const double* pnorm, const double* qbar,
+                               const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
+                               hipStream_t st);
 
 // angular records (Qbar_lm polynomials) and ilexp series tables for these parameters
 void build_angular_tables(const DevParams& P, DevTables& T);

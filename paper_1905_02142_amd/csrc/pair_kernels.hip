@@ -404,7 +404,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
 }
 
 // vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm} of atom
-// i, written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
+// i (qbar = qbar + qbar2 when qbar2 is not null, in that order), written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
 // NMAX]) with zeros in the sink column lm = LL and in the channels k >= n_max.
 // vb: K doubles of LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a
 // block barrier.  The global reads are issued eight per lane at a time; with
@@ -413,13 +413,14 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
 template <int NMAX>
 __device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
-                                 const double* __restrict__ qbar, int qbar_pitch, double* cb, double* vb, int* abx,
-                                 int lane) {
+                                 const double* __restrict__ qbar, const double* __restrict__ qbar2, int qbar_pitch,
+                                 double* cb, double* vb, int* abx, int lane) {
   constexpr int B = 8;  // loads per lane in flight
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const double* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
   const double* qb = qbar + (size_t)i * qbar_pitch;
+  const double* qb2 = qbar2 ? qbar2 + (size_t)i * qbar_pitch : nullptr;  // a second part of qbar, added
   if (ns == 1) {
     const int nc = NMAX * LLP;
     for (int t0 = 0; t0 < nc; t0 += 64 * B) {
@@ -440,6 +441,10 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
       a[u] = qi[k];
       g[u] = qb[k];
     }
+    if (qb2) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) g[u] += qb2[min(k0 + lane + 64 * u, K - 1)];
+    }
 #pragma unroll
     for (int u = 0; u < B; ++u)
       if (k0 + lane + 64 * u < K) dot = fma(a[u], g[u], dot);
@@ -454,6 +459,10 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
       const int k = min(k0 + lane + 64 * u, K - 1);
       a[u] = qi[k];
       g[u] = qb[k];
+    }
+    if (qb2) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) g[u] += qb2[min(k0 + lane + 64 * u, K - 1)];
     }
 #pragma unroll
     for (int u = 0; u < B; ++u)
@@ -642,6 +651,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
                                                                        const double* __restrict__ q, int q_pitch,
                                                                        const double* __restrict__ pnorm,
                                                                        const double* __restrict__ qbar,
+                                                                       const double* __restrict__ qbar2,
                                                                        int qbar_pitch, double* __restrict__ gx,
                                                                        double* __restrict__ gy,
                                                                        double* __restrict__ gz) {
@@ -661,7 +671,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
   {
     const int nrec_d = nrec * NC + 2 * nrec;
     int* abx = reinterpret_cast<int*>(rc + (nrec_d > P.K ? nrec_d : P.K));
-    form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar_pitch, cb, rc, abx, lane);  // vbar in the record region
+    form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);  // vbar in the record region
   }
   {
     // the record table, every global read of a lane issued before its stores
@@ -865,13 +875,14 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                                const int* nj, const int* species, const double* rows, const double* c,
-                               const double* q, int q_pitch, const double* pnorm, const double* qbar, int qbar_pitch,
-                               double* gx, double* gy, double* gz, hipStream_t st) {
+                               const double* q, int q_pitch, const double* pnorm, const double* qbar,
+                               const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
+                               hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
     hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
-                       rows, c, q, q_pitch, pnorm, qbar, qbar_pitch, gx, gy, gz);
+                       rows, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, gx, gy, gz);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
