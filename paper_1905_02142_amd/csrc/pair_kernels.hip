@@ -403,14 +403,55 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   if (lane == 0 && pnorm_out) pnorm_out[i] = nrm;
 }
 
+// cbar = M(l) c in place for every column lm < LL of one species' cb, one
+// column per lane: M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b),
+// vbar packed a <= b then l
+template <int NMAX>
+__device__ inline void transform_columns(int n, int nch, int LL, int L1, double* cb, const double* vb, int lane) {
+  for (int lm = lane; lm < LL; lm += 64) {
+    const int l = isqrt_small(lm);
+    double* col = cb + (size_t)lm * NMAX;
+    double cv[NMAX];
+#pragma unroll
+    for (int kb = 0; kb < NMAX; kb += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(col + kb);
+      cv[kb] = v.x;
+      cv[kb + 1] = v.y;
+    }
+    // each vbar entry of the symmetric M(l) is read once; every acc[k] still
+    // takes its terms in the order kb = 0, 1, ...
+    double acc[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NMAX; ++a)
+#pragma unroll
+      for (int b = a; b < NMAX; ++b)
+        if (b < n) {
+          const double v = vb[(a * nch - a * (a - 1) / 2 + (b - a)) * L1 + l];
+          if (a == b) {
+            acc[a] = fma(2.0 * v, cv[a], acc[a]);
+          } else {
+            const double w = kSqrt2 * v;
+            acc[a] = fma(w, cv[b], acc[a]);
+            acc[b] = fma(w, cv[a], acc[b]);
+          }
+        }
+#pragma unroll
+    for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(col + k) = double2{acc[k], acc[k + 1]};
+  }
+}
+
 // vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm} of atom
 // i (qbar = qbar + qbar2 when qbar2 is not null, in that order), written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
 // NMAX]) with zeros in the sink column lm = LL and in the channels k >= n_max.
 // vb: K doubles of LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a
-// block barrier.  The global reads are issued eight per lane at a time; with
-// one species the atom's c is first copied into cb, where each lane transforms
-// whole columns in place (a column of cbar needs only the same column of c).
-template <int NMAX>
+// block barrier.  With one species the atom's c is first copied into cb, where
+// each lane transforms whole columns in place (a column of cbar needs only the
+// same column of c); up to NMAX = 8 every global read of that case (c, q, qbar,
+// qbar2, |p|) is issued at once and q, qbar stay in registers from the dot
+// product to vbar.  Otherwise the reads go eight per lane at a time.
+template <int NMAX, int LMAX>
 __device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
                                  const double* __restrict__ qbar, const double* __restrict__ qbar2, int qbar_pitch,
@@ -421,6 +462,48 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
   const double* qi = q + (size_t)i * q_pitch;
   const double* qb = qbar + (size_t)i * qbar_pitch;
   const double* qb2 = qbar2 ? qbar2 + (size_t)i * qbar_pitch : nullptr;  // a second part of qbar, added
+  if constexpr (NMAX <= 8) {
+    constexpr int KPL = (NMAX * (NMAX + 1) / 2 * (LMAX + 1) + 63) / 64;   // K per lane, one species
+    constexpr int CPL = (NMAX * ((LMAX + 1) * (LMAX + 1) + 1) + 63) / 64;  // c per lane
+    const int nc = NMAX * LLP;
+    if (ns == 1 && K <= 64 * KPL && nc <= 64 * CPL) {
+      double cv[CPL], a[KPL], g[KPL], g2[KPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) cv[u] = csh[min(lane + 64 * u, nc - 1)];
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) {
+        const int k = min(lane + 64 * u, K - 1);
+        a[u] = qi[k];
+        g[u] = qb[k];
+      }
+      if (qb2) {
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) g2[u] = qb2[min(lane + 64 * u, K - 1)];
+      }
+      const double nrm = pnorm[i];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < nc) cb[lane + 64 * u] = cv[u];
+      if (qb2) {
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) g[u] += g2[u];
+      }
+      // the same terms in the same order as the batched loop below
+      double dot = 0.0;
+#pragma unroll
+      for (int u = 0; u < KPL; ++u)
+        if (lane + 64 * u < K) dot = fma(a[u], g[u], dot);
+      dot = wave_sum(dot);
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+#pragma unroll
+      for (int u = 0; u < KPL; ++u)
+        if (lane + 64 * u < K) vb[lane + 64 * u] = (g[u] - a[u] * dot) * inv;
+      __syncthreads();
+      transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+      __syncthreads();
+      return;
+    }
+  }
   if (ns == 1) {
     const int nc = NMAX * LLP;
     for (int t0 = 0; t0 < nc; t0 += 64 * B) {
@@ -474,40 +557,8 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
     abx[r] = ab_index(a < b ? a : b, a < b ? b : a, nch) * L1;
   }
   __syncthreads();
-  // M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b), vbar packed a <= b then l
   if (ns == 1) {
-    for (int lm = lane; lm < LL; lm += 64) {
-      const int l = isqrt_small(lm);
-      double* col = cb + (size_t)lm * NMAX;
-      double cv[NMAX];
-#pragma unroll
-      for (int kb = 0; kb < NMAX; kb += 2) {
-        const double2 v = *reinterpret_cast<const double2*>(col + kb);
-        cv[kb] = v.x;
-        cv[kb + 1] = v.y;
-      }
-      // each vbar entry of the symmetric M(l) is read once; every acc[k] still
-      // takes its terms in the order kb = 0, 1, ...
-      double acc[NMAX];
-#pragma unroll
-      for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
-#pragma unroll
-      for (int a = 0; a < NMAX; ++a)
-#pragma unroll
-        for (int b = a; b < NMAX; ++b)
-          if (b < n) {
-            const double v = vb[(a * nch - a * (a - 1) / 2 + (b - a)) * L1 + l];
-            if (a == b) {
-              acc[a] = fma(2.0 * v, cv[a], acc[a]);
-            } else {
-              const double w = kSqrt2 * v;
-              acc[a] = fma(w, cv[b], acc[a]);
-              acc[b] = fma(w, cv[a], acc[b]);
-            }
-          }
-#pragma unroll
-      for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(col + k) = double2{acc[k], acc[k + 1]};
-    }
+    transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
     __syncthreads();
     return;
   }
@@ -669,12 +720,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
   double* rc = dyn + ncb;
   int* ri = reinterpret_cast<int*>(rc + nrec * NC);
   {
-    const int nrec_d = nrec * NC + 2 * nrec;
-    int* abx = reinterpret_cast<int*>(rc + (nrec_d > P.K ? nrec_d : P.K));
-    form_cbar<NMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);  // vbar in the record region
-  }
-  {
-    // the record table, every global read of a lane issued before its stores
+    // the record table; its global reads are issued before form_cbar, its
+    // stores follow it (vbar lives in the record region until then)
     constexpr int RPL = (S::NREC * NC + 63) / 64;
     double v[RPL];
 #pragma unroll
@@ -691,6 +738,9 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       lc[k] = T->rec_lm[jj][slot][0];
       ls[k] = T->rec_lm[jj][slot][1];
     }
+    const int nrec_d = nrec * NC + 2 * nrec;
+    int* abx = reinterpret_cast<int*>(rc + (nrec_d > P.K ? nrec_d : P.K));
+    form_cbar<NMAX, LMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
 #pragma unroll
     for (int k = 0; k < RPL; ++k)
       if (lane + 64 * k < nrec * NC) rc[lane + 64 * k] = v[k];
