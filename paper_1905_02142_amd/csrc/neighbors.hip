@@ -96,11 +96,13 @@ __global__ void k_bin_atoms(int n_atoms, const double* __restrict__ pos, const S
 
 // the bins of up to PER atoms per thread (t + k * kSmallBinThreads) of one
 // structure's geometry M, counted into the LDS bin counters; mybin[k] stays -1
-// for k beyond the atoms
+// for k beyond the atoms; the positions of the first four (k < 4) are kept in
+// kx, ky, kz
 template <int PER>
 __device__ inline void bin_block(int n_atoms, const double* __restrict__ pos, const StructMeta& M, int t,
                                  int* __restrict__ atom_bin, int* __restrict__ atom_wrap, int* __restrict__ cnt,
-                                 int* __restrict__ err, int (&mybin)[PER], int (&mywrap)[PER]) {
+                                 int* __restrict__ err, int (&mybin)[PER], int (&mywrap)[PER], double (&kx)[4],
+                                 double (&ky)[4], double (&kz)[4]) {
 #pragma unroll
   for (int k0 = 0; k0 < PER; k0 += 4) {
     if (k0 * kSmallBinThreads >= n_atoms) break;  // the same for every thread
@@ -112,6 +114,14 @@ __device__ inline void bin_block(int n_atoms, const double* __restrict__ pos, co
       px[k] = pos[3 * a];
       py[k] = pos[3 * a + 1];
       pz[k] = pos[3 * a + 2];
+    }
+    if (k0 == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        kx[k] = px[k];
+        ky[k] = py[k];
+        kz[k] = pz[k];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -150,10 +160,12 @@ __global__ __launch_bounds__(kSmallBinThreads) void k_bin_small(int n_atoms, con
   int mybin[PER], mywrap[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) mybin[k] = mywrap[k] = -1;
-  if (n_struct == 1) {
+  double kx[4], ky[4], kz[4];  // the positions of the thread's first four atoms, one structure only
+  const bool kept = n_struct == 1;
+  if (kept) {
     // one structure: its geometry sits in scalar registers for every atom
     const StructMeta M = meta[0];
-    bin_block<PER>(n_atoms, pos, M, t, atom_bin, atom_wrap, cnt, err, mybin, mywrap);
+    bin_block<PER>(n_atoms, pos, M, t, atom_bin, atom_wrap, cnt, err, mybin, mywrap, kx, ky, kz);
   } else {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -210,12 +222,21 @@ __global__ __launch_bounds__(kSmallBinThreads) void k_bin_small(int n_atoms, con
   for (int k0 = 0; k0 < PER; k0 += 4) {
     if (k0 * kSmallBinThreads >= n_atoms) break;
     double px[4], py[4], pz[4];
+    if (k0 == 0 && kept) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int a = min(t + (k0 + k) * kSmallBinThreads, n_atoms - 1);
-      px[k] = pos[3 * a];
-      py[k] = pos[3 * a + 1];
-      pz[k] = pos[3 * a + 2];
+      for (int k = 0; k < 4; ++k) {
+        px[k] = kx[k];
+        py[k] = ky[k];
+        pz[k] = kz[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int a = min(t + (k0 + k) * kSmallBinThreads, n_atoms - 1);
+        px[k] = pos[3 * a];
+        py[k] = pos[3 * a + 1];
+        pz[k] = pos[3 * a + 2];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
