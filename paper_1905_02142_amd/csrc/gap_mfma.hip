@@ -354,6 +354,27 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
     const int gs = s0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
     al_y[y] = gs < M ? (E)alpha[gs] : (E)0;
   }
+  // s^(zeta - 1) of every element, the running product 1, s, s s, (s s) s, ...:
+  // with one pass, one loop over the power for all of the lane's elements at
+  // once; the split mode, whose two passes would keep them all live, forms it
+  // per element in each pass
+  E pw[TM][TN][4];
+  if constexpr (!P::kSplit) {
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pw[x][y][r] = (E)1;
+    for (int t = 1; t < zeta; ++t) {
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pw[x][y][r] *= (E)acc[x][y][r];
+    }
+  }
 #pragma unroll
   for (int pass = 0; pass < (P::kSplit ? 2 : 1); ++pass) {
 #pragma unroll
@@ -365,8 +386,13 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
           const int lr = wm * (P::BM / 2) + acc_row<P>(x, r, lane);
           const int lc = wn * (P::BN / 2) + y * 16 + (lane & 15);
           const E sv = (E)acc[x][y][r];
-          E sz1 = (E)1;
-          for (int t = 1; t < zeta; ++t) sz1 *= sv;
+          E sz1;
+          if constexpr (P::kSplit) {
+            sz1 = (E)1;
+            for (int t = 1; t < zeta; ++t) sz1 *= sv;
+          } else {
+            sz1 = pw[x][y][r];
+          }
           const E al = al_y[y];
           const double g = (double)((E)zeta * al * sz1);
           if (pass == 0) {
