@@ -115,6 +115,10 @@ DESC_CASES = {
     "n10l10": (dict(n_max=10, l_max=10, r_cut=5.5, sigma0_r=0.5, sigma0_perp=0.5), 150, 11.5, 1, 10),
     "lweight1_nocentral": (dict(n_max=5, l_max=7, r_cut=4.0, sigma0_r=0.4, sigma0_perp=0.6, l_weight=1,
                                 central_weight=0.0), 60, 8.4, 1, 11),
+    # 0.28 atoms per A^3: every atom has 138..151 neighbours, so each list takes
+    # three 64-pair rounds in the adjoint and the force gather and five 32-pair
+    # chunks in the descriptor
+    "dense60_n8l8": (dict(n_max=8, l_max=8, r_cut=5.0, sigma0_r=0.5, sigma0_perp=0.5), 60, 6.0, 1, 13),
 }
 
 # n_max = 10: the FP64 radial transform amplifies rounding to ~1e-9 (the basis
@@ -158,7 +162,7 @@ def _energy_forces_case(kw, n, L, ns, seed, M, zeta):
 
 @pytest.mark.parametrize("name,M,zeta", [("box64_n6l6", 50, 4), ("hp_buffer_n8l8", 80, 3), ("hp_n8l8", 70, 3),
                                          ("species3_n4l4", 40, 2), ("box300_n8l8", 130, 4),
-                                         ("lweight1_nocentral", 33, 1)])
+                                         ("lweight1_nocentral", 33, 1), ("dense60_n8l8", 64, 4)])
 def test_energy_forces_match_oracle(name, M, zeta):
     kw, n, L, ns, seed = DESC_CASES[name]
     e, F, ab, eo, Fo, abo = _energy_forces_case(kw, n, L, ns, seed, M, zeta)
