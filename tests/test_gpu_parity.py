@@ -259,6 +259,44 @@ def test_zero_neighbour_atoms():
     assert abs(np.linalg.norm(q[0]) - 1) < 1e-14
 
 
+def test_no_atoms():
+    # an empty system: an empty list, descriptor and gradient, no energies, dE/dalpha = 0
+    soap = _soap(n_max=4, l_max=3, r_cut=3.0, sigma0_r=0.5, sigma0_perp=0.5)
+    pos = torch.zeros((0, 3), dtype=torch.float64, device=DEV)
+    nl = soap.neighbors(pos, np.eye(3) * 10.0, np.ones(3, np.int32))
+    spec = torch.zeros(0, dtype=torch.int32, device=DEV)
+    q = soap.descriptor(nl, spec)
+    e, F, ab = soap.energy_forces(nl, spec, _t(synth.sparse_set(8, soap.dim, 1)), _t(synth.sparse_weights(8, 2)), 2)
+    g = soap.descriptor_grad(nl, spec, torch.zeros((0, soap.dim), dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    assert nl.n_pairs == 0
+    assert q.shape == (0, soap.dim) and e.shape == (0,) and F.shape == (0, 3) and g.shape == (0, 3)
+    assert np.all(ab.cpu().numpy() == 0.0)
+
+
+def test_batch_with_empty_structure():
+    # three structures, the middle one without atoms: the other two match the
+    # oracle run on each alone, and dE/dalpha is the sum of theirs
+    kw = dict(n_max=4, l_max=3, r_cut=3.5, sigma0_r=0.5, sigma0_perp=0.5)
+    a, b = synth.rsa_box(20, 6.0, 1.2, 70), synth.rsa_box(12, 5.5, 1.2, 71)
+    soap = _soap(**kw)
+    cells = np.stack([a.cell, np.eye(3) * 7.0, b.cell])
+    pbc = np.stack([a.pbc, np.ones(3, np.int32), b.pbc])
+    nl = soap.neighbors(_t(np.concatenate([a.positions, b.positions])), cells, pbc, np.array([0, 20, 20, 32]))
+    spec = np.zeros(32, np.int32)
+    qs, al = synth.sparse_set(16, soap.dim, 3), synth.sparse_weights(16, 4)
+    e, F, ab = soap.energy_forces(nl, _t(spec), _t(qs), _t(al), 2)
+    torch.cuda.synchronize()
+    e, F, ab = e.cpu().numpy(), F.cpu().numpy(), ab.cpu().numpy()
+    abo = np.zeros_like(ab)
+    for s, lo, hi in ((a, 0, 20), (b, 20, 32)):
+        eo, Fo, abs_ = oracle.energy_forces(_oparams(**kw), s.positions, s.cell, s.pbc, spec[lo:hi], qs, al, 2)
+        assert np.abs(e[lo:hi] - eo).max() < 1e-10 * np.abs(eo).max()
+        assert np.abs(F[lo:hi] - Fo).max() < 1e-10 * np.abs(Fo).max()
+        abo += abs_
+    assert np.abs(ab - abo).max() < 1e-10 * np.abs(abo).max()
+
+
 def test_capacity_overflow_and_regrow():
     from paper_1905_02142_amd import _lib
 
