@@ -55,7 +55,9 @@ def workload_setup(name, precision, dev):
 def cpu_oracle_rate(st, budget_s=15.0):
     """The oracle's atoms/s on a bounded sample of centres spread evenly over the
     workload (neighbour list, descriptor and, with a sparse set, GAP energies and
-    the pair gradients of those centres), sized from a pilot to take ~budget_s."""
+    the pair gradients of those centres), sized from a pilot to take ~budget_s.
+    A workload whose every centre takes less than half the budget is run whole,
+    in as many passes as fill about two thirds of it."""
     import numpy as np
 
     import oracle
@@ -86,9 +88,14 @@ def cpu_oracle_rate(st, budget_s=15.0):
         if t >= 0.5 * budget_s or k >= offs[-1]:
             break
         k, t = run(int(min(offs[-1], max(k + 1, k * budget_s / max(t, 1e-3)))))
-    return {"value": round(k / t, 2), "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
+    passes = 1
+    if k >= offs[-1] and t < 0.5 * budget_s:
+        passes = int(np.ceil(2.0 * budget_s / 3.0 / max(t, 1e-3)))
+        t = sum(run(k)[1] for _ in range(passes))
+    return {"value": round(k * passes / t, 2), "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{k} of {offs[-1]} centres evenly spread over the workload (their neighbour lists, "
-                      f"descriptors" + (", GAP energies and pair gradients" if st["gap"] else "") + f"), {t:.1f} s"}
+                      f"descriptors" + (", GAP energies and pair gradients" if st["gap"] else "") +
+                      (f"), {passes} passes, {t:.1f} s" if passes > 1 else f"), {t:.1f} s")}
 
 
 # stages that are exactly one kernel (the roofline is quoted for one kernel)
