@@ -318,6 +318,34 @@ def test_capacity_overflow_and_regrow():
     assert nl2.n_pairs == want
 
 
+def test_size_limits_rejected():
+    # a list capacity beyond 32-bit pair indices, and a cell so thin that the
+    # lattice images needed exceed the packed image range, are refused before
+    # any device work
+    from paper_1905_02142_amd import _lib
+    from paper_1905_02142_amd.soap import NeighbourList
+
+    soap = _soap(n_max=4, l_max=2, r_cut=3.7, sigma0_r=0.5, sigma0_perp=0.5)
+    s = synth.rsa_box(8, 6.0, 1.2, 5)
+    pos = _t(s.positions)
+    cells = np.ascontiguousarray(s.cell.reshape(1, 9))
+    pbc = np.ascontiguousarray(s.pbc.reshape(1, 3).astype(np.int32))
+    nl = NeighbourList(8, 64, torch.device(DEV))
+    stream = torch.cuda.current_stream().cuda_stream
+    c = nl.c_struct()
+    c.capacity = 2 ** 31
+    with pytest.raises(_lib.SoapError) as ei:
+        _lib.soap_build_neighbors(soap.ctx, 8, pos.data_ptr(), cells.ctypes.data, pbc.ctypes.data, None, 1, c, stream)
+    assert ei.value.status == _lib.SOAP_ENOTSUP
+    thin = np.ascontiguousarray(np.diag([6.0, 6.0, 0.005]).reshape(1, 9))
+    with pytest.raises(_lib.SoapError) as ei:
+        _lib.soap_build_neighbors(soap.ctx, 8, pos.data_ptr(), thin.ctypes.data, pbc.ctypes.data, None, 1,
+                                  nl.c_struct(), stream)
+    assert ei.value.status == _lib.SOAP_ENOTSUP
+    # the context stays usable
+    assert soap.neighbors(pos, s.cell, s.pbc).n_pairs == oracle.neighbors(s.positions, s.cell, s.pbc, 3.7).n_pairs
+
+
 def test_invalid_inputs_rejected():
     from paper_1905_02142_amd import _lib
 
