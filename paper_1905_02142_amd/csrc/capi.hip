@@ -198,8 +198,9 @@ struct StageTimer {
 };
 
 // forward descriptor into the context's buffers (c, q, |p|)
+// (qc: optional bf16 copy of q for the GAP contraction, row pitch qc_pitch)
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
-                    bool deriv, hipStream_t st) {
+                    bool deriv, hipStream_t st, void* qc = nullptr, int qc_pitch = 0) {
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
@@ -213,7 +214,7 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
   SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                         (const double*)ctx->rows.p, (const double*)ctx->bc.p, (double*)ctx->c.p, q,
-                                        P.K, pnorm, st));
+                                        P.K, pnorm, qc, qc_pitch, st));
   return SOAP_OK;
 }
 
@@ -623,10 +624,18 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   }
   SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
   SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
-  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, forces != nullptr, st)) != SOAP_OK)
-    return s;
   const int prec = (int)ctx->prm.precision;
   const bool fused = forces && ctx->tune.gap_fused && soap::gap_fused_supported(P.K, prec);
+  // unfused BF16: the descriptor kernel also writes the bf16 operand copy of q
+  // into the GAP workspace, and the scores pass converts only the sparse set
+  void* qc = nullptr;
+  if (!fused) {
+    SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
+    qc = soap::gap_q_operand(prec, (int)N, M, P.K, ctx->gapw.p);
+  }
+  if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, forces != nullptr, st, qc,
+                   soap::gap_q_pitch(P.K))) != SOAP_OK)
+    return s;
   // the unfused Qbar pass splits its contraction over the sparse points into
   // parts that the adjoint adds
   const int slices = fused ? 1 : soap::gap_qbar_slices(M, prec);
@@ -642,12 +651,11 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_HIP(ctx, soap::launch_gap_fused(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta, e_atom,
                                          alpha_grad, qbar, ctx->gapw.p, target, st));
   } else {
-    SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
     {
       StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
       // with forces the Qbar pass also finishes the energy and dE/dalpha sums
       SOAP_HIP(ctx, soap::launch_gap_scores(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta,
-                                            e_atom, alpha_grad, qbar == nullptr, ctx->gapw.p, st));
+                                            e_atom, alpha_grad, qbar == nullptr, qc != nullptr, ctx->gapw.p, st));
     }
     if (qbar) {
       StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);

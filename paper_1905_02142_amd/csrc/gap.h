@@ -13,7 +13,14 @@ size_t gap_workspace_bytes(int N, int M, int K, int prec);
 // sums false the per-tile partial sums are left in work for launch_gap_qbar to
 // finish (e and alpha_bar are then written by that call)
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                             int zeta, double* e, double* alpha_bar, bool sums, void* work, hipStream_t st);
+                             int zeta, double* e, double* alpha_bar, bool sums, bool q_ready, void* work,
+                             hipStream_t st);
+// BF16 (prec 2) only: the N x gap_q_pitch(K) bf16 copy of Q inside work, for a
+// producer of q that writes it itself (row i at element i Kp: (bf16)(float) q_ik,
+// zero for the columns K..Kp-1), after which launch_gap_scores runs with q_ready
+// and converts only the sparse set; nullptr for the other modes
+void* gap_q_operand(int prec, int N, int M, int K, void* work);
+int gap_q_pitch(int K);
 // Qbar = G Q_s, from the operands the scores pass left in work, as `slices`
 // parts (Qbar + s N K, s < slices, each N x K) that sum to it: part s contracts
 // over the sparse points s Mp / slices .. (s + 1) Mp / slices - 1, which

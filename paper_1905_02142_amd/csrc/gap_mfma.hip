@@ -118,10 +118,10 @@ __global__ void k_convert(int rows, int cols, int rows_p, int cols_p, const doub
 // I: the element index type, int when N Kp + 2 Mp Kp fits (its divisions are
 // much cheaper than 64-bit ones), else long long
 template <typename T, bool SPLIT, typename I>
-__global__ void k_convert3(int N, int M, int K, int Kp, int Mp, const double* __restrict__ Q,
+__global__ void k_convert3(int N, int M, int K, int Kp, int Mp, I e0, const double* __restrict__ Q,
                            const double* __restrict__ Qs, T* __restrict__ qc, T* __restrict__ qc_lo,
                            T* __restrict__ qsc, T* __restrict__ qsc_lo, T* __restrict__ qst, T* __restrict__ qst_lo) {
-  I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  I e = e0 + (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;  // e0 = N Kp when Q is already converted
   const I n1 = (I)N * Kp, n2 = (I)Mp * Kp;
   double x;
   T* dst;
@@ -913,7 +913,7 @@ Layout layout(int N, int M, int K) {
 
 template <typename P>
 hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta,
-                       double* e, double* alpha_bar, bool sums, void* work, hipStream_t st) {
+                       double* e, double* alpha_bar, bool sums, bool q_ready, void* work, hipStream_t st) {
   using T = typename P::T;
   const Layout L = layout<P>(N, M, K);
   char* w = (char*)work;
@@ -922,13 +922,13 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
   T *qst = (T*)(w + L.qst), *qst_lo = (T*)(w + L.qst_lo), *G = (T*)(w + L.g), *G_lo = (T*)(w + L.g_lo);
   double *e_part = (double*)(w + L.e_part), *ab_part = (double*)(w + L.ab_part);
   auto blocks = [](long long n) { return dim3((unsigned)((n + 255) / 256)); };
-  const long long nconv = (long long)N * Kp + 2LL * Mp * Kp;
+  const long long nconv = (long long)N * Kp + 2LL * Mp * Kp, e0 = q_ready ? (long long)N * Kp : 0;
   if (nconv < 2147483647LL - 256)
-    hipLaunchKernelGGL((k_convert3<T, P::kSplit, int>), blocks(nconv), dim3(256), 0, st, N, M, K, Kp, Mp, Q, Qs, qc,
-                       qc_lo, qsc, qsc_lo, qst, qst_lo);
+    hipLaunchKernelGGL((k_convert3<T, P::kSplit, int>), blocks(nconv - e0), dim3(256), 0, st, N, M, K, Kp, Mp, (int)e0,
+                       Q, Qs, qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
   else
-    hipLaunchKernelGGL((k_convert3<T, P::kSplit, long long>), blocks(nconv), dim3(256), 0, st, N, M, K, Kp, Mp, Q, Qs,
-                       qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
+    hipLaunchKernelGGL((k_convert3<T, P::kSplit, long long>), blocks(nconv - e0), dim3(256), 0, st, N, M, K, Kp, Mp,
+                       e0, Q, Qs, qc, qc_lo, qsc, qsc_lo, qst, qst_lo);
   const int nst = (Mp + P::BN - 1) / P::BN, nit = (N + P::BM - 1) / P::BM;
   static bool attr = false;  // operand tiles above 64 KB of LDS need the opt-in
   if (!attr && sizeof(Smem<P>) > 65536) {
@@ -977,15 +977,24 @@ size_t gap_workspace_bytes(int N, int M, int K, int prec) {
 }
 
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                             int zeta, double* e, double* alpha_bar, bool sums, void* work, hipStream_t st) {
+                             int zeta, double* e, double* alpha_bar, bool sums, bool q_ready, void* work,
+                             hipStream_t st) {
   if (N == 0) return hipSuccess;
+  if (q_ready && !gap_q_operand(prec, N, M, K, work)) return hipErrorInvalidValue;
   switch (prec) {
-    case 0: return scores_impl<PF64>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
-    case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
-    case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
-    default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, work, st);
+    case 0: return scores_impl<PF64>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
+    case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
+    case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
+    default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
   }
 }
+
+void* gap_q_operand(int prec, int N, int M, int K, void* work) {
+  if (prec != 2 || !work) return nullptr;
+  return static_cast<char*>(work) + layout<PBF16>(N, M, K).qc;
+}
+
+int gap_q_pitch(int K) { return padded(K); }
 
 bool gap_fused_supported(int K, int prec) { return prec != 0 && (K + 31) / 32 * 32 <= kFusedK; }
 

@@ -31,10 +31,12 @@ hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_
 size_t pair_rows_bytes(const DevParams& P, long long n_pairs);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
+// qc (nullable): a bf16 copy of q as well, row i at element i qc_pitch,
+// (bf16)(float) q_ik and zero for the columns K..qc_pitch-1
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                              const int* nj,
                              const int* species, const double* rows, const double* bc, double* c, double* q,
-                             int q_pitch, double* pnorm, hipStream_t st);
+                             int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st);
 
 // pair gradients g_p = dE/dd_p (SoA) from qbar = dE/dq (n_atoms rows of
 // qbar_pitch; with qbar2 non-null, qbar + qbar2, the two parts of a sliced GAP

@@ -259,7 +259,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
                                                                      const double* __restrict__ bc_in,
                                                                      double* __restrict__ c_out,
                                                                      double* __restrict__ q_out, int q_pitch,
-                                                                     double* __restrict__ pnorm_out) {
+                                                                     double* __restrict__ pnorm_out,
+                                                                     __bf16* __restrict__ qc, int qc_pitch) {
   using S = Shape<NMAX, LMAX>;
   constexpr int E2 = S::E2, NC = S::NC, CH = S::CH, FRP = S::FRP;
   extern __shared__ __align__(16) double dyn[];
@@ -392,13 +393,23 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   ss = wave_sum(ss);
   const double nrm = sqrt(ss);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  // qc: the bf16 operand row of the GAP contraction, the same rounding of the
+  // same q values as a separate conversion pass would apply
+  __bf16* __restrict__ qci = qc ? qc + (size_t)i * qc_pitch : nullptr;
   if (pv != qi) {  // p in LDS: every lane writes a contiguous part of q
     __syncthreads();
     for (int k = lane; k < q_pitch; k += 64) qi[k] = k < P.K ? pv[k] * inv : 0.0;
+    if (qci)
+      for (int k = lane; k < qc_pitch; k += 64) qci[k] = (__bf16)(float)(k < P.K ? pv[k] * inv : 0.0);
   } else {
     for (int ab = lane; ab < nab; ab += 64)
-      for (int l = 0; l < L1; ++l) qi[ab * L1 + l] *= inv;
+      for (int l = 0; l < L1; ++l) {
+        qi[ab * L1 + l] *= inv;
+        if (qci) qci[ab * L1 + l] = (__bf16)(float)qi[ab * L1 + l];
+      }
     for (int k = P.K + lane; k < q_pitch; k += 64) qi[k] = 0.0;
+    if (qci)
+      for (int k = P.K + lane; k < qc_pitch; k += 64) qci[k] = (__bf16)0.0f;
   }
   if (lane == 0 && pnorm_out) pnorm_out[i] = nrm;
 }
@@ -912,12 +923,13 @@ hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                              const int* nj,
                              const int* species, const double* rows, const double* bc, double* c, double* q,
-                             int q_pitch, double* pnorm, hipStream_t st) {
+                             int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
+  if (qc && qc_pitch < P.K) return hipErrorInvalidValue;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
     hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
-                       rows, bc, c, q, q_pitch, pnorm);
+                       rows, bc, c, q, q_pitch, pnorm, static_cast<__bf16*>(qc), qc_pitch);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
