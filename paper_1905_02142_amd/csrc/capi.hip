@@ -50,7 +50,7 @@ struct soap_ctx {
   Buf meta, so, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_unsorted, bin_cand, counts, opre,
       scan_part, errflag;
   // descriptor / adjoint
-  Buf rows, bc, c, q, pnorm, qbar, gx, gy, gz, gapw, e_tmp;
+  Buf rows, bc, c, q, pnorm, qbar, gx, gapw, e_tmp;  // gx: the pair gradients, (x, y, z, 0) per pair
   // stage timing
   struct Rec {
     int stage;
@@ -295,7 +295,7 @@ void soap_destroy(soap_ctx* ctx) {
   if (!ctx) return;
   Buf* bufs[] = {&ctx->meta, &ctx->so, &ctx->atom_bin, &ctx->atom_wrap, &ctx->bin_count, &ctx->bin_start,
                  &ctx->bin_cursor, &ctx->bin_unsorted, &ctx->bin_cand, &ctx->counts, &ctx->opre, &ctx->scan_part, &ctx->errflag, &ctx->rows, &ctx->bc, &ctx->c,
-                 &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->gapw, &ctx->e_tmp, &ctx->tune_out};
+                 &ctx->q, &ctx->pnorm, &ctx->qbar, &ctx->gx, &ctx->gapw, &ctx->e_tmp, &ctx->tune_out};
   for (Buf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& r : ctx->prof) {
@@ -559,20 +559,18 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
   SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
-  SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
-  SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
-  SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
+  SOAP_ENSURE(ctx, ctx->gx, 4 * sizeof(double) * NP);  // (x, y, z, 0) per pair
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, true, st)) != SOAP_OK) return s;
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                             (const double*)ctx->rows.p, (const double*)ctx->c.p,
                                             (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, q_bar, nullptr,
-                                            P.K, (double*)ctx->gx.p, (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+                                            P.K, (double*)ctx->gx.p, nullptr, nullptr, 4, st));
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
   SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
-                                          (const double*)ctx->gy.p, (const double*)ctx->gz.p, pos_grad, true, st));
+                                          nullptr, nullptr, 4, pos_grad, true, st));
   return SOAP_OK;
 }
 
@@ -601,7 +599,7 @@ soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const 
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                             (const double*)ctx->rows.p, (const double*)ctx->c.p,
                                             (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qb, nullptr, P.K,
-                                            tile, tile + NP, tile + 2 * NP, st));
+                                            tile, tile + NP, tile + 2 * NP, 1, st));
   }
   return SOAP_OK;
 }
@@ -663,20 +661,18 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     }
   }
   if (forces) {
-    SOAP_ENSURE(ctx, ctx->gx, sizeof(double) * NP);
-    SOAP_ENSURE(ctx, ctx->gy, sizeof(double) * NP);
-    SOAP_ENSURE(ctx, ctx->gz, sizeof(double) * NP);
+    SOAP_ENSURE(ctx, ctx->gx, 4 * sizeof(double) * NP);  // (x, y, z, 0) per pair
     {
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
                                               (const double*)ctx->rows.p, (const double*)ctx->c.p,
                                               (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qbar,
                                               slices == 2 ? qbar + N * P.K : nullptr, P.K, (double*)ctx->gx.p,
-                                              (double*)ctx->gy.p, (double*)ctx->gz.p, st));
+                                              nullptr, nullptr, 4, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
-                                            (const double*)ctx->gy.p, (const double*)ctx->gz.p, forces, false, st));
+                                            nullptr, nullptr, 4, forces, false, st));
   }
   return SOAP_OK;
 }

@@ -38,15 +38,16 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
                              const int* species, const double* rows, const double* bc, double* c, double* q,
                              int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st);
 
-// pair gradients g_p = dE/dd_p (SoA) from qbar = dE/dq (n_atoms rows of
+// pair gradients g_p = dE/dd_p from qbar = dE/dq (n_atoms rows of
 // qbar_pitch; with qbar2 non-null, qbar + qbar2, the two parts of a sliced GAP
 // contraction), the forward c, q, |p| and the pair rows with derivatives; cbar
-// is formed per atom inside the kernel
+// is formed per atom inside the kernel.  gstride 1: three arrays gx, gy, gz;
+// gstride 4: one record (x, y, z, 0) per pair at gx + 4 p (gy, gz unused)
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                                const int* nj, const int* species, const double* rows, const double* c,
                                const double* q, int q_pitch, const double* pnorm, const double* qbar,
                                const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
-                               hipStream_t st);
+                               int gstride, hipStream_t st);
 
 // angular records (Qbar_lm polynomials) and ilexp series tables for these parameters
 void build_angular_tables(const DevParams& P, DevTables& T);
@@ -55,8 +56,9 @@ void build_angular_tables(const DevParams& P, DevTables& T);
 // and kclear (the previous kset, set to zero) are written
 hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qbar, hipStream_t st);
 
-// out = F (overwrite) or pos_grad -= F (accumulate_grad)
+// out = F (overwrite) or pos_grad -= F (accumulate_grad), from pair gradients
+// laid out as launch_pair_adjoint writes them for gstride
 hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
-                               const double* gz, double* out, bool accumulate_grad, hipStream_t st);
+                               const double* gz, int gstride, double* out, bool accumulate_grad, hipStream_t st);
 
 }  // namespace soap

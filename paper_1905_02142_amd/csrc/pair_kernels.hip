@@ -44,6 +44,8 @@ namespace soap {
 
 namespace {
 
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -716,7 +718,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
                                                                        const double* __restrict__ qbar2,
                                                                        int qbar_pitch, double* __restrict__ gx,
                                                                        double* __restrict__ gy,
-                                                                       double* __restrict__ gz) {
+                                                                       double* __restrict__ gz, int gstride) {
   using S = Shape<NMAX, LMAX>;
   constexpr int NC = S::NC;
   extern __shared__ __align__(16) double dyn[];
@@ -793,9 +795,16 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       const double ir = F(S::FR + S::XU + 2);
       // d u / d d = (I - u u^T) / r
       const double ut = ux * sx + uy * sy + uz * sz;
-      gx[p] = on ? sr * ux + (sx - ux * ut) * ir : 0.0;
-      gy[p] = on ? sr * uy + (sy - uy * ut) * ir : 0.0;
-      gz[p] = on ? sr * uz + (sz - uz * ut) * ir : 0.0;
+      const double g0 = on ? sr * ux + (sx - ux * ut) * ir : 0.0;
+      const double g1 = on ? sr * uy + (sy - uy * ut) * ir : 0.0;
+      const double g2 = on ? sr * uz + (sz - uz * ut) * ir : 0.0;
+      if (gstride == 4) {  // one 32-byte record (x, y, z, 0) per pair
+        *reinterpret_cast<dvec4*>(gx + 4 * (size_t)p) = dvec4{g0, g1, g2, 0.0};
+      } else {
+        gx[p] = g0;
+        gy[p] = g1;
+        gz[p] = g2;
+      }
     }
   }
 }
@@ -808,17 +817,27 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
 __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets, int bound,
                                                       const int* __restrict__ rev, const double* __restrict__ gx,
                                                       const double* __restrict__ gy, const double* __restrict__ gz,
-                                                      double* __restrict__ out, int accumulate_grad) {
+                                                      int gstride, double* __restrict__ out, int accumulate_grad) {
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= n_atoms) return;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   const int q1 = min(offsets[k + 1], bound);
-  for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
-    const int r = rev[q];
-    fx += gx[q] - gx[r];
-    fy += gy[q] - gy[r];
-    fz += gz[q] - gz[r];
+  if (gstride == 4) {  // (x, y, z, 0) records: one 32-byte read per pair, also for the reverse one
+    const dvec4* __restrict__ g = reinterpret_cast<const dvec4*>(gx);
+    for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
+      const dvec4 a = g[q], b = g[rev[q]];
+      fx += a.x - b.x;
+      fy += a.y - b.y;
+      fz += a.z - b.z;
+    }
+  } else {
+    for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
+      const int r = rev[q];
+      fx += gx[q] - gx[r];
+      fy += gy[q] - gy[r];
+      fz += gz[q] - gz[r];
+    }
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -939,12 +958,13 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
                                const int* nj, const int* species, const double* rows, const double* c,
                                const double* q, int q_pitch, const double* pnorm, const double* qbar,
                                const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
-                               hipStream_t st) {
+                               int gstride, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
+  if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
     hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
-                       rows, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, gx, gy, gz);
+                       rows, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
@@ -970,10 +990,11 @@ hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qba
 }
 
 hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
-                               const double* gz, double* out, bool accumulate_grad, hipStream_t st) {
+                               const double* gz, int gstride, double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
+  if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 3) / 4), dim3(256), 0, st, n_atoms, offsets, bound, rev, gx, gy, gz,
-                     out, accumulate_grad ? 1 : 0);
+                     gstride, out, accumulate_grad ? 1 : 0);
   return hipGetLastError();
 }
 
