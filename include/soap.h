@@ -51,14 +51,29 @@ typedef enum {
 } soap_status;
 
 /* Arithmetic of the GAP kernel contraction (S = Q Q_s^T and Qbar = G Q_s).
- * The radial recursion, exp/erf terms and the orthonormal transform W are FP64
- * in every mode; c_nlm, p and q are FP64 in every mode. */
+ * The exp/erf terms are FP64 in every mode, the radial recursion and the
+ * orthonormal transform W are FP64 or double-double (soap_radial_precision);
+ * c_nlm, p and q are FP64 in every mode. */
 typedef enum {
   SOAP_FP64 = 0,        /* FP64 MFMA */
   SOAP_MIXED_F32 = 1,   /* FP32 operands, FP32 accumulation (MFMA) */
   SOAP_MIXED_BF16 = 2,  /* BF16 operands, FP32 accumulation (MFMA) */
   SOAP_MIXED_BF16X3 = 3 /* split-BF16 (hi/lo, three products), FP32 accumulation */
 } soap_precision;
+
+/* Arithmetic of the radial stage (Sec. III.A): the integration-by-parts
+ * recursion of Eq. (04) and b = W b_alpha.  The overlap matrix S of the basis is
+ * nearly singular (smallest eigenvalue ~1e-11 at n_max = 8, ~1e-14 at 10, ~4e-18
+ * at 12), so W = S^{-1/2} has entries up to ~1e5, ~5e6 and ~2e8 and multiplies
+ * every rounding of b_alpha: in FP64 the per-pair b_n carry relative errors of
+ * ~3e-11 (n_max = 8), ~1e-9 (10) and ~4e-8 (12).  In double-double the recursion
+ * and W b_alpha (with W itself to 106 bits) hold b_n to ~1e-14 (10) and ~2e-13
+ * (12); the erf and exp seeds stay FP64. */
+typedef enum {
+  SOAP_RADIAL_AUTO = 0, /* double-double when precision is SOAP_FP64 and n_max >= 8, else FP64 */
+  SOAP_RADIAL_FP64 = 1,
+  SOAP_RADIAL_DD = 2
+} soap_radial_precision;
 
 /* Hyper-parameters: Eq. (15) and Sec. III.B.  Defaults in brackets. */
 typedef struct {
@@ -76,6 +91,7 @@ typedef struct {
   double central_weight; /* weight of the central-atom Gaussian; 0 drops it [1.0] */
   int l_weight;          /* 0: factor 2l+1 of Eq. (08) as printed [0]; 1: factor 1 */
   soap_precision precision; /* GAP contraction arithmetic [SOAP_FP64] */
+  soap_radial_precision radial_precision; /* radial stage arithmetic [SOAP_RADIAL_AUTO] */
 } soap_params;
 
 /* Opaque context: owns the basis tables (W = S^{-1/2} computed on the host in
@@ -116,7 +132,8 @@ typedef struct {
 /* Validate `p` and build the basis tables.  Returns SOAP_EINVAL for n_max
  * outside 2..12, l_max outside 0..12, n_species < 1, non-positive r_cut or
  * widths, r_soft outside (0, r_cut], n_f <= 0, negative alpha_r, alpha_perp or
- * a, l_weight not 0/1, or an unknown precision.  Needs a current HIP device. */
+ * a, l_weight not 0/1, or an unknown precision or radial precision.  Needs a
+ * current HIP device. */
 soap_status soap_create(const soap_params* p /* host */, soap_ctx** out /* host */);
 void soap_destroy(soap_ctx* ctx);
 
@@ -173,7 +190,12 @@ soap_status soap_neighbors_check(soap_ctx* ctx, const soap_nlist* nl, long long*
 
 /*
  * Descriptors q (n_atoms x K, FP64) of every atom of `nl`, and |p| (n_atoms,
- * nullable).  species: n_atoms labels in 0..n_species-1 (an atom with another
+ * nullable).  Defined by Eq. (08) (c_nlm summed over the neighbours, with the
+ * radial coefficients of Sec. III.A and the angular factors of Sec. III.C),
+ * Eq. (09) (the power spectrum p_{nn'l}, here over species channels) and the
+ * normalisation q = p / |p| of Sec. I; q_i is packed as channel pairs a <= b
+ * (a outer), then l, with the factor sqrt(2) on a != b so that the packed norm
+ * equals the full one.  species: n_atoms labels in 0..n_species-1 (an atom with another
  * label contributes to no density; with n_species = 1 the labels are not read).
  * Atoms with p = 0 get q = 0.  The coefficients c_nlm are kept in the context for a following
  * soap_descriptor_grad / gap_energy_forces call on the same list.
@@ -183,7 +205,13 @@ soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* 
 
 /*
  * Vector-Jacobian product of the descriptor: pos_grad (n_atoms x 3) +=
- * sum_i (dq_i/dr)^T q_bar_i, with q_bar (n_atoms x K).  Recomputes c_nlm and the
+ * sum_i (dq_i/dr)^T q_bar_i, with q_bar (n_atoms x K) in the packing of
+ * soap_descriptor.  The derivative of the chain Eq. (08) -> Eq. (09) -> q = p/|p|
+ * with respect to the atomic positions (the paper gives the forward maps only;
+ * the kernel derivatives it reports missing in Sec. IV.A are built on this
+ * product).  Invalid arguments: SOAP_EINVAL (null species, q_bar or pos_grad with
+ * n_atoms > 0), SOAP_ENOTSUP (a descriptor too large for one workgroup's LDS).
+ * Recomputes c_nlm and the
  * per-pair radial/angular terms and their derivatives instead of storing a
  * per-pair Jacobian.  Deterministic: each atom gathers its pair terms in a
  * fixed order through the reverse-pair index.
@@ -208,11 +236,20 @@ soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const 
                                      double* jac, hipStream_t stream);
 
 /*
- * GAP energies and forces.  q_sparse: M x K sparse descriptors (FP64; cast by
+ * GAP energies and forces.  The local energy of Sec. IV.A, e_i = sum_s alpha_s
+ * k(q_i, q_s), with the dot-product kernel k = (q_i . q_s)^zeta of Sec. I
+ * (no constant offset, no prefactor: both are absorbed into alpha); forces
+ * F = -dE/dr through the derivative of the descriptor (as soap_descriptor_grad).
+ * q_sparse: M x K sparse descriptors (FP64; cast by
  * the library to the context's precision), alpha: M weights, zeta >= 1 integer.
  * Outputs: e_atom (n_atoms) local energies; forces (n_atoms x 3, nullable =>
  * energies only) = -dE/dr, overwritten; alpha_grad (M, nullable) = dE/dalpha_s
  * = sum_i (q_i . q_s)^zeta, overwritten.  Computes the descriptor internally.
+ * Errors: SOAP_EINVAL for M < 1, zeta < 1 (non-integer powers of the possibly
+ * negative q_i . q_s are not defined) or null required pointers; SOAP_ENOTSUP
+ * when the workspace would have to grow while `stream` is being captured.
+ * Enqueues kernels only (no memset, copy or synchronisation), so a call whose
+ * workspace is already large enough can be captured in a HIP graph.
  */
 soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
                               const double* q_sparse, const double* alpha, int M, int zeta,
@@ -252,6 +289,14 @@ const char* soap_stage_name(int stage);
 
 /* Bytes of device workspace the context currently holds. */
 long long soap_workspace_bytes(const soap_ctx* ctx);
+
+/* Number of times the context's workspace has been reallocated so far (-1 for a
+ * null context).  The workspace grows, by freeing and allocating, when a call
+ * needs more than it holds; a HIP graph captured before a growth names freed
+ * memory, so a caller that replays graphs compares this number with its value
+ * at capture and captures again when it has changed.  Growth is refused with
+ * SOAP_ENOTSUP while the caller's stream is being captured. */
+long long soap_workspace_generation(const soap_ctx* ctx);
 
 /*
  * Verlet skin: later neighbour builds on ctx list every pair closer than

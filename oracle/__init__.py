@@ -118,6 +118,8 @@ def _lib(precision: str = "ld"):
     lib.or_radial.restype = None
     lib.or_ilexp.argtypes = [d, i, vp, vp]
     lib.or_ilexp.restype = None
+    lib.or_set_num_threads.argtypes = [ctypes.c_int]
+    lib.or_set_num_threads.restype = None
     lib.or_ylm_conj.argtypes = [i, i, vp, vp, vp, vp, vp]
     lib.or_ylm_conj.restype = None
     lib.or_gauss_basis_overlap.argtypes = [d, d, d, vp]
@@ -286,7 +288,7 @@ def descriptor_vjp(p: Params, nl: NeighbourList, species, qbar, precision: str =
     return g
 
 
-def gap(q, q_sparse, alpha, zeta: int, want_grad: bool = True):
+def gap(q, q_sparse, alpha, zeta: int, want_grad: bool = True, precision: str = "ld"):
     """GAP local energies e_i = sum_s alpha_s (q_i . q_s)^zeta, with dE/dq and dE/dalpha."""
     if int(zeta) != zeta or zeta < 1:
         raise ValueError("zeta must be a positive integer")
@@ -298,7 +300,7 @@ def gap(q, q_sparse, alpha, zeta: int, want_grad: bool = True):
     e = np.zeros(N)
     qbar = np.zeros((N, K)) if want_grad else None
     abar = np.zeros(M) if want_grad else None
-    _lib().or_gap(N, K, _ptr(q), M, _ptr(qs), _ptr(al), int(zeta), _ptr(e), _ptr(qbar), _ptr(abar))
+    _lib(precision).or_gap(N, K, _ptr(q), M, _ptr(qs), _ptr(al), int(zeta), _ptr(e), _ptr(qbar), _ptr(abar))
     return e, qbar, abar
 
 
@@ -380,9 +382,14 @@ def gauss_basis_overlap(mu, s, sigma0):
     return out
 
 
-def num_threads() -> int:
+def num_threads(precision: str = "ld") -> int:
     """OpenMP threads the oracle's parallel loops use."""
-    return int(_lib().or_num_threads())
+    return int(_lib(precision).or_num_threads())
+
+
+def set_num_threads(n: int, precision: str = "ld") -> None:
+    """Threads for the oracle's later parallel loops (each build keeps its own setting)."""
+    _lib(precision).or_set_num_threads(int(n))
 
 
 def amplitude(p: Params, r):

@@ -659,6 +659,9 @@ double or_amplitude(const or_params* P, double r, double* dA) {
 
 int or_real_bits(void) { return (int)(sizeof(R) == sizeof(double) ? 53 : 64); }
 
+/* threads for the following parallel regions of this library (n >= 1) */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 /* threads an OpenMP parallel region of this library uses */
 int or_num_threads(void) {
   int n = 1;

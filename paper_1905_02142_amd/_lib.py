@@ -14,6 +14,7 @@ LIB_PATH = os.environ.get("SOAP_LIBRARY", LIB_PATH)
 
 SOAP_OK, SOAP_EINVAL, SOAP_ENOMEM, SOAP_EOVERFLOW, SOAP_EHIP, SOAP_ENOTSUP = 0, -1, -2, -3, -4, -5
 SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3 = 0, 1, 2, 3
+SOAP_RADIAL_AUTO, SOAP_RADIAL_FP64, SOAP_RADIAL_DD = 0, 1, 2
 SOAP_PAIRS_DEFERRED = -1
 
 # every function include/soap.h declares
@@ -23,7 +24,7 @@ EXPORTED = (
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
     "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
     "soap_build_neighbors_async", "soap_neighbors_check", "soap_descriptor_jacobian", "soap_set_neighbor_skin",
-    "soap_update_pair_vectors",
+    "soap_update_pair_vectors", "soap_workspace_generation",
 )
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
           "pair_prep", "cbar")
@@ -36,6 +37,7 @@ class soap_params(ctypes.Structure):
         ("sigma0_r", ctypes.c_double), ("sigma0_perp", ctypes.c_double),
         ("alpha_r", ctypes.c_double), ("alpha_perp", ctypes.c_double), ("a", ctypes.c_double),
         ("central_weight", ctypes.c_double), ("l_weight", ctypes.c_int), ("precision", ctypes.c_int),
+        ("radial_precision", ctypes.c_int),
     ]
 
 
@@ -89,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.soap_last_error.restype = ctypes.c_char_p
     lib.soap_workspace_bytes.argtypes = [vp]
     lib.soap_workspace_bytes.restype = ll
+    lib.soap_workspace_generation.argtypes = [vp]
+    lib.soap_workspace_generation.restype = ll
     lib.soap_build_neighbors.argtypes = [vp, i, vp, vp, vp, vp, i, P(soap_nlist), P(ll), vp]
     lib.soap_build_neighbors.restype = i
     lib.soap_build_neighbors_async.argtypes = [vp, i, vp, vp, vp, vp, i, P(soap_nlist), vp]
@@ -157,6 +161,10 @@ def soap_descriptor_dim(ctx: int) -> int:
 
 def soap_workspace_bytes(ctx: int) -> int:
     return load().soap_workspace_bytes(ctx)
+
+
+def soap_workspace_generation(ctx: int) -> int:
+    return load().soap_workspace_generation(ctx)
 
 
 def soap_build_neighbors(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl: soap_nlist,

@@ -17,6 +17,7 @@
 #include "soap_device.h"
 
 extern "C" int soap_host_basis_table(int n_max, double r_cut, double sigma0_r, double* W, double* Wlo, double* eig);
+extern "C" int soap_host_radial_consts(int n_max, double r_cut, double* invN_hi, double* invN_lo, double* rc4);
 
 namespace {
 
@@ -35,6 +36,7 @@ struct soap_ctx {
   int device = 0;
   std::string err;
   long long ws_bytes = 0;
+  long long ws_gen = 0;  // bumped whenever a workspace buffer is reallocated
   int* pinned = nullptr;  // host-pinned staging for structure-geometry uploads
   hipEvent_t pinned_ev = nullptr;  // completes when the last upload from the staging has been read
   int* report = nullptr;  // host-pinned pair count and error bits, written by a kernel
@@ -78,10 +80,17 @@ soap_status hip_fail(soap_ctx* ctx, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);   \
   } while (0)
 
-// grow-only device buffer
-bool ensure(soap_ctx* ctx, Buf& b, size_t bytes) {
+// grow-only device buffer.  Growth frees the old allocation, which a HIP graph
+// captured earlier may still name, so it bumps ctx->ws_gen (callers that replay
+// graphs compare it), and it is refused while `st` is being captured (the
+// allocation would not be part of the graph).  0: ok, 1: allocation failed,
+// 2: growth needed under capture.
+int ensure(soap_ctx* ctx, Buf& b, size_t bytes, hipStream_t st) {
   if (bytes == 0) bytes = 8;
-  if (b.cap >= bytes) return true;
+  if (b.cap >= bytes) return 0;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return 2;
+  ++ctx->ws_gen;
   if (b.p) {
     hipFree(b.p);
     ctx->ws_bytes -= (long long)b.cap;
@@ -91,11 +100,11 @@ bool ensure(soap_ctx* ctx, Buf& b, size_t bytes) {
   size_t want = bytes + bytes / 4;
   if (hipMalloc(&b.p, want) != hipSuccess) {
     b.p = nullptr;
-    return false;
+    return 1;
   }
   b.cap = want;
   ctx->ws_bytes += (long long)want;
-  return true;
+  return 0;
 }
 
 bool ensure_pinned(soap_ctx* ctx, size_t bytes) {
@@ -109,9 +118,13 @@ bool ensure_pinned(soap_ctx* ctx, size_t bytes) {
   return true;
 }
 
-#define SOAP_ENSURE(ctx, buf, bytes)                                                     \
-  do {                                                                                   \
-    if (!ensure(ctx, buf, bytes)) return fail(ctx, SOAP_ENOMEM, "device allocation failed"); \
+// (expects the caller's stream as `st` in scope)
+#define SOAP_ENSURE(ctx, buf, bytes)                                                                     \
+  do {                                                                                                   \
+    const int e_ = ensure(ctx, buf, bytes, st);                                                          \
+    if (e_ == 1) return fail(ctx, SOAP_ENOMEM, "device allocation failed");                              \
+    if (e_ == 2)                                                                                         \
+      return fail(ctx, SOAP_ENOTSUP, "workspace must grow during stream capture (run once outside it)"); \
   } while (0)
 
 soap_status check_params(const soap_params* p, std::string& why) {
@@ -128,6 +141,8 @@ soap_status check_params(const soap_params* p, std::string& why) {
   if (!std::isfinite(p->central_weight)) return why = "central_weight must be finite", SOAP_EINVAL;
   if (p->l_weight != 0 && p->l_weight != 1) return why = "l_weight must be 0 or 1", SOAP_EINVAL;
   if (p->precision < SOAP_FP64 || p->precision > SOAP_MIXED_BF16X3) return why = "unknown precision", SOAP_EINVAL;
+  if (p->radial_precision < SOAP_RADIAL_AUTO || p->radial_precision > SOAP_RADIAL_DD)
+    return why = "unknown radial precision", SOAP_EINVAL;
   return SOAP_OK;
 }
 
@@ -199,6 +214,33 @@ struct StageTimer {
 
 // forward descriptor into the context's buffers (c, q, |p|)
 // (qc: optional bf16 copy of q for the GAP contraction, row pitch qc_pitch)
+// the same into caller-provided buffers: pair rows (pair_rows_bytes), c
+// (c_doubles_per_atom per atom) and the central-atom factors (kMaxN doubles);
+// with `timed`, the stages record their events while profiling is on
+soap_status forward_into(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
+                         bool deriv, hipStream_t st, double* rows, double* c, double* bc, void* qc, int qc_pitch,
+                         bool timed) {
+  const soap::DevParams& P = ctx->dp;
+  const size_t NP = (size_t)pair_bound(nl);
+  const unsigned mask = ctx->prof_mask;
+  if (!timed) ctx->prof_mask = 0;
+  soap_status s = SOAP_OK;
+  {
+    StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
+    const hipError_t e = soap::launch_pair_prep(P, ctx->dt, (long long)NP, pair_count(nl), nl->dx, nl->dy, nl->dz,
+                                                rows, deriv, bc, ctx->tune.prep_block, st);
+    if (e != hipSuccess) s = hip_fail(ctx, e, "launch_pair_prep");
+  }
+  if (s == SOAP_OK) {
+    StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
+    const hipError_t e = soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species, rows,
+                                                 bc, c, q, P.K, pnorm, qc, qc_pitch, st);
+    if (e != hipSuccess) s = hip_fail(ctx, e, "launch_descriptor");
+  }
+  ctx->prof_mask = mask;
+  return s;
+}
+
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
                     bool deriv, hipStream_t st, void* qc = nullptr, int qc_pitch = 0) {
   const soap::DevParams& P = ctx->dp;
@@ -206,16 +248,8 @@ soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species,
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
   SOAP_ENSURE(ctx, ctx->rows, soap::pair_rows_bytes(P, (long long)NP));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
-  {
-    StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
-    SOAP_HIP(ctx, soap::launch_pair_prep(P, ctx->dt, (long long)NP, pair_count(nl), nl->dx, nl->dy, nl->dz,
-                                         (double*)ctx->rows.p, deriv, (double*)ctx->bc.p, ctx->tune.prep_block, st));
-  }
-  StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
-  SOAP_HIP(ctx, soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                        (const double*)ctx->rows.p, (const double*)ctx->bc.p, (double*)ctx->c.p, q,
-                                        P.K, pnorm, qc, qc_pitch, st));
-  return SOAP_OK;
+  return forward_into(ctx, nl, species, q, pnorm, deriv, st, (double*)ctx->rows.p, (double*)ctx->c.p,
+                      (double*)ctx->bc.p, qc, qc_pitch, true);
 }
 
 }  // namespace
@@ -238,6 +272,8 @@ const char* soap_last_error(const soap_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 long long soap_workspace_bytes(const soap_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
 
+long long soap_workspace_generation(const soap_ctx* ctx) { return ctx ? ctx->ws_gen : -1; }
+
 int soap_descriptor_dim(const soap_ctx* ctx) { return ctx ? ctx->dp.K : 0; }
 
 soap_status soap_create(const soap_params* p, soap_ctx** out) {
@@ -257,6 +293,8 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
   d.K = d.nch * (d.nch + 1) / 2 * (d.l + 1);
   d.buffer = p->r_soft < p->r_cut ? 1 : 0;
   d.l_weight = p->l_weight;
+  d.radial_dd = p->radial_precision == SOAP_RADIAL_DD ||
+                (p->radial_precision == SOAP_RADIAL_AUTO && p->precision == SOAP_FP64 && p->n_max >= 8);
   d.rc = p->r_cut;
   d.rs = p->r_soft;
   d.nf = p->n_f;
@@ -268,14 +306,17 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
   d.a = p->a;
   d.cw = p->central_weight;
   soap::DevTables& t = ctx->ht;
-  double W[16 * 16];
-  if (soap_host_basis_table(d.n, d.rc, d.s0r, W, nullptr, nullptr) != 0) {
+  double W[16 * 16], Wl[16 * 16];
+  if (soap_host_basis_table(d.n, d.rc, d.s0r, W, Wl, nullptr) != 0 ||
+      soap_host_radial_consts(d.n, d.rc, t.invN, t.invNl, t.rcinv) != 0) {
     delete ctx;
     return SOAP_EINVAL;
   }
   for (int k = 0; k < d.n; ++k)
-    for (int al = 0; al < d.n; ++al) t.W[k * soap::kMaxN + al] = W[k * d.n + al];
-  for (int al = 1; al < d.n; ++al) t.invN[al - 1] = std::sqrt((2.0 * al + 5.0) / d.rc);
+    for (int al = 0; al < d.n; ++al) {
+      t.W[k * soap::kMaxN + al] = W[k * d.n + al];
+      t.Wl[k * soap::kMaxN + al] = Wl[k * d.n + al];
+    }
   for (int l = 0; l <= soap::kMaxL + 1; ++l) t.lw[l] = p->l_weight ? 1.0 : 2.0 * l + 1.0;
   soap::build_angular_tables(d, t);
   if (hipGetDevice(&ctx->device) != hipSuccess || hipMalloc((void**)&ctx->dt, sizeof(soap::DevTables)) != hipSuccess) {
@@ -570,7 +611,7 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   }
   StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
   SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
-                                          nullptr, nullptr, 4, pos_grad, true, st));
+                                          pos_grad, true, st));
   return SOAP_OK;
 }
 
@@ -617,7 +658,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   if (N == 0) {
-    if (alpha_grad) SOAP_HIP(ctx, hipMemsetAsync(alpha_grad, 0, sizeof(double) * M, st));
+    if (alpha_grad) SOAP_HIP(ctx, soap::launch_fill(alpha_grad, M, 0.0, st));  // a kernel, capturable
     return SOAP_OK;
   }
   SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
@@ -672,7 +713,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,
-                                            nullptr, nullptr, 4, forces, false, st));
+                                            forces, false, st));
   }
   return SOAP_OK;
 }

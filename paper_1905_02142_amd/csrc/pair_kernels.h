@@ -56,9 +56,12 @@ void build_angular_tables(const DevParams& P, DevTables& T);
 // and kclear (the previous kset, set to zero) are written
 hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qbar, hipStream_t st);
 
-// out = F (overwrite) or pos_grad -= F (accumulate_grad), from pair gradients
-// laid out as launch_pair_adjoint writes them for gstride
-hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
-                               const double* gz, int gstride, double* out, bool accumulate_grad, hipStream_t st);
+// out = F (overwrite) or pos_grad -= F (accumulate_grad), from the pair
+// gradients as (x, y, z, 0) records (launch_pair_adjoint with gstride 4)
+hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* g,
+                               double* out, bool accumulate_grad, hipStream_t st);
+
+// p[0..n) = v, as a kernel (so that it may be captured in a graph)
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t st);
 
 }  // namespace soap

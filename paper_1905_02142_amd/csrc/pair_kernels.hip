@@ -130,7 +130,8 @@ __device__ inline void azimuthal_step(double& cr, double& ci, double ux, double 
 // dB_k/dr) and odd blocks the angular ones (w_l e_l, its derivative, the
 // azimuthal powers, u and 1/r), so each pair's serial FP64 chain is split in
 // two and twice as many wavefronts share the latency.
-template <int NMAX, int LMAX, bool DERIV>
+// DD: the radial stage in double-double arithmetic (radial<..., true>)
+template <int NMAX, int LMAX, bool DERIV, bool DD>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
                                                      const int* __restrict__ count, const double* __restrict__ dx,
                                                      const double* __restrict__ dy, const double* __restrict__ dz,
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
     double B[NMAX], dB[NMAX];
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;
-    radial<NMAX, false>(P, tab, 0.0, B, dB);
+    radial<NMAX, false, DD>(P, tab, 0.0, B, dB);
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) bc[k] = P.cw * B[k] * tab.lw[0] * 0.28209479177387814;
   }
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
     double B[NMAX], dB[NMAX];
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;  // channels k >= n_max stay zero
-    radial<NMAX, DERIV>(P, tab, r, B, dB);
+    radial<NMAX, DERIV, DD>(P, tab, r, B, dB);
     if (!(r < P.rc)) {  // a pair of a list built with a skin beyond r_cut: no density, no gradient
 #pragma unroll
       for (int k = 0; k < NMAX; ++k) B[k] = dB[k] = 0.0;
@@ -810,34 +811,24 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
 }
 
 // F_k = sum over k's pairs q of (g_q - g_rev(q)) (= -dE/dr_k); mode 1 adds -F_k into
-// pos_grad.  One wavefront per atom, one pair per lane (an atom's list is
-// usually shorter than 64, so its reverse indices and both gradients are read
-// in one round); the lane sums are combined by a fixed butterfly, so the result
-// is the same on every run.
+// pos_grad.  The pair gradients are (x, y, z, 0) records, so a pair and its reverse
+// pair cost one 32-byte read each.  One wavefront per atom, one pair per lane (an
+// atom's list is usually shorter than 64, so its reverse indices and both
+// gradients are read in one round); the lane sums are combined by a fixed
+// butterfly, so the result is the same on every run.
 __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets, int bound,
-                                                      const int* __restrict__ rev, const double* __restrict__ gx,
-                                                      const double* __restrict__ gy, const double* __restrict__ gz,
-                                                      int gstride, double* __restrict__ out, int accumulate_grad) {
+                                                      const int* __restrict__ rev, const dvec4* __restrict__ g,
+                                                      double* __restrict__ out, int accumulate_grad) {
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= n_atoms) return;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   const int q1 = min(offsets[k + 1], bound);
-  if (gstride == 4) {  // (x, y, z, 0) records: one 32-byte read per pair, also for the reverse one
-    const dvec4* __restrict__ g = reinterpret_cast<const dvec4*>(gx);
-    for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
-      const dvec4 a = g[q], b = g[rev[q]];
-      fx += a.x - b.x;
-      fy += a.y - b.y;
-      fz += a.z - b.z;
-    }
-  } else {
-    for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
-      const int r = rev[q];
-      fx += gx[q] - gx[r];
-      fy += gy[q] - gy[r];
-      fz += gz[q] - gz[r];
-    }
+  for (int q = min(offsets[k], bound) + lane; q < q1; q += 64) {
+    const dvec4 a = g[q], b = g[rev[q]];
+    fx += a.x - b.x;
+    fy += a.y - b.y;
+    fz += a.z - b.z;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -856,6 +847,11 @@ __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __
       out[3 * k + 2] = fz;
     }
   }
+}
+
+__global__ void k_fill(double* __restrict__ p, long long n, double v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
 }
 
 // compile-time (n_max, l_max) buckets: the kernels handle any n <= NMAX, l <= LMAX
@@ -928,12 +924,18 @@ hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_
   const int blocks = 2 * ((int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0));
   auto f = [&]<int N, int LM>() {
     const int np = (int)n_pairs;
-    if (deriv)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy, dz,
-                         rows, bc);
+    if (deriv && P.radial_dd)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
+                         dz, rows, bc);
+    else if (deriv)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
+                         dz, rows, bc);
+    else if (P.radial_dd)
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
+                         dz, rows, bc);
     else
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy, dz,
-                         rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
+                         dz, rows, bc);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
@@ -989,12 +991,17 @@ hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qba
   return hipGetLastError();
 }
 
-hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* gx, const double* gy,
-                               const double* gz, int gstride, double* out, bool accumulate_grad, hipStream_t st) {
+hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* g,
+                               double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 3) / 4), dim3(256), 0, st, n_atoms, offsets, bound, rev, gx, gy, gz,
-                     gstride, out, accumulate_grad ? 1 : 0);
+  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 3) / 4), dim3(256), 0, st, n_atoms, offsets, bound, rev,
+                     reinterpret_cast<const dvec4*>(g), out, accumulate_grad ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

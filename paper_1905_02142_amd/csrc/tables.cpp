@@ -126,3 +126,20 @@ extern "C" int soap_host_basis_table(int n_max, double r_cut, double sigma0_r, d
   }
   return 0;
 }
+
+// Constants of the radial stage in double-double form (value = hi + lo to about
+// 106 bits, from binary128): 1 / N_alpha = sqrt((2 alpha + 5) / r_c) for
+// alpha = 1..n_max-1 (stored at alpha - 1), and rc4 = (1/r_c, remainder,
+// 1/r_c^2, remainder).  Returns 0, or -1 for invalid sizes.
+extern "C" int soap_host_radial_consts(int n_max, double r_cut, double* invN_hi, double* invN_lo, double* rc4) {
+  if (n_max < 2 || n_max > 16 || !(r_cut > 0)) return -1;
+  Q rc = r_cut;
+  auto split = [](Q x, double* hi, double* lo) {
+    *hi = (double)x;
+    *lo = (double)(x - (Q)*hi);
+  };
+  for (int a = 1; a < n_max; ++a) split(sqrtq((Q)(2 * a + 5) / rc), invN_hi + a - 1, invN_lo + a - 1);
+  split(1 / rc, rc4, rc4 + 1);
+  split(1 / (rc * rc), rc4 + 2, rc4 + 3);
+  return 0;
+}

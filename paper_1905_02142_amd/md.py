@@ -10,7 +10,18 @@ list rebuilt, into the same buffers, with the pair count left on the device.  On
 so a step issues no host-side launches.  The array operations of the
 integrator are plain torch element-wise work; all of the force evaluation runs in
 the library's kernels.
+
+The host does not wait for the device every step.  Steps run in chunks of
+``check_every`` replays; inside the graph each step marks, on the device, every
+atom that is further than skin / 2 from its position at the last build (the one
+condition under which the list may miss a pair inside r_cut).  After a chunk the
+host reads the marks once: if none is set, every step of the chunk used a valid
+list; if one is, the chunk is undone from a copy of the state taken before it and
+run again one step at a time, rebuilding the list before any step whose drift
+could reach the limit.  Between chunks the list is also rebuilt ahead of time
+when the coming chunk would probably reach the limit, so that repeats are rare.
 """
+
 from __future__ import annotations
 
 import torch
@@ -30,9 +41,10 @@ class GapMD:
     """
 
     def __init__(self, soap: Soap, positions, masses, cell, pbc, species, q_sparse, alpha, zeta: int,
-                 dt: float = 0.5, skin: float = 0.4, velocities=None, reserve: float = 0.3):
+                 dt: float = 0.5, skin: float = 0.4, velocities=None, reserve: float = 0.3, check_every: int = 10):
         self.soap, self.cell, self.pbc = soap, cell, pbc
         self.dt, self.skin = float(dt), float(skin)
+        self.check_every = max(1, int(check_every))
         dev = positions.device
         self.pos = positions.to(torch.float64).contiguous().clone()
         n = self.pos.shape[0]
@@ -48,17 +60,27 @@ class GapMD:
         first = soap.neighbors(self.pos, cell, pbc)
         self.nl = NeighbourList(n, int(first.n_pairs * (1.0 + reserve)) + 256, dev)
         self.pos_at_build = torch.empty_like(self.pos)
+        self.moved = torch.zeros(n, dtype=torch.bool, device=dev)  # atoms beyond skin / 2 since the build
         self.rebuilds = -1
         self._rebuild()
         self.e = torch.empty(n, dtype=torch.float64, device=dev)
         self.F = torch.empty(n, 3, dtype=torch.float64, device=dev)
         self.ab = torch.empty(self.qs.shape[0], dtype=torch.float64, device=dev)
         self._forces()  # forces of the initial positions; also sizes the workspace
+        self.captures = 0
+        self._capture()
+        self.steps = 0
+        self.host_syncs = 0  # host waits for the device inside step()
+        self.repeated_chunks = 0
+
+    def _capture(self):
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self._step_ops()
-        self.steps = 0
+        # a later growth of the library's workspace frees memory the graph names
+        self._ws_gen = _lib.soap_workspace_generation(self.soap.ctx)
+        self.captures += 1
 
     def _forces(self):
         self.soap.energy_forces(self.nl, self.spec, self.qs, self.al, self.zeta, out=(self.e, self.F, self.ab))
@@ -67,6 +89,10 @@ class GapMD:
         h = 0.5 * self.dt
         self.vel.add_(self.F * self.inv_m, alpha=h)
         self.pos.add_(self.vel, alpha=self.dt)
+        d = self.pos - self.pos_at_build
+        lim2 = (0.5 * self.skin) ** 2
+        torch.logical_or(self.moved, d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2] > lim2,
+                         out=self.moved)
         self.soap.update_pair_vectors(self.nl, self.pos)
         self._forces()
         self.vel.add_(self.F * self.inv_m, alpha=h)
@@ -78,21 +104,52 @@ class GapMD:
         # for every rebuilt list
         self.nl.n_pairs = _lib.SOAP_PAIRS_DEFERRED
         self.pos_at_build.copy_(self.pos)
+        self.moved.zero_()
         self.rebuilds += 1
 
+    def _reach(self):
+        """(atoms marked, largest displacement since the build, coming drift |v + dt F / 2m| dt)
+        in one read-back."""
+        disp = (self.pos - self.pos_at_build).norm(dim=1).max()
+        drift = (self.vel + (0.5 * self.dt) * self.F * self.inv_m).norm(dim=1).max() * self.dt
+        self.host_syncs += 1
+        marked, disp, drift = torch.stack([self.moved.any().to(torch.float64), disp, drift]).tolist()
+        return marked > 0, disp, drift
+
+    def _checked_step(self):
+        """One step after the host has checked the list: rebuilt first if the coming
+        drift could take some atom further than skin / 2 from its position at the build."""
+        _, disp, drift = self._reach()
+        if disp + drift > 0.5 * self.skin:
+            if drift > 0.5 * self.skin:
+                raise ValueError("one step moves atoms further than skin / 2: raise the skin or lower dt")
+            self._rebuild()
+        self.graph.replay()
+
     def step(self, n: int = 1) -> None:
-        """n timesteps; before each, the list is rebuilt if the coming drift could
-        take some atom further than skin / 2 from its position at the last build."""
-        for _ in range(n):
-            disp = (self.pos - self.pos_at_build).norm(dim=1).max()
-            # a bound on the coming drift: |v + dt F / 2m| dt
-            drift = (self.vel + (0.5 * self.dt) * self.F * self.inv_m).norm(dim=1).max() * self.dt
-            if (disp + drift).item() > 0.5 * self.skin:
-                self._rebuild()
-                if drift.item() > 0.5 * self.skin:
-                    raise ValueError("one step moves atoms further than skin / 2: raise the skin or lower dt")
-            self.graph.replay()
-            self.steps += 1
+        """n timesteps, in chunks of check_every graph replays with one host read-back each."""
+        done = 0
+        while done < n:
+            k = min(self.check_every, n - done)
+            if _lib.soap_workspace_generation(self.soap.ctx) != self._ws_gen:
+                self._capture()
+            saved = [t.clone() for t in (self.pos, self.vel, self.e, self.F, self.ab)]
+            for _ in range(k):
+                self.graph.replay()
+            marked, disp, drift = self._reach()
+            if marked:
+                # some step of the chunk ran on a list that may miss pairs: undo it and
+                # take its steps one at a time
+                for t, v in zip((self.pos, self.vel, self.e, self.F, self.ab), saved):
+                    t.copy_(v)
+                self.moved.zero_()
+                self.repeated_chunks += 1
+                for _ in range(k):
+                    self._checked_step()
+            elif disp + k * drift > 0.5 * self.skin:
+                self._rebuild()  # ahead of a chunk that would probably reach the limit
+            done += k
+            self.steps += k
 
     def energies(self):
         """(potential, kinetic) in eV at the current step."""

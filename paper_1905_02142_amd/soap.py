@@ -11,6 +11,7 @@ from . import _lib
 
 PRECISIONS = {"fp64": _lib.SOAP_FP64, "f32": _lib.SOAP_MIXED_F32, "bf16": _lib.SOAP_MIXED_BF16,
               "bf16x3": _lib.SOAP_MIXED_BF16X3}
+RADIAL_PRECISIONS = {"auto": _lib.SOAP_RADIAL_AUTO, "fp64": _lib.SOAP_RADIAL_FP64, "dd": _lib.SOAP_RADIAL_DD}
 
 
 @dataclass(frozen=True)
@@ -31,12 +32,14 @@ class SoapParams:
     central_weight: float = 1.0
     l_weight: int = 0
     precision: str = "fp64"
+    radial_precision: str = "auto"  # "auto": double-double in the fp64 mode for n_max >= 8
 
     def c_struct(self) -> _lib.soap_params:
         return _lib.soap_params(self.n_max, self.l_max, self.n_species, self.r_cut,
                                 self.r_cut if self.r_soft is None else self.r_soft, self.n_f,
                                 self.sigma0_r, self.sigma0_perp, self.alpha_r, self.alpha_perp, self.a,
-                                self.central_weight, self.l_weight, PRECISIONS[self.precision])
+                                self.central_weight, self.l_weight, PRECISIONS[self.precision],
+                                RADIAL_PRECISIONS[self.radial_precision])
 
     @property
     def dim(self) -> int:
@@ -165,8 +168,9 @@ class Soap:
         return n
 
     # ---------------------------------------------------------------- descriptor
-    def descriptor(self, nl: NeighbourList, species: torch.Tensor, with_norm: bool = False):
-        q = torch.empty(nl.n_atoms, self.dim, dtype=torch.float64, device=nl.device)
+    def descriptor(self, nl: NeighbourList, species: torch.Tensor, with_norm: bool = False, out=None):
+        q = torch.empty(nl.n_atoms, self.dim, dtype=torch.float64, device=nl.device) if out is None else out
+        assert q.dtype == torch.float64 and q.is_contiguous() and q.shape == (nl.n_atoms, self.dim)
         pn = torch.empty(nl.n_atoms, dtype=torch.float64, device=nl.device)
         sp = species.to(torch.int32).contiguous()
         _lib.soap_descriptor(self.ctx, nl.c_struct(), sp.data_ptr(), q.data_ptr(), pn.data_ptr(), _stream())

@@ -38,8 +38,8 @@ def test_header_declarations_are_exported():
 
 def test_struct_layouts():
     L = _lib()
-    # soap_params: 3 ints, padding, 9 doubles, 2 ints
-    assert ctypes.sizeof(L.soap_params) == 4 * 3 + 4 + 8 * 9 + 4 * 2
+    # soap_params: 3 ints, padding, 9 doubles, 3 ints, padding
+    assert ctypes.sizeof(L.soap_params) == 4 * 3 + 4 + 8 * 9 + 4 * 3 + 4
     assert ctypes.sizeof(L.soap_nlist) == 4 + 4 + 8 + 8 + 8 * 8
 
 
@@ -56,7 +56,7 @@ def test_radial_table_matches_oracle(n, rc, s0):
 
 @pytest.mark.parametrize("bad", [dict(n_max=1), dict(n_max=13), dict(l_max=13), dict(l_max=-1), dict(n_species=0),
                                  dict(r_cut=0.0), dict(sigma0_r=0.0), dict(r_soft=6.0), dict(alpha_r=-0.1),
-                                 dict(a=-1.0), dict(l_weight=2), dict(precision=7)])
+                                 dict(a=-1.0), dict(l_weight=2), dict(precision=7), dict(radial_precision=3)])
 def test_invalid_parameters_rejected_on_host(bad):
     L = _lib()
     kw = dict(n_max=8, l_max=8, n_species=1, r_cut=5.0, r_soft=5.0, n_f=4.0, sigma0_r=0.5, sigma0_perp=0.5,

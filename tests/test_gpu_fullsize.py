@@ -79,14 +79,20 @@ def test_slab_three_species_sampled():
     _sampled(w, e, F, np.concatenate([dense, sparse, edge]), 1e-10)
 
 
-def test_slab_three_species_bf16_bounds():
-    w = synth.workload("slab32768_3sp_n8l8")
+@pytest.mark.parametrize("name", ["box4096_n8l8", "slab32768_3sp_n8l8", "batch256_n8l6", "box262144_n10l10"])
+def test_mixed_mode_force_rmse(name):
+    # each workload's mixed-precision mode (the one its benchmark line times)
+    # against the fp64 path: force RMSE at most 1e-4 eV/A, and the mode's
+    # relative bound on energies and forces
+    w = synth.workload(name)
+    mode = w["mixed"]
     e, F, ab, _ = _run(w)
-    eb, Fb, abb, _ = _run(w, "bf16")
+    eb, Fb, abb, _ = _run(w, mode)
     rmse = np.sqrt(np.mean((Fb - F) ** 2))
-    print(f"bf16 vs fp64: force RMSE {rmse:.3e} eV/A, RMS force {np.sqrt(np.mean(F ** 2)):.3e}")
-    assert np.abs(eb - e).max() <= 5e-2 * np.abs(e).max()
-    assert np.abs(Fb - F).max() <= 5e-2 * np.abs(F).max()
+    print(f"{mode} vs fp64: force RMSE {rmse:.3e} eV/A, RMS force {np.sqrt(np.mean(F ** 2)):.3e}")
+    bound = {"bf16": 5e-2, "bf16x3": 1e-3, "f32": 1e-4}[mode]
+    assert np.abs(eb - e).max() <= bound * np.abs(e).max()
+    assert np.abs(Fb - F).max() <= bound * np.abs(F).max()
     assert rmse <= 1e-4
 
 
@@ -113,5 +119,6 @@ def test_box262144_n10l10_sampled():
     print(f"pairs {n_pairs}")
     _whole_system_checks(w, e, F, ab)
     atoms = np.random.default_rng(78).choice(len(e), 8, replace=False)
-    # n_max = 10: the near-singular overlap matrix amplifies rounding of b_alpha
-    _sampled(w, e, F, atoms, 5e-9)
+    # n_max = 10: W's entries reach ~5e6, which the double-double radial stage of
+    # the fp64 mode absorbs
+    _sampled(w, e, F, atoms, 1e-10)

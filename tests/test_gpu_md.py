@@ -11,6 +11,7 @@
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 torch = pytest.importorskip("torch")
@@ -32,6 +33,17 @@ def _model(soap, M=60, seed=31, scale=1.0):
     return _t(qs), _t(al)
 
 
+def _oracle_check(positions, cell, pbc, qs, al, zeta, e, F, tol=1e-10):
+    """Energies and forces at these positions against the oracle (an exact r_cut list)."""
+    n = len(positions)
+    eo, Fo, _ = oracle.energy_forces(oracle.Params(**KW), positions, cell, pbc, np.zeros(n, np.int32),
+                                     qs.cpu().numpy(), al.cpu().numpy(), zeta)
+    de = np.abs(e - eo).max() / np.abs(eo).max()
+    dF = np.abs(F - Fo).max() / np.abs(Fo).max()
+    print(f"vs oracle: rel e {de:.2e}, rel F {dF:.2e}")
+    assert de <= tol and dF <= tol
+
+
 def test_skin_list_gives_the_same_results():
     from paper_1905_02142_amd import Soap, SoapParams
 
@@ -50,6 +62,7 @@ def test_skin_list_gives_the_same_results():
     q1 = sk.descriptor(nl1, sp).cpu().numpy()
     for a, b in ((q1, q0), (e1, e0), (F1, F0), (ab1, ab0)):
         assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    _oracle_check(s.positions, s.cell, s.pbc, qs, al, 3, e1, F1)
     from paper_1905_02142_amd import _lib
     with pytest.raises(_lib.SoapError):
         sk.set_neighbor_skin(-0.1)
@@ -89,6 +102,7 @@ def test_pair_vector_refresh_matches_a_fresh_list():
     e0, F0, _ = (t.cpu().numpy() for t in ref.energy_forces(nl0, sp, qs, al, 3))
     assert np.abs(e1 - e0).max() <= 1e-12 * np.abs(e0).max()
     assert np.abs(F1 - F0).max() <= 1e-12 * np.abs(F0).max()
+    _oracle_check(moved, s.cell, s.pbc, qs, al, 3, e1, F1)
 
 
 def test_md_rebuilds_replays_and_conserves_energy():
@@ -113,8 +127,11 @@ def test_md_rebuilds_replays_and_conserves_energy():
         ep, ek = md.energies()
         tot.append(ep + ek)
     torch.cuda.synchronize()
-    print("rebuilds", md.rebuilds, "E0", ep0 + ek0, "drift", max(abs(x - (ep0 + ek0)) for x in tot), "Ek0", ek0)
+    print("rebuilds", md.rebuilds, "repeated chunks", md.repeated_chunks, "host syncs", md.host_syncs,
+          "E0", ep0 + ek0, "drift", max(abs(x - (ep0 + ek0)) for x in tot), "Ek0", ek0)
     assert md.steps == 400 and md.rebuilds >= 2
+    # one host read-back per chunk of check_every steps, plus one per step of a repeated chunk
+    assert md.host_syncs <= md.steps // md.check_every + md.check_every * md.repeated_chunks
     # energy: constant to well below the kinetic energy's scale
     assert max(abs(x - (ep0 + ek0)) for x in tot) <= 2e-3 * ek0
     # forces at the end equal those of a fresh exact-cutoff list at the final positions
@@ -123,3 +140,5 @@ def test_md_rebuilds_replays_and_conserves_energy():
     _, F, _ = ref.energy_forces(nl, sp, qs, al, 3)
     F, Fm = F.cpu().numpy(), md.F.cpu().numpy()
     assert np.abs(Fm - F).max() <= 1e-10 * np.abs(F).max()
+    # and the oracle's at the same positions
+    _oracle_check(md.pos.cpu().numpy(), s.cell, s.pbc, qs, al, 3, md.e.cpu().numpy(), Fm)

@@ -119,11 +119,21 @@ DESC_CASES = {
     # three 64-pair rounds in the adjoint and the force gather and five 32-pair
     # chunks in the descriptor
     "dense60_n8l8": (dict(n_max=8, l_max=8, r_cut=5.0, sigma0_r=0.5, sigma0_perp=0.5), 60, 6.0, 1, 13),
+    # the largest compiled basis bucket (n_max, l_max up to 12)
+    "n11l12": (dict(n_max=11, l_max=12, r_cut=5.0, sigma0_r=0.5, sigma0_perp=0.5), 60, 8.4, 1, 14),
+    "n12l11": (dict(n_max=12, l_max=11, r_cut=5.0, sigma0_r=0.5, sigma0_perp=0.5), 60, 8.4, 1, 15),
 }
 
-# n_max = 10: the FP64 radial transform amplifies rounding to ~1e-9 (the basis
-# overlap matrix has condition ~1e15); every other case meets 1e-10
-Q_TOL = {"n10l10": 5e-9}
+# Every descriptor and energy case meets 1e-10: in the fp64 mode the radial
+# recursion and W b_alpha run in double-double, which holds b_n to ~1e-13 even
+# where W's entries reach ~2e8 (n_max = 12).  The forces at n_max = 12 are held
+# to the oracle's own accuracy instead: its long-double dB/dr (the textbook
+# derivative of the overlap integrals, W applied in 64-bit arithmetic) differs
+# from 40-digit quadrature by up to 4.5e-10 per pair at n_max = 12 (3e-12 at 10,
+# 1.4e-10 at 11 with the narrow widths of the hyper-parameter cases), so the
+# bound there is 2e-9, about four times that.
+Q_TOL = {}
+F_TOL = {"n12l11": 2e-9}
 
 
 def _species(n, ns, seed):
@@ -162,12 +172,16 @@ def _energy_forces_case(kw, n, L, ns, seed, M, zeta):
 
 @pytest.mark.parametrize("name,M,zeta", [("box64_n6l6", 50, 4), ("hp_buffer_n8l8", 80, 3), ("hp_n8l8", 70, 3),
                                          ("species3_n4l4", 40, 2), ("box300_n8l8", 130, 4),
-                                         ("lweight1_nocentral", 33, 1), ("dense60_n8l8", 64, 4)])
+                                         ("lweight1_nocentral", 33, 1), ("dense60_n8l8", 64, 4),
+                                         ("n10l10", 90, 4), ("n11l12", 40, 3), ("n12l11", 40, 4)])
 def test_energy_forces_match_oracle(name, M, zeta):
     kw, n, L, ns, seed = DESC_CASES[name]
     e, F, ab, eo, Fo, abo = _energy_forces_case(kw, n, L, ns, seed, M, zeta)
-    assert np.abs(e - eo).max() < 1e-10 * np.abs(eo).max()
-    assert np.abs(F - Fo).max() < 1e-10 * np.abs(Fo).max()
+    de = np.abs(e - eo).max() / np.abs(eo).max()
+    dF = np.abs(F - Fo).max() / np.abs(Fo).max()
+    print(f"{name}: rel e {de:.2e}, rel F {dF:.2e}")
+    assert de < 1e-10
+    assert dF < F_TOL.get(name, 1e-10)
     assert np.abs(ab - abo).max() < 1e-10 * np.abs(abo).max()
     assert np.abs(F.sum(0)).max() < 1e-12 * np.abs(F).max()
 
