@@ -204,6 +204,33 @@ soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* 
                             double* p_norm, hipStream_t stream);
 
 /*
+ * soap_descriptor for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same results, bit for bit, from the same kernels, but every intermediate
+ * buffer (the per-pair fields, c_nlm, the central-atom factors and |p| when
+ * p_norm is NULL) lives in one fixed array of SOAP_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device for the life of the process.  The call makes
+ * no device allocation, free or copy and does not grow the context's workspace;
+ * the caller still passes q (and p_norm) and the neighbour list.
+ * Limits and errors: the buffers take 8 ROW 64 ceil(P / 64) bytes for P pairs
+ * (P = nl->capacity while the count is deferred), 8 n_species NB ((l_max+1)^2 + 1)
+ * bytes per atom, 96 bytes and, with p_norm NULL, 8 bytes per atom, each rounded
+ * up to 256 bytes, where ROW and NB come from the compiled basis bucket (ROW = 56,
+ * NB = 8 at n_max = l_max = 8; ROW = 68, NB = 10 at 10): 4096 atoms with 211,320
+ * pairs at n_max = l_max = 8 take 116 MB.  A call needing more than
+ * SOAP_NOALLOC_SCRATCH_BYTES returns SOAP_ENOTSUP before
+ * any device work, with the sizes in soap_last_error; SOAP_EINVAL as
+ * soap_descriptor, or when the current device is not the context's; SOAP_EHIP if
+ * the scratch array's address could not be looked up at soap_create.
+ * Every call on one device shares that device's array and leaves its contents
+ * behind: calls that overlap in time on one device (other streams, other
+ * contexts, other threads) race and must be ordered by the caller.
+ */
+#define SOAP_NOALLOC_SCRATCH_BYTES (128LL << 20)
+soap_status soap_descriptor_noalloc(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q,
+                                    double* p_norm, hipStream_t stream);
+
+/*
  * Vector-Jacobian product of the descriptor: pos_grad (n_atoms x 3) +=
  * sum_i (dq_i/dr)^T q_bar_i, with q_bar (n_atoms x K) in the packing of
  * soap_descriptor.  The derivative of the chain Eq. (08) -> Eq. (09) -> q = p/|p|

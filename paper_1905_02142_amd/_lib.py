@@ -24,8 +24,9 @@ EXPORTED = (
     "soap_radial_basis_table", "soap_workspace_bytes", "soap_profile", "soap_profile_read", "soap_stage_name",
     "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
     "soap_build_neighbors_async", "soap_neighbors_check", "soap_descriptor_jacobian", "soap_set_neighbor_skin",
-    "soap_update_pair_vectors", "soap_workspace_generation",
+    "soap_update_pair_vectors", "soap_workspace_generation", "soap_descriptor_noalloc",
 )
+SOAP_NOALLOC_SCRATCH_BYTES = 128 << 20
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
           "pair_prep", "cbar")
 
@@ -101,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.soap_neighbors_check.restype = i
     lib.soap_descriptor.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
     lib.soap_descriptor.restype = i
+    lib.soap_descriptor_noalloc.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
+    lib.soap_descriptor_noalloc.restype = i
     lib.soap_descriptor_grad.argtypes = [vp, P(soap_nlist), vp, vp, vp, vp]
     lib.soap_descriptor_grad.restype = i
     lib.soap_update_pair_vectors.argtypes = [vp, P(soap_nlist), vp, vp]
@@ -198,6 +201,10 @@ def soap_neighbors_check(ctx, nl: soap_nlist, stream) -> tuple[int, int]:
 
 def soap_descriptor(ctx, nl: soap_nlist, species, q, p_norm, stream) -> None:
     check(load().soap_descriptor(ctx, ctypes.byref(nl), species, q, p_norm, stream), ctx)
+
+
+def soap_descriptor_noalloc(ctx, nl: soap_nlist, species, q, p_norm, stream) -> None:
+    check(load().soap_descriptor_noalloc(ctx, ctypes.byref(nl), species, q, p_norm, stream), ctx)
 
 
 def soap_descriptor_grad(ctx, nl: soap_nlist, species, q_bar, pos_grad, stream) -> None:

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,12 +29,44 @@ struct Buf {
 
 }  // namespace
 
+// Scratch of soap_descriptor_noalloc (pair rows, c, the central-atom factors and
+// |p|), for callers that cannot allocate.  Every device the library runs on
+// holds one copy for the life of the process.  In host code the name is not a
+// device address: host code uses only the address that hipGetSymbolAddress
+// returns for the current device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[SOAP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // the device address of `scratch`, per device
+
+// The address of `scratch` on `device`, which must be current: looked up once per
+// device, then kept.
+hipError_t noalloc_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
+}  // namespace
+
 struct soap_ctx {
   soap_params prm{};
   soap::DevParams dp{};
   soap::DevTables ht{};
   soap::DevTables* dt = nullptr;
   int device = 0;
+  void* scratch = nullptr;  // this device's copy of the no-allocation scratch array
+  hipError_t scratch_err = hipSuccess;  // why `scratch` could not be looked up
   std::string err;
   long long ws_bytes = 0;
   long long ws_gen = 0;  // bumped whenever a workspace buffer is reallocated
@@ -328,6 +361,10 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
     delete ctx;
     return SOAP_EHIP;
   }
+  // set-up of soap_descriptor_noalloc: the address of this device's scratch array
+  // (a failure disables that entry point only, which reports it)
+  ctx->scratch_err = noalloc_scratch(ctx->device, &ctx->scratch);
+  if (ctx->scratch_err != hipSuccess) ctx->scratch = nullptr;
   *out = ctx;
   return SOAP_OK;
 }
@@ -586,6 +623,38 @@ soap_status soap_descriptor(soap_ctx* ctx, const soap_nlist* nl, const int32_t* 
     pn = (double*)ctx->pnorm.p;
   }
   return forward(ctx, nl, species, q, pn, false, st);
+}
+
+soap_status soap_descriptor_noalloc(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q,
+                                    double* p_norm, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  soap_status s = check_nlist(ctx, nl);
+  if (s != SOAP_OK) return s;
+  if ((s = check_lds(ctx)) != SOAP_OK) return s;
+  if (nl->n_atoms > 0 && (!species || !q)) return fail(ctx, SOAP_EINVAL, "null species or output");
+  const soap::DevParams& P = ctx->dp;
+  const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_rows = up(soap::pair_rows_bytes(P, (long long)NP));
+  const size_t b_c = up(sizeof(double) * N * soap::c_doubles_per_atom(P));
+  const size_t b_bc = up(sizeof(double) * soap::kMaxN);
+  const size_t b_pn = p_norm ? 0 : up(sizeof(double) * N);
+  const size_t need = b_rows + b_c + b_bc + b_pn;
+  if (need > (size_t)SOAP_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, SOAP_ENOTSUP,
+                "soap_descriptor_noalloc needs " + std::to_string(need) + " bytes of scratch for " +
+                    std::to_string(N) + " atoms and " + std::to_string(NP) + " pairs; it has " +
+                    std::to_string((size_t)SOAP_NOALLOC_SCRATCH_BYTES));
+  if (!ctx->scratch) return hip_fail(ctx, ctx->scratch_err, "soap_descriptor_noalloc scratch address");
+  int cur = -1;
+  SOAP_HIP(ctx, hipGetDevice(&cur));
+  if (cur != ctx->device) return fail(ctx, SOAP_EINVAL, "the current device is not the context's");
+  char* base = static_cast<char*>(ctx->scratch);
+  double* rows = reinterpret_cast<double*>(base);
+  double* c = reinterpret_cast<double*>(base + b_rows);
+  double* bc = reinterpret_cast<double*>(base + b_rows + b_c);
+  double* pn = p_norm ? p_norm : reinterpret_cast<double*>(base + b_rows + b_c + b_bc);
+  return forward_into(ctx, nl, species, q, pn, false, st, rows, c, bc, nullptr, 0, false);
 }
 
 soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_bar,
