@@ -296,7 +296,7 @@ soap_status soap_radial_basis_table(int n_max, double r_cut, double sigma0_r, do
  * waits for the recorded events, writes per stage the summed milliseconds and
  * the number of launches (host arrays of SOAP_STAGE_COUNT entries) and clears
  * the record.  Recording adds two event records per timed stage.  Stages 1, 4,
- * 7 and 8 are one kernel each. */
+ * 5, 7 and 9 are one kernel each. */
 typedef enum {
   SOAP_STAGE_NEIGHBORS = 0,     /* cell list, pair count and fill, reverse index */
   SOAP_STAGE_DESCRIPTOR = 1,    /* c_nlm, power spectrum, q (one kernel) */
@@ -305,9 +305,10 @@ typedef enum {
   SOAP_STAGE_PAIR_ADJOINT = 4,  /* the per-pair gradients (one kernel) */
   SOAP_STAGE_FORCE_GATHER = 5,  /* per-atom force sums */
   SOAP_STAGE_GAP_FUSED = 6,     /* S, the zeta epilogue and Qbar = G Q_s in one pass (16/32-bit modes) */
-  SOAP_STAGE_PAIR_PREP = 7,     /* per-pair radial, ilexp and azimuthal factors (one kernel) */
+  SOAP_STAGE_PAIR_PREP = 7,     /* per-pair radial factors B_k, dB_k/dr, Sec. III.A (one kernel) */
   SOAP_STAGE_CBAR = 8,          /* reserved: vbar and cbar = M c are now formed inside pair_adjoint (no launches) */
-  SOAP_STAGE_COUNT = 9
+  SOAP_STAGE_PAIR_ANGULAR = 9,  /* per-pair ilexp and azimuthal factors, Sec. III.C (one kernel) */
+  SOAP_STAGE_COUNT = 10
 } soap_stage;
 soap_status soap_profile(soap_ctx* ctx, int enable);
 soap_status soap_profile_stages(soap_ctx* ctx, unsigned mask);

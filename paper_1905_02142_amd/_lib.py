@@ -28,7 +28,7 @@ EXPORTED = (
 )
 SOAP_NOALLOC_SCRATCH_BYTES = 128 << 20
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
-          "pair_prep", "cbar")
+          "pair_prep", "cbar", "pair_angular")
 
 
 class soap_params(ctypes.Structure):

@@ -258,10 +258,10 @@ soap_status forward_into(soap_ctx* ctx, const soap_nlist* nl, const int32_t* spe
   const unsigned mask = ctx->prof_mask;
   if (!timed) ctx->prof_mask = 0;
   soap_status s = SOAP_OK;
-  {
-    StageTimer tm(ctx, SOAP_STAGE_PAIR_PREP, st);
+  for (int part = 1; part <= 2 && s == SOAP_OK; ++part) {
+    StageTimer tm(ctx, part == 1 ? SOAP_STAGE_PAIR_PREP : SOAP_STAGE_PAIR_ANGULAR, st);
     const hipError_t e = soap::launch_pair_prep(P, ctx->dt, (long long)NP, pair_count(nl), nl->dx, nl->dy, nl->dz,
-                                                rows, deriv, bc, ctx->tune.prep_block, st);
+                                                rows, deriv, bc, ctx->tune.prep_block, part, st);
     if (e != hipSuccess) s = hip_fail(ctx, e, "launch_pair_prep");
   }
   if (s == SOAP_OK) {
@@ -924,8 +924,9 @@ soap_status soap_profile_read(soap_ctx* ctx, double* ms, long long* launches) {
 }
 
 const char* soap_stage_name(int stage) {
-  static const char* names[SOAP_STAGE_COUNT] = {"neighbors",    "descriptor",   "gap_scores", "gap_qbar", "pair_adjoint",
-                                                "force_gather", "gap_fused",    "pair_prep",  "cbar"};
+  static const char* names[SOAP_STAGE_COUNT] = {"neighbors",    "descriptor", "gap_scores", "gap_qbar",
+                                                "pair_adjoint", "force_gather", "gap_fused", "pair_prep",
+                                                "cbar",         "pair_angular"};
   return (stage >= 0 && stage < SOAP_STAGE_COUNT) ? names[stage] : "unknown";
 }
 

@@ -24,10 +24,11 @@ size_t pair_row_doubles(const DevParams& P);
 // field-major, pair_rows_bytes in all) for n_pairs neighbours (or, with count
 // non-null, for min(*count, n_pairs)), the derivative fields only if deriv, and
 // the central-atom radial factors bc (n_max doubles); block: threads per block
-// (64, 128 or 256)
+// (64, 128 or 256); part 1: the radial fields and bc, part 2: the angular fields
+// (two launches, both needed before the descriptor)
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
-                            int block, hipStream_t st);
+                            int block, int part, hipStream_t st);
 size_t pair_rows_bytes(const DevParams& P, long long n_pairs);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|

@@ -12,10 +12,11 @@
 //
 // k_descriptor, one 64-lane wavefront per centre atom.  Its neighbours of one
 // species are compacted with a wave ballot and their fields staged in LDS, 32
-// at a time.  Each lane owns one (l, m) record (two for l_max >= 10) and takes the
-// neighbours one after the other: it evaluates Qbar_lm(u_z) as a short
-// polynomial and accumulates both real harmonics of its record times every B_k
-// in registers:
+// at a time.  Each lane owns one (l, m) record (l_max = 8, 12: both real
+// harmonics) or whole columns lm of c (l_max = 6, 10, where that fills the lanes
+// better) and takes the neighbours one after the other: it evaluates
+// Qbar_lm(u_z) as a short polynomial and accumulates its harmonics times every
+// B_k in registers:
 //   c_{k,lm} += B_k w_l e_l Y_lm                                    (Eq. (08))
 // so no cross-lane sum is needed; the central atom joins l = 0 and c goes to
 // HBM.  The power spectrum p_{ab l} = sum_m c_{a,lm} c_{b,lm}
@@ -25,9 +26,11 @@
 // Adjoint: each wave of k_pair_adjoint first forms, for its atom, vbar =
 // (qbar - q (q.qbar)) / |p| and cbar = M c
 // (M_aa = 2 vbar_aal, M_ab = sqrt(2) vbar_abl), the derivative of the power
-// spectrum and of the normalisation.  k_pair_adjoint takes one pair per lane:
-// the lane reads its pair's fields and runs over every record (l, m), with the
-// cbar of the neighbour's species and the record table read from LDS:
+// spectrum and of the normalisation.  k_pair_adjoint then takes the pairs in
+// rounds of up to 64, one pair per lane, or R = 2, 4, 8 lanes per pair in a round
+// with fewer pairs left (each lane a share of the degrees l): a lane reads its
+// pair's fields and runs over its records (l, m), with the cbar of the
+// neighbour's species and the record table read from LDS:
 //   U_lm = sum_k cbar_{k,lm} dB_k/dr,  V_lm = sum_k cbar_{k,lm} B_k,
 //   dE/dd = sum_lm [(U_lm a_lm + V_lm da_lm/dr) u + V_lm w_l e_l (I - u u^T) grad_u Y_lm / r]
 // with a_lm = w_l e_l Y_lm, summed in the lane's registers.  Forces are gathered
@@ -88,7 +91,44 @@ struct Shape {
   // forward kernel: fields of CH pairs staged in LDS rows of FRP doubles (even,
   // for 16-byte reads, and 2 mod 4, so the staging writes spread over the banks)
   static constexpr int CH = 32, FRP = FR | 2;
+  // forward lanes: one (l, m) record (both real harmonics) per lane slot, or one
+  // column lm of c per lane slot where that fills the 64 lanes better: l_max = 6
+  // has 28 records but 49 columns (one pass either way), l_max = 10 66 records
+  // (two passes, the second with 2 live lanes) but 121 columns (two passes)
+  static constexpr bool COLS = LMAX == 6 || LMAX == 10;
+  static constexpr int EC = ((LMAX + 1) * (LMAX + 1) + 63) / 64;  // columns per lane
 };
+
+// columns lane + 64 e (e < EC) of a whole wave: lm = l^2 + l + m', the cos part of
+// record (l, |m'|) for m' >= 0 and its sin part for m' < 0; the record's
+// polynomial from the tables (records m outer, l = m..L inner); columns past
+// (L + 1)^2: zero polynomial and the sink column
+template <int EC, int NC>
+struct LaneColumns {
+  double cf[EC][NC];
+  int l[EC], m[EC], par[EC], sn[EC], lm[EC];
+};
+
+template <int EC, int NC>
+__device__ inline void lane_columns(const DevTables* __restrict__ T, int lane, int L, int LL, LaneColumns<EC, NC>& C) {
+#pragma unroll
+  for (int e = 0; e < EC; ++e) {
+    const int j = lane + 64 * e;
+    const bool ok = j < LL;
+    int l = 0;
+    while (ok && (l + 1) * (l + 1) <= j) ++l;
+    const int ms = ok ? j - l * l - l : 0, m = ms < 0 ? -ms : ms;
+    const int rec = m * (L + 1) - m * (m - 1) / 2 + (l - m);
+    const int jj = rec % kRecLanes, slot = rec / kRecLanes;
+    C.l[e] = l;
+    C.m[e] = m;
+    C.par[e] = ok ? (T->rec_lmp[jj][slot] >> 16) : 0;
+    C.sn[e] = ms < 0 ? 1 : 0;
+    C.lm[e] = ok ? j : LL;
+#pragma unroll
+    for (int x = 0; x < NC; ++x) C.cf[e][x] = ok ? T->rec_coef[jj][slot][x] : 0.0;
+  }
+}
 
 // records lane + 64 e (e < E2) of a whole wave, read straight from the tables;
 // records past NREC: zero polynomial, sink columns
@@ -126,12 +166,13 @@ __device__ inline void azimuthal_step(double& cr, double& ci, double ux, double 
   cr = nr;
 }
 
-// Two workgroups per block of pairs: even blocks write the radial fields (B_k,
-// dB_k/dr) and odd blocks the angular ones (w_l e_l, its derivative, the
-// azimuthal powers, u and 1/r), so each pair's serial FP64 chain is split in
-// two and twice as many wavefronts share the latency.
+// Two launches per list: PART 1 writes the radial fields (B_k, dB_k/dr) and the
+// central atom's factors, PART 2 the angular ones (w_l e_l, its derivative, the
+// azimuthal powers, u and 1/r).  Each pair's serial FP64 chain is split in two,
+// each half runs with the registers it needs (the double-double radial stage
+// needs about twice those of the angular one), and the two are timed apart.
 // DD: the radial stage in double-double arithmetic (radial<..., true>)
-template <int NMAX, int LMAX, bool DERIV, bool DD>
+template <int NMAX, int LMAX, bool DERIV, bool DD, int PART>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
                                                      const int* __restrict__ count, const double* __restrict__ dx,
                                                      const double* __restrict__ dy, const double* __restrict__ dz,
@@ -140,8 +181,8 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   __shared__ PairTab<NMAX, LMAX> tab;
   // pairs 0..n_pairs: the bound, or the device-side count cut at the bound
   const int n_pairs = count ? min(bound, max(*count, 0)) : bound;
-  const int pblock = blockIdx.x >> 1;
-  const bool angular = blockIdx.x & 1;
+  const int pblock = blockIdx.x;
+  constexpr bool angular = PART == 2;
   if (pblock > 0 && (int)(pblock * blockDim.x) >= n_pairs) return;  // block 0 also writes bc
   const int p = pblock * blockDim.x + threadIdx.x;
   double x = 0.0, y = 0.0, z = 0.0;
@@ -152,7 +193,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   }
   stage_pair_tables<NMAX, LMAX>(T, tab, threadIdx.x, blockDim.x);
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (!angular && blockIdx.x == 0 && threadIdx.x == 0) {
     // central atom: a Gaussian at r = 0, where e_0 = 1, e_{l>0} = 0, Y_00 = 1 / sqrt(4 pi)
     double B[NMAX], dB[NMAX];
 #pragma unroll
@@ -276,15 +317,23 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
   const int si = P.ns == 1 ? 0 : species[i];
   double* __restrict__ ci_out = c_out + (size_t)i * P.ns * NMAX * LLP;
-  LaneRecords<E2, NC> R;
-  lane_records<E2, NC>(T, lane, S::NREC, LL, R);
+  constexpr bool COLS = S::COLS;
+  constexpr int EC = S::EC;
+  // record mode: acc[e][part][k]; column mode: acc[e][0][k] (EC columns)
+  constexpr int NE = COLS ? EC : E2, NP = COLS ? 1 : 2;
+  LaneRecords<COLS ? 1 : E2, NC> R;
+  LaneColumns<COLS ? EC : 1, NC> C;
+  if constexpr (COLS) lane_columns<EC, NC>(T, lane, P.l, LL, C);
+  else lane_records<E2, NC>(T, lane, S::NREC, LL, R);
 
   for (int s = 0; s < P.ns; ++s) {
-    double acc[E2][2][NMAX];
+    double acc[NE][NP][NMAX];
 #pragma unroll
-    for (int e = 0; e < E2; ++e)
+    for (int e = 0; e < NE; ++e)
 #pragma unroll
-      for (int k = 0; k < NMAX; ++k) acc[e][0][k] = acc[e][1][k] = 0.0;
+      for (int h = 0; h < NP; ++h)
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) acc[e][h][k] = 0.0;
     for (int w0 = p0; w0 < p1; w0 += CH) {
       const int pp = w0 + lane;
       const bool take = lane < CH && pp < p1 && (P.ns == 1 || species[nj[pp]] == s);
@@ -307,18 +356,33 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
           b[k + 1] = v.y;
         }
         const double uz = row(S::FU), x2 = uz * uz;
+        if constexpr (COLS) {
+          // the same products as the record mode (a column is one of its two parts)
 #pragma unroll
-        for (int e = 0; e < E2; ++e) {
-          double Rv = R.cf[e][NC - 1];
+          for (int e = 0; e < EC; ++e) {
+            double Rv = C.cf[e][NC - 1];
 #pragma unroll
-          for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, R.cf[e][t2]);
-          const double Q = R.par[e] ? uz * Rv : Rv;
-          const double a = row(S::FW + R.l[e]) * Q;
-          const double a0 = a * row(S::FZ + 2 * R.m[e]), a1 = a * row(S::FZ + 2 * R.m[e] + 1);
+            for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, C.cf[e][t2]);
+            const double Q = C.par[e] ? uz * Rv : Rv;
+            const double a = row(S::FW + C.l[e]) * Q;
+            const double a0 = a * row(S::FZ + 2 * C.m[e] + C.sn[e]);
 #pragma unroll
-          for (int k = 0; k < NMAX; ++k) {
-            acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
-            acc[e][1][k] = fma(a1, b[k], acc[e][1][k]);
+            for (int k = 0; k < NMAX; ++k) acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < E2; ++e) {
+            double Rv = R.cf[e][NC - 1];
+#pragma unroll
+            for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, R.cf[e][t2]);
+            const double Q = R.par[e] ? uz * Rv : Rv;
+            const double a = row(S::FW + R.l[e]) * Q;
+            const double a0 = a * row(S::FZ + 2 * R.m[e]), a1 = a * row(S::FZ + 2 * R.m[e] + 1);
+#pragma unroll
+            for (int k = 0; k < NMAX; ++k) {
+              acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
+              acc[e][NP - 1][k] = fma(a1, b[k], acc[e][NP - 1][k]);
+            }
           }
         }
       }
@@ -329,8 +393,23 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
     double* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
     const bool c_lds = P.ns == 1;
     if (c_lds) __syncthreads();
+    if constexpr (COLS) {
 #pragma unroll
-    for (int e = 0; e < E2; ++e) {
+      for (int e = 0; e < EC; ++e) {
+        if (C.lm[e] == LL) continue;
+        const bool central = C.lm[e] == 0 && s == si;
+        double* __restrict__ dc = cs + C.lm[e] * NMAX;
+#pragma unroll
+        for (int k = 0; k < NMAX; k += 2) {
+          const double2 v{acc[e][0][k] + (central ? bc_in[k] : 0.0),
+                          acc[e][0][k + 1] + (central ? bc_in[k + 1] : 0.0)};
+          *reinterpret_cast<double2*>(dc + k) = v;
+          if (c_lds) *reinterpret_cast<double2*>(dyn + C.lm[e] * NMAX + k) = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < (COLS ? 0 : E2); ++e) {
       if (lane + 64 * e >= S::NREC || R.lmc[e] == LL) continue;
       const bool central = R.lmc[e] == 0 && s == si;
       double* __restrict__ dc = cs + R.lmc[e] * NMAX;
@@ -344,7 +423,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
         double* __restrict__ ds = cs + R.lms[e] * NMAX;
 #pragma unroll
         for (int k = 0; k < NMAX; k += 2) {
-          const double2 v{acc[e][1][k], acc[e][1][k + 1]};
+          const double2 v{acc[e][NP - 1][k], acc[e][NP - 1][k + 1]};
           *reinterpret_cast<double2*>(ds + k) = v;
           if (c_lds) *reinterpret_cast<double2*>(dyn + R.lms[e] * NMAX + k) = v;
         }
@@ -626,17 +705,19 @@ struct AdjLds {
   }
 };
 
-// the pair's contraction with the cbar of one species over every record (l, m),
-// l outer and m inner: S_r, S_x, S_y, S_z of the gradient
+// the pair's contraction with the cbar of one species over the records (l, m) with
+// l = l_first, l_first + l_step, ... (l outer, m inner): S_r, S_x, S_y, S_z of
+// the gradient (partial sums when l_step > 1)
 template <int NMAX, int LMAX, typename FieldFn>
-__device__ inline void adjoint_records(int L, const double* __restrict__ cb, const double* __restrict__ rc,
+__device__ inline void adjoint_records(int L, int l_first, int l_step, const double* __restrict__ cb,
+                                       const double* __restrict__ rc,
                                        const int* __restrict__ ri, FieldFn F, const double (&b)[NMAX],
                                        const double (&db)[NMAX], double uz, double ux, double uy, double& sr,
                                        double& sx, double& sy, double& sz) {
   using S = Shape<NMAX, LMAX>;
   constexpr int NC = S::NC;
   const double x2 = uz * uz;
-  for (int l = 0; l <= L; ++l) {
+  for (int l = l_first; l <= L; l += l_step) {
     const double we = F(S::FW + l), wd = F(S::FR + S::XW + l);
     // Qbar_lm = x^par R(x^2), R of degree (l - m) / 2: the higher table
     // coefficients are zero, so Horner starts at the top non-zero one (the same
@@ -700,10 +781,13 @@ __device__ inline void adjoint_records(int L, const double* __restrict__ cb, con
   }
 }
 
-// One wave per centre atom, one lane per pair (64 pairs per round): each lane
-// reads its pair's fields (coalesced across the lanes), contracts them with the
-// cbar of the neighbour's species over all records and writes the pair
-// gradient g = dE/dd, summed in the lane's registers.  The wave first forms the
+// One wave per centre atom, in rounds of up to 64 pairs: a full round takes one
+// pair per lane; a round with fewer pairs left (the tail of a long list, or a
+// short list) gives each pair R = 2, 4 or 8 lanes, lane sub of a pair taking the
+// records with l = sub, sub + R, ..., and the R partial sums are added by a fixed
+// butterfly.  Each lane reads its pair's fields (coalesced across the pairs),
+// contracts them with the cbar of the neighbour's species over its records and
+// the pair gradient g = dE/dd follows from the sums.  The wave first forms the
 // atom's cbar in LDS (form_cbar), then stages the record table; both are read
 // as broadcasts.
 template <int NMAX, int LMAX>
@@ -769,8 +853,11 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
     }
   }
   __syncthreads();
-  for (int pb = p0; pb < p1; pb += 64) {
-    const int p = pb + lane;
+  for (int pb = p0; pb < p1;) {
+    const int left = p1 - pb;
+    const int lgR = left > 32 ? 0 : (left > 16 ? 1 : (left > 8 ? 2 : 3)), R = 1 << lgR;
+    const int sub = lane & (R - 1), p = pb + (lane >> lgR);
+    pb += 64 >> lgR;
     const bool live = p < p1;
     const int pq = live ? p : p0;  // idle lanes read a valid row
     const double* __restrict__ row = rows + (size_t)(pq >> 6) * (S::ROW * 64) + (pq & 63);
@@ -791,8 +878,15 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       on = on && sj >= 0 && sj < P.ns;
       sj = on ? sj : 0;
     }
-    adjoint_records<NMAX, LMAX>(L, cb + (size_t)sj * LLP * NMAX, rc, ri, F, b, db, uz, ux, uy, sr, sx, sy, sz);
-    if (live) {
+    adjoint_records<NMAX, LMAX>(L, sub, R, cb + (size_t)sj * LLP * NMAX, rc, ri, F, b, db, uz, ux, uy, sr, sx, sy,
+                                sz);
+    for (int o = 1; o < R; o <<= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      sx += __shfl_xor(sx, o, 64);
+      sy += __shfl_xor(sy, o, 64);
+      sz += __shfl_xor(sz, o, 64);
+    }
+    if (live && sub == 0) {
       const double ir = F(S::FR + S::XU + 2);
       // d u / d d = (I - u u^T) / r
       const double ut = ux * sx + uy * sy + uz * sz;
@@ -918,24 +1012,28 @@ size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P); }
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
-                            int block, hipStream_t st) {
+                            int block, int part, hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
-  // two workgroups (radial, angular) per block of pairs; block 0 also writes bc
-  const int blocks = 2 * ((int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0));
+  if (part != 1 && part != 2) return hipErrorInvalidValue;
+  // one workgroup per block of pairs; block 0 of the radial launch also writes bc
+  const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);
   auto f = [&]<int N, int LM>() {
     const int np = (int)n_pairs;
-    if (deriv && P.radial_dd)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
-                         dz, rows, bc);
-    else if (deriv)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
-                         dz, rows, bc);
-    else if (P.radial_dd)
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
-                         dz, rows, bc);
-    else
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false>), dim3(blocks), dim3(block), 0, st, P, T, np, count, dx, dy,
-                         dz, rows, bc);
+    const dim3 g(blocks), b(block);
+    if (part == 2) {
+      if (deriv)
+        hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 2>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+      else
+        hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 2>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+    } else if (deriv && P.radial_dd) {
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+    } else if (deriv) {
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+    } else if (P.radial_dd) {
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+    } else {
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+    }
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);

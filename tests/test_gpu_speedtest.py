@@ -65,4 +65,5 @@ def test_speedtest_tool_runs(capsys):
     assert [(r["n_max"], r["l_max"]) for r in lines] == [(3, 5), (4, 5)]
     for r in lines:
         assert r["n_atoms"] == 10000 and r["ms_per_call"] > 0
-        assert set(r["stage_ms"]) == {"pair_prep", "descriptor"}
+        assert set(r["stage_ms"]) == {"pair_prep", "pair_angular", "descriptor"}
+        assert set(r["paper_split_ms"]) == {"radial", "angular", "vector"}
