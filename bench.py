@@ -323,7 +323,7 @@ def rate_fn(run, prec_key, P):
     w = run["w"]
     n, l_max, nch = w["n_max"], w["l_max"], w["n_max"] * w["n_species"]
     gemm_peak = {"fp64": PEAK["fp64_TFs"], "f32": PEAK["fp32_TFs"], "bf16": PEAK["bf16_TFs"],
-                 "bf16x3": PEAK["bf16_TFs"]}[prec_key]
+                 "bf16x3": PEAK["bf16_TFs"], "bf16ps": PEAK["bf16_TFs"]}[prec_key]
 
     def rate(name, avg_ms):
         work, unit = algorithmic_work(name, run["N"], P, run["M"], w["K"], n, l_max, nch)
@@ -377,10 +377,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="box262144_n10l10")
-    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "f32", "bf16", "bf16x3"],
-                    help="GAP contraction precision (the rest of the path is FP64); auto: the workload's mixed "
-                         "mode (the lowest precision within the 1e-4 eV/A force RMSE bar there).  The FP64 path "
-                         "is timed alongside any other mode and the force error against it reported")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "f32", "bf16", "bf16x3", "bf16ps"],
+                    help="GAP contraction precision (the rest of the path is FP64, except the power spectrum and "
+                         "its adjoint in bf16ps); auto: the workload's mixed mode (the lowest precision within "
+                         "the 1e-4 eV/A force RMSE bar there).  The FP64 path is timed alongside any other mode "
+                         "and the force error against it reported")
     ap.add_argument("--also", default="box4096_n8l8",
                     help="comma-separated extra workloads timed the same way (mixed mode and FP64 path), "
                          "reported under 'workloads'; 'none' for none")

@@ -53,12 +53,15 @@ typedef enum {
 /* Arithmetic of the GAP kernel contraction (S = Q Q_s^T and Qbar = G Q_s).
  * The exp/erf terms are FP64 in every mode, the radial recursion and the
  * orthonormal transform W are FP64 or double-double (soap_radial_precision);
- * c_nlm, p and q are FP64 in every mode. */
+ * c_nlm is FP64 in every mode, p and q are FP64 except in SOAP_MIXED_BF16_PS. */
 typedef enum {
   SOAP_FP64 = 0,        /* FP64 MFMA */
   SOAP_MIXED_F32 = 1,   /* FP32 operands, FP32 accumulation (MFMA) */
   SOAP_MIXED_BF16 = 2,  /* BF16 operands, FP32 accumulation (MFMA) */
-  SOAP_MIXED_BF16X3 = 3 /* split-BF16 (hi/lo, three products), FP32 accumulation */
+  SOAP_MIXED_BF16X3 = 3, /* split-BF16 (hi/lo, three products), FP32 accumulation */
+  SOAP_MIXED_BF16_PS = 4 /* BF16 GAP contractions as SOAP_MIXED_BF16, and the power spectrum
+                            P_l = C_l C_l^T (Eq. (09)) and its adjoint cbar_l = M_l C_l on the
+                            matrix cores in BF16 with FP32 accumulation (n_species n_max <= 48) */
 } soap_precision;
 
 /* Arithmetic of the radial stage (Sec. III.A): the integration-by-parts

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libsoap.so")
 LIB_PATH = os.environ.get("SOAP_LIBRARY", LIB_PATH)
 
 SOAP_OK, SOAP_EINVAL, SOAP_ENOMEM, SOAP_EOVERFLOW, SOAP_EHIP, SOAP_ENOTSUP = 0, -1, -2, -3, -4, -5
-SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3 = 0, 1, 2, 3
+SOAP_FP64, SOAP_MIXED_F32, SOAP_MIXED_BF16, SOAP_MIXED_BF16X3, SOAP_MIXED_BF16_PS = 0, 1, 2, 3, 4
 SOAP_RADIAL_AUTO, SOAP_RADIAL_FP64, SOAP_RADIAL_DD = 0, 1, 2
 SOAP_PAIRS_DEFERRED = -1
 

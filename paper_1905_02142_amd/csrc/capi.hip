@@ -160,6 +160,12 @@ bool ensure_pinned(soap_ctx* ctx, size_t bytes) {
       return fail(ctx, SOAP_ENOTSUP, "workspace must grow during stream capture (run once outside it)"); \
   } while (0)
 
+// the operand precision of the GAP contractions (the kernels' 0..3): the
+// matrix-core power-spectrum mode contracts in BF16
+int gap_precision(const soap_ctx* ctx) {
+  return ctx->prm.precision == SOAP_MIXED_BF16_PS ? (int)SOAP_MIXED_BF16 : (int)ctx->prm.precision;
+}
+
 soap_status check_params(const soap_params* p, std::string& why) {
   if (!p) return why = "null parameters", SOAP_EINVAL;
   if (p->n_max < 2 || p->n_max > soap::kMaxN) return why = "n_max must be in 2..12", SOAP_EINVAL;
@@ -173,7 +179,9 @@ soap_status check_params(const soap_params* p, std::string& why) {
     return why = "alpha_r, alpha_perp and a must be >= 0", SOAP_EINVAL;
   if (!std::isfinite(p->central_weight)) return why = "central_weight must be finite", SOAP_EINVAL;
   if (p->l_weight != 0 && p->l_weight != 1) return why = "l_weight must be 0 or 1", SOAP_EINVAL;
-  if (p->precision < SOAP_FP64 || p->precision > SOAP_MIXED_BF16X3) return why = "unknown precision", SOAP_EINVAL;
+  if (p->precision < SOAP_FP64 || p->precision > SOAP_MIXED_BF16_PS) return why = "unknown precision", SOAP_EINVAL;
+  if (p->precision == SOAP_MIXED_BF16_PS && p->n_species * p->n_max > 48)
+    return why = "the matrix-core power spectrum takes at most 48 channels (n_species * n_max)", SOAP_ENOTSUP;
   if (p->radial_precision < SOAP_RADIAL_AUTO || p->radial_precision > SOAP_RADIAL_DD)
     return why = "unknown radial precision", SOAP_EINVAL;
   return SOAP_OK;
@@ -326,6 +334,7 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
   d.K = d.nch * (d.nch + 1) / 2 * (d.l + 1);
   d.buffer = p->r_soft < p->r_cut ? 1 : 0;
   d.l_weight = p->l_weight;
+  d.ps_mfma = p->precision == SOAP_MIXED_BF16_PS ? 1 : 0;
   d.radial_dd = p->radial_precision == SOAP_RADIAL_DD ||
                 (p->radial_precision == SOAP_RADIAL_AUTO && p->precision == SOAP_FP64 && p->n_max >= 8);
   d.rc = p->r_cut;
@@ -732,7 +741,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
   }
   SOAP_ENSURE(ctx, ctx->q, sizeof(double) * N * P.K);
   SOAP_ENSURE(ctx, ctx->pnorm, sizeof(double) * N);
-  const int prec = (int)ctx->prm.precision;
+  const int prec = gap_precision(ctx);
   const bool fused = forces && ctx->tune.gap_fused && soap::gap_fused_supported(P.K, prec);
   // unfused BF16: the descriptor kernel also writes the bf16 operand copy of q
   // into the GAP workspace, and the scores pass converts only the sparse set
@@ -855,7 +864,7 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
   soap_tuning best = ctx->tune;
   float best_ms = 0.0f;
   soap_status s = time_it(best_ms);
-  const bool fusable = soap::gap_fused_supported(ctx->dp.K, (int)ctx->prm.precision);
+  const bool fusable = soap::gap_fused_supported(ctx->dp.K, gap_precision(ctx));
   struct Axis {
     int soap_tuning::*field;
     std::vector<int> cand;

@@ -48,6 +48,8 @@ namespace soap {
 namespace {
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -285,6 +287,51 @@ __device__ inline void stage_fields(const double* __restrict__ rows, const int* 
   }
 }
 
+// The power spectrum P_l = C_l C_l^T of one atom (C_l: n_ch x (2l + 1), the
+// real form of Eq. (09)) on the matrix cores: BF16 operands, FP32 accumulation,
+// one v_mfma_f32_16x16x32_bf16 per 16 x 16 tile of channel pairs and per l
+// (2l + 1 <= 25 fits one 32-deep step).  c is read from csh in its layout
+// [species][lm][k]; the packed entries a <= b (sqrt(2) off the diagonal) go to
+// pv[ab L1 + l].  Operand lane layout: lane j holds row j % 16 and contraction
+// positions 8 (j / 16) .. 8 (j / 16) + 7; result lane j holds rows
+// 4 (j / 16) .. + 3 of column j % 16.  Returns this lane's sum of squares.
+template <int NMAX>
+__device__ inline double power_spectrum_mfma(const DevParams& P, const double* csh, double* pv, int lane) {
+  const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
+  const int r16 = lane & 15, kq = lane >> 4, T = (nch + 15) / 16;
+  // operand: channel row a, positions m' = 8 kq + j of degree l
+  auto operand = [&](int a, int l) {
+    bf16x8 v;
+    const int sa = a / n, ka = a - sa * n;
+    const double* c = csh + ((size_t)sa * LLP + l * l) * NMAX + ka;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int m = 8 * kq + j;
+      v[j] = (__bf16)(float)((a < nch && m <= 2 * l) ? c[m * NMAX] : 0.0);
+    }
+    return v;
+  };
+  double ss = 0.0;
+  for (int ta = 0; ta < T; ++ta)
+    for (int tb = ta; tb < T; ++tb)
+      for (int l = 0; l < L1; ++l) {
+        const bf16x8 A = operand(16 * ta + r16, l);
+        const bf16x8 B = tb == ta ? A : operand(16 * tb + r16, l);
+        const f32x4 D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const int b = 16 * tb + r16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * ta + 4 * kq + r;
+          if (a < nch && b < nch && a <= b) {
+            const double v = (double)D[r] * (a != b ? kSqrt2 : 1.0);
+            pv[ab_index(a, b, nch) * L1 + l] = v;
+            ss = fma(v, v, ss);
+          }
+        }
+      }
+  return ss;
+}
+
 // the forward keeps the power spectrum in LDS when c and p of one atom together
 // stay within the row staging area or within 16 KB
 template <int NMAX, int LMAX>
@@ -452,7 +499,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   }
   const int L1 = P.l + 1, nab = nch * (nch + 1) / 2;
   double ss = 0.0;
-  for (int ab = lane; ab < nab; ab += 64) {
+  if (P.ps_mfma) ss = power_spectrum_mfma<NMAX>(P, csh, pv, lane);
+  for (int ab = P.ps_mfma ? nab : lane; ab < nab; ab += 64) {
     int a, b;
     ab_decode(ab, nch, a, b);
     const int sa = a / n, sb = b / n;
@@ -483,6 +531,18 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
     for (int k = lane; k < q_pitch; k += 64) qi[k] = k < P.K ? pv[k] * inv : 0.0;
     if (qci)
       for (int k = lane; k < qc_pitch; k += 64) qci[k] = (__bf16)(float)(k < P.K ? pv[k] * inv : 0.0);
+  } else if (P.ps_mfma) {
+    // p in the q row, written by the lanes that hold the matrix-core results: every
+    // lane rescales a contiguous part once those stores are visible to the wave
+    __threadfence_block();
+    __syncthreads();
+    for (int k = lane; k < P.K; k += 64) {
+      qi[k] *= inv;
+      if (qci) qci[k] = (__bf16)(float)qi[k];
+    }
+    for (int k = P.K + lane; k < q_pitch; k += 64) qi[k] = 0.0;
+    if (qci)
+      for (int k = P.K + lane; k < qc_pitch; k += 64) qci[k] = (__bf16)0.0f;
   } else {
     for (int ab = lane; ab < nab; ab += 64)
       for (int l = 0; l < L1; ++l) {
@@ -532,6 +592,75 @@ __device__ inline void transform_columns(int n, int nch, int LL, int L1, double*
         }
 #pragma unroll
     for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(col + k) = double2{acc[k], acc[k + 1]};
+  }
+}
+
+// cbar_l = M(l) C_l for every l (M(l)_aa = 2 vbar_aal, M(l)_ab = sqrt(2) vbar_abl,
+// vbar packed a <= b then l) on the matrix cores: BF16 operands, FP32
+// accumulation, v_mfma_f32_16x16x32_bf16 over 16 channel rows x 16 columns m'
+// of degree l, contracted over the channels b in steps of 32.  c comes from
+// csrc ([species][lm][k]; it may be cb itself: every tile of an l is formed in
+// registers before any of them is written); the result goes to cb in the same
+// layout.  Entries outside the channels and columns (the sink column, channels
+// k >= n_max) are left as they are.  n_ch <= 48.
+template <int NMAX>
+__device__ inline void cbar_mfma(const DevParams& P, const double* csrc, double* cb, const double* vb, int lane) {
+  const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int TA = (nch + 15) / 16, TK = (nch + 31) / 32;
+  for (int l = 0; l < L1; ++l) {
+    const int w = 2 * l + 1, TM = (w + 15) / 16;
+    f32x4 D[3][2];
+#pragma unroll
+    for (int ta = 0; ta < 3; ++ta)
+#pragma unroll
+      for (int tm = 0; tm < 2; ++tm) D[ta][tm] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tk = 0; tk < TK; ++tk) {
+      bf16x8 Bm[2];
+#pragma unroll
+      for (int tm = 0; tm < 2; ++tm) {
+        const int m = 16 * tm + r16;  // column of C_l
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int b = 32 * tk + 8 * kq + j, sb = b / n;
+          Bm[tm][j] = (__bf16)(float)((tm < TM && b < nch && m < w)
+                                          ? csrc[((size_t)sb * LLP + l * l + m) * NMAX + (b - sb * n)]
+                                          : 0.0);
+        }
+      }
+#pragma unroll
+      for (int ta = 0; ta < 3; ++ta) {
+        if (ta >= TA) break;
+        const int a = 16 * ta + r16;
+        bf16x8 A;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int b = 32 * tk + 8 * kq + j;
+          double v = 0.0;
+          if (a < nch && b < nch)
+            v = (a == b ? 2.0 : kSqrt2) * vb[ab_index(a < b ? a : b, a < b ? b : a, nch) * L1 + l];
+          A[j] = (__bf16)(float)v;
+        }
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm)
+          if (tm < TM) D[ta][tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bm[tm], D[ta][tm], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int ta = 0; ta < 3; ++ta)
+#pragma unroll
+      for (int tm = 0; tm < 2; ++tm) {
+        const int m = 16 * tm + r16;
+        if (ta >= TA || tm >= TM || m >= w) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * ta + 4 * kq + r;
+          if (a < nch) {
+            const int sa = a / n;
+            cb[((size_t)sa * LLP + l * l + m) * NMAX + (a - sa * n)] = (double)D[ta][tm][r];
+          }
+        }
+      }
   }
 }
 
@@ -592,7 +721,8 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
       for (int u = 0; u < KPL; ++u)
         if (lane + 64 * u < K) vb[lane + 64 * u] = (g[u] - a[u] * dot) * inv;
       __syncthreads();
-      transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+      if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
+      else transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
       __syncthreads();
       return;
     }
@@ -651,7 +781,15 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
   }
   __syncthreads();
   if (ns == 1) {
-    transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+    if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
+    else transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+    __syncthreads();
+    return;
+  }
+  if (P.ps_mfma) {
+    // the sink column and the channels k >= n_max stay zero; the rest is written
+    for (int t = lane; t < ns * LLP * NMAX; t += 64) cb[t] = 0.0;
+    cbar_mfma<NMAX>(P, csh, cb, vb, lane);
     __syncthreads();
     return;
   }

@@ -64,6 +64,7 @@ struct DevParams {
   int buffer;   // r_soft < r_cut
   int l_weight;
   int radial_dd;  // radial recursion and W b in double-double arithmetic
+  int ps_mfma;    // power spectrum and its adjoint on the matrix cores (BF16 operands, FP32 accumulation)
   double rc, rs, nf;
   double inv_rc;
   double s0r, s0p, ar, ap, a;

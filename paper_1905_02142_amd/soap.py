@@ -10,7 +10,7 @@ import torch
 from . import _lib
 
 PRECISIONS = {"fp64": _lib.SOAP_FP64, "f32": _lib.SOAP_MIXED_F32, "bf16": _lib.SOAP_MIXED_BF16,
-              "bf16x3": _lib.SOAP_MIXED_BF16X3}
+              "bf16x3": _lib.SOAP_MIXED_BF16X3, "bf16ps": _lib.SOAP_MIXED_BF16_PS}
 RADIAL_PRECISIONS = {"auto": _lib.SOAP_RADIAL_AUTO, "fp64": _lib.SOAP_RADIAL_FP64, "dd": _lib.SOAP_RADIAL_DD}
 
 

@@ -177,14 +177,16 @@ def batch_of_structures(n_struct: int, n_lo: int, n_hi: int, rho_lo: float, rho_
 # Angstrom.  ``sigma`` is sigma_0r = sigma_0perp; alpha_r = alpha_perp = a = 0.
 # ``mixed`` names the mixed-precision mode run on a workload with a sparse set:
 # the lowest-precision one whose force RMSE against the fp64 path stays within
-# 1e-4 eV/A there (the 256-cell batch, at zeta = 2, needs split BF16).
+# 1e-4 eV/A there (the 256-cell batch, at zeta = 2, needs split BF16; the
+# three-species slab, 24 channels, also takes its power spectrum on the matrix
+# cores, where that is faster than the FP64 one).
 WORKLOADS = {
     "box64_n6l6": dict(n_atoms=64, box=8.6, d_min=1.2, r_cut=3.7, sigma=0.5, n_max=6, l_max=6,
                        n_species=1, M=0, zeta=0, seed=1001),
     "box4096_n8l8": dict(n_atoms=4096, box=34.5, d_min=1.2, r_cut=5.0, sigma=0.5, n_max=8, l_max=8,
                          n_species=1, M=2000, zeta=4, seed=1002, mixed="bf16"),
     "slab32768_3sp_n8l8": dict(n_atoms=32768, box=(32768 / 0.06) ** (1.0 / 3.0), d_min=1.2, r_cut=5.0,
-                               sigma=0.5, n_max=8, l_max=8, n_species=3, M=2000, zeta=4, seed=1003, mixed="bf16",
+                               sigma=0.5, n_max=8, l_max=8, n_species=3, M=2000, zeta=4, seed=1003, mixed="bf16ps",
                                species_probs=(0.5, 0.3, 0.2)),
     "batch256_n8l6": dict(n_struct=256, n_lo=16, n_hi=2048, rho_lo=0.05, rho_hi=0.12, d_min=1.2,
                           r_cut=4.5, sigma=0.5, n_max=8, l_max=6, n_species=1, M=1000, zeta=2,

@@ -68,6 +68,17 @@ def test_invalid_parameters_rejected_on_host(bad):
     assert not ctx.value
 
 
+def test_matrix_core_power_spectrum_channel_limit():
+    # the BF16 matrix-core power spectrum takes at most 48 channels (n_species * n_max)
+    L = _lib()
+    kw = dict(n_max=8, l_max=6, n_species=7, r_cut=5.0, r_soft=5.0, n_f=4.0, sigma0_r=0.5, sigma0_perp=0.5,
+              alpha_r=0.0, alpha_perp=0.0, a=0.0, central_weight=1.0, l_weight=0, precision=L.SOAP_MIXED_BF16_PS)
+    p = L.soap_params(**kw)
+    ctx = ctypes.c_void_p()
+    assert L.load().soap_create(ctypes.byref(p), ctypes.byref(ctx)) == L.SOAP_ENOTSUP
+    assert not ctx.value
+
+
 def test_status_strings():
     lib = _lib().load()
     for s in (0, -1, -2, -3, -4, -5):
