@@ -12,8 +12,8 @@ size_t adjoint_lds_bytes(const DevParams& P);
 // c and cbar workspace per atom: [species][lm < LL + 1][k < NMAX] doubles (NMAX =
 // the compiled n_max bucket; the column lm = LL is a sink for unused records)
 size_t c_doubles_per_atom(const DevParams& P);
-// doubles per neighbour pair of the shared pair rows (radial, ilexp, azimuthal
-// factors and their r-derivatives)
+// doubles per neighbour pair of the shared pair rows (radial values, ilexp, the
+// direction u and their r-derivatives)
 size_t pair_row_doubles(const DevParams& P);
 
 // Every per-pair launch takes a pair bound: the exact pair count, or the list

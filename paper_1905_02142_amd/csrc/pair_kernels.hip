@@ -7,8 +7,9 @@
 // adjoint kernels share:
 //   B_k = 4 pi A b_k          radial overlaps, Eqs. (02), (04), (19), (06), Eq. (15)
 //   w_l e_l                   ilexp, Sec. III.C
-//   (u_x + i u_y)^m, u_z      the azimuthal factors of the real harmonics
-// and, for forces, dB_k/dr, d(w_l e_l)/dr, u_x, u_y and 1/r.
+//   u_z, u_x, u_y             the direction (the real harmonics' arguments)
+// and, for forces, dB_k/dr, d(w_l e_l)/dr and 1/r.  The azimuthal powers
+// (u_x + i u_y)^m are formed from u_x, u_y by the kernels that use them.
 //
 // k_descriptor, one 64-lane wavefront per centre atom.  Its neighbours of one
 // species are compacted with a wave ballot and their fields staged in LDS, 32
@@ -81,18 +82,21 @@ struct Shape {
   static constexpr int NREC = (LMAX + 1) * (LMAX + 2) / 2;
   static constexpr int E2 = (NREC + 63) / 64;  // records per lane of the forward kernel
   static constexpr int NC = LMAX / 2 + 1;  // polynomial terms in u_z^2
-  // pair row, forward part: (u_x + i u_y)^m (m = 0..LMAX) | B_k | w_l e_l | u_z
-  static constexpr int FZ = 0, FB = 2 * (LMAX + 1), FW = FB + NMAX, FU = FW + LMAX + 1;
-  static constexpr int FR = even(FU + 1);
-  // derivative part: dB_k/dr | d(w_l e_l)/dr | u_x u_y 1/r
-  static constexpr int XD = 0, XW = NMAX, XU = XW + LMAX + 1;
-  static constexpr int XR = even(XU + 3);
+  // pair row, forward part: B_k | w_l e_l | u_z u_x u_y
+  static constexpr int FB = 0, FW = NMAX, FU = FW + LMAX + 1, FX = FU + 1, FY = FU + 2;
+  static constexpr int FR = even(FY + 1);
+  // derivative part: dB_k/dr | d(w_l e_l)/dr | 1/r
+  static constexpr int XD = 0, XW = NMAX, XI = XW + LMAX + 1;
+  static constexpr int XR = even(XI + 1);
   // HBM: blocks of 64 pairs, field-major inside a block (field f of pair p at
   // (p / 64) * ROW * 64 + f * 64 + p % 64)
   static constexpr int ROW = FR + XR;  // doubles per pair
-  // forward kernel: fields of CH pairs staged in LDS rows of FRP doubles (even,
-  // for 16-byte reads, and 2 mod 4, so the staging writes spread over the banks)
-  static constexpr int CH = 32, FRP = FR | 2;
+  // forward kernel: CH pairs staged in LDS rows of FRP doubles: the azimuthal
+  // powers (u_x + i u_y)^m, m = 0..LMAX (LZ doubles, formed there from u_x, u_y),
+  // then the forward part of the pair row.  FRP is even, for 16-byte reads, and
+  // 2 mod 4, so that the staging writes spread over the banks
+  static constexpr int LZ = 2 * (LMAX + 1);
+  static constexpr int CH = 32, FRP = (LZ + FR) | 2;
   // forward lanes: one (l, m) record (both real harmonics) per lane slot, or one
   // column lm of c per lane slot where that fills the 64 lanes better: l_max = 6
   // has 28 records but 49 columns (one pass either way), l_max = 10 66 records
@@ -169,8 +173,9 @@ __device__ inline void azimuthal_step(double& cr, double& ci, double ux, double 
 }
 
 // Two launches per list: PART 1 writes the radial fields (B_k, dB_k/dr) and the
-// central atom's factors, PART 2 the angular ones (w_l e_l, its derivative, the
-// azimuthal powers, u and 1/r).  Each pair's serial FP64 chain is split in two,
+// central atom's factors, PART 2 the angular ones (w_l e_l, its derivative, u
+// and 1/r; the azimuthal powers are formed where they are used, which costs less
+// than moving them through HBM).  Each pair's serial FP64 chain is split in two,
 // each half runs with the registers it needs (the double-double radial stage
 // needs about twice those of the angular one), and the two are timed apart.
 // DD: the radial stage in double-double arithmetic (radial<..., true>)
@@ -240,21 +245,14 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
 #pragma unroll
   for (int l = 0; l <= LMAX; ++l) st(S::FW + l, tab.lw[l] * e[l]);
   st(S::FU, uz);
-  double cr = 1.0, ci = 0.0;
-#pragma unroll
-  for (int m = 0; m <= LMAX; ++m) {
-    st(S::FZ + 2 * m, cr);
-    st(S::FZ + 2 * m + 1, ci);
-    azimuthal_step(cr, ci, ux, uy);
-  }
+  st(S::FX, ux);
+  st(S::FY, uy);
   if (DERIV) {
     // d e_l / dz = e_{l+1} + (l/z - 1) e_l
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l)
       st(S::FR + S::XW + l, tab.lw[l] * (e[l + 1] + ((double)l * izz - 1.0) * e[l]) * dzdr);
-    st(S::FR + S::XU, ux);
-    st(S::FR + S::XU + 1, uy);
-    st(S::FR + S::XU + 2, ir);
+    st(S::FR + S::XI, ir);
   }
 }
 
@@ -389,11 +387,24 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      stage_fields<S::FR, S::ROW, CH, FRP, 6>(rows, idx, cnt, dyn, lane);
+      stage_fields<S::FR, S::ROW, CH, FRP, 6>(rows, idx, cnt, dyn + S::LZ, lane);
+      __syncthreads();
+      if (lane < cnt) {  // the azimuthal powers of staged pair `lane`
+        double* __restrict__ zt = dyn + lane * FRP;
+        const double ux = zt[S::LZ + S::FX], uy = zt[S::LZ + S::FY];
+        double cr = 1.0, ci = 0.0;
+#pragma unroll
+        for (int m = 0; m <= LMAX; ++m) {
+          zt[2 * m] = cr;
+          zt[2 * m + 1] = ci;
+          azimuthal_step(cr, ci, ux, uy);
+        }
+      }
       __syncthreads();
 #pragma unroll 2
       for (int t = 0; t < cnt; ++t) {
-        const double* __restrict__ rt = dyn + t * FRP;
+        const double* __restrict__ zt = dyn + t * FRP;  // (u_x + i u_y)^m at 2m, 2m + 1
+        const double* __restrict__ rt = zt + S::LZ;     // the forward fields
         auto row = [&](int f) { return rt[f]; };
         double b[NMAX];
 #pragma unroll
@@ -412,7 +423,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
             for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, C.cf[e][t2]);
             const double Q = C.par[e] ? uz * Rv : Rv;
             const double a = row(S::FW + C.l[e]) * Q;
-            const double a0 = a * row(S::FZ + 2 * C.m[e] + C.sn[e]);
+            const double a0 = a * zt[2 * C.m[e] + C.sn[e]];
 #pragma unroll
             for (int k = 0; k < NMAX; ++k) acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
           }
@@ -424,7 +435,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
             for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, R.cf[e][t2]);
             const double Q = R.par[e] ? uz * Rv : Rv;
             const double a = row(S::FW + R.l[e]) * Q;
-            const double a0 = a * row(S::FZ + 2 * R.m[e]), a1 = a * row(S::FZ + 2 * R.m[e] + 1);
+            const double a0 = a * zt[2 * R.m[e]], a1 = a * zt[2 * R.m[e] + 1];
 #pragma unroll
             for (int k = 0; k < NMAX; ++k) {
               acc[e][0][k] = fma(a0, b[k], acc[e][0][k]);
@@ -1006,7 +1017,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       b[k] = F(S::FB + k);
       db[k] = F(S::FR + S::XD + k);
     }
-    const double uz = F(S::FU), ux = F(S::FR + S::XU), uy = F(S::FR + S::XU + 1);
+    const double uz = F(S::FU), ux = F(S::FX), uy = F(S::FY);
     double sr = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     bool on = live;
     int sj = 0;
@@ -1025,7 +1036,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       sz += __shfl_xor(sz, o, 64);
     }
     if (live && sub == 0) {
-      const double ir = F(S::FR + S::XU + 2);
+      const double ir = F(S::FR + S::XI);
       // d u / d d = (I - u u^T) / r
       const double ut = ux * sx + uy * sy + uz * sz;
       const double g0 = on ? sr * ux + (sx - ux * ut) * ir : 0.0;
