@@ -606,6 +606,54 @@ __device__ inline void transform_columns(int n, int nch, int LL, int L1, double*
   }
 }
 
+// The same transform in place for several species: task (column lm, output
+// species sa) takes the column's c of every species from cb and forms the n_max
+// rows of species sa.  A pass holds whole columns (64 / ns of them), so every
+// read of a column precedes the writes to it (one wavefront: its LDS operations
+// complete in order).  abx[a][b] = (packed index of {a, b}) * (l_max + 1).  Each
+// output takes its terms in the order (sb, kb).
+template <int NMAX>
+__device__ inline void transform_columns_species(int n, int ns, int nch, int LL, int L1, double* cb, const double* vb,
+                                                 const int* abx, int lane) {
+  const int LLP = LL + 1, cpp = 64 / ns;  // columns per pass
+  const int lmo = lane / ns, sa = lane - lmo * ns;
+  for (int c0 = 0; c0 < LL; c0 += cpp) {
+    const int lm = c0 + lmo;
+    const bool live = lmo < cpp && lm < LL;
+    double acc[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) acc[k] = 0.0;
+    if (live) {
+      const int l = isqrt_small(lm);
+      for (int sb = 0; sb < ns; ++sb) {
+        const double* col = cb + (size_t)(sb * LLP + lm) * NMAX;
+        double cv[NMAX];
+#pragma unroll
+        for (int kb = 0; kb < NMAX; kb += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(col + kb);
+          cv[kb] = v.x;
+          cv[kb + 1] = v.y;
+        }
+#pragma unroll
+        for (int ka = 0; ka < NMAX; ++ka) {
+          const int a = sa * n + ka;
+          if (ka < n) {
+            const int* __restrict__ row = abx + a * nch + sb * n;
+#pragma unroll
+            for (int kb = 0; kb < NMAX; ++kb)
+              if (kb < n) acc[ka] = fma((sb * n + kb == a ? 2.0 : kSqrt2) * vb[row[kb] + l], cv[kb], acc[ka]);
+          }
+        }
+      }
+    }
+    if (live) {
+      double* dst = cb + (size_t)(sa * LLP + lm) * NMAX;
+#pragma unroll
+      for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(dst + k) = double2{acc[k], acc[k + 1]};
+    }
+  }
+}
+
 // cbar_l = M(l) C_l for every l (M(l)_aa = 2 vbar_aal, M(l)_ab = sqrt(2) vbar_abl,
 // vbar packed a <= b then l) on the matrix cores: BF16 operands, FP32
 // accumulation, v_mfma_f32_16x16x32_bf16 over 16 channel rows x 16 columns m'
@@ -676,20 +724,21 @@ __device__ inline void cbar_mfma(const DevParams& P, const double* csrc, double*
 }
 
 // vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm} of atom
-// i (qbar = qbar + qbar2 when qbar2 is not null, in that order), written into cb (LDS) in the padded layout of c ([species][lm < LL + 1][k <
-// NMAX]) with zeros in the sink column lm = LL and in the channels k >= n_max.
-// vb: K doubles of LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a
-// block barrier.  With one species the atom's c is first copied into cb, where
-// each lane transforms whole columns in place (a column of cbar needs only the
-// same column of c); up to NMAX = 8 every global read of that case (c, q, qbar,
-// qbar2, |p|) is issued at once and q, qbar stay in registers from the dot
-// product to vbar.  Otherwise the reads go eight per lane at a time.
+// i (qbar = qbar + qbar2 when qbar2 is not null, in that order), written into cb
+// (LDS) in the padded layout of c ([species][lm < LL + 1][k < NMAX]) with zeros
+// in the sink column lm = LL and in the channels k >= n_max.  vb: K doubles of
+// LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a block barrier.  The
+// atom's c (every species) is first copied into cb and transformed there in
+// place: a column of cbar needs only the same column of c.  With one species and
+// NMAX <= 8 every global read (c, q, qbar, qbar2, |p|) is issued at once and q,
+// qbar stay in registers from the dot product to vbar; otherwise the reads go
+// eight per lane at a time.
 template <int NMAX, int LMAX>
 __device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
                                  const double* __restrict__ qbar, const double* __restrict__ qbar2, int qbar_pitch,
                                  double* cb, double* vb, int* abx, int lane) {
-  constexpr int B = 8;  // loads per lane in flight
+  constexpr int B = 16;  // loads per lane in flight
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const double* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
@@ -738,8 +787,9 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
       return;
     }
   }
-  if (ns == 1) {
-    const int nc = NMAX * LLP;
+  {
+    // the atom's c, every species, into cb (transformed there in place below)
+    const int nc = ns * NMAX * LLP;
     for (int t0 = 0; t0 < nc; t0 += 64 * B) {
       double v[B];
 #pragma unroll
@@ -749,41 +799,39 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
         if (t0 + lane + 64 * u < nc) cb[t0 + lane + 64 * u] = v[u];
     }
   }
+  // dot = q . qbar, with qbar kept in vb; then vbar in place, q read again (now
+  // from the caches).  Each lane reads back only the entries it wrote.
   double dot = 0.0;
   for (int k0 = 0; k0 < K; k0 += 64 * B) {
-    double a[B], g[B];
+    double a[B], g[B], g2[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int k = min(k0 + lane + 64 * u, K - 1);
       a[u] = qi[k];
       g[u] = qb[k];
-    }
-    if (qb2) {
-#pragma unroll
-      for (int u = 0; u < B; ++u) g[u] += qb2[min(k0 + lane + 64 * u, K - 1)];
+      if (qb2) g2[u] = qb2[k];
     }
 #pragma unroll
-    for (int u = 0; u < B; ++u)
-      if (k0 + lane + 64 * u < K) dot = fma(a[u], g[u], dot);
+    for (int u = 0; u < B; ++u) {
+      if (qb2) g[u] += g2[u];
+      if (k0 + lane + 64 * u < K) {
+        dot = fma(a[u], g[u], dot);
+        vb[k0 + lane + 64 * u] = g[u];
+      }
+    }
   }
   dot = wave_sum(dot);
   const double nrm = pnorm[i];
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int k0 = 0; k0 < K; k0 += 64 * B) {
-    double a[B], g[B];
+    double a[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) a[u] = qi[min(k0 + lane + 64 * u, K - 1)];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
-      const int k = min(k0 + lane + 64 * u, K - 1);
-      a[u] = qi[k];
-      g[u] = qb[k];
+      const int k = k0 + lane + 64 * u;
+      if (k < K) vb[k] = (vb[k] - a[u] * dot) * inv;
     }
-    if (qb2) {
-#pragma unroll
-      for (int u = 0; u < B; ++u) g[u] += qb2[min(k0 + lane + 64 * u, K - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < B; ++u)
-      if (k0 + lane + 64 * u < K) vb[k0 + lane + 64 * u] = (g[u] - a[u] * dot) * inv;
   }
   // abx[a][b] = (packed index of the pair {a, b}) * (l_max + 1), the row of vbar
   for (int r = lane; r < (ns > 1 ? nch * nch : 0); r += 64) {
@@ -791,51 +839,11 @@ __device__ inline void form_cbar(const DevParams& P, int i, const double* __rest
     abx[r] = ab_index(a < b ? a : b, a < b ? b : a, nch) * L1;
   }
   __syncthreads();
-  if (ns == 1) {
-    if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
-    else transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
-    __syncthreads();
-    return;
-  }
-  if (P.ps_mfma) {
-    // the sink column and the channels k >= n_max stay zero; the rest is written
-    for (int t = lane; t < ns * LLP * NMAX; t += 64) cb[t] = 0.0;
-    cbar_mfma<NMAX>(P, csh, cb, vb, lane);
-    __syncthreads();
-    return;
-  }
-  // several species: task = (column (s, lm), half of the NMAX channels), c read from HBM
-  constexpr int KH = NMAX / 2;
-  const double inv_llp = 1.0 / (double)LLP;
-  for (int task = lane; task < 2 * ns * LLP; task += 64) {
-    const int col = task >> 1, h = task & 1;
-    const int s = (int)(((double)col + 0.5) * inv_llp), lm = col - s * LLP;  // exact for these sizes
-    double acc[KH];
-#pragma unroll
-    for (int kk = 0; kk < KH; ++kk) acc[kk] = 0.0;
-    if (lm < LL) {
-      const int l = isqrt_small(lm);
-      for (int sb = 0; sb < ns; ++sb) {
-        double cv[NMAX];
-#pragma unroll
-        for (int kb = 0; kb < NMAX; ++kb) cv[kb] = kb < n ? csh[(sb * LLP + lm) * NMAX + kb] : 0.0;
-#pragma unroll
-        for (int kk = 0; kk < KH; ++kk) {
-          const int k = h * KH + kk, a = s * n + k;
-          if (k < n) {
-            const int* __restrict__ row = abx + a * nch + sb * n;
-#pragma unroll
-            for (int kb = 0; kb < NMAX; ++kb)
-              if (kb < n)
-                acc[kk] = fma((sb * n + kb == a ? 2.0 : kSqrt2) * vb[row[kb] + l], cv[kb], acc[kk]);
-          }
-        }
-      }
-    }
-    double* dst = cb + (size_t)col * NMAX + h * KH;
-#pragma unroll
-    for (int kk = 0; kk < KH; ++kk) dst[kk] = acc[kk];
-  }
+  // c of every species is in cb; the sink column and the channels k >= n_max are
+  // zero there and stay so
+  if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
+  else if (ns == 1) transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+  else transform_columns_species<NMAX>(n, ns, nch, LL, L1, cb, vb, abx, lane);
   __syncthreads();
 }
 
