@@ -263,6 +263,8 @@ def run_mode(workload, precision, steps, warmup, dev, autotune=True, sync_neighb
         else:  # a workload without a sparse set times the descriptor alone
             soap.descriptor(nl, st["spec"], out=q)
 
+    if autotune:  # the neighbour build's cell_split, then the GAP call's launch shapes
+        soap.autotune_neighbors(st["pos"], *geo, nl, struct_offsets=st["so"])
     if not autotune or not st["gap"]:
         tuning = soap.tuning
     else:

@@ -367,12 +367,19 @@ soap_status soap_update_pair_vectors(soap_ctx* ctx, const soap_nlist* nl, const 
  *               periodic axis (1, 2 or 3); a centre scans (2 cell_split + 1)^3
  *               bins, fewer candidate atoms for larger values.  Takes effect at
  *               the next neighbour build.
+ *   gap_tile    BF16 tile shapes of the two unfused GAP passes (SOAP_MIXED_BF16
+ *               and SOAP_MIXED_BF16_PS; ignored otherwise): 0: scores 128 x 128
+ *               with one buffer of 128-wide K-tiles, Qbar 128 x 128 with
+ *               double-buffered 64-wide K-tiles; 1: scores 128 x 128
+ *               double-buffered 64-wide, Qbar 64 x 64 with 128-wide K-tiles.
+ *               Same products, same summation order: bitwise the same results.
  */
 typedef struct {
   int gap_fused;
   int gap_slices;
   int prep_block;
   int cell_split;
+  int gap_tile;
 } soap_tuning;
 
 /* Current setting of ctx (host struct).  SOAP_EINVAL on null arguments. */
@@ -380,14 +387,77 @@ soap_status soap_get_tuning(const soap_ctx* ctx, soap_tuning* out /* host */);
 /* Install a setting; SOAP_EINVAL if a field is out of range. */
 soap_status soap_set_tuning(soap_ctx* ctx, const soap_tuning* t /* host */);
 /* Autotuner: times gap_energy_forces (energies and forces) on the caller's
- * inputs for each candidate of each field in turn (coordinate search, `repeats`
- * timed calls per candidate after one warm-up, HIP events on `stream`), keeps
- * the fastest, installs it in ctx and returns it in *chosen (host, nullable).
- * Outputs go to context-owned scratch; the call synchronises `stream`.  Errors
- * as gap_energy_forces. */
+ * inputs for each candidate of each field in turn (coordinate search over
+ * prep_block, gap_fused, gap_slices and gap_tile; cell_split is left as set, see
+ * soap_autotune_neighbors; `repeats` timed calls per candidate after one
+ * warm-up, HIP events on `stream`), keeps the fastest, installs it in ctx and
+ * returns it in *chosen (host, nullable).  With a cache attached
+ * (soap_set_tuning_cache) a stored setting for the same key is installed
+ * instead, and a newly tuned one is stored.  Outputs go to context-owned
+ * scratch; the call synchronises `stream`.  Errors as gap_energy_forces, and
+ * SOAP_ENOMEM if the cache file cannot be written. */
 soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_sparse,
                           const double* alpha, int M, int zeta, int repeats, soap_tuning* chosen /* host */,
                           hipStream_t stream);
+
+/* Neighbour-build autotuner: times soap_build_neighbors_async on these inputs
+ * (same arguments as soap_build_neighbors) for cell_split = 1, 2, 3 (`repeats`
+ * timed builds each after one warm-up, HIP events on `stream`), installs the
+ * fastest in ctx and returns the whole setting in *chosen (host, nullable).  It
+ * ends with one more build with the chosen setting, so that nl holds the list
+ * the context's setting gives (the pair order depends on cell_split).  Returns
+ * SOAP_EOVERFLOW (with *chosen untouched) if the list does not fit nl->capacity,
+ * otherwise the errors of soap_build_neighbors.  Synchronises `stream`. */
+soap_status soap_autotune_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                    const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                    soap_nlist* nl, int repeats, soap_tuning* chosen /* host */,
+                                    hipStream_t stream);
+
+/* ------------------------------------------------------------- tuning cache
+ * Tuned settings kept in a text file across processes.  An entry is keyed by
+ * what the fastest launch shapes depend on; entries written under another
+ * SOAP_TUNING_CACHE_VERSION are ignored (a library whose kernels change bumps
+ * the version).  One line per entry:
+ *   soap-tuning <version> <arch> <n_channels> <l_max> <K> <M> <precision>
+ *     <radial_dd> <size_class> = <gap_fused> <gap_slices> <prep_block>
+ *     <cell_split> <gap_tile>
+ * A store replaces the entry with the same key, or appends one, and writes the
+ * file anew through a temporary file and a rename.  Concurrent writers are not
+ * coordinated (the last rename wins). */
+#define SOAP_TUNING_CACHE_VERSION 1
+typedef struct {
+  int version;     /* SOAP_TUNING_CACHE_VERSION */
+  int n_channels;  /* n_species * n_max */
+  int l_max;
+  int K;           /* descriptor length */
+  int M;           /* sparse points */
+  int precision;   /* soap_precision */
+  int radial_dd;   /* 1: radial stage in double-double, 0: FP64 */
+  int size_class;  /* floor(log2(n_atoms)) + 1; 0 for no atoms */
+  char arch[32];   /* device architecture (gcnArchName up to the first ':'), NUL-terminated */
+} soap_tuning_key;
+
+/* The key of ctx's parameters for n_atoms atoms and M sparse points, on ctx's
+ * device (host struct out).  SOAP_EINVAL on null arguments or negative sizes,
+ * SOAP_EHIP if the device cannot be queried. */
+soap_status soap_tuning_key_for(const soap_ctx* ctx, int n_atoms, int M, soap_tuning_key* out /* host */);
+/* Host only (no device needed).  *found (host) = 1 and *out = the stored
+ * setting if `path` holds an entry with this key (and the key's version), else
+ * *found = 0; a missing file is an empty cache.  SOAP_EINVAL on null
+ * arguments. */
+soap_status soap_tuning_cache_lookup(const char* path, const soap_tuning_key* key, soap_tuning* out /* host */,
+                                     int* found /* host */);
+/* Host only.  Writes the entry (see above).  SOAP_EINVAL on null arguments or a
+ * key that cannot be written on one line; SOAP_EHIP is not used; an I/O failure
+ * returns SOAP_ENOMEM with the file unchanged. */
+soap_status soap_tuning_cache_store(const char* path, const soap_tuning_key* key, const soap_tuning* t);
+/* Attach a cache file to ctx (the path is copied; NULL detaches).  While one is
+ * attached, soap_autotune first looks up the key of its inputs (soap_tuning_key_for
+ * with nl->n_atoms and M): on a hit it installs the stored setting without
+ * timing anything; on a miss it tunes and stores the result. */
+soap_status soap_set_tuning_cache(soap_ctx* ctx, const char* path);
+/* Number of soap_autotune calls on ctx answered from the cache (-1 for null). */
+long long soap_tuning_cache_hits(const soap_ctx* ctx);
 
 #ifdef __cplusplus
 }

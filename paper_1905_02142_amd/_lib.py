@@ -25,7 +25,10 @@ EXPORTED = (
     "soap_get_tuning", "soap_set_tuning", "soap_autotune", "soap_profile_stages",
     "soap_build_neighbors_async", "soap_neighbors_check", "soap_descriptor_jacobian", "soap_set_neighbor_skin",
     "soap_update_pair_vectors", "soap_workspace_generation", "soap_descriptor_noalloc",
+    "soap_autotune_neighbors", "soap_tuning_key_for", "soap_tuning_cache_lookup", "soap_tuning_cache_store",
+    "soap_set_tuning_cache", "soap_tuning_cache_hits",
 )
+SOAP_TUNING_CACHE_VERSION = 1
 SOAP_NOALLOC_SCRATCH_BYTES = 128 << 20
 STAGES = ("neighbors", "descriptor", "gap_scores", "gap_qbar", "pair_adjoint", "force_gather", "gap_fused",
           "pair_prep", "cbar", "pair_angular")
@@ -44,10 +47,16 @@ class soap_params(ctypes.Structure):
 
 class soap_tuning(ctypes.Structure):
     _fields_ = [("gap_fused", ctypes.c_int), ("gap_slices", ctypes.c_int), ("prep_block", ctypes.c_int),
-                ("cell_split", ctypes.c_int)]
+                ("cell_split", ctypes.c_int), ("gap_tile", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class soap_tuning_key(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int), ("n_channels", ctypes.c_int), ("l_max", ctypes.c_int),
+                ("K", ctypes.c_int), ("M", ctypes.c_int), ("precision", ctypes.c_int), ("radial_dd", ctypes.c_int),
+                ("size_class", ctypes.c_int), ("arch", ctypes.c_char * 32)]
 
 
 class soap_nlist(ctypes.Structure):
@@ -130,6 +139,18 @@ def load(path: str = LIB_PATH):
     lib.soap_set_tuning.restype = i
     lib.soap_autotune.argtypes = [vp, P(soap_nlist), vp, vp, vp, i, i, i, P(soap_tuning), vp]
     lib.soap_autotune.restype = i
+    lib.soap_autotune_neighbors.argtypes = [vp, i, vp, vp, vp, vp, i, P(soap_nlist), i, P(soap_tuning), vp]
+    lib.soap_autotune_neighbors.restype = i
+    lib.soap_tuning_key_for.argtypes = [vp, i, i, P(soap_tuning_key)]
+    lib.soap_tuning_key_for.restype = i
+    lib.soap_tuning_cache_lookup.argtypes = [ctypes.c_char_p, P(soap_tuning_key), P(soap_tuning), P(i)]
+    lib.soap_tuning_cache_lookup.restype = i
+    lib.soap_tuning_cache_store.argtypes = [ctypes.c_char_p, P(soap_tuning_key), P(soap_tuning)]
+    lib.soap_tuning_cache_store.restype = i
+    lib.soap_set_tuning_cache.argtypes = [vp, ctypes.c_char_p]
+    lib.soap_set_tuning_cache.restype = i
+    lib.soap_tuning_cache_hits.argtypes = [vp]
+    lib.soap_tuning_cache_hits.restype = ll
     _lib = lib
     return lib
 
@@ -270,3 +291,15 @@ def soap_autotune(ctx, nl: soap_nlist, species, q_sparse, alpha, M, zeta, repeat
     check(load().soap_autotune(ctx, ctypes.byref(nl), species, q_sparse, alpha, M, zeta, repeats, ctypes.byref(t),
                                stream), ctx)
     return t
+
+
+def soap_tuning_cache_lookup(path: str, key: soap_tuning_key):
+    """(setting, found) for key in the cache file at path (host only)."""
+    t = soap_tuning()
+    found = ctypes.c_int(0)
+    check(load().soap_tuning_cache_lookup(os.fsencode(path), ctypes.byref(key), ctypes.byref(t), ctypes.byref(found)))
+    return t, bool(found.value)
+
+
+def soap_tuning_cache_store(path: str, key: soap_tuning_key, t: soap_tuning) -> None:
+    check(load().soap_tuning_cache_store(os.fsencode(path), ctypes.byref(key), ctypes.byref(t)))

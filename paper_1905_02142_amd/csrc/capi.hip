@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -76,7 +78,9 @@ struct soap_ctx {
   int* report_dev = nullptr;  // the same memory as the device addresses it
   std::vector<char> meta_host;  // the structure geometry last uploaded, and where
   void* meta_dev = nullptr;
-  soap_tuning tune{0, 0, 256, 2};
+  soap_tuning tune{0, 0, 256, 2, 0};
+  std::string tune_cache;  // attached tuning-cache file ("" = none)
+  long long tune_cache_hits = 0;
   double skin = 0.0;  // neighbour lists are built to r_cut + skin
   int built_atoms = -1, built_structures = 0;  // the geometry of the last build (meta on the device)
   Buf tune_out;  // scratch outputs of the autotuner
@@ -755,7 +759,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     return s;
   // the unfused Qbar pass splits its contraction over the sparse points into
   // parts that the adjoint adds
-  const int slices = fused ? 1 : soap::gap_qbar_slices(M, prec);
+  const int slices = fused ? 1 : soap::gap_qbar_slices(M, prec, ctx->tune.gap_tile);
   double* qbar = nullptr;
   if (forces) {
     SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * slices * N * P.K);
@@ -772,11 +776,13 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
       StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
       // with forces the Qbar pass also finishes the energy and dE/dalpha sums
       SOAP_HIP(ctx, soap::launch_gap_scores(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta,
-                                            e_atom, alpha_grad, qbar == nullptr, qc != nullptr, ctx->gapw.p, st));
+                                            e_atom, alpha_grad, qbar == nullptr, qc != nullptr, ctx->gapw.p,
+                                            ctx->tune.gap_tile, st));
     }
     if (qbar) {
       StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
-      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, e_atom, alpha_grad, ctx->gapw.p, slices, st));
+      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, e_atom, alpha_grad, ctx->gapw.p, slices,
+                                          ctx->tune.gap_tile, st));
     }
   }
   if (forces) {
@@ -828,7 +834,7 @@ soap_status soap_set_tuning(soap_ctx* ctx, const soap_tuning* t) {
   if (!ctx || !t) return SOAP_EINVAL;
   if ((t->gap_fused != 0 && t->gap_fused != 1) || t->gap_slices < 0 || t->gap_slices > (1 << 20) ||
       (t->prep_block != 64 && t->prep_block != 128 && t->prep_block != 256) || t->cell_split < 1 ||
-      t->cell_split > 3)
+      t->cell_split > 3 || (t->gap_tile != 0 && t->gap_tile != 1))
     return fail(ctx, SOAP_EINVAL, "tuning field out of range");
   ctx->tune = *t;
   return SOAP_OK;
@@ -838,6 +844,20 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
                           const double* alpha, int M, int zeta, int repeats, soap_tuning* chosen, hipStream_t st) {
   if (!ctx) return SOAP_EINVAL;
   if (!nl || repeats < 1) return fail(ctx, SOAP_EINVAL, "null neighbour list or repeats < 1");
+  soap_tuning_key key{};
+  const bool cached = !ctx->tune_cache.empty();
+  if (cached) {
+    soap_status ks = soap_tuning_key_for(ctx, nl->n_atoms, M, &key);
+    if (ks != SOAP_OK) return fail(ctx, ks, "tuning key: device query failed");
+    soap_tuning hit{};
+    int found = 0;
+    if (soap_tuning_cache_lookup(ctx->tune_cache.c_str(), &key, &hit, &found) == SOAP_OK && found &&
+        soap_set_tuning(ctx, &hit) == SOAP_OK) {
+      ++ctx->tune_cache_hits;
+      if (chosen) *chosen = hit;
+      return SOAP_OK;
+    }
+  }
   const size_t N = (size_t)std::max(0, nl->n_atoms);
   SOAP_ENSURE(ctx, ctx->tune_out, sizeof(double) * (4 * N + (size_t)std::max(M, 0) + 1));
   double* e = (double*)ctx->tune_out.p;
@@ -865,6 +885,7 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
   float best_ms = 0.0f;
   soap_status s = time_it(best_ms);
   const bool fusable = soap::gap_fused_supported(ctx->dp.K, gap_precision(ctx));
+  const bool tiles = gap_precision(ctx) == SOAP_MIXED_BF16;  // two BF16 tile shapes
   struct Axis {
     int soap_tuning::*field;
     std::vector<int> cand;
@@ -873,10 +894,12 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
       {&soap_tuning::prep_block, {64, 128, 256}},
       {&soap_tuning::gap_fused, fusable ? std::vector<int>{0, 1} : std::vector<int>{0}},
       {&soap_tuning::gap_slices, fusable ? std::vector<int>{256, 512, 1024, 2048} : std::vector<int>{}},
+      {&soap_tuning::gap_tile, tiles ? std::vector<int>{0, 1} : std::vector<int>{}},
   };
   for (const Axis& ax : axes) {
     if (s != SOAP_OK) break;
     if (ax.field == &soap_tuning::gap_slices && !best.gap_fused) continue;
+    if (ax.field == &soap_tuning::gap_tile && best.gap_fused) continue;
     for (int v : ax.cand) {
       if (v == best.*ax.field) continue;
       ctx->tune = best;
@@ -895,8 +918,175 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_nlist* nl, const int32_t* sp
   ctx->prof_mask = prof;
   if (s != SOAP_OK) return s;
   if (chosen) *chosen = best;
+  if (cached && soap_tuning_cache_store(ctx->tune_cache.c_str(), &key, &best) != SOAP_OK)
+    return fail(ctx, SOAP_ENOMEM, "tuning cache: cannot write " + ctx->tune_cache);
   return SOAP_OK;
 }
+
+soap_status soap_autotune_neighbors(soap_ctx* ctx, int n_atoms, const double* pos, const double* cells,
+                                    const int32_t* pbc, const int32_t* struct_offsets, int n_structures,
+                                    soap_nlist* nl, int repeats, soap_tuning* chosen, hipStream_t st) {
+  if (!ctx) return SOAP_EINVAL;
+  if (!nl || repeats < 1) return fail(ctx, SOAP_EINVAL, "null neighbour list or repeats < 1");
+  const soap_tuning start = ctx->tune;
+  const unsigned prof = ctx->prof_mask;
+  ctx->prof_mask = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    ctx->prof_mask = prof;
+    return fail(ctx, SOAP_EHIP, "event creation failed");
+  }
+  soap_status s = SOAP_OK;
+  soap_tuning best = start;
+  float best_ms = 0.0f;
+  for (int split = 1; split <= 3 && s == SOAP_OK; ++split) {
+    ctx->tune = start;
+    ctx->tune.cell_split = split;
+    // warm-up build, checked: every setting lists the same pairs, so an
+    // overflow here is an overflow for all of them
+    s = soap_build_neighbors_async(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl, st);
+    if (s == SOAP_OK) s = soap_neighbors_check(ctx, nl, nullptr, st);
+    if (s != SOAP_OK) break;
+    if (hipEventRecord(a, st) != hipSuccess) {
+      s = fail(ctx, SOAP_EHIP, "event record failed");
+      break;
+    }
+    for (int r = 0; r < repeats && s == SOAP_OK; ++r)
+      s = soap_build_neighbors_async(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl, st);
+    float ms = 0.0f;
+    if (s == SOAP_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                         hipEventElapsedTime(&ms, a, b) != hipSuccess))
+      s = fail(ctx, SOAP_EHIP, "event timing failed");
+    if (s == SOAP_OK && (split == 1 || ms < best_ms)) {
+      best_ms = ms;
+      best = ctx->tune;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  ctx->prof_mask = prof;
+  ctx->tune = s == SOAP_OK ? best : start;
+  if (s != SOAP_OK) return s;
+  // the list of the chosen setting, with the host-side count
+  long long required = 0;
+  if ((s = soap_build_neighbors(ctx, n_atoms, pos, cells, pbc, struct_offsets, n_structures, nl, &required, st)) !=
+      SOAP_OK)
+    return s;
+  if (chosen) *chosen = best;
+  return SOAP_OK;
+}
+
+// ------------------------------------------------------------ tuning cache
+namespace {
+
+bool key_text(const soap_tuning_key* k, std::string& out) {
+  const size_t n = strnlen(k->arch, sizeof(k->arch));
+  if (n == 0 || n == sizeof(k->arch)) return false;
+  for (size_t t = 0; t < n; ++t)
+    if (k->arch[t] <= ' ' || k->arch[t] > '~') return false;  // one printable token
+  std::ostringstream o;
+  o << "soap-tuning " << k->version << ' ' << std::string(k->arch, n) << ' ' << k->n_channels << ' ' << k->l_max
+    << ' ' << k->K << ' ' << k->M << ' ' << k->precision << ' ' << k->radial_dd << ' ' << k->size_class;
+  out = o.str();
+  return true;
+}
+
+// the setting of a line "<key text> = a b c d e" whose key text equals `key`
+bool parse_entry(const std::string& line, const std::string& key, soap_tuning& t) {
+  const size_t eq = line.find(" = ");
+  if (eq == std::string::npos || line.compare(0, eq, key) != 0 || eq != key.size()) return false;
+  std::istringstream v(line.substr(eq + 3));
+  soap_tuning r{};
+  if (!(v >> r.gap_fused >> r.gap_slices >> r.prep_block >> r.cell_split >> r.gap_tile)) return false;
+  std::string rest;
+  if (v >> rest) return false;
+  t = r;
+  return true;
+}
+
+}  // namespace
+
+soap_status soap_tuning_key_for(const soap_ctx* ctx, int n_atoms, int M, soap_tuning_key* out) {
+  if (!ctx || !out || n_atoms < 0 || M < 0) return SOAP_EINVAL;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return SOAP_EHIP;
+  soap_tuning_key k{};
+  k.version = SOAP_TUNING_CACHE_VERSION;
+  k.n_channels = ctx->dp.nch;
+  k.l_max = ctx->prm.l_max;
+  k.K = ctx->dp.K;
+  k.M = M;
+  k.precision = (int)ctx->prm.precision;
+  k.radial_dd = ctx->dp.radial_dd;
+  int c = 0;
+  for (long long v = n_atoms; v > 0; v >>= 1) ++c;
+  k.size_class = c;
+  size_t t = 0;
+  for (; t + 1 < sizeof(k.arch) && prop.gcnArchName[t] && prop.gcnArchName[t] != ':'; ++t)
+    k.arch[t] = prop.gcnArchName[t];
+  k.arch[t] = '\0';
+  *out = k;
+  return SOAP_OK;
+}
+
+soap_status soap_tuning_cache_lookup(const char* path, const soap_tuning_key* key, soap_tuning* out, int* found) {
+  if (!path || !key || !out || !found) return SOAP_EINVAL;
+  *found = 0;
+  std::string kt;
+  if (!key_text(key, kt)) return SOAP_EINVAL;
+  std::ifstream f(path);
+  if (!f) return SOAP_OK;  // no file: an empty cache
+  std::string line;
+  while (std::getline(f, line)) {
+    soap_tuning t{};
+    if (parse_entry(line, kt, t)) {  // the last matching entry wins
+      *out = t;
+      *found = 1;
+    }
+  }
+  return SOAP_OK;
+}
+
+soap_status soap_tuning_cache_store(const char* path, const soap_tuning_key* key, const soap_tuning* t) {
+  if (!path || !key || !t) return SOAP_EINVAL;
+  std::string kt;
+  if (!key_text(key, kt)) return SOAP_EINVAL;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line;
+    soap_tuning dummy{};
+    while (f && std::getline(f, line))
+      if (!parse_entry(line, kt, dummy)) lines.push_back(line);
+  }
+  std::ostringstream e;
+  e << kt << " = " << t->gap_fused << ' ' << t->gap_slices << ' ' << t->prep_block << ' ' << t->cell_split << ' '
+    << t->gap_tile;
+  lines.push_back(e.str());
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    for (const std::string& l : lines) o << l << '\n';
+    o.flush();
+    if (!o) {
+      std::remove(tmp.c_str());
+      return SOAP_ENOMEM;
+    }
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return SOAP_ENOMEM;
+  }
+  return SOAP_OK;
+}
+
+soap_status soap_set_tuning_cache(soap_ctx* ctx, const char* path) {
+  if (!ctx) return SOAP_EINVAL;
+  ctx->tune_cache = path ? path : "";
+  return SOAP_OK;
+}
+
+long long soap_tuning_cache_hits(const soap_ctx* ctx) { return ctx ? ctx->tune_cache_hits : -1; }
 
 soap_status soap_profile(soap_ctx* ctx, int enable) {
   if (!ctx) return SOAP_EINVAL;

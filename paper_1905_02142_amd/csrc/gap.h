@@ -12,8 +12,9 @@ size_t gap_workspace_bytes(int N, int M, int K, int prec);
 // e (N) and alpha_bar (M, nullable); G stays in work for the qbar pass.  With
 // sums false the per-tile partial sums are left in work for launch_gap_qbar to
 // finish (e and alpha_bar are then written by that call)
+// tile: the BF16 tile shapes (soap_tuning.gap_tile), 0 or 1; ignored in the other modes
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                             int zeta, double* e, double* alpha_bar, bool sums, bool q_ready, void* work,
+                             int zeta, double* e, double* alpha_bar, bool sums, bool q_ready, void* work, int tile,
                              hipStream_t st);
 // BF16 (prec 2) only: the N x gap_q_pitch(K) bf16 copy of Q inside work, for a
 // producer of q that writes it itself (row i at element i Kp: (bf16)(float) q_ik,
@@ -27,9 +28,9 @@ int gap_q_pitch(int K);
 // multiplies the workgroups of this long contraction.  With e non-null it also
 // finishes e and alpha_bar (nullable) from the partial sums
 hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar,
-                           const void* work, int slices, hipStream_t st);
+                           const void* work, int slices, int tile, hipStream_t st);
 // the slice count launch_gap_qbar accepts and that pays off for M sparse points: 1 or 2
-int gap_qbar_slices(int M, int prec);
+int gap_qbar_slices(int M, int prec, int tile);
 
 // Fused scores + Qbar (prec 1..3, padded K <= 352): e, alpha_bar (nullable) and
 // Qbar in one pass with no N x M intermediate in HBM

@@ -14,8 +14,12 @@
 // previous one is multiplied from LDS.  Precision policies:
 //   FP64    v_mfma_f64_16x16x4_f64, FP64 accumulation, 64 x 64 tiles
 //   F32     v_mfma_f32_16x16x4_f32, FP32 accumulation, 64 x 64 tiles
-//   BF16    v_mfma_f32_16x16x32_bf16, FP32 accumulation, 128 x 128 tiles
-//           (scores) and 64 x 64 tiles (Qbar), both with 128-wide K-tiles
+//   BF16    v_mfma_f32_16x16x32_bf16, FP32 accumulation, 128 x 128 tiles; the
+//           scores pass with 128-wide K-tiles, the Qbar pass with 64-wide ones
+//           double-buffered in LDS (the next K-tile is stored while the current
+//           one is multiplied: one barrier per K-tile) in rows of 128 bytes whose
+//           16-byte pieces are permuted by row % 8 (XOR), so that the 16-byte
+//           operand reads of eight consecutive rows hit distinct banks
 //   BF16X3  a = a_hi + a_lo in BF16, a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
 // Row / column sums of the epilogue go to per-tile partial arrays that are
 // added in a fixed order, so results do not depend on scheduling.
@@ -35,12 +39,15 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte move
 
+// kSwizzled: double-buffered K-tiles of 128-byte rows, 16-byte pieces XOR-permuted
+// by row % 8 (needs KT * sizeof(T) = 128); otherwise one buffer, rows padded by 16 bytes
 struct PF64 {
   using T = double;
   using Acc = d4;
   static constexpr int BM = 64, BN = 64, KT = 32;
   static constexpr bool kSplit = false;
   static constexpr bool kRowsInterleaved = true;  // D[l/16 + 4r][l%16]
+  static constexpr bool kSwizzled = false;
 };
 struct PF32 {
   using T = float;
@@ -48,6 +55,7 @@ struct PF32 {
   static constexpr int BM = 64, BN = 64, KT = 32;
   static constexpr bool kSplit = false;
   static constexpr bool kRowsInterleaved = false;  // D[4(l/16) + r][l%16]
+  static constexpr bool kSwizzled = false;
 };
 struct PBF16 {
   using T = __bf16;
@@ -55,6 +63,12 @@ struct PBF16 {
   static constexpr int BM = 128, BN = 128, KT = 128;
   static constexpr bool kSplit = false;
   static constexpr bool kRowsInterleaved = false;
+  static constexpr bool kSwizzled = false;
+};
+// the alternative BF16 scores tile (tile shape 1): 64-wide K-tiles, double-buffered
+struct PBF16D : PBF16 {
+  static constexpr int KT = 64;
+  static constexpr bool kSwizzled = true;
 };
 struct PBF16X3 {
   using T = __bf16;
@@ -62,16 +76,25 @@ struct PBF16X3 {
   static constexpr int BM = 128, BN = 128, KT = 32;
   static constexpr bool kSplit = true;
   static constexpr bool kRowsInterleaved = false;
+  static constexpr bool kSwizzled = false;
 };
 // the Qbar pass (N x K output, K ~ 300) in 64 x 64 tiles, so that it fills the chip
 template <typename P>
 struct QbarTile : P {
   static constexpr int BM = 64, BN = 64;
 };
-// BF16 Qbar: the contraction runs over all sparse points (Mp ~ 2000), 128 per K-tile
+// BF16 Qbar: the contraction runs over all sparse points (Mp ~ 2000) in 128 x 128
+// tiles, double-buffered 64-wide K-tiles (the scores pass, with its heavier
+// epilogue, keeps one buffer of 128-wide K-tiles: measured faster there)
 template <>
 struct QbarTile<PBF16> : PBF16 {
+  static constexpr int KT = 64;
+  static constexpr bool kSwizzled = true;
+};
+// the alternative BF16 Qbar tile (tile shape 1): 64 x 64, one buffer of 128-wide K-tiles
+struct QbarSmallBF16 : PBF16 {
   static constexpr int BM = 64, BN = 64, KT = 128;
+  static constexpr bool kSwizzled = false;
 };
 template <>
 struct QbarTile<PF64> : PF64 {};
@@ -152,11 +175,19 @@ __global__ void k_convert3(int N, int M, int K, int Kp, int Mp, I e0, const doub
 template <typename P>
 struct Smem {
   static constexpr int EPV = 16 / sizeof(typename P::T);  // elements per 16-byte vector
-  static constexpr int PITCH = P::KT + EPV;                // row pitch in elements (16-byte multiple)
-  alignas(16) typename P::T a[P::BM * PITCH];
-  alignas(16) typename P::T b[P::BN * PITCH];
+  static constexpr bool SW = P::kSwizzled;
+  static_assert(!SW || (P::KT * sizeof(typename P::T) == 128 && !P::kSplit), "swizzled rows are 128 bytes");
+  static constexpr int PITCH = SW ? P::KT : P::KT + EPV;  // row pitch in elements (16-byte multiple)
+  static constexpr int NB = SW ? 2 : 1;                   // K-tile buffers
+  alignas(16) typename P::T a[NB * P::BM * PITCH];
+  alignas(16) typename P::T b[NB * P::BN * PITCH];
   alignas(16) typename P::T a_lo[P::kSplit ? P::BM * PITCH : 1];
   alignas(16) typename P::T b_lo[P::kSplit ? P::BN * PITCH : 1];
+  // element offset of (row r, column c) of a K-tile, c a multiple of EPV
+  __device__ static inline int off(int r, int c) {
+    if constexpr (SW) return r * PITCH + (((c / EPV) ^ (r & 7)) * EPV);
+    else return r * PITCH + c;
+  }
 };
 
 // Register staging of one K-tile of a (rows x KT) block: 16-byte vectors
@@ -179,7 +210,7 @@ struct Stage {
 #pragma unroll
     for (int t = 0; t < NV; ++t) {
       const int idx = tid + 256 * t, r = idx / VPR, c = (idx % VPR) * EPV;
-      *(u4*)(s + r * Smem<P>::PITCH + c) = v[t];
+      *(u4*)(s + Smem<P>::off(r, c)) = v[t];
     }
   }
 };
@@ -189,11 +220,12 @@ struct Frag {
   static constexpr int TM = P::BM / 32, TN = P::BN / 32;  // 16 x 16 tiles per wave
 };
 
-// acc[x][y] += A(wave rows x) B(wave cols y)^T over the K-tile in LDS
+// acc[x][y] += A(wave rows x) B(wave cols y)^T over the K-tile in LDS (buffer buf)
 template <typename P>
-__device__ inline void mma_ktile(const Smem<P>& sm, int wm, int wn, int lane,
+__device__ inline void mma_ktile(const Smem<P>& sm, int buf, int wm, int wn, int lane,
                                  typename P::Acc (&acc)[Frag<P>::TM][Frag<P>::TN]) {
   constexpr int PITCH = Smem<P>::PITCH, TM = Frag<P>::TM, TN = Frag<P>::TN;
+  using Sm = Smem<P>;
   const int r16 = lane & 15, kq = lane >> 4;
   const int ra = wm * (P::BM / 2), rb = wn * (P::BN / 2);
   if constexpr (sizeof(typename P::T) >= 4) {
@@ -215,18 +247,20 @@ __device__ inline void mma_ktile(const Smem<P>& sm, int wm, int wn, int lane,
         }
     }
   } else {
+    const typename P::T* sa = sm.a + buf * P::BM * PITCH;
+    const typename P::T* sb = sm.b + buf * P::BN * PITCH;
 #pragma unroll
     for (int ks = 0; ks < P::KT; ks += 32) {
       b8 a[TM], b[TN], al[TM], bl[TN];
 #pragma unroll
       for (int x = 0; x < TM; ++x) {
-        a[x] = *(const b8*)&sm.a[(ra + x * 16 + r16) * PITCH + ks + 8 * kq];
-        if constexpr (P::kSplit) al[x] = *(const b8*)&sm.a_lo[(ra + x * 16 + r16) * PITCH + ks + 8 * kq];
+        a[x] = *(const b8*)&sa[Sm::off(ra + x * 16 + r16, ks + 8 * kq)];
+        if constexpr (P::kSplit) al[x] = *(const b8*)&sm.a_lo[Sm::off(ra + x * 16 + r16, ks + 8 * kq)];
       }
 #pragma unroll
       for (int y = 0; y < TN; ++y) {
-        b[y] = *(const b8*)&sm.b[(rb + y * 16 + r16) * PITCH + ks + 8 * kq];
-        if constexpr (P::kSplit) bl[y] = *(const b8*)&sm.b_lo[(rb + y * 16 + r16) * PITCH + ks + 8 * kq];
+        b[y] = *(const b8*)&sb[Sm::off(rb + y * 16 + r16, ks + 8 * kq)];
+        if constexpr (P::kSplit) bl[y] = *(const b8*)&sm.b_lo[Sm::off(rb + y * 16 + r16, ks + 8 * kq)];
       }
 #pragma unroll
       for (int x = 0; x < TM; ++x)
@@ -258,24 +292,49 @@ __device__ inline void gemm_tile(Smem<P>& sm, const typename P::T* __restrict__ 
     sal.load(A_lo, lda, row0, arows, 0, tid);
     sbl.load(B_lo, ldb, col0, brows, 0, tid);
   }
-  for (int k0 = 0; k0 < kdim; k0 += P::KT) {
+  if constexpr (Smem<P>::SW) {
+    // double buffer: K-tile t is multiplied from buffer t % 2 while tile t + 1,
+    // already in registers, is stored into the other one; the barrier that ends
+    // step t also guarantees that no wave still reads the buffer step t + 1 fills
+    constexpr int AB = P::BM * Smem<P>::PITCH, BB = P::BN * Smem<P>::PITCH;
     sa.store(sm.a, tid);
     sb.store(sm.b, tid);
-    if constexpr (P::kSplit) {
-      sal.store(sm.a_lo, tid);
-      sbl.store(sm.b_lo, tid);
-    }
     __syncthreads();
-    if (k0 + P::KT < kdim) {  // prefetch the next K-tile while this one is multiplied
-      sa.load(A, lda, row0, arows, k0 + P::KT, tid);
-      sb.load(B, ldb, col0, brows, k0 + P::KT, tid);
-      if constexpr (P::kSplit) {
-        sal.load(A_lo, lda, row0, arows, k0 + P::KT, tid);
-        sbl.load(B_lo, ldb, col0, brows, k0 + P::KT, tid);
+    int buf = 0;
+    for (int k0 = 0; k0 < kdim; k0 += P::KT) {
+      const bool more = k0 + P::KT < kdim;
+      if (more) {
+        sa.load(A, lda, row0, arows, k0 + P::KT, tid);
+        sb.load(B, ldb, col0, brows, k0 + P::KT, tid);
       }
+      mma_ktile<P>(sm, buf, wm, wn, lane, acc);
+      if (more) {
+        sa.store(sm.a + (buf ^ 1) * AB, tid);
+        sb.store(sm.b + (buf ^ 1) * BB, tid);
+      }
+      __syncthreads();
+      buf ^= 1;
     }
-    mma_ktile<P>(sm, wm, wn, lane, acc);
-    __syncthreads();
+  } else {
+    for (int k0 = 0; k0 < kdim; k0 += P::KT) {
+      sa.store(sm.a, tid);
+      sb.store(sm.b, tid);
+      if constexpr (P::kSplit) {
+        sal.store(sm.a_lo, tid);
+        sbl.store(sm.b_lo, tid);
+      }
+      __syncthreads();
+      if (k0 + P::KT < kdim) {  // prefetch the next K-tile while this one is multiplied
+        sa.load(A, lda, row0, arows, k0 + P::KT, tid);
+        sb.load(B, ldb, col0, brows, k0 + P::KT, tid);
+        if constexpr (P::kSplit) {
+          sal.load(A_lo, lda, row0, arows, k0 + P::KT, tid);
+          sbl.load(B_lo, ldb, col0, brows, k0 + P::KT, tid);
+        }
+      }
+      mma_ktile<P>(sm, 0, wm, wn, lane, acc);
+      __syncthreads();
+    }
   }
 }
 
@@ -340,10 +399,11 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
   constexpr int EPV = 16 / sizeof(T), GP = P::BN + EPV, VPR = P::BN / EPV;
   static_assert(sizeof(T) * P::BM * GP <= sizeof(Smem<P>), "G tile must fit in the operand LDS");
   T* gt = reinterpret_cast<T*>(&sm);
-  double rows[TM][4] = {}, cols[TN] = {};
-  // 16-bit operands: the zeta power in FP32 (its rounding is far below that of
-  // the operands); otherwise in FP64
+  // 16-bit operands: the zeta power and the tile's row and column sums (at most
+  // BN and BM terms, added in FP64 across tiles) in FP32, whose rounding is far
+  // below that of the operands; otherwise in FP64
   using E = typename std::conditional<sizeof(T) == 2, float, double>::type;
+  E rows[TM][4] = {}, cols[TN] = {};
   // the weights of this lane's columns, read once; a padding column (gs >= M)
   // has weight 0, and its scores, like those of padding rows, are exactly 0
   // (zero operand rows), so the tile needs no per-element bounds test: padding
@@ -394,14 +454,14 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
             sz1 = pw[x][y][r];
           }
           const E al = al_y[y];
-          const double g = (double)((E)zeta * al * sz1);
+          const E g = (E)zeta * al * sz1;
           if (pass == 0) {
-            const double kv = (double)(sz1 * sv);
-            rows[x][r] = fma((double)al, kv, rows[x][r]);
+            const E kv = sz1 * sv;
+            rows[x][r] = fma(al, kv, rows[x][r]);
             cols[y] += kv;
           }
-          const T gh = cvt<T>(g);
-          gt[lr * GP + lc] = pass == 0 ? gh : cvt_lo_any<T>(g, gh);
+          const T gh = cvt<T>((double)g);
+          gt[lr * GP + lc] = pass == 0 ? gh : cvt_lo_any<T>((double)g, gh);
         }
     __syncthreads();
     T* __restrict__ dst = pass == 0 ? G : G_lo;
@@ -415,17 +475,17 @@ __global__ __launch_bounds__(256) void k_scores(int N, int M, int Mp, int Kp, co
   for (int x = 0; x < TM; ++x)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      double v = rows[x][r];
+      E v = rows[x][r];
 #pragma unroll
       for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
-      if ((lane & 15) == 0) rowsum[wn][wm * (P::BM / 2) + acc_row<P>(x, r, lane)] = v;
+      if ((lane & 15) == 0) rowsum[wn][wm * (P::BM / 2) + acc_row<P>(x, r, lane)] = (double)v;
     }
 #pragma unroll
   for (int y = 0; y < TN; ++y) {
-    double v = cols[y];
+    E v = cols[y];
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
-    if (lane < 16) colsum[wm][wn * (P::BN / 2) + y * 16 + lane] = v;
+    if (lane < 16) colsum[wm][wn * (P::BN / 2) + y * 16 + lane] = (double)v;
   }
   __syncthreads();
   for (int t = tid; t < P::BM + P::BN; t += 256) {
@@ -466,7 +526,8 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, int 
                                               double* __restrict__ e, int nta, const double* __restrict__ ab_part,
                                               double* __restrict__ ab) {
   constexpr int TM = Frag<P>::TM, TN = Frag<P>::TN;
-  __shared__ Smem<P> sm;
+  extern __shared__ __align__(16) char dsm[];  // the operand tiles, sizeof(Smem<P>)
+  Smem<P>& sm = *reinterpret_cast<Smem<P>*>(dsm);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
   int tc, tr;
   xcd_tile(tc, tr, 8, 1);  // few column tiles: an XCD takes whole rows of tiles
@@ -945,7 +1006,9 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
   return hipGetLastError();
 }
 
-template <typename P>
+// P: the scores pass's policy (its tile counts index the partial sums), Q: the
+// Qbar pass's tile
+template <typename P, typename Q = QbarTile<P>>
 hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work, int slices,
                      hipStream_t st) {
   using T = typename P::T;
@@ -954,13 +1017,19 @@ hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha
   const int Kp = padded(K), Mp = padded(M);
   const T *qst = (const T*)(w + L.qst), *qst_lo = (const T*)(w + L.qst_lo);
   const T *G = (const T*)(w + L.g), *G_lo = (const T*)(w + L.g_lo);
-  using Q = QbarTile<P>;
   const int nit = (N + Q::BM - 1) / Q::BM, nct = (Kp + Q::BN - 1) / Q::BN;
   const double* e_part = (const double*)(w + L.e_part);
   const double* ab_part = (const double*)(w + L.ab_part);
   const int nst = Mp / P::BN, nsi = (N + P::BM - 1) / P::BM;  // the scores pass's tile counts
   if (slices < 1 || Mp % (slices * Q::KT) != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit, slices), dim3(256), 0, st, N, K, Mp, Kp, Mp / slices, G, G_lo, qst,
+  static bool attr = false;  // operand tiles above 64 KB of LDS need the opt-in
+  if (!attr && sizeof(Smem<Q>) > 65536) {
+    const hipError_t a = hipFuncSetAttribute((const void*)k_qbar<Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)sizeof(Smem<Q>));
+    if (a != hipSuccess) return a;
+  }
+  attr = true;
+  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit, slices), dim3(256), sizeof(Smem<Q>), st, N, K, Mp, Kp, Mp / slices, G, G_lo, qst,
                      qst_lo, Qbar, M, nst, e_part, e, nsi, ab_part, alpha_bar);
   return hipGetLastError();
 }
@@ -977,14 +1046,17 @@ size_t gap_workspace_bytes(int N, int M, int K, int prec) {
 }
 
 hipError_t launch_gap_scores(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                             int zeta, double* e, double* alpha_bar, bool sums, bool q_ready, void* work,
+                             int zeta, double* e, double* alpha_bar, bool sums, bool q_ready, void* work, int tile,
                              hipStream_t st) {
   if (N == 0) return hipSuccess;
   if (q_ready && !gap_q_operand(prec, N, M, K, work)) return hipErrorInvalidValue;
   switch (prec) {
     case 0: return scores_impl<PF64>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
     case 1: return scores_impl<PF32>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
-    case 2: return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
+    case 2:
+      if (tile == 1)
+        return scores_impl<PBF16D>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
+      return scores_impl<PBF16>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
     default: return scores_impl<PBF16X3>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, sums, q_ready, work, st);
   }
 }
@@ -1027,13 +1099,13 @@ hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, cons
   }
 }
 
-int gap_qbar_slices(int M, int prec) {
+int gap_qbar_slices(int M, int prec, int tile) {
   const int Mp = padded(M);
   int kt;
   switch (prec) {
     case 0: kt = QbarTile<PF64>::KT; break;
     case 1: kt = QbarTile<PF32>::KT; break;
-    case 2: kt = QbarTile<PBF16>::KT; break;
+    case 2: kt = tile == 1 ? QbarSmallBF16::KT : QbarTile<PBF16>::KT; break;
     default: kt = QbarTile<PBF16X3>::KT; break;
   }
   // two slices once each keeps at least four K-steps
@@ -1041,12 +1113,16 @@ int gap_qbar_slices(int M, int prec) {
 }
 
 hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work,
-                           int slices, hipStream_t st) {
+                           int slices, int tile, hipStream_t st) {
   if (N == 0) return hipSuccess;
   switch (prec) {
     case 0: return qbar_impl<PF64>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
     case 1: return qbar_impl<PF32>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
-    case 2: return qbar_impl<PBF16>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+    case 2:
+      // both scores tiles are 128 x 128, so the partial sums are indexed alike
+      static_assert(PBF16::BM == PBF16D::BM && PBF16::BN == PBF16D::BN, "scores tiles of one shape");
+      if (tile == 1) return qbar_impl<PBF16, QbarSmallBF16>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+      return qbar_impl<PBF16>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
     default: return qbar_impl<PBF16X3>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
   }
 }

@@ -2,6 +2,8 @@
 every computation is one call into libsoap.so (see include/soap.h)."""
 from __future__ import annotations
 
+import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -230,12 +232,47 @@ class Soap:
     def tuning(self) -> dict:
         return _lib.soap_get_tuning(self.ctx).as_dict()
 
-    def set_tuning(self, gap_fused: int = 0, gap_slices: int = 0, prep_block: int = 256, cell_split: int = 2) -> None:
-        _lib.soap_set_tuning(self.ctx, _lib.soap_tuning(gap_fused, gap_slices, prep_block, cell_split))
+    def set_tuning(self, gap_fused: int = 0, gap_slices: int = 0, prep_block: int = 256, cell_split: int = 2,
+                   gap_tile: int = 0) -> None:
+        _lib.soap_set_tuning(self.ctx, _lib.soap_tuning(gap_fused, gap_slices, prep_block, cell_split, gap_tile))
+
+    def set_tuning_cache(self, path: str | None) -> None:
+        """soap_set_tuning_cache: autotune() then answers from / stores into this file."""
+        _lib.check(_lib.load().soap_set_tuning_cache(self.ctx, None if path is None else os.fsencode(path)),
+                   self.ctx)
+
+    @property
+    def tuning_cache_hits(self) -> int:
+        return int(_lib.load().soap_tuning_cache_hits(self.ctx))
+
+    def tuning_key(self, n_atoms: int, M: int) -> _lib.soap_tuning_key:
+        k = _lib.soap_tuning_key()
+        _lib.check(_lib.load().soap_tuning_key_for(self.ctx, int(n_atoms), int(M), ctypes.byref(k)), self.ctx)
+        return k
+
+    def autotune_neighbors(self, positions: torch.Tensor, cells, pbc, nl: NeighbourList, struct_offsets=None,
+                           repeats: int = 3) -> dict:
+        """soap_autotune_neighbors: times the build for cell_split 1, 2, 3, installs the
+        fastest and leaves nl built with it."""
+        pos = positions.contiguous()
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.shape[0] == nl.n_atoms
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 9))
+        pbc = np.ascontiguousarray(np.asarray(pbc, dtype=np.int32).reshape(-1, 3))
+        so = None if struct_offsets is None else np.ascontiguousarray(np.asarray(struct_offsets, dtype=np.int32))
+        c = nl.c_struct()
+        t = _lib.soap_tuning()
+        _lib.check(_lib.load().soap_autotune_neighbors(self.ctx, nl.n_atoms, pos.data_ptr(), cells.ctypes.data,
+                                                       pbc.ctypes.data, None if so is None else so.ctypes.data,
+                                                       cells.shape[0], ctypes.byref(c), int(repeats),
+                                                       ctypes.byref(t), _stream()), self.ctx)
+        nl.n_pairs = int(c.n_pairs)
+        nl.n_structures = cells.shape[0]
+        return t.as_dict()
 
     def autotune(self, nl: NeighbourList, species: torch.Tensor, q_sparse: torch.Tensor, alpha: torch.Tensor,
                  zeta: int, repeats: int = 3) -> dict:
-        """soap_autotune on these inputs; installs and returns the fastest setting."""
+        """soap_autotune on these inputs; installs and returns the fastest setting (from the
+        attached cache when it holds one for these inputs)."""
         qs = q_sparse.to(torch.float64).contiguous()
         al = alpha.to(torch.float64).contiguous()
         sp = species.to(torch.int32).contiguous()

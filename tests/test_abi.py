@@ -41,6 +41,50 @@ def test_struct_layouts():
     # soap_params: 3 ints, padding, 9 doubles, 3 ints, padding
     assert ctypes.sizeof(L.soap_params) == 4 * 3 + 4 + 8 * 9 + 4 * 3 + 4
     assert ctypes.sizeof(L.soap_nlist) == 4 + 4 + 8 + 8 + 8 * 8
+    assert ctypes.sizeof(L.soap_tuning) == 5 * 4
+    assert ctypes.sizeof(L.soap_tuning_key) == 8 * 4 + 32
+
+
+def _key(**kw):
+    L = _lib()
+    k = L.soap_tuning_key(version=L.SOAP_TUNING_CACHE_VERSION, n_channels=10, l_max=10, K=605, M=4000, precision=2,
+                          radial_dd=0, size_class=19, arch=b"gfx950")
+    for name, v in kw.items():
+        setattr(k, name, v)
+    return k
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    # host-only: store, look up, replace, keys that differ in any field or in the
+    # version are separate, a missing file is an empty cache, junk lines are kept
+    # and ignored
+    L = _lib()
+    path = str(tmp_path / "tuning.txt")
+    a, b = _key(), _key(M=2000)
+    t, found = L.soap_tuning_cache_lookup(path, a)
+    assert not found
+    with open(path, "w") as f:
+        f.write("a line that is not an entry\n")
+    ta = L.soap_tuning(0, 0, 128, 2, 1)
+    tb = L.soap_tuning(1, 1024, 256, 3, 0)
+    L.soap_tuning_cache_store(path, a, ta)
+    L.soap_tuning_cache_store(path, b, tb)
+    for k, want in ((a, ta), (b, tb)):
+        got, found = L.soap_tuning_cache_lookup(path, k)
+        assert found and got.as_dict() == want.as_dict()
+    ta2 = L.soap_tuning(0, 0, 64, 1, 0)
+    L.soap_tuning_cache_store(path, a, ta2)  # replaces a's entry
+    got, found = L.soap_tuning_cache_lookup(path, a)
+    assert found and got.as_dict() == ta2.as_dict()
+    lines = open(path).read().splitlines()
+    assert lines[0] == "a line that is not an entry" and len(lines) == 3
+    for other in (_key(version=L.SOAP_TUNING_CACHE_VERSION + 1), _key(arch=b"gfx942"), _key(size_class=18),
+                  _key(precision=4), _key(radial_dd=1), _key(K=606), _key(l_max=8), _key(n_channels=24)):
+        assert not L.soap_tuning_cache_lookup(path, other)[1]
+    with pytest.raises(L.SoapError):
+        L.soap_tuning_cache_store(path, _key(arch=b"gfx 950"), ta)  # not one token
+    with pytest.raises(L.SoapError):
+        L.soap_tuning_cache_store(path, _key(arch=b""), ta)
 
 
 @pytest.mark.parametrize("n,rc,s0", [(6, 3.7, 0.5), (8, 5.0, 0.5), (10, 5.5, 0.5), (8, 4.3, 0.12)])

@@ -14,10 +14,11 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 KW = dict(n_max=8, l_max=6, r_cut=4.5, sigma0_r=0.5, sigma0_perp=0.5)
 BOUNDS = {"fp64": 1e-10, "bf16": 5e-2}
-SETTINGS = [dict(gap_fused=0, gap_slices=0, prep_block=256, cell_split=2),
-            dict(gap_fused=0, gap_slices=0, prep_block=64, cell_split=2),
-            dict(gap_fused=1, gap_slices=256, prep_block=128, cell_split=2),
-            dict(gap_fused=1, gap_slices=2048, prep_block=256, cell_split=2)]
+SETTINGS = [dict(gap_fused=0, gap_slices=0, prep_block=256, cell_split=2, gap_tile=0),
+            dict(gap_fused=0, gap_slices=0, prep_block=64, cell_split=2, gap_tile=0),
+            dict(gap_fused=1, gap_slices=256, prep_block=128, cell_split=2, gap_tile=0),
+            dict(gap_fused=1, gap_slices=2048, prep_block=256, cell_split=2, gap_tile=0),
+            dict(gap_fused=0, gap_slices=0, prep_block=256, cell_split=2, gap_tile=1)]
 
 
 @pytest.fixture(scope="module")
@@ -77,6 +78,80 @@ def test_invalid_setting_rejected():
         soap.set_tuning(gap_fused=2)
     with pytest.raises(_lib.SoapError):
         soap.set_tuning(cell_split=4)
+    with pytest.raises(_lib.SoapError):
+        soap.set_tuning(gap_tile=2)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16ps"])
+def test_gap_tile_shapes_bitwise_equal(case, prec):
+    # the two BF16 tile shapes take the same products in the same order
+    from paper_1905_02142_amd import Soap, SoapParams
+
+    s, spec, qs, al, eo, Fo, abo = case
+    soap = Soap(SoapParams(precision=prec, **KW))
+    nl = soap.neighbors(_t(s.positions), s.cell, s.pbc)
+    outs = []
+    for tile in (0, 1):
+        soap.set_tuning(gap_tile=tile)
+        outs.append([t.cpu().numpy() for t in soap.energy_forces(nl, _t(spec), _t(qs), _t(al), 3)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+
+
+def test_tuning_cache_reused(case, tmp_path):
+    """The first autotune with a cache attached tunes and stores one entry; a
+    second context with the same parameters and inputs takes it from the file
+    without timing, and installs the same setting."""
+    from paper_1905_02142_amd import Soap, SoapParams, _lib
+
+    s, spec, qs, al, eo, Fo, abo = case
+    path = str(tmp_path / "tuning.txt")
+    first = Soap(SoapParams(precision="bf16", **KW))
+    first.set_tuning_cache(path)
+    nl = first.neighbors(_t(s.positions), s.cell, s.pbc)
+    chosen = first.autotune(nl, _t(spec), _t(qs), _t(al), 3, repeats=1)
+    assert first.tuning_cache_hits == 0
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("soap-tuning %d " % _lib.SOAP_TUNING_CACHE_VERSION)
+    key = first.tuning_key(s.n_atoms, len(al))
+    stored, found = _lib.soap_tuning_cache_lookup(path, key)
+    assert found and stored.as_dict() == chosen
+    second = Soap(SoapParams(precision="bf16", **KW))
+    second.set_tuning_cache(path)
+    nl2 = second.neighbors(_t(s.positions), s.cell, s.pbc)
+    again = second.autotune(nl2, _t(spec), _t(qs), _t(al), 3, repeats=1)
+    assert second.tuning_cache_hits == 1 and again == chosen and second.tuning == chosen
+    assert open(path).read().splitlines() == lines
+    # another precision is another key: tuned and stored beside the first entry
+    third = Soap(SoapParams(precision="fp64", **KW))
+    third.set_tuning_cache(path)
+    nl3 = third.neighbors(_t(s.positions), s.cell, s.pbc)
+    third.autotune(nl3, _t(spec), _t(qs), _t(al), 3, repeats=1)
+    assert third.tuning_cache_hits == 0 and len(open(path).read().splitlines()) == 2
+
+
+def test_autotune_neighbors():
+    # times cell_split 1..3, installs the fastest and leaves the list built with it:
+    # the same pair set as a build with the default setting
+    from paper_1905_02142_amd import Soap, SoapParams
+
+    s = synth.rsa_box(3000, 40.0, 1.2, 1302)
+    soap = Soap(SoapParams(**KW))
+    pos = _t(s.positions)
+    ref = soap.neighbors(pos, s.cell, s.pbc)
+    n0 = ref.n_pairs
+    key0 = np.lexsort((ref.img[:n0].cpu().numpy(), ref.j[:n0].cpu().numpy(), ref.center[:n0].cpu().numpy()))
+    want = np.stack([ref.center[:n0].cpu().numpy()[key0], ref.j[:n0].cpu().numpy()[key0],
+                     ref.img[:n0].cpu().numpy()[key0]])
+    nl = soap.neighbors(pos, s.cell, s.pbc)
+    chosen = soap.autotune_neighbors(pos, s.cell, s.pbc, nl, repeats=2)
+    print("cell_split chosen", chosen["cell_split"])
+    assert chosen["cell_split"] in (1, 2, 3) and soap.tuning == chosen
+    n = nl.n_pairs
+    assert n == n0
+    c, j, img = (getattr(nl, k)[:n].cpu().numpy() for k in ("center", "j", "img"))
+    order = np.lexsort((img, j, c))
+    assert np.array_equal(np.stack([c[order], j[order], img[order]]), want)
 
 
 def test_autotune_installs_its_choice(case):
