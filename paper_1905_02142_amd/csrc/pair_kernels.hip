@@ -294,7 +294,7 @@ __device__ inline void stage_fields(const double* __restrict__ rows, const int* 
 // positions 8 (j / 16) .. 8 (j / 16) + 7; result lane j holds rows
 // 4 (j / 16) .. + 3 of column j % 16.  Returns this lane's sum of squares.
 template <int NMAX>
-__device__ inline double power_spectrum_mfma(const DevParams& P, const double* csh, double* pv, int lane) {
+__device__ __forceinline__ double power_spectrum_mfma(const DevParams& P, const double* csh, double* pv, int lane) {
   const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
   const int r16 = lane & 15, kq = lane >> 4, T = (nch + 15) / 16;
   // operand: channel row a, positions m' = 8 kq + j of degree l
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
 // column per lane: M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b),
 // vbar packed a <= b then l
 template <int NMAX>
-__device__ inline void transform_columns(int n, int nch, int LL, int L1, double* cb, const double* vb, int lane) {
+__device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1, double* cb, const double* vb, int lane) {
   for (int lm = lane; lm < LL; lm += 64) {
     const int l = isqrt_small(lm);
     double* col = cb + (size_t)lm * NMAX;
@@ -613,7 +613,7 @@ __device__ inline void transform_columns(int n, int nch, int LL, int L1, double*
 // complete in order).  abx[a][b] = (packed index of {a, b}) * (l_max + 1).  Each
 // output takes its terms in the order (sb, kb).
 template <int NMAX>
-__device__ inline void transform_columns_species(int n, int ns, int nch, int LL, int L1, double* cb, const double* vb,
+__device__ __forceinline__ void transform_columns_species(int n, int ns, int nch, int LL, int L1, double* cb, const double* vb,
                                                  const int* abx, int lane) {
   const int LLP = LL + 1, cpp = 64 / ns;  // columns per pass
   const int lmo = lane / ns, sa = lane - lmo * ns;
@@ -663,7 +663,7 @@ __device__ inline void transform_columns_species(int n, int ns, int nch, int LL,
 // layout.  Entries outside the channels and columns (the sink column, channels
 // k >= n_max) are left as they are.  n_ch <= 48.
 template <int NMAX>
-__device__ inline void cbar_mfma(const DevParams& P, const double* csrc, double* cb, const double* vb, int lane) {
+__device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc, double* cb, const double* vb, int lane) {
   const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
   const int r16 = lane & 15, kq = lane >> 4;
   const int TA = (nch + 15) / 16, TK = (nch + 31) / 32;
@@ -734,7 +734,7 @@ __device__ inline void cbar_mfma(const DevParams& P, const double* csrc, double*
 // qbar stay in registers from the dot product to vbar; otherwise the reads go
 // eight per lane at a time.
 template <int NMAX, int LMAX>
-__device__ inline void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
+__device__ __forceinline__ void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
                                  const double* __restrict__ qbar, const double* __restrict__ qbar2, int qbar_pitch,
                                  double* cb, double* vb, int* abx, int lane) {
@@ -866,7 +866,7 @@ struct AdjLds {
 // l = l_first, l_first + l_step, ... (l outer, m inner): S_r, S_x, S_y, S_z of
 // the gradient (partial sums when l_step > 1)
 template <int NMAX, int LMAX, typename FieldFn>
-__device__ inline void adjoint_records(int L, int l_first, int l_step, const double* __restrict__ cb,
+__device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, const double* __restrict__ cb,
                                        const double* __restrict__ rc,
                                        const int* __restrict__ ri, FieldFn F, const double (&b)[NMAX],
                                        const double (&db)[NMAX], double uz, double ux, double uy, double& sr,
