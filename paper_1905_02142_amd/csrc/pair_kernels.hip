@@ -570,11 +570,16 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
 // cbar = M(l) c in place for every column lm < LL of one species' cb, one
 // column per lane: M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b),
 // vbar packed a <= b then l
-template <int NMAX>
-__device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1, double* cb, const double* vb, int lane) {
+template <int NMAX, int LMAX, bool FULL>
+__device__ __forceinline__ void transform_columns_t(int n, int nch, int LL, int L1, double* cb, const double* vb,
+                                                    int lane) {
+  // FULL: n_max and l_max fill the compiled bucket, so every vbar index is a
+  // compile-time offset from the column's l (no index arithmetic per entry)
+  const int n_ = FULL ? NMAX : n, nch_ = FULL ? NMAX : nch, L1_ = FULL ? LMAX + 1 : L1;
   for (int lm = lane; lm < LL; lm += 64) {
     const int l = isqrt_small(lm);
     double* col = cb + (size_t)lm * NMAX;
+    const double* __restrict__ vl = vb + l;
     double cv[NMAX];
 #pragma unroll
     for (int kb = 0; kb < NMAX; kb += 2) {
@@ -591,8 +596,8 @@ __device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1
     for (int a = 0; a < NMAX; ++a)
 #pragma unroll
       for (int b = a; b < NMAX; ++b)
-        if (b < n) {
-          const double v = vb[(a * nch - a * (a - 1) / 2 + (b - a)) * L1 + l];
+        if (b < n_) {
+          const double v = vl[(a * nch_ - a * (a - 1) / 2 + (b - a)) * L1_];
           if (a == b) {
             acc[a] = fma(2.0 * v, cv[a], acc[a]);
           } else {
@@ -604,6 +609,13 @@ __device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1
 #pragma unroll
     for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(col + k) = double2{acc[k], acc[k + 1]};
   }
+}
+
+template <int NMAX, int LMAX>
+__device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1, double* cb, const double* vb,
+                                                  int lane) {
+  if (n == NMAX && L1 == LMAX + 1) transform_columns_t<NMAX, LMAX, true>(n, nch, LL, L1, cb, vb, lane);
+  else transform_columns_t<NMAX, LMAX, false>(n, nch, LL, L1, cb, vb, lane);
 }
 
 // The same transform in place for several species: task (column lm, output
@@ -782,7 +794,7 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const doubl
         if (lane + 64 * u < K) vb[lane + 64 * u] = (g[u] - a[u] * dot) * inv;
       __syncthreads();
       if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
-      else transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+      else transform_columns<NMAX, LMAX>(n, nch, LL, L1, cb, vb, lane);
       __syncthreads();
       return;
     }
@@ -842,7 +854,7 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const doubl
   // c of every species is in cb; the sink column and the channels k >= n_max are
   // zero there and stay so
   if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
-  else if (ns == 1) transform_columns<NMAX>(n, nch, LL, L1, cb, vb, lane);
+  else if (ns == 1) transform_columns<NMAX, LMAX>(n, nch, LL, L1, cb, vb, lane);
   else transform_columns_species<NMAX>(n, ns, nch, LL, L1, cb, vb, abx, lane);
   __syncthreads();
 }
