@@ -950,6 +950,79 @@ __device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, 
   }
 }
 
+// whole rounds of the adjoint take the compile-time record loop in the buckets
+// compiled for two waves per SIMD up to l_max = 10 (66 records): at four waves per
+// SIMD (128 VGPRs) it spills, and l_max = 12 (91 records) would not fit the
+// instruction cache
+template <int NMAX, int LMAX>
+constexpr bool kFullRecords = NMAX > 8 && LMAX <= 10;
+
+// adjoint_records for a whole round of one pair per lane with l_max equal to the
+// compiled bucket: the same sums in the same order, with every loop bound and
+// index fixed at compile time (record (l, m) at m (l_max + 1) - m (m - 1) / 2 +
+// l - m, c columns l^2 + l + m and l^2 + l - m, parity (l - m) mod 2), so the
+// Horner steps, the table and cbar reads and the parity selects need no runtime
+// index arithmetic, loop control or branches
+template <int NMAX, int LMAX, typename FieldFn>
+__device__ __forceinline__ void adjoint_records_full(const double* __restrict__ cb, const double* __restrict__ rc,
+                                                     FieldFn F, const double (&b)[NMAX], const double (&db)[NMAX],
+                                                     double uz, double ux, double uy, double& sr, double& sx,
+                                                     double& sy, double& sz) {
+  using S = Shape<NMAX, LMAX>;
+  constexpr int NC = S::NC;
+  const double x2 = uz * uz;
+#pragma unroll
+  for (int l = 0; l <= LMAX; ++l) {
+    const double we = F(S::FW + l), wd = F(S::FR + S::XW + l);
+    double zr = 1.0, zi = 0.0, zr1 = 1.0, zi1 = 0.0;
+#pragma unroll
+    for (int m = 0; m <= l; ++m) {
+      const int r = m * (LMAX + 1) - m * (m - 1) / 2 + (l - m), d = (l - m) >> 1;
+      const bool par = (l - m) & 1;
+      const double* __restrict__ cf = rc + r * NC;
+      double Rv = cf[d], Rd = 0.0;
+#pragma unroll
+      for (int t2 = d - 1; t2 >= 0; --t2) {
+        Rd = fma(Rd, x2, Rv);
+        Rv = fma(Rv, x2, cf[t2]);
+      }
+      const double Q = par ? uz * Rv : Rv;
+      const double Qd = par ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
+      const double* __restrict__ c0 = cb + (l * l + l + m) * NMAX;
+      if (m == 0) {
+        double U0 = 0.0, V0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+          U0 = fma(c0[k], db[k], U0);
+          V0 = fma(c0[k], b[k], V0);
+        }
+        sr = fma(Q, fma(U0, we, V0 * wd), sr);
+        sz = fma(Qd, V0 * we, sz);
+        continue;
+      }
+      zr1 = zr;
+      zi1 = zi;
+      azimuthal_step(zr, zi, ux, uy);
+      const double* __restrict__ c1 = cb + (l * l + l - m) * NMAX;
+      double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) {
+        U0 = fma(c0[k], db[k], U0);
+        V0 = fma(c0[k], b[k], V0);
+        U1 = fma(c1[k], db[k], U1);
+        V1 = fma(c1[k], b[k], V1);
+      }
+      const double fm = (double)m;
+      sr = fma(Q, fma(fma(U0, we, V0 * wd), zr, fma(U1, we, V1 * wd) * zi), sr);
+      const double W0 = V0 * we, W1 = V1 * we;
+      const double qm = Q * fm;
+      sx = fma(qm, fma(W0, zr1, W1 * zi1), sx);
+      sy = fma(qm, fma(W1, zr1, -W0 * zi1), sy);
+      sz = fma(Qd, fma(W0, zr, W1 * zi), sz);
+    }
+  }
+}
+
 // One wave per centre atom, in rounds of up to 64 pairs: a full round takes one
 // pair per lane; a round with fewer pairs left (the tail of a long list, or a
 // short list) gives each pair R = 2, 4 or 8 lanes, lane sub of a pair taking the
@@ -1047,8 +1120,11 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParam
       on = on && sj >= 0 && sj < P.ns;
       sj = on ? sj : 0;
     }
-    adjoint_records<NMAX, LMAX>(L, sub, R, cb + (size_t)sj * LLP * NMAX, rc, ri, F, b, db, uz, ux, uy, sr, sx, sy,
-                                sz);
+    const double* __restrict__ cbj = cb + (size_t)sj * LLP * NMAX;
+    if (kFullRecords<NMAX, LMAX> && R == 1 && L == LMAX)
+      adjoint_records_full<NMAX, LMAX>(cbj, rc, F, b, db, uz, ux, uy, sr, sx, sy, sz);
+    else
+      adjoint_records<NMAX, LMAX>(L, sub, R, cbj, rc, ri, F, b, db, uz, ux, uy, sr, sx, sy, sz);
     for (int o = 1; o < R; o <<= 1) {
       sr += __shfl_xor(sr, o, 64);
       sx += __shfl_xor(sx, o, 64);
