@@ -950,12 +950,10 @@ __device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, 
   }
 }
 
-// whole rounds of the adjoint take the compile-time record loop in the buckets
-// compiled for two waves per SIMD up to l_max = 10 (66 records): at four waves per
-// SIMD (128 VGPRs) it spills, and l_max = 12 (91 records) would not fit the
-// instruction cache
+// whole rounds of the adjoint take the compile-time record loop up to l_max = 10
+// (66 records); l_max = 12 (91 records) would not fit the instruction cache
 template <int NMAX, int LMAX>
-constexpr bool kFullRecords = NMAX > 8 && LMAX <= 10;
+constexpr bool kFullRecords = LMAX <= 10;
 
 // adjoint_records for a whole round of one pair per lane with l_max equal to the
 // compiled bucket: the same sums in the same order, with every loop bound and
@@ -1031,9 +1029,11 @@ __device__ __forceinline__ void adjoint_records_full(const double* __restrict__ 
 // contracts them with the cbar of the neighbour's species over its records and
 // the pair gradient g = dE/dd follows from the sums.  The wave first forms the
 // atom's cbar in LDS (form_cbar), then stages the record table; both are read
-// as broadcasts.
+// as broadcasts.  Registers: up to 168 per lane (3 waves per SIMD) in the buckets
+// up to n_max = 8, where the compile-time record loop spills at 128; the larger
+// buckets need up to 256 (2 waves per SIMD).
 template <int NMAX, int LMAX>
-__global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
+__global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
                                                                        int n_atoms, const int* __restrict__ offsets,
                                                                        int bound, const int* __restrict__ nj,
                                                                        const int* __restrict__ species,
