@@ -115,11 +115,41 @@ struct LaneColumns {
   int l[EC], m[EC], par[EC], sn[EC], lm[EC];
 };
 
-template <int EC, int NC>
+// the columns lm = l^2 + l + m' of l_max = LMAX in the order of the degree
+// (l - |m'|) / 2 of their polynomial in u_z^2, highest first, so that the lane
+// slots 64.. of a wave (the second column of every lane) need fewer Horner steps;
+// terms[e]: the polynomial terms that slots 64 e .. 64 e + 63 need
+constexpr int column_degree(int lm) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= lm) ++l;
+  const int ms = lm - l * l - l;
+  return (l - (ms < 0 ? -ms : ms)) >> 1;
+}
+
+template <int LMAX>
+struct ColumnOrder {
+  static constexpr int NCOL = (LMAX + 1) * (LMAX + 1), NG = (NCOL + 63) / 64;
+  short lm[NCOL];
+  int terms[NG];
+  constexpr ColumnOrder() : lm(), terms() {
+    int k = 0;
+    for (int d = LMAX / 2; d >= 0; --d)
+      for (int c = 0; c < NCOL; ++c)
+        if (column_degree(c) == d) lm[k++] = (short)c;
+    for (int g = 0; g < NG; ++g) terms[g] = column_degree(lm[64 * g]) + 1;
+  }
+};
+
+template <int LMAX>
+__device__ constexpr ColumnOrder<LMAX> kColumnOrder{};
+
+template <int LMAX, int EC, int NC>
 __device__ inline void lane_columns(const DevTables* __restrict__ T, int lane, int L, int LL, LaneColumns<EC, NC>& C) {
+  constexpr int NCOL = (LMAX + 1) * (LMAX + 1);
 #pragma unroll
   for (int e = 0; e < EC; ++e) {
-    const int j = lane + 64 * e;
+    const int sl = lane + 64 * e;
+    const int j = sl < NCOL ? kColumnOrder<LMAX>.lm[sl] : NCOL;
     const bool ok = j < LL;
     int l = 0;
     while (ok && (l + 1) * (l + 1) <= j) ++l;
@@ -285,6 +315,33 @@ __device__ inline void stage_fields(const double* __restrict__ rows, const int* 
   }
 }
 
+// fields 0..WIDTH-1 of the cnt consecutive pairs w0.. into registers, in the
+// order stage_prefetched stores them (field u / CH of pair u % CH for u = lane +
+// 64 k); the forward issues them one chunk ahead, so that their latency overlaps
+// the arithmetic of the chunk before
+template <int WIDTH, int ROW, int CH>
+__device__ __forceinline__ void prefetch_fields(const double* __restrict__ rows, int w0, int cnt,
+                                                double (&v)[(WIDTH * CH + 63) / 64], int lane) {
+  constexpr int ITER = (WIDTH * CH + 63) / 64;
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int u = lane + 64 * k, f = u / CH, t = u % CH, p = w0 + t;
+    const bool ok = u < WIDTH * CH && t < cnt;
+    v[k] = rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
+  }
+}
+
+template <int WIDTH, int CH, int STRIDE>
+__device__ __forceinline__ void stage_prefetched(const double (&v)[(WIDTH * CH + 63) / 64], int cnt,
+                                                 double* __restrict__ dst, int lane) {
+  constexpr int ITER = (WIDTH * CH + 63) / 64;
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int u = lane + 64 * k, f = u / CH, t = u % CH;
+    if (u < WIDTH * CH && t < cnt) dst[t * STRIDE + f] = v[k];
+  }
+}
+
 // The power spectrum P_l = C_l C_l^T of one atom (C_l: n_ch x (2l + 1), the
 // real form of Eq. (09)) on the matrix cores: BF16 operands, FP32 accumulation,
 // one v_mfma_f32_16x16x32_bf16 per 16 x 16 tile of channel pairs and per l
@@ -368,9 +425,14 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   constexpr int NE = COLS ? EC : E2, NP = COLS ? 1 : 2;
   LaneRecords<COLS ? 1 : E2, NC> R;
   LaneColumns<COLS ? EC : 1, NC> C;
-  if constexpr (COLS) lane_columns<EC, NC>(T, lane, P.l, LL, C);
+  if constexpr (COLS) lane_columns<LMAX, EC, NC>(T, lane, P.l, LL, C);
   else lane_records<E2, NC>(T, lane, S::NREC, LL, R);
 
+  // one species: the pairs are taken in order, and each chunk's fields are
+  // loaded while the chunk before is processed
+  constexpr bool PF = NMAX > 8 && LMAX <= 10;  // the registers spill in the other buckets
+  double pf[(S::FR * CH + 63) / 64];
+  if (PF && P.ns == 1 && p0 < p1) prefetch_fields<S::FR, S::ROW, CH>(rows, p0, min(CH, p1 - p0), pf, lane);
   for (int s = 0; s < P.ns; ++s) {
     double acc[NE][NP][NMAX];
 #pragma unroll
@@ -387,7 +449,12 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      stage_fields<S::FR, S::ROW, CH, FRP, 6>(rows, idx, cnt, dyn + S::LZ, lane);
+      if (PF && P.ns == 1) {
+        stage_prefetched<S::FR, CH, FRP>(pf, cnt, dyn + S::LZ, lane);
+        if (w0 + CH < p1) prefetch_fields<S::FR, S::ROW, CH>(rows, w0 + CH, min(CH, p1 - w0 - CH), pf, lane);
+      } else {
+        stage_fields<S::FR, S::ROW, CH, FRP, 6>(rows, idx, cnt, dyn + S::LZ, lane);
+      }
       __syncthreads();
       if (lane < cnt) {  // the azimuthal powers of staged pair `lane`
         double* __restrict__ zt = dyn + lane * FRP;
@@ -418,9 +485,13 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
           // the same products as the record mode (a column is one of its two parts)
 #pragma unroll
           for (int e = 0; e < EC; ++e) {
-            double Rv = C.cf[e][NC - 1];
+            // the higher coefficients of this group's columns are zero (the same
+            // bits as running over all NC terms); e is unrolled, so NT is a constant
+            constexpr ColumnOrder<LMAX> order{};
+            const int NT = e == 0 ? order.terms[0] : order.terms[ColumnOrder<LMAX>::NG - 1];
+            double Rv = C.cf[e][NT - 1];
 #pragma unroll
-            for (int t2 = NC - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, C.cf[e][t2]);
+            for (int t2 = NT - 2; t2 >= 0; --t2) Rv = fma(Rv, x2, C.cf[e][t2]);
             const double Q = C.par[e] ? uz * Rv : Rv;
             const double a = row(S::FW + C.l[e]) * Q;
             const double a0 = a * zt[2 * C.m[e] + C.sn[e]];
