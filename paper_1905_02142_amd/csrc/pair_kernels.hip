@@ -202,6 +202,14 @@ __device__ inline void azimuthal_step(double& cr, double& ci, double ux, double 
   cr = nr;
 }
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8), each
+// with its own L2.  The per-atom kernels number their atoms XCD by XCD (workgroup
+// b takes atom (b mod 8) per + b / 8 with per = ceil(n / 8)), so that atoms next
+// to each other, whose pair ranges share the cache lines at their ends, meet in
+// one L2; the grid is 8 per workgroups, and those past n do nothing.
+__host__ __device__ inline int xcd_per(int n) { return (n + 7) >> 3; }
+__device__ inline int xcd_item(int b, int n) { return (b & 7) * xcd_per(n) + (b >> 3); }
+
 // Two launches per list: PART 1 writes the radial fields (B_k, dB_k/dr) and the
 // central atom's factors, PART 2 the angular ones (w_l e_l, its derivative, u
 // and 1/r; the azimuthal powers are formed where they are used, which costs less
@@ -412,7 +420,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   extern __shared__ __align__(16) double dyn[];
   __shared__ int idx[CH];
 
-  const int i = blockIdx.x;
+  const int i = xcd_item(blockIdx.x, n_atoms);
   if (i >= n_atoms) return;
   const int lane = threadIdx.x;
   const int n = P.n, LL = P.LL, LLP = LL + 1, nch = P.nch;
@@ -1120,7 +1128,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
   using S = Shape<NMAX, LMAX>;
   constexpr int NC = S::NC;
   extern __shared__ __align__(16) double dyn[];
-  const int i = blockIdx.x;
+  const int i = xcd_item(blockIdx.x, n_atoms);
   if (i >= n_atoms) return;
   const int lane = threadIdx.x;
   const int LLP = P.LL + 1, L = P.l, nrec = (L + 1) * (L + 2) / 2;
@@ -1229,7 +1237,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
 __global__ __launch_bounds__(256) void k_force_gather(int n_atoms, const int* __restrict__ offsets, int bound,
                                                       const int* __restrict__ rev, const dvec4* __restrict__ g,
                                                       double* __restrict__ out, int accumulate_grad) {
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int k = xcd_item(blockIdx.x, (n_atoms + 3) / 4) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= n_atoms) return;
   double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -1363,7 +1371,7 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
   if (qc && qc_pitch < P.K) return hipErrorInvalidValue;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
+    hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
                        rows, bc, c, q, q_pitch, pnorm, static_cast<__bf16*>(qc), qc_pitch);
     return hipGetLastError();
   };
@@ -1379,7 +1387,7 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
   if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(n_atoms), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
+    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
                        rows, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
     return hipGetLastError();
   };
@@ -1408,7 +1416,7 @@ hipError_t launch_unit_rows(int n_rows, int K, int kset, int kclear, double* qba
 hipError_t launch_force_gather(int n_atoms, const int* offsets, int bound, const int* rev, const double* g,
                                double* out, bool accumulate_grad, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_force_gather, dim3((n_atoms + 3) / 4), dim3(256), 0, st, n_atoms, offsets, bound, rev,
+  hipLaunchKernelGGL(k_force_gather, dim3(8 * xcd_per((n_atoms + 3) / 4)), dim3(256), 0, st, n_atoms, offsets, bound, rev,
                      reinterpret_cast<const dvec4*>(g), out, accumulate_grad ? 1 : 0);
   return hipGetLastError();
 }
