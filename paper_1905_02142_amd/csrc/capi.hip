@@ -351,6 +351,20 @@ soap_status soap_create(const soap_params* p, soap_ctx** out) {
   d.ap = p->alpha_perp;
   d.a = p->a;
   d.cw = p->central_weight;
+  for (int g = 0; g < 3; ++g) {
+    // degree l has l + 1 records (l, m >= 0): longest first, each to the lane with
+    // the fewest so far (the lowest such lane on a tie)
+    const int R = 2 << g;
+    int load[8] = {};
+    for (int u = 0; u < 8; ++u) d.tail_deg[g][u] = 0;
+    for (int l = d.l; l >= 0; --l) {
+      int b = 0;
+      for (int u = 1; u < R; ++u)
+        if (load[u] < load[b]) b = u;
+      d.tail_deg[g][b] |= (unsigned short)(1u << l);
+      load[b] += l + 1;
+    }
+  }
   soap::DevTables& t = ctx->ht;
   double W[16 * 16], Wl[16 * 16];
   if (soap_host_basis_table(d.n, d.rc, d.s0r, W, Wl, nullptr) != 0 ||
@@ -759,7 +773,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     return s;
   // the unfused Qbar pass splits its contraction over the sparse points into
   // parts that the adjoint adds
-  const int slices = fused ? 1 : soap::gap_qbar_slices(M, prec, ctx->tune.gap_tile);
+  const int slices = fused ? 1 : soap::gap_qbar_slices((int)N, M, P.K, prec, ctx->tune.gap_tile);
   double* qbar = nullptr;
   if (forces) {
     SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * slices * N * P.K);

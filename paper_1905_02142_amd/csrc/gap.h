@@ -29,8 +29,9 @@ int gap_q_pitch(int K);
 // finishes e and alpha_bar (nullable) from the partial sums
 hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar,
                            const void* work, int slices, int tile, hipStream_t st);
-// the slice count launch_gap_qbar accepts and that pays off for M sparse points: 1 or 2
-int gap_qbar_slices(int M, int prec, int tile);
+// the slice count launch_gap_qbar accepts and that pays off for an N x K output
+// contracted over M sparse points: 1 or 2
+int gap_qbar_slices(int N, int M, int K, int prec, int tile);
 
 // Fused scores + Qbar (prec 1..3, padded K <= 352): e, alpha_bar (nullable) and
 // Qbar in one pass with no N x M intermediate in HBM

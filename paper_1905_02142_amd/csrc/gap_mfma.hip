@@ -1099,15 +1099,23 @@ hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, cons
   }
 }
 
-int gap_qbar_slices(int M, int prec, int tile) {
+int gap_qbar_slices(int N, int M, int K, int prec, int tile) {
   const int Mp = padded(M);
-  int kt;
+  int kt, bm, bn;
   switch (prec) {
-    case 0: kt = QbarTile<PF64>::KT; break;
-    case 1: kt = QbarTile<PF32>::KT; break;
-    case 2: kt = tile == 1 ? QbarSmallBF16::KT : QbarTile<PBF16>::KT; break;
-    default: kt = QbarTile<PBF16X3>::KT; break;
+    case 0: kt = QbarTile<PF64>::KT, bm = QbarTile<PF64>::BM, bn = QbarTile<PF64>::BN; break;
+    case 1: kt = QbarTile<PF32>::KT, bm = QbarTile<PF32>::BM, bn = QbarTile<PF32>::BN; break;
+    case 2:
+      if (tile == 1) kt = QbarSmallBF16::KT, bm = QbarSmallBF16::BM, bn = QbarSmallBF16::BN;
+      else kt = QbarTile<PBF16>::KT, bm = QbarTile<PBF16>::BM, bn = QbarTile<PBF16>::BN;
+      break;
+    default: kt = QbarTile<PBF16X3>::KT, bm = QbarTile<PBF16X3>::BM, bn = QbarTile<PBF16X3>::BN; break;
   }
+  // one slice already has eight workgroups per CU: a second would only add a
+  // second N x K part to write here and to read in the adjoint (262,144 atoms,
+  // n = l = 10: Qbar 2.17 -> 1.98 ms, adjoint 5.12 -> 5.03 ms with one slice)
+  const long long grid = (long long)((N + bm - 1) / bm) * ((K + bn - 1) / bn);
+  if (grid >= 2048) return 1;
   // two slices once each keeps at least four K-steps
   return (Mp % (2 * kt) == 0 && Mp / 2 >= 4 * kt) ? 2 : 1;
 }

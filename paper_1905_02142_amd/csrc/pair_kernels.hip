@@ -953,11 +953,11 @@ struct AdjLds {
   }
 };
 
-// the pair's contraction with the cbar of one species over the records (l, m) with
-// l = l_first, l_first + l_step, ... (l outer, m inner): S_r, S_x, S_y, S_z of
-// the gradient (partial sums when l_step > 1)
+// the pair's contraction with the cbar of one species over the records (l, m) of
+// the degrees l set in deg (l outer, ascending, m inner): S_r, S_x, S_y, S_z of
+// the gradient (partial sums when deg holds only some degrees)
 template <int NMAX, int LMAX, typename FieldFn>
-__device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, const double* __restrict__ cb,
+__device__ __forceinline__ void adjoint_records(int L, unsigned deg, const double* __restrict__ cb,
                                        const double* __restrict__ rc,
                                        const int* __restrict__ ri, FieldFn F, const double (&b)[NMAX],
                                        const double (&db)[NMAX], double uz, double ux, double uy, double& sr,
@@ -965,16 +965,18 @@ __device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, 
   using S = Shape<NMAX, LMAX>;
   constexpr int NC = S::NC;
   const double x2 = uz * uz;
-  for (int l = l_first; l <= L; l += l_step) {
+  for (unsigned dm = deg; dm; dm &= dm - 1) {
+    const int l = __builtin_ctz(dm);
     const double we = F(S::FW + l), wd = F(S::FR + S::XW + l);
-    // Qbar_lm = x^par R(x^2), R of degree (l - m) / 2: the higher table
-    // coefficients are zero, so Horner starts at the top non-zero one (the same
-    // bits as running over all NC)
-    auto qbar = [&](int r, int m, double& Q, double& Qd) {
+    // Qbar_lm = x^par R(x^2): Horner over all NC table terms, unrolled (the
+    // coefficients above degree (l - m) / 2 are zero, so the steps before the top
+    // non-zero one leave Rv = Rd = 0: the same bits as starting there)
+    auto qbar = [&](int r, double& Q, double& Qd) {
       const double* __restrict__ cf = rc + r * NC;
-      const int par = ri[4 * r], d = (l - m) >> 1;
-      double Rv = cf[d], Rd = 0.0;
-      for (int t2 = d - 1; t2 >= 0; --t2) {
+      const int par = ri[4 * r];
+      double Rv = cf[NC - 1], Rd = 0.0;
+#pragma unroll
+      for (int t2 = NC - 2; t2 >= 0; --t2) {
         Rd = fma(Rd, x2, Rv);
         Rv = fma(Rv, x2, cf[t2]);
       }
@@ -985,7 +987,7 @@ __device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, 
       // m = 0 (record r = l): only the cos column (the sin column is the sink, all
       // zeros), no azimuthal factor and no contribution to S_x, S_y
       double Q, Qd;
-      qbar(l, 0, Q, Qd);
+      qbar(l, Q, Qd);
       const double* __restrict__ c0 = cb + ri[4 * l + 1] * NMAX;
       double U0 = 0.0, V0 = 0.0;
 #pragma unroll
@@ -1004,7 +1006,7 @@ __device__ __forceinline__ void adjoint_records(int L, int l_first, int l_step, 
       const int r = m * (L + 1) - m * (m - 1) / 2 + (l - m);
       const int lc = ri[4 * r + 1], ls = ri[4 * r + 2];
       double Q, Qd;
-      qbar(r, m, Q, Qd);
+      qbar(r, Q, Qd);
       zr1 = zr;
       zi1 = zi;
       azimuthal_step(zr, zi, ux, uy);
@@ -1203,7 +1205,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
     if (kFullRecords<NMAX, LMAX> && R == 1 && L == LMAX)
       adjoint_records_full<NMAX, LMAX>(cbj, rc, F, b, db, uz, ux, uy, sr, sx, sy, sz);
     else
-      adjoint_records<NMAX, LMAX>(L, sub, R, cbj, rc, ri, F, b, db, uz, ux, uy, sr, sx, sy, sz);
+      adjoint_records<NMAX, LMAX>(L, R == 1 ? (2u << L) - 1u : (unsigned)P.tail_deg[lgR - 1][sub], cbj, rc, ri, F,
+                                  b, db, uz, ux, uy, sr, sx, sy, sz);
     for (int o = 1; o < R; o <<= 1) {
       sr += __shfl_xor(sr, o, 64);
       sx += __shfl_xor(sx, o, 64);

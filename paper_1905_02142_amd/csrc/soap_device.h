@@ -69,6 +69,10 @@ struct DevParams {
   double inv_rc;
   double s0r, s0p, ar, ap, a;
   double cw;    // central-atom weight
+  // the adjoint's partial rounds give each pair R = 2, 4, 8 lanes; lane sub takes
+  // the degrees l set in tail_deg[log2 R - 1][sub], the records of 0..l_max dealt
+  // out longest first to the least loaded lane
+  unsigned short tail_deg[3][8];
 };
 
 // The per-pair tables of one (n_max, l_max) bucket, staged in LDS once per
