@@ -263,8 +263,8 @@ struct StageTimer {
 // (c_doubles_per_atom per atom) and the central-atom factors (kMaxN doubles);
 // with `timed`, the stages record their events while profiling is on
 soap_status forward_into(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
-                         bool deriv, hipStream_t st, double* rows, double* c, double* bc, void* qc, int qc_pitch,
-                         bool timed) {
+                         bool deriv, hipStream_t st, void* rows, bool rows_f32, double* c, double* bc, void* qc,
+                         int qc_pitch, bool timed) {
   const soap::DevParams& P = ctx->dp;
   const size_t NP = (size_t)pair_bound(nl);
   const unsigned mask = ctx->prof_mask;
@@ -273,27 +273,29 @@ soap_status forward_into(soap_ctx* ctx, const soap_nlist* nl, const int32_t* spe
   for (int part = 1; part <= 2 && s == SOAP_OK; ++part) {
     StageTimer tm(ctx, part == 1 ? SOAP_STAGE_PAIR_PREP : SOAP_STAGE_PAIR_ANGULAR, st);
     const hipError_t e = soap::launch_pair_prep(P, ctx->dt, (long long)NP, pair_count(nl), nl->dx, nl->dy, nl->dz,
-                                                rows, deriv, bc, ctx->tune.prep_block, part, st);
+                                                rows, rows_f32, deriv, bc, ctx->tune.prep_block, part, st);
     if (e != hipSuccess) s = hip_fail(ctx, e, "launch_pair_prep");
   }
   if (s == SOAP_OK) {
     StageTimer tm(ctx, SOAP_STAGE_DESCRIPTOR, st);
     const hipError_t e = soap::launch_descriptor(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species, rows,
-                                                 bc, c, q, P.K, pnorm, qc, qc_pitch, st);
+                                                 rows_f32, bc, c, q, P.K, pnorm, qc, qc_pitch, st);
     if (e != hipSuccess) s = hip_fail(ctx, e, "launch_descriptor");
   }
   ctx->prof_mask = mask;
   return s;
 }
 
+// rows_f32: the pair fields stored in FP32 (the mixed modes' energy and force
+// path with the FP64 radial stage; the arithmetic stays FP64)
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
-                    bool deriv, hipStream_t st, void* qc = nullptr, int qc_pitch = 0) {
+                    bool deriv, hipStream_t st, void* qc = nullptr, int qc_pitch = 0, bool rows_f32 = false) {
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
   SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
-  SOAP_ENSURE(ctx, ctx->rows, soap::pair_rows_bytes(P, (long long)NP));
+  SOAP_ENSURE(ctx, ctx->rows, soap::pair_rows_bytes(P, (long long)NP, rows_f32));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
-  return forward_into(ctx, nl, species, q, pnorm, deriv, st, (double*)ctx->rows.p, (double*)ctx->c.p,
+  return forward_into(ctx, nl, species, q, pnorm, deriv, st, ctx->rows.p, rows_f32, (double*)ctx->c.p,
                       (double*)ctx->bc.p, qc, qc_pitch, true);
 }
 
@@ -681,7 +683,7 @@ soap_status soap_descriptor_noalloc(soap_ctx* ctx, const soap_nlist* nl, const i
   double* c = reinterpret_cast<double*>(base + b_rows);
   double* bc = reinterpret_cast<double*>(base + b_rows + b_c);
   double* pn = p_norm ? p_norm : reinterpret_cast<double*>(base + b_rows + b_c + b_bc);
-  return forward_into(ctx, nl, species, q, pn, false, st, rows, c, bc, nullptr, 0, false);
+  return forward_into(ctx, nl, species, q, pn, false, st, rows, false, c, bc, nullptr, 0, false);
 }
 
 soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, const double* q_bar,
@@ -701,7 +703,7 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                            (const double*)ctx->rows.p, (const double*)ctx->c.p,
+                                            ctx->rows.p, false, (const double*)ctx->c.p,
                                             (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, q_bar, nullptr,
                                             P.K, (double*)ctx->gx.p, nullptr, nullptr, 4, st));
   }
@@ -734,7 +736,7 @@ soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const 
     double* tile = jac + (size_t)(k - k0) * 3 * NP;
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                            (const double*)ctx->rows.p, (const double*)ctx->c.p,
+                                            ctx->rows.p, false, (const double*)ctx->c.p,
                                             (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qb, nullptr, P.K,
                                             tile, tile + NP, tile + 2 * NP, 1, st));
   }
@@ -768,8 +770,11 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
     qc = soap::gap_q_operand(prec, (int)N, M, P.K, ctx->gapw.p);
   }
+  // the mixed modes store the pair fields in FP32 (their rounding, about 6e-8
+  // relative, is far below that of the GAP operands); the arithmetic stays FP64
+  const bool rows_f32 = prec != 0 && !P.radial_dd;
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, forces != nullptr, st, qc,
-                   soap::gap_q_pitch(P.K))) != SOAP_OK)
+                   soap::gap_q_pitch(P.K), rows_f32)) != SOAP_OK)
     return s;
   // the unfused Qbar pass splits its contraction over the sparse points into
   // parts that the adjoint adds
@@ -804,7 +809,7 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     {
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                              (const double*)ctx->rows.p, (const double*)ctx->c.p,
+                                              ctx->rows.p, rows_f32, (const double*)ctx->c.p,
                                               (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qbar,
                                               slices == 2 ? qbar + N * P.K : nullptr, P.K, (double*)ctx->gx.p,
                                               nullptr, nullptr, 4, st));

@@ -21,23 +21,24 @@ size_t pair_row_doubles(const DevParams& P);
 // atom's range at the bound, so an overflowed list is read only where written.
 
 // pair rows (pair_row_doubles fields each; blocks of 64 pairs stored
-// field-major, pair_rows_bytes in all) for n_pairs neighbours (or, with count
+// field-major, pair_rows_bytes in all; FP64, or FP32 with rows_f32, which needs
+// the FP64 radial stage) for n_pairs neighbours (or, with count
 // non-null, for min(*count, n_pairs)), the derivative fields only if deriv, and
 // the central-atom radial factors bc (n_max doubles); block: threads per block
 // (64, 128 or 256); part 1: the radial fields and bc, part 2: the angular fields
 // (two launches, both needed before the descriptor)
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
-                            const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
-                            int block, int part, hipStream_t st);
-size_t pair_rows_bytes(const DevParams& P, long long n_pairs);
+                            const double* dx, const double* dy, const double* dz, void* rows, bool rows_f32,
+                            bool deriv, double* bc, int block, int part, hipStream_t st);
+size_t pair_rows_bytes(const DevParams& P, long long n_pairs, bool f32 = false);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
 // qc (nullable): a bf16 copy of q as well, row i at element i qc_pitch,
 // (bf16)(float) q_ik and zero for the columns K..qc_pitch-1
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                              const int* nj,
-                             const int* species, const double* rows, const double* bc, double* c, double* q,
-                             int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st);
+                             const int* species, const void* rows, bool rows_f32, const double* bc, double* c,
+                             double* q, int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st);
 
 // pair gradients g_p = dE/dd_p from qbar = dE/dq (n_atoms rows of
 // qbar_pitch; with qbar2 non-null, qbar + qbar2, the two parts of a sliced GAP
@@ -45,7 +46,7 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
 // is formed per atom inside the kernel.  gstride 1: three arrays gx, gy, gz;
 // gstride 4: one record (x, y, z, 0) per pair at gx + 4 p (gy, gz unused)
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
-                               const int* nj, const int* species, const double* rows, const double* c,
+                               const int* nj, const int* species, const void* rows, bool rows_f32, const double* c,
                                const double* q, int q_pitch, const double* pnorm, const double* qbar,
                                const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
                                int gstride, hipStream_t st);

@@ -217,11 +217,13 @@ __device__ inline int xcd_item(int b, int n) { return (b & 7) * xcd_per(n) + (b 
 // each half runs with the registers it needs (the double-double radial stage
 // needs about twice those of the angular one), and the two are timed apart.
 // DD: the radial stage in double-double arithmetic (radial<..., true>)
-template <int NMAX, int LMAX, bool DERIV, bool DD, int PART>
+// RT: the storage type of the pair fields (double, or float in the mixed modes,
+// where the arithmetic stays FP64 and only the stored values are rounded)
+template <int NMAX, int LMAX, bool DERIV, bool DD, int PART, typename RT>
 __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables* __restrict__ T, int bound,
                                                      const int* __restrict__ count, const double* __restrict__ dx,
                                                      const double* __restrict__ dy, const double* __restrict__ dz,
-                                                     double* __restrict__ rows, double* __restrict__ bc) {
+                                                     RT* __restrict__ rows, double* __restrict__ bc) {
   using S = Shape<NMAX, LMAX>;
   __shared__ PairTab<NMAX, LMAX> tab;
   // pairs 0..n_pairs: the bound, or the device-side count cut at the bound
@@ -250,8 +252,8 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   if (p >= n_pairs) return;
   const double r = sqrt(x * x + y * y + z * z);
   // field f of this pair: one coalesced 512-byte segment per field for each 64 pairs
-  double* __restrict__ row = rows + (size_t)(p >> 6) * (S::ROW * 64) + (p & 63);
-  auto st = [&](int f, double v) { row[f * 64] = v; };
+  RT* __restrict__ row = rows + (size_t)(p >> 6) * (S::ROW * 64) + (p & 63);
+  auto st = [&](int f, double v) { row[f * 64] = (RT)v; };
   if (!angular) {
     double B[NMAX], dB[NMAX];
 #pragma unroll
@@ -299,8 +301,8 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
 // contiguous runs in HBM.  BATCH loads per lane are issued before the first is
 // stored, so the wave waits for memory ceil(WIDTH CH / (64 BATCH)) times instead
 // of once per load; out-of-range slots read the first field of the first block.
-template <int WIDTH, int ROW, int CH, int STRIDE, int BATCH>
-__device__ inline void stage_fields(const double* __restrict__ rows, const int* idx, int cnt,
+template <int WIDTH, int ROW, int CH, int STRIDE, int BATCH, typename RT>
+__device__ inline void stage_fields(const RT* __restrict__ rows, const int* idx, int cnt,
                                     double* __restrict__ dst, int lane) {
   constexpr int ITER = (WIDTH * CH + 63) / 64;
 #pragma unroll 1
@@ -312,7 +314,7 @@ __device__ inline void stage_fields(const double* __restrict__ rows, const int* 
       const int f = u / CH, t = u % CH;
       const bool ok = k0 + k < ITER && u < WIDTH * CH && t < cnt;
       const int p = ok ? idx[t] : 0;
-      v[k] = rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
+      v[k] = (double)rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
     }
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
@@ -327,15 +329,15 @@ __device__ inline void stage_fields(const double* __restrict__ rows, const int* 
 // order stage_prefetched stores them (field u / CH of pair u % CH for u = lane +
 // 64 k); the forward issues them one chunk ahead, so that their latency overlaps
 // the arithmetic of the chunk before
-template <int WIDTH, int ROW, int CH>
-__device__ __forceinline__ void prefetch_fields(const double* __restrict__ rows, int w0, int cnt,
+template <int WIDTH, int ROW, int CH, typename RT>
+__device__ __forceinline__ void prefetch_fields(const RT* __restrict__ rows, int w0, int cnt,
                                                 double (&v)[(WIDTH * CH + 63) / 64], int lane) {
   constexpr int ITER = (WIDTH * CH + 63) / 64;
 #pragma unroll
   for (int k = 0; k < ITER; ++k) {
     const int u = lane + 64 * k, f = u / CH, t = u % CH, p = w0 + t;
     const bool ok = u < WIDTH * CH && t < cnt;
-    v[k] = rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
+    v[k] = (double)rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
   }
 }
 
@@ -404,12 +406,12 @@ __host__ __device__ inline bool fwd_p_in_lds(const DevParams& P) {
   return need <= S::CH * S::FRP || need * (int)sizeof(double) <= 16384;
 }
 
-template <int NMAX, int LMAX>
+template <int NMAX, int LMAX, typename RT>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams P, const DevTables* __restrict__ T,
                                                                      int n_atoms, const int* __restrict__ offsets,
                                                                      int bound, const int* __restrict__ nj,
                                                                      const int* __restrict__ species,
-                                                                     const double* __restrict__ rows,
+                                                                     const RT* __restrict__ rows,
                                                                      const double* __restrict__ bc_in,
                                                                      double* __restrict__ c_out,
                                                                      double* __restrict__ q_out, int q_pitch,
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   // loaded while the chunk before is processed
   constexpr bool PF = NMAX > 8 && LMAX <= 10;  // the registers spill in the other buckets
   double pf[(S::FR * CH + 63) / 64];
-  if (PF && P.ns == 1 && p0 < p1) prefetch_fields<S::FR, S::ROW, CH>(rows, p0, min(CH, p1 - p0), pf, lane);
+  if (PF && P.ns == 1 && p0 < p1) prefetch_fields<S::FR, S::ROW, CH, RT>(rows, p0, min(CH, p1 - p0), pf, lane);
   for (int s = 0; s < P.ns; ++s) {
     double acc[NE][NP][NMAX];
 #pragma unroll
@@ -459,9 +461,9 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       __syncthreads();
       if (PF && P.ns == 1) {
         stage_prefetched<S::FR, CH, FRP>(pf, cnt, dyn + S::LZ, lane);
-        if (w0 + CH < p1) prefetch_fields<S::FR, S::ROW, CH>(rows, w0 + CH, min(CH, p1 - w0 - CH), pf, lane);
+        if (w0 + CH < p1) prefetch_fields<S::FR, S::ROW, CH, RT>(rows, w0 + CH, min(CH, p1 - w0 - CH), pf, lane);
       } else {
-        stage_fields<S::FR, S::ROW, CH, FRP, 6>(rows, idx, cnt, dyn + S::LZ, lane);
+        stage_fields<S::FR, S::ROW, CH, FRP, 6, RT>(rows, idx, cnt, dyn + S::LZ, lane);
       }
       __syncthreads();
       if (lane < cnt) {  // the azimuthal powers of staged pair `lane`
@@ -1113,12 +1115,12 @@ __device__ __forceinline__ void adjoint_records_full(const double* __restrict__ 
 // as broadcasts.  Registers: up to 168 per lane (3 waves per SIMD) in the buckets
 // up to n_max = 8, where the compile-time record loop spills at 128; the larger
 // buckets need up to 256 (2 waves per SIMD).
-template <int NMAX, int LMAX>
+template <int NMAX, int LMAX, typename RT>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
                                                                        int n_atoms, const int* __restrict__ offsets,
                                                                        int bound, const int* __restrict__ nj,
                                                                        const int* __restrict__ species,
-                                                                       const double* __restrict__ rows,
+                                                                       const RT* __restrict__ rows,
                                                                        const double* __restrict__ c,
                                                                        const double* __restrict__ q, int q_pitch,
                                                                        const double* __restrict__ pnorm,
@@ -1183,8 +1185,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
     pb += 64 >> lgR;
     const bool live = p < p1;
     const int pq = live ? p : p0;  // idle lanes read a valid row
-    const double* __restrict__ row = rows + (size_t)(pq >> 6) * (S::ROW * 64) + (pq & 63);
-    auto F = [&](int f) { return row[f * 64]; };
+    const RT* __restrict__ row = rows + (size_t)(pq >> 6) * (S::ROW * 64) + (pq & 63);
+    auto F = [&](int f) { return (double)row[f * 64]; };
     double b[NMAX], db[NMAX];
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
@@ -1327,9 +1329,9 @@ size_t c_doubles_per_atom(const DevParams& P) {
 size_t pair_row_doubles(const DevParams& P) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return (size_t)Shape<N, LM>::ROW; });
 }
-size_t pair_rows_bytes(const DevParams& P, long long n_pairs) {
+size_t pair_rows_bytes(const DevParams& P, long long n_pairs, bool f32) {
   const size_t blocks = (size_t)((n_pairs + 63) / 64);
-  return sizeof(double) * (blocks > 0 ? blocks : 1) * 64 * pair_row_doubles(P);
+  return (f32 ? sizeof(float) : sizeof(double)) * (blocks > 0 ? blocks : 1) * 64 * pair_row_doubles(P);
 }
 
 size_t descriptor_lds_bytes(const DevParams& P) {
@@ -1338,28 +1340,42 @@ size_t descriptor_lds_bytes(const DevParams& P) {
 size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P); }
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
-                            const double* dx, const double* dy, const double* dz, double* rows, bool deriv, double* bc,
-                            int block, int part, hipStream_t st) {
+                            const double* dx, const double* dy, const double* dz, void* rows_v, bool rows_f32,
+                            bool deriv, double* bc, int block, int part, hipStream_t st) {
   if (block != 64 && block != 128) block = 256;
   if (part != 1 && part != 2) return hipErrorInvalidValue;
+  if (rows_f32 && P.radial_dd) return hipErrorInvalidValue;  // FP32 rows only with the FP64 radial stage
   // one workgroup per block of pairs; block 0 of the radial launch also writes bc
   const int blocks = (int)((n_pairs + block - 1) / block) + (n_pairs == 0 ? 1 : 0);
   auto f = [&]<int N, int LM>() {
     const int np = (int)n_pairs;
     const dim3 g(blocks), b(block);
+    if (rows_f32) {
+      float* rf = static_cast<float*>(rows_v);
+      if (part == 2 && deriv)
+        hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 2, float>), g, b, 0, st, P, T, np, count, dx, dy, dz, rf, bc);
+      else if (part == 2)
+        hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 2, float>), g, b, 0, st, P, T, np, count, dx, dy, dz, rf, bc);
+      else if (deriv)
+        hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 1, float>), g, b, 0, st, P, T, np, count, dx, dy, dz, rf, bc);
+      else
+        hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 1, float>), g, b, 0, st, P, T, np, count, dx, dy, dz, rf, bc);
+      return hipGetLastError();
+    }
+    double* rows = static_cast<double*>(rows_v);
     if (part == 2) {
       if (deriv)
-        hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 2>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+        hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 2, double>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
       else
-        hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 2>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+        hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 2, double>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
     } else if (deriv && P.radial_dd) {
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, true, 1, double>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
     } else if (deriv) {
-      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, true, false, 1, double>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
     } else if (P.radial_dd) {
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, true, 1, double>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
     } else {
-      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 1>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
+      hipLaunchKernelGGL((k_pair_prep<N, LM, false, false, 1, double>), g, b, 0, st, P, T, np, count, dx, dy, dz, rows, bc);
     }
     return hipGetLastError();
   };
@@ -1368,21 +1384,27 @@ hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_
 
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                              const int* nj,
-                             const int* species, const double* rows, const double* bc, double* c, double* q,
-                             int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st) {
+                             const int* species, const void* rows, bool rows_f32, const double* bc, double* c,
+                             double* q, int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   if (qc && qc_pitch < P.K) return hipErrorInvalidValue;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_descriptor<N, LM>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
-                       rows, bc, c, q, q_pitch, pnorm, static_cast<__bf16*>(qc), qc_pitch);
+    if (rows_f32)
+      hipLaunchKernelGGL((k_descriptor<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms,
+                         offsets, bound, nj, species, static_cast<const float*>(rows), bc, c, q, q_pitch, pnorm,
+                         static_cast<__bf16*>(qc), qc_pitch);
+    else
+      hipLaunchKernelGGL((k_descriptor<N, LM, double>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms,
+                         offsets, bound, nj, species, static_cast<const double*>(rows), bc, c, q, q_pitch, pnorm,
+                         static_cast<__bf16*>(qc), qc_pitch);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
-                               const int* nj, const int* species, const double* rows, const double* c,
+                               const int* nj, const int* species, const void* rows, bool rows_f32, const double* c,
                                const double* q, int q_pitch, const double* pnorm, const double* qbar,
                                const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
                                int gstride, hipStream_t st) {
@@ -1390,8 +1412,14 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
   if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    hipLaunchKernelGGL((k_pair_adjoint<N, LM>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms, offsets, bound, nj, species,
-                       rows, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
+    if (rows_f32)
+      hipLaunchKernelGGL((k_pair_adjoint<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
+                         n_atoms, offsets, bound, nj, species, static_cast<const float*>(rows), c, q, q_pitch, pnorm,
+                         qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
+    else
+      hipLaunchKernelGGL((k_pair_adjoint<N, LM, double>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
+                         n_atoms, offsets, bound, nj, species, static_cast<const double*>(rows), c, q, q_pitch, pnorm,
+                         qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
