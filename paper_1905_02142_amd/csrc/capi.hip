@@ -263,7 +263,7 @@ struct StageTimer {
 // (c_doubles_per_atom per atom) and the central-atom factors (kMaxN doubles);
 // with `timed`, the stages record their events while profiling is on
 soap_status forward_into(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
-                         bool deriv, hipStream_t st, void* rows, bool rows_f32, double* c, double* bc, void* qc,
+                         bool deriv, hipStream_t st, void* rows, bool rows_f32, void* c, double* bc, void* qc,
                          int qc_pitch, bool timed) {
   const soap::DevParams& P = ctx->dp;
   const size_t NP = (size_t)pair_bound(nl);
@@ -286,17 +286,17 @@ soap_status forward_into(soap_ctx* ctx, const soap_nlist* nl, const int32_t* spe
   return s;
 }
 
-// rows_f32: the pair fields stored in FP32 (the mixed modes' energy and force
-// path with the FP64 radial stage; the arithmetic stays FP64)
+// store_f32: the pair fields and c stored in FP32 (the mixed modes' energy and
+// force path with the FP64 radial stage; the arithmetic stays FP64)
 soap_status forward(soap_ctx* ctx, const soap_nlist* nl, const int32_t* species, double* q, double* pnorm,
-                    bool deriv, hipStream_t st, void* qc = nullptr, int qc_pitch = 0, bool rows_f32 = false) {
+                    bool deriv, hipStream_t st, void* qc = nullptr, int qc_pitch = 0, bool store_f32 = false) {
   const soap::DevParams& P = ctx->dp;
   const size_t N = (size_t)nl->n_atoms, NP = (size_t)pair_bound(nl);
-  SOAP_ENSURE(ctx, ctx->c, sizeof(double) * N * soap::c_doubles_per_atom(P));
-  SOAP_ENSURE(ctx, ctx->rows, soap::pair_rows_bytes(P, (long long)NP, rows_f32));
+  SOAP_ENSURE(ctx, ctx->c, (store_f32 ? sizeof(float) : sizeof(double)) * N * soap::c_doubles_per_atom(P));
+  SOAP_ENSURE(ctx, ctx->rows, soap::pair_rows_bytes(P, (long long)NP, store_f32));
   SOAP_ENSURE(ctx, ctx->bc, sizeof(double) * soap::kMaxN);
-  return forward_into(ctx, nl, species, q, pnorm, deriv, st, ctx->rows.p, rows_f32, (double*)ctx->c.p,
-                      (double*)ctx->bc.p, qc, qc_pitch, true);
+  return forward_into(ctx, nl, species, q, pnorm, deriv, st, ctx->rows.p, store_f32, ctx->c.p, (double*)ctx->bc.p, qc,
+                      qc_pitch, true);
 }
 
 }  // namespace
@@ -703,7 +703,7 @@ soap_status soap_descriptor_grad(soap_ctx* ctx, const soap_nlist* nl, const int3
   {
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                            ctx->rows.p, false, (const double*)ctx->c.p,
+                                            ctx->rows.p, false, ctx->c.p,
                                             (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, q_bar, nullptr,
                                             P.K, (double*)ctx->gx.p, nullptr, nullptr, 4, st));
   }
@@ -736,7 +736,7 @@ soap_status soap_descriptor_jacobian(soap_ctx* ctx, const soap_nlist* nl, const 
     double* tile = jac + (size_t)(k - k0) * 3 * NP;
     StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
     SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                            ctx->rows.p, false, (const double*)ctx->c.p,
+                                            ctx->rows.p, false, ctx->c.p,
                                             (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qb, nullptr, P.K,
                                             tile, tile + NP, tile + 2 * NP, 1, st));
   }
@@ -770,26 +770,28 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     SOAP_ENSURE(ctx, ctx->gapw, soap::gap_workspace_bytes((int)N, M, P.K, prec));
     qc = soap::gap_q_operand(prec, (int)N, M, P.K, ctx->gapw.p);
   }
-  // the mixed modes store the pair fields in FP32 (their rounding, about 6e-8
-  // relative, is far below that of the GAP operands); the arithmetic stays FP64
-  const bool rows_f32 = prec != 0 && !P.radial_dd;
+  // the mixed modes store the pair fields, c and Qbar in FP32 (their rounding,
+  // about 6e-8 relative, is far below that of the GAP operands; Qbar is an FP32
+  // accumulator there anyway); the arithmetic stays FP64
+  const bool store_f32 = prec != 0 && !P.radial_dd;
+  const size_t es = store_f32 ? sizeof(float) : sizeof(double);
   if ((s = forward(ctx, nl, species, (double*)ctx->q.p, (double*)ctx->pnorm.p, forces != nullptr, st, qc,
-                   soap::gap_q_pitch(P.K), rows_f32)) != SOAP_OK)
+                   soap::gap_q_pitch(P.K), store_f32)) != SOAP_OK)
     return s;
   // the unfused Qbar pass splits its contraction over the sparse points into
   // parts that the adjoint adds
   const int slices = fused ? 1 : soap::gap_qbar_slices((int)N, M, P.K, prec, ctx->tune.gap_tile);
-  double* qbar = nullptr;
+  void* qbar = nullptr;
   if (forces) {
-    SOAP_ENSURE(ctx, ctx->qbar, sizeof(double) * slices * N * P.K);
-    qbar = (double*)ctx->qbar.p;
+    SOAP_ENSURE(ctx, ctx->qbar, es * slices * N * P.K);
+    qbar = ctx->qbar.p;
   }
   if (fused) {
     const int target = ctx->tune.gap_slices > 0 ? ctx->tune.gap_slices : 512;
     SOAP_ENSURE(ctx, ctx->gapw, soap::gap_fused_workspace_bytes((int)N, M, P.K, prec, target));
     StageTimer tm(ctx, SOAP_STAGE_GAP_FUSED, st);
     SOAP_HIP(ctx, soap::launch_gap_fused(prec, (int)N, M, P.K, (const double*)ctx->q.p, q_sparse, alpha, zeta, e_atom,
-                                         alpha_grad, qbar, ctx->gapw.p, target, st));
+                                         alpha_grad, qbar, store_f32, ctx->gapw.p, target, st));
   } else {
     {
       StageTimer tm(ctx, SOAP_STAGE_GAP_SCORES, st);
@@ -800,8 +802,8 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     }
     if (qbar) {
       StageTimer tm(ctx, SOAP_STAGE_GAP_QBAR, st);
-      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, e_atom, alpha_grad, ctx->gapw.p, slices,
-                                          ctx->tune.gap_tile, st));
+      SOAP_HIP(ctx, soap::launch_gap_qbar(prec, (int)N, M, P.K, qbar, store_f32, e_atom, alpha_grad, ctx->gapw.p,
+                                          slices, ctx->tune.gap_tile, st));
     }
   }
   if (forces) {
@@ -809,10 +811,10 @@ soap_status gap_energy_forces(soap_ctx* ctx, const soap_nlist* nl, const int32_t
     {
       StageTimer tm(ctx, SOAP_STAGE_PAIR_ADJOINT, st);
       SOAP_HIP(ctx, soap::launch_pair_adjoint(P, ctx->dt, nl->n_atoms, nl->offsets, (int)NP, nl->j, species,
-                                              ctx->rows.p, rows_f32, (const double*)ctx->c.p,
-                                              (const double*)ctx->q.p, P.K, (const double*)ctx->pnorm.p, qbar,
-                                              slices == 2 ? qbar + N * P.K : nullptr, P.K, (double*)ctx->gx.p,
-                                              nullptr, nullptr, 4, st));
+                                              ctx->rows.p, store_f32, ctx->c.p, (const double*)ctx->q.p, P.K,
+                                              (const double*)ctx->pnorm.p, qbar,
+                                              slices == 2 ? (char*)qbar + es * N * P.K : nullptr, P.K,
+                                              (double*)ctx->gx.p, nullptr, nullptr, 4, st));
     }
     StageTimer tm(ctx, SOAP_STAGE_FORCE_GATHER, st);
     SOAP_HIP(ctx, soap::launch_force_gather(nl->n_atoms, nl->offsets, (int)NP, nl->rev, (const double*)ctx->gx.p,

@@ -26,8 +26,9 @@ int gap_q_pitch(int K);
 // parts (Qbar + s N K, s < slices, each N x K) that sum to it: part s contracts
 // over the sparse points s Mp / slices .. (s + 1) Mp / slices - 1, which
 // multiplies the workgroups of this long contraction.  With e non-null it also
-// finishes e and alpha_bar (nullable) from the partial sums
-hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar,
+// finishes e and alpha_bar (nullable) from the partial sums.  Qbar is FP32 with
+// f32 (the modes that accumulate in FP32; not prec 0), FP64 otherwise
+hipError_t launch_gap_qbar(int prec, int N, int M, int K, void* Qbar, bool f32, double* e, double* alpha_bar,
                            const void* work, int slices, int tile, hipStream_t st);
 // the slice count launch_gap_qbar accepts and that pays off for an N x K output
 // contracted over M sparse points: 1 or 2
@@ -38,8 +39,9 @@ int gap_qbar_slices(int N, int M, int K, int prec, int tile);
 bool gap_fused_supported(int K, int prec);
 // target: number of workgroups the sparse-set slices should fill
 size_t gap_fused_workspace_bytes(int N, int M, int K, int prec, int target);
+// Qbar: FP32 with f32, FP64 otherwise
 hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, int target,
+                            int zeta, double* e, double* alpha_bar, void* Qbar, bool f32, void* work, int target,
                             hipStream_t st);
 
 }  // namespace soap

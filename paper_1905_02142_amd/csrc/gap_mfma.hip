@@ -516,12 +516,13 @@ __device__ inline double ordered_sum(const double* __restrict__ part, int n, int
 }
 
 // Qbar tile = G (N x Mp) Q_s^T-converted (Kp x Mp)^T, written for descriptor columns < K
-template <typename P>
+// OT: the storage type of Qbar (double, or float for the FP32 accumulators)
+template <typename P, typename OT>
 __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, int kslice,
                                               const typename P::T* __restrict__ G,
                                               const typename P::T* __restrict__ G_lo,
                                               const typename P::T* __restrict__ QsT,
-                                              const typename P::T* __restrict__ QsT_lo, double* __restrict__ Qbar,
+                                              const typename P::T* __restrict__ QsT_lo, OT* __restrict__ Qbar,
                                               int M, int nte, const double* __restrict__ e_part,
                                               double* __restrict__ e, int nta, const double* __restrict__ ab_part,
                                               double* __restrict__ ab) {
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, int 
   // (z + 1) kslice - 1, into its own N x K part of Qbar
   const int z = blockIdx.z, k0 = z * kslice;
   gemm_tile<P>(sm, G + k0, G_lo + k0, Mp, N, QsT + k0, QsT_lo + k0, Mp, Kp, kslice, i0, c0, acc);
-  double* __restrict__ Qz = Qbar + (size_t)z * N * K;
+  OT* __restrict__ Qz = Qbar + (size_t)z * N * K;
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
@@ -550,7 +551,7 @@ __global__ __launch_bounds__(256) void k_qbar(int N, int K, int Mp, int Kp, int 
       for (int r = 0; r < 4; ++r) {
         const int gi = i0 + wm * (P::BM / 2) + acc_row<P>(x, r, lane);
         const int gc = c0 + wn * (P::BN / 2) + y * 16 + (lane & 15);
-        if (gi < N && gc < K) Qz[(size_t)gi * K + gc] = (double)acc[x][y][r];
+        if (gi < N && gc < K) Qz[(size_t)gi * K + gc] = (OT)acc[x][y][r];
       }
   // the scores pass's per-tile partial sums, finished here (e non-null) by the
   // first slice: each workgroup takes one part of the N + M outputs, each
@@ -698,7 +699,7 @@ struct RegTile {
   }
 };
 
-template <typename F>
+template <typename F, typename OT>
 __global__ __launch_bounds__(256) void k_gap_fused(int N, int M, int K, int Kf, int Mp, int chunks_per_slice,
                                                    const double* __restrict__ Q,
                                                    const typename F::T* __restrict__ QsC,
@@ -707,7 +708,7 @@ __global__ __launch_bounds__(256) void k_gap_fused(int N, int M, int K, int Kf, 
                                                    const typename F::T* __restrict__ QsT_lo,
                                                    const double* __restrict__ alpha, int zeta,
                                                    double* __restrict__ e_out, float* __restrict__ qbar_part,
-                                                   double* __restrict__ qbar_out, double* __restrict__ ab_part) {
+                                                   OT* __restrict__ qbar_out, double* __restrict__ ab_part) {
   using T = typename F::T;
   using Sm = FusedSmem<F>;
   constexpr int BM = F::BM, BN = F::BN, TMs = BM / 32, TNs = BN / 32, TMq = BM / 16;
@@ -845,7 +846,7 @@ __global__ __launch_bounds__(256) void k_gap_fused(int N, int M, int K, int Kf, 
         const int row = 16 * x + 4 * (lane >> 4) + r;
         const int col = wv * 16 * kFusedTNq + 16 * y + (lane & 15);
         if (i0 + row < N && col < K) {
-          if (nsp == 1) qbar_out[(size_t)(i0 + row) * K + col] = (double)aq[x][y][r];
+          if (nsp == 1) qbar_out[(size_t)(i0 + row) * K + col] = (OT)aq[x][y][r];
           else qbar_part[((size_t)sp * N + i0 + row) * K + col] = aq[x][y][r];
         }
       }
@@ -853,15 +854,16 @@ __global__ __launch_bounds__(256) void k_gap_fused(int N, int M, int K, int Kf, 
 
 // e[i] = sum_sp e_part[sp][i]; Qbar = sum_sp qbar_part[sp] (when nsp > 1); ab[s] = sum_rb ab_part[rb][s],
 // all in a fixed order
+template <typename OT>
 __global__ void k_gap_reduce(int N, int K, int M, int nsp, int nrb, const double* __restrict__ e_part,
                              const float* __restrict__ qbar_part, const double* __restrict__ ab_part,
-                             double* __restrict__ e, double* __restrict__ qbar, double* __restrict__ ab) {
+                             double* __restrict__ e, OT* __restrict__ qbar, double* __restrict__ ab) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nq = nsp > 1 ? (long long)N * K : 0;
   if (t < nq) {
     double v = 0.0;
     for (int s = 0; s < nsp; ++s) v += (double)qbar_part[(size_t)s * N * K + t];
-    qbar[t] = v;
+    qbar[t] = (OT)v;
   } else if (t < nq + N) {
     const int i = (int)(t - nq);
     double v = 0.0;
@@ -911,9 +913,9 @@ FusedLayout fused_layout(int N, int M, int K, int target) {
   return L;
 }
 
-template <typename F>
+template <typename F, typename OT>
 hipError_t fused_impl(int N, int M, int K, const double* Q, const double* Qs, const double* alpha, int zeta, double* e,
-                      double* alpha_bar, double* Qbar, void* work, int target, hipStream_t st) {
+                      double* alpha_bar, OT* Qbar, void* work, int target, hipStream_t st) {
   using T = typename F::T;
   const FusedLayout L = fused_layout<F>(N, M, K, target);
   char* w = (char*)work;
@@ -925,11 +927,11 @@ hipError_t fused_impl(int N, int M, int K, const double* Q, const double* Qs, co
                      L.Kf, Qs, qsc, qsc_lo);
   hipLaunchKernelGGL((k_convert<T, F::kSplit, true>), blocks((long long)L.Kf * L.Mp), dim3(256), 0, st, M, K, L.Kf,
                      L.Mp, Qs, qst, qst_lo);
-  hipLaunchKernelGGL(k_gap_fused<F>, dim3(L.nrb, L.nsp), dim3(256), sizeof(FusedSmem<F>), st, N, M, K, L.Kf, L.Mp,
+  hipLaunchKernelGGL((k_gap_fused<F, OT>), dim3(L.nrb, L.nsp), dim3(256), sizeof(FusedSmem<F>), st, N, M, K, L.Kf, L.Mp,
                      L.cps, Q, qsc, qsc_lo, qst, qst_lo, alpha, zeta, e_part, qbar_part, Qbar, ab_part);
   const long long nred = (L.nsp > 1 ? (long long)N * K : 0) + N + M;
-  hipLaunchKernelGGL(k_gap_reduce, blocks(nred), dim3(256), 0, st, N, K, M, L.nsp, L.nrb, e_part, qbar_part, ab_part,
-                     e, Qbar, alpha_bar);
+  hipLaunchKernelGGL(k_gap_reduce<OT>, blocks(nred), dim3(256), 0, st, N, K, M, L.nsp, L.nrb, e_part, qbar_part,
+                     ab_part, e, Qbar, alpha_bar);
   return hipGetLastError();
 }
 
@@ -1009,8 +1011,8 @@ hipError_t scores_impl(int N, int M, int K, const double* Q, const double* Qs, c
 // P: the scores pass's policy (its tile counts index the partial sums), Q: the
 // Qbar pass's tile
 template <typename P, typename Q = QbarTile<P>>
-hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work, int slices,
-                     hipStream_t st) {
+hipError_t qbar_impl(int N, int M, int K, void* Qbar, bool f32, double* e, double* alpha_bar, const void* work,
+                     int slices, hipStream_t st) {
   using T = typename P::T;
   const Layout L = layout<P>(N, M, K);
   const char* w = (const char*)work;
@@ -1022,16 +1024,25 @@ hipError_t qbar_impl(int N, int M, int K, double* Qbar, double* e, double* alpha
   const double* ab_part = (const double*)(w + L.ab_part);
   const int nst = Mp / P::BN, nsi = (N + P::BM - 1) / P::BM;  // the scores pass's tile counts
   if (slices < 1 || Mp % (slices * Q::KT) != 0) return hipErrorInvalidValue;
-  static bool attr = false;  // operand tiles above 64 KB of LDS need the opt-in
-  if (!attr && sizeof(Smem<Q>) > 65536) {
-    const hipError_t a = hipFuncSetAttribute((const void*)k_qbar<Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)sizeof(Smem<Q>));
-    if (a != hipSuccess) return a;
+  auto run = [&]<typename OT>() {
+    static bool attr = false;  // operand tiles above 64 KB of LDS need the opt-in
+    if (!attr && sizeof(Smem<Q>) > 65536) {
+      const hipError_t a = hipFuncSetAttribute((const void*)k_qbar<Q, OT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)sizeof(Smem<Q>));
+      if (a != hipSuccess) return a;
+    }
+    attr = true;
+    hipLaunchKernelGGL((k_qbar<Q, OT>), dim3(nct, nit, slices), dim3(256), sizeof(Smem<Q>), st, N, K, Mp, Kp,
+                       Mp / slices, G, G_lo, qst, qst_lo, static_cast<OT*>(Qbar), M, nst, e_part, e, nsi, ab_part,
+                       alpha_bar);
+    return hipGetLastError();
+  };
+  if constexpr (sizeof(T) == 8) {  // FP64 operands accumulate in FP64
+    if (f32) return hipErrorInvalidValue;
+    return run.template operator()<double>();
+  } else {
+    return f32 ? run.template operator()<float>() : run.template operator()<double>();
   }
-  attr = true;
-  hipLaunchKernelGGL(k_qbar<Q>, dim3(nct, nit, slices), dim3(256), sizeof(Smem<Q>), st, N, K, Mp, Kp, Mp / slices, G, G_lo, qst,
-                     qst_lo, Qbar, M, nst, e_part, e, nsi, ab_part, alpha_bar);
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -1079,18 +1090,21 @@ size_t gap_fused_workspace_bytes(int N, int M, int K, int prec, int target) {
 }
 
 hipError_t launch_gap_fused(int prec, int N, int M, int K, const double* Q, const double* Qs, const double* alpha,
-                            int zeta, double* e, double* alpha_bar, double* Qbar, void* work, int target,
+                            int zeta, double* e, double* alpha_bar, void* Qbar, bool f32, void* work, int target,
                             hipStream_t st) {
   if (N == 0) return hipSuccess;
-  static bool attr_set[4] = {false, false, false, false};
+  static bool attr_set[4][2] = {};
   auto run = [&]<typename F>() {
-    if (!attr_set[prec]) {  // opt in to more than 64 KB of LDS per workgroup
-      hipError_t a = hipFuncSetAttribute((const void*)k_gap_fused<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)sizeof(FusedSmem<F>));
-      if (a != hipSuccess) return a;
-      attr_set[prec] = true;
-    }
-    return fused_impl<F>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, Qbar, work, target, st);
+    auto go = [&]<typename OT>() {
+      if (!attr_set[prec][sizeof(OT) == 4]) {  // opt in to more than 64 KB of LDS per workgroup
+        hipError_t a = hipFuncSetAttribute((const void*)k_gap_fused<F, OT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(FusedSmem<F>));
+        if (a != hipSuccess) return a;
+        attr_set[prec][sizeof(OT) == 4] = true;
+      }
+      return fused_impl<F, OT>(N, M, K, Q, Qs, alpha, zeta, e, alpha_bar, static_cast<OT*>(Qbar), work, target, st);
+    };
+    return f32 ? go.template operator()<float>() : go.template operator()<double>();
   };
   switch (prec) {
     case 1: return run.template operator()<FF32>();
@@ -1120,18 +1134,18 @@ int gap_qbar_slices(int N, int M, int K, int prec, int tile) {
   return (Mp % (2 * kt) == 0 && Mp / 2 >= 4 * kt) ? 2 : 1;
 }
 
-hipError_t launch_gap_qbar(int prec, int N, int M, int K, double* Qbar, double* e, double* alpha_bar, const void* work,
-                           int slices, int tile, hipStream_t st) {
+hipError_t launch_gap_qbar(int prec, int N, int M, int K, void* Qbar, bool f32, double* e, double* alpha_bar,
+                           const void* work, int slices, int tile, hipStream_t st) {
   if (N == 0) return hipSuccess;
   switch (prec) {
-    case 0: return qbar_impl<PF64>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
-    case 1: return qbar_impl<PF32>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+    case 0: return qbar_impl<PF64>(N, M, K, Qbar, f32, e, alpha_bar, work, slices, st);
+    case 1: return qbar_impl<PF32>(N, M, K, Qbar, f32, e, alpha_bar, work, slices, st);
     case 2:
       // both scores tiles are 128 x 128, so the partial sums are indexed alike
       static_assert(PBF16::BM == PBF16D::BM && PBF16::BN == PBF16D::BN, "scores tiles of one shape");
-      if (tile == 1) return qbar_impl<PBF16, QbarSmallBF16>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
-      return qbar_impl<PBF16>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
-    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, e, alpha_bar, work, slices, st);
+      if (tile == 1) return qbar_impl<PBF16, QbarSmallBF16>(N, M, K, Qbar, f32, e, alpha_bar, work, slices, st);
+      return qbar_impl<PBF16>(N, M, K, Qbar, f32, e, alpha_bar, work, slices, st);
+    default: return qbar_impl<PBF16X3>(N, M, K, Qbar, f32, e, alpha_bar, work, slices, st);
   }
 }
 

@@ -34,21 +34,23 @@ size_t pair_rows_bytes(const DevParams& P, long long n_pairs, bool f32 = false);
 
 // c (n_atoms x c_doubles_per_atom), q (n_atoms rows of q_pitch >= K, zero beyond K) and |p|
 // qc (nullable): a bf16 copy of q as well, row i at element i qc_pitch,
-// (bf16)(float) q_ik and zero for the columns K..qc_pitch-1
+// (bf16)(float) q_ik and zero for the columns K..qc_pitch-1.  store_f32: the
+// pair rows are read and c is written in FP32 (double otherwise); q stays FP64
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                              const int* nj,
-                             const int* species, const void* rows, bool rows_f32, const double* bc, double* c,
+                             const int* species, const void* rows, bool store_f32, const double* bc, void* c,
                              double* q, int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st);
 
 // pair gradients g_p = dE/dd_p from qbar = dE/dq (n_atoms rows of
 // qbar_pitch; with qbar2 non-null, qbar + qbar2, the two parts of a sliced GAP
 // contraction), the forward c, q, |p| and the pair rows with derivatives; cbar
 // is formed per atom inside the kernel.  gstride 1: three arrays gx, gy, gz;
-// gstride 4: one record (x, y, z, 0) per pair at gx + 4 p (gy, gz unused)
+// gstride 4: one record (x, y, z, 0) per pair at gx + 4 p (gy, gz unused).
+// store_f32: the pair rows, c, qbar and qbar2 are FP32 (double otherwise)
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
-                               const int* nj, const int* species, const void* rows, bool rows_f32, const double* c,
-                               const double* q, int q_pitch, const double* pnorm, const double* qbar,
-                               const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
+                               const int* nj, const int* species, const void* rows, bool store_f32, const void* c,
+                               const double* q, int q_pitch, const double* pnorm, const void* qbar,
+                               const void* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
                                int gstride, hipStream_t st);
 
 // angular records (Qbar_lm polynomials) and ilexp series tables for these parameters

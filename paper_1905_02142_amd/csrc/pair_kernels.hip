@@ -296,6 +296,19 @@ __global__ __launch_bounds__(256) void k_pair_prep(DevParams P, const DevTables*
   }
 }
 
+// two consecutive FP64 values to or from storage of type double or float (the
+// mixed modes store the pair fields, c and qbar of the energy and force path in
+// FP32; the arithmetic stays FP64)
+__device__ __forceinline__ void store_pair(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+__device__ __forceinline__ void store_pair(float* p, double2 v) {
+  *reinterpret_cast<float2*>(p) = float2{(float)v.x, (float)v.y};
+}
+__device__ __forceinline__ double2 load_pair(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ double2 load_pair(const float* p) {
+  const float2 f = *reinterpret_cast<const float2*>(p);
+  return double2{(double)f.x, (double)f.y};
+}
+
 // fields 0..WIDTH-1 of the compacted pairs idx[0..cnt) copied into LDS rows,
 // dst[t * STRIDE + f]; for consecutive pairs each field is one or two
 // contiguous runs in HBM.  BATCH loads per lane are issued before the first is
@@ -406,14 +419,14 @@ __host__ __device__ inline bool fwd_p_in_lds(const DevParams& P) {
   return need <= S::CH * S::FRP || need * (int)sizeof(double) <= 16384;
 }
 
-template <int NMAX, int LMAX, typename RT>
+template <int NMAX, int LMAX, typename ST>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams P, const DevTables* __restrict__ T,
                                                                      int n_atoms, const int* __restrict__ offsets,
                                                                      int bound, const int* __restrict__ nj,
                                                                      const int* __restrict__ species,
-                                                                     const RT* __restrict__ rows,
+                                                                     const ST* __restrict__ rows,
                                                                      const double* __restrict__ bc_in,
-                                                                     double* __restrict__ c_out,
+                                                                     ST* __restrict__ c_out,
                                                                      double* __restrict__ q_out, int q_pitch,
                                                                      double* __restrict__ pnorm_out,
                                                                      __bf16* __restrict__ qc, int qc_pitch) {
@@ -428,7 +441,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   const int n = P.n, LL = P.LL, LLP = LL + 1, nch = P.nch;
   const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
   const int si = P.ns == 1 ? 0 : species[i];
-  double* __restrict__ ci_out = c_out + (size_t)i * P.ns * NMAX * LLP;
+  ST* __restrict__ ci_out = c_out + (size_t)i * P.ns * NMAX * LLP;
   constexpr bool COLS = S::COLS;
   constexpr int EC = S::EC;
   // record mode: acc[e][part][k]; column mode: acc[e][0][k] (EC columns)
@@ -442,7 +455,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   // loaded while the chunk before is processed
   constexpr bool PF = NMAX > 8 && LMAX <= 10;  // the registers spill in the other buckets
   double pf[(S::FR * CH + 63) / 64];
-  if (PF && P.ns == 1 && p0 < p1) prefetch_fields<S::FR, S::ROW, CH, RT>(rows, p0, min(CH, p1 - p0), pf, lane);
+  if (PF && P.ns == 1 && p0 < p1) prefetch_fields<S::FR, S::ROW, CH, ST>(rows, p0, min(CH, p1 - p0), pf, lane);
   for (int s = 0; s < P.ns; ++s) {
     double acc[NE][NP][NMAX];
 #pragma unroll
@@ -461,9 +474,9 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       __syncthreads();
       if (PF && P.ns == 1) {
         stage_prefetched<S::FR, CH, FRP>(pf, cnt, dyn + S::LZ, lane);
-        if (w0 + CH < p1) prefetch_fields<S::FR, S::ROW, CH, RT>(rows, w0 + CH, min(CH, p1 - w0 - CH), pf, lane);
+        if (w0 + CH < p1) prefetch_fields<S::FR, S::ROW, CH, ST>(rows, w0 + CH, min(CH, p1 - w0 - CH), pf, lane);
       } else {
-        stage_fields<S::FR, S::ROW, CH, FRP, 6, RT>(rows, idx, cnt, dyn + S::LZ, lane);
+        stage_fields<S::FR, S::ROW, CH, FRP, 6, ST>(rows, idx, cnt, dyn + S::LZ, lane);
       }
       __syncthreads();
       if (lane < cnt) {  // the azimuthal powers of staged pair `lane`
@@ -529,7 +542,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
     // c of species s: LL + 1 columns lm (the last one a sink, left zero) of NMAX
     // channels; with one species it also goes to LDS, where the power spectrum
     // reads it, once the wave is done with the staged rows
-    double* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
+    ST* __restrict__ cs = ci_out + (size_t)s * LLP * NMAX;
     const bool c_lds = P.ns == 1;
     if (c_lds) __syncthreads();
     if constexpr (COLS) {
@@ -537,12 +550,12 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       for (int e = 0; e < EC; ++e) {
         if (C.lm[e] == LL) continue;
         const bool central = C.lm[e] == 0 && s == si;
-        double* __restrict__ dc = cs + C.lm[e] * NMAX;
+        ST* __restrict__ dc = cs + C.lm[e] * NMAX;
 #pragma unroll
         for (int k = 0; k < NMAX; k += 2) {
           const double2 v{acc[e][0][k] + (central ? bc_in[k] : 0.0),
                           acc[e][0][k + 1] + (central ? bc_in[k + 1] : 0.0)};
-          *reinterpret_cast<double2*>(dc + k) = v;
+          store_pair(dc + k, v);
           if (c_lds) *reinterpret_cast<double2*>(dyn + C.lm[e] * NMAX + k) = v;
         }
       }
@@ -551,25 +564,25 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
     for (int e = 0; e < (COLS ? 0 : E2); ++e) {
       if (lane + 64 * e >= S::NREC || R.lmc[e] == LL) continue;
       const bool central = R.lmc[e] == 0 && s == si;
-      double* __restrict__ dc = cs + R.lmc[e] * NMAX;
+      ST* __restrict__ dc = cs + R.lmc[e] * NMAX;
 #pragma unroll
       for (int k = 0; k < NMAX; k += 2) {
         const double2 v{acc[e][0][k] + (central ? bc_in[k] : 0.0), acc[e][0][k + 1] + (central ? bc_in[k + 1] : 0.0)};
-        *reinterpret_cast<double2*>(dc + k) = v;
+        store_pair(dc + k, v);
         if (c_lds) *reinterpret_cast<double2*>(dyn + R.lmc[e] * NMAX + k) = v;
       }
       if (R.lms[e] != LL) {
-        double* __restrict__ ds = cs + R.lms[e] * NMAX;
+        ST* __restrict__ ds = cs + R.lms[e] * NMAX;
 #pragma unroll
         for (int k = 0; k < NMAX; k += 2) {
           const double2 v{acc[e][NP - 1][k], acc[e][NP - 1][k + 1]};
-          *reinterpret_cast<double2*>(ds + k) = v;
+          store_pair(ds + k, v);
           if (c_lds) *reinterpret_cast<double2*>(dyn + R.lms[e] * NMAX + k) = v;
         }
       }
     }
     if (lane < NMAX) {
-      cs[LL * NMAX + lane] = 0.0;
+      cs[LL * NMAX + lane] = (ST)0;
       if (c_lds) dyn[LL * NMAX + lane] = 0.0;
     }
   }
@@ -586,7 +599,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   double* __restrict__ pv = fwd_p_in_lds<NMAX, LMAX>(P) ? dyn + per_atom : qi;
   if (P.ns > 1) {
     for (int t = lane; t < per_atom / 2; t += 64)
-      reinterpret_cast<double2*>(csh)[t] = reinterpret_cast<const double2*>(ci_out)[t];
+      reinterpret_cast<double2*>(csh)[t] = load_pair(ci_out + 2 * t);
     __syncthreads();
   }
   const int L1 = P.l + 1, nab = nch * (nch + 1) / 2;
@@ -826,17 +839,17 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
 // NMAX <= 8 every global read (c, q, qbar, qbar2, |p|) is issued at once and q,
 // qbar stay in registers from the dot product to vbar; otherwise the reads go
 // eight per lane at a time.
-template <int NMAX, int LMAX>
-__device__ __forceinline__ void form_cbar(const DevParams& P, int i, const double* __restrict__ c,
+template <int NMAX, int LMAX, typename ST>
+__device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
-                                 const double* __restrict__ qbar, const double* __restrict__ qbar2, int qbar_pitch,
+                                 const ST* __restrict__ qbar, const ST* __restrict__ qbar2, int qbar_pitch,
                                  double* cb, double* vb, int* abx, int lane) {
   constexpr int B = 16;  // loads per lane in flight
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
-  const double* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
+  const ST* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
-  const double* qb = qbar + (size_t)i * qbar_pitch;
-  const double* qb2 = qbar2 ? qbar2 + (size_t)i * qbar_pitch : nullptr;  // a second part of qbar, added
+  const ST* qb = qbar + (size_t)i * qbar_pitch;
+  const ST* qb2 = qbar2 ? qbar2 + (size_t)i * qbar_pitch : nullptr;  // a second part of qbar, added
   if constexpr (NMAX <= 8) {
     constexpr int KPL = (NMAX * (NMAX + 1) / 2 * (LMAX + 1) + 63) / 64;   // K per lane, one species
     constexpr int CPL = (NMAX * ((LMAX + 1) * (LMAX + 1) + 1) + 63) / 64;  // c per lane
@@ -1115,17 +1128,17 @@ __device__ __forceinline__ void adjoint_records_full(const double* __restrict__ 
 // as broadcasts.  Registers: up to 168 per lane (3 waves per SIMD) in the buckets
 // up to n_max = 8, where the compile-time record loop spills at 128; the larger
 // buckets need up to 256 (2 waves per SIMD).
-template <int NMAX, int LMAX, typename RT>
+template <int NMAX, int LMAX, typename ST>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
                                                                        int n_atoms, const int* __restrict__ offsets,
                                                                        int bound, const int* __restrict__ nj,
                                                                        const int* __restrict__ species,
-                                                                       const RT* __restrict__ rows,
-                                                                       const double* __restrict__ c,
+                                                                       const ST* __restrict__ rows,
+                                                                       const ST* __restrict__ c,
                                                                        const double* __restrict__ q, int q_pitch,
                                                                        const double* __restrict__ pnorm,
-                                                                       const double* __restrict__ qbar,
-                                                                       const double* __restrict__ qbar2,
+                                                                       const ST* __restrict__ qbar,
+                                                                       const ST* __restrict__ qbar2,
                                                                        int qbar_pitch, double* __restrict__ gx,
                                                                        double* __restrict__ gy,
                                                                        double* __restrict__ gz, int gstride) {
@@ -1163,7 +1176,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
     }
     const int nrec_d = nrec * NC + 2 * nrec;
     int* abx = reinterpret_cast<int*>(rc + (nrec_d > P.K ? nrec_d : P.K));
-    form_cbar<NMAX, LMAX>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
+    form_cbar<NMAX, LMAX, ST>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
 #pragma unroll
     for (int k = 0; k < RPL; ++k)
       if (lane + 64 * k < nrec * NC) rc[lane + 64 * k] = v[k];
@@ -1185,7 +1198,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
     pb += 64 >> lgR;
     const bool live = p < p1;
     const int pq = live ? p : p0;  // idle lanes read a valid row
-    const RT* __restrict__ row = rows + (size_t)(pq >> 6) * (S::ROW * 64) + (pq & 63);
+    const ST* __restrict__ row = rows + (size_t)(pq >> 6) * (S::ROW * 64) + (pq & 63);
     auto F = [&](int f) { return (double)row[f * 64]; };
     double b[NMAX], db[NMAX];
 #pragma unroll
@@ -1384,42 +1397,44 @@ hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_
 
 hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
                              const int* nj,
-                             const int* species, const void* rows, bool rows_f32, const double* bc, double* c,
+                             const int* species, const void* rows, bool store_f32, const double* bc, void* c,
                              double* q, int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   if (qc && qc_pitch < P.K) return hipErrorInvalidValue;
   const size_t dyn = fwd_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    if (rows_f32)
+    if (store_f32)
       hipLaunchKernelGGL((k_descriptor<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms,
-                         offsets, bound, nj, species, static_cast<const float*>(rows), bc, c, q, q_pitch, pnorm,
-                         static_cast<__bf16*>(qc), qc_pitch);
+                         offsets, bound, nj, species, static_cast<const float*>(rows), bc, static_cast<float*>(c), q,
+                         q_pitch, pnorm, static_cast<__bf16*>(qc), qc_pitch);
     else
       hipLaunchKernelGGL((k_descriptor<N, LM, double>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms,
-                         offsets, bound, nj, species, static_cast<const double*>(rows), bc, c, q, q_pitch, pnorm,
-                         static_cast<__bf16*>(qc), qc_pitch);
+                         offsets, bound, nj, species, static_cast<const double*>(rows), bc, static_cast<double*>(c),
+                         q, q_pitch, pnorm, static_cast<__bf16*>(qc), qc_pitch);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
 }
 
 hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_atoms, const int* offsets, int bound,
-                               const int* nj, const int* species, const void* rows, bool rows_f32, const double* c,
-                               const double* q, int q_pitch, const double* pnorm, const double* qbar,
-                               const double* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
+                               const int* nj, const int* species, const void* rows, bool store_f32, const void* c,
+                               const double* q, int q_pitch, const double* pnorm, const void* qbar,
+                               const void* qbar2, int qbar_pitch, double* gx, double* gy, double* gz,
                                int gstride, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
   const size_t dyn = adj_dyn_bytes(P);
   auto f = [&]<int N, int LM>() {
-    if (rows_f32)
+    if (store_f32)
       hipLaunchKernelGGL((k_pair_adjoint<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
-                         n_atoms, offsets, bound, nj, species, static_cast<const float*>(rows), c, q, q_pitch, pnorm,
-                         qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
+                         n_atoms, offsets, bound, nj, species, static_cast<const float*>(rows),
+                         static_cast<const float*>(c), q, q_pitch, pnorm, static_cast<const float*>(qbar),
+                         static_cast<const float*>(qbar2), qbar_pitch, gx, gy, gz, gstride);
     else
       hipLaunchKernelGGL((k_pair_adjoint<N, LM, double>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
-                         n_atoms, offsets, bound, nj, species, static_cast<const double*>(rows), c, q, q_pitch, pnorm,
-                         qbar, qbar2, qbar_pitch, gx, gy, gz, gstride);
+                         n_atoms, offsets, bound, nj, species, static_cast<const double*>(rows),
+                         static_cast<const double*>(c), q, q_pitch, pnorm, static_cast<const double*>(qbar),
+                         static_cast<const double*>(qbar2), qbar_pitch, gx, gy, gz, gstride);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
