@@ -299,12 +299,14 @@ __device__ inline unsigned long long bit_range(int lo, int hi) {
 // candidates 64 at a time.  Hits are compacted with a ballot, so the pair order
 // (offset order, then ascending atom index within a bin) is fixed.
 //
-// Count pass: count[i], and opre[i][o] = the hits of i before offset o.
+// Count pass: count[i], and opre[m(i)][o] = the hits of i before offset o, where
+// m(i) is i's slot in the cell list (bin order, so that the centres near each
+// other, which the fill pass looks up together, have neighbouring rows).
 // Fill pass: the pairs, and rev of each.  For the pair (i -> j, T) found at
 // offset o with bin shift g, centre j meets i's bin at offset n_off - 1 - o
 // with shift -g; among that bin's atoms (ascending index) the ones before i that
 // j reaches precede (j -> i, -T) in j's list, so
-//   rev = offsets[j] + opre[j][n_off - 1 - o] + #{a in bin(i), a < i, j reaches a},
+//   rev = offsets[j] + opre[m(j)][n_off - 1 - o] + #{a in bin(i), a < i, j reaches a},
 // where "j reaches a" is evaluated with exactly the arithmetic of j's own scan.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __restrict__ pos,
@@ -321,10 +323,13 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
   __shared__ int s_start[4][64];  // first cand slot of each offset
   __shared__ int s_shift[4][64];  // lattice shift of each offset (packed)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // the centre is uniform over the wavefront: its data and its structure's
-  // geometry are read once into scalar registers
-  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
-  if (i >= n_atoms) return;
+  // centres are taken in cell-list order: wavefront mc takes the atom in slot mc,
+  // so neighbouring wavefronts scan neighbouring bins (their candidate records and
+  // hit prefixes meet in the caches).  The centre is uniform over the wavefront:
+  // its data and its structure's geometry are read once into scalar registers
+  const int mc = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+  if (mc >= n_atoms) return;
+  const int i = __builtin_amdgcn_readfirstlane(cand[mc].j);
   const StructMeta& M = meta[n_struct == 1 ? 0 : find_structure(so, n_struct, i)];
   double cell[9];
 #pragma unroll
@@ -341,14 +346,14 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
   unpack_img(atom_wrap[i], wi);
   const int n0 = 2 * R0 + 1, n1 = 2 * R1 + 1, n2 = 2 * R2 + 1;
   const int n_off = n0 * n1 * n2;
-  // opre of centre a of this structure: opre + obase_a + a * n_off
-  int* const opre_s = opre + (M.obase - (long long)M.atom0 * n_off);
+  // the hit prefixes of the centre in slot m of this structure (whose slots
+  // start at bin_start[bin0]): opre + obase + (m - bin_start[bin0]) n_off
+  int* const opre_s = opre + (M.obase - (long long)bin_start[bin0] * n_off);
   long long out = FILL ? offsets[i] : 0;
-  // fill: the slots of i's bin holding atoms with a smaller index than i
+  // fill: the slots of i's bin holding atoms with a smaller index than i (a bin
+  // holds its atoms in index order, i at slot mc)
   const int m0 = FILL ? bin_start[bi] : 0;
-  int m1 = m0;
-  if (FILL)
-    while (cand[m1].j < i) ++m1;  // i itself is in the bin, so this stops
+  const int m1 = FILL ? mc : 0;
   int cnt = 0;
   for (int g0 = 0; g0 < n_off; g0 += 64) {
     const int o = g0 + lane;
@@ -383,7 +388,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
       bool hit = false;
-      int lo = 0, j = 0, T0 = 0, T1 = 0, T2 = 0;
+      int lo = 0, j = 0, mj = 0, T0 = 0, T1 = 0, T2 = 0;
       Cand a;
       a.x = a.y = a.z = 0.0;
       a.j = a.wrap = 0;
@@ -396,7 +401,8 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
           if (s_pref[wv][mid] <= c) lo = mid;
           else hi = mid;
         }
-        a = cand[s_start[wv][lo] + (c - s_pref[wv][lo])];
+        mj = s_start[wv][lo] + (c - s_pref[wv][lo]);  // j's slot
+        a = cand[mj];
         j = a.j;
         int gsh[3], wj[3];
         unpack_img(s_shift[wv][lo], gsh);
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
               rank += __fma_rn(ez, ez, __fma_rn(ey, ey, ex * ex)) < rc2;
             }
           }
-          const long long rq = (long long)offsets[j] + opre_s[(long long)j * n_off + (n_off - 1 - (g0 + lo))] + rank;
+          const long long rq = (long long)offsets[j] + opre_s[(long long)mj * n_off + (n_off - 1 - (g0 + lo))] + rank;
           nj[q] = j;
           nimg[q] = pack_img(T0, T1, T2);
           ncenter[q] = i;
@@ -465,7 +471,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
         if (lane >= d) h += v;
       }
       const int group_hits = __shfl(h, 63, 64);  // read by every lane, outside the branch below
-      if (o < n_off) opre_s[(long long)i * n_off + o] = cnt - group_hits + (h - my_hits);
+      if (o < n_off) opre_s[(long long)mc * n_off + o] = cnt - group_hits + (h - my_hits);
     }
     __builtin_amdgcn_wave_barrier();
   }
