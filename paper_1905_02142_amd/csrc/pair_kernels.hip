@@ -338,33 +338,6 @@ __device__ inline void stage_fields(const RT* __restrict__ rows, const int* idx,
   }
 }
 
-// fields 0..WIDTH-1 of the cnt consecutive pairs w0.. into registers, in the
-// order stage_prefetched stores them (field u / CH of pair u % CH for u = lane +
-// 64 k); the forward issues them one chunk ahead, so that their latency overlaps
-// the arithmetic of the chunk before
-template <int WIDTH, int ROW, int CH, typename RT>
-__device__ __forceinline__ void prefetch_fields(const RT* __restrict__ rows, int w0, int cnt,
-                                                double (&v)[(WIDTH * CH + 63) / 64], int lane) {
-  constexpr int ITER = (WIDTH * CH + 63) / 64;
-#pragma unroll
-  for (int k = 0; k < ITER; ++k) {
-    const int u = lane + 64 * k, f = u / CH, t = u % CH, p = w0 + t;
-    const bool ok = u < WIDTH * CH && t < cnt;
-    v[k] = (double)rows[ok ? (size_t)(p >> 6) * (ROW * 64) + f * 64 + (p & 63) : 0];
-  }
-}
-
-template <int WIDTH, int CH, int STRIDE>
-__device__ __forceinline__ void stage_prefetched(const double (&v)[(WIDTH * CH + 63) / 64], int cnt,
-                                                 double* __restrict__ dst, int lane) {
-  constexpr int ITER = (WIDTH * CH + 63) / 64;
-#pragma unroll
-  for (int k = 0; k < ITER; ++k) {
-    const int u = lane + 64 * k, f = u / CH, t = u % CH;
-    if (u < WIDTH * CH && t < cnt) dst[t * STRIDE + f] = v[k];
-  }
-}
-
 // The power spectrum P_l = C_l C_l^T of one atom (C_l: n_ch x (2l + 1), the
 // real form of Eq. (09)) on the matrix cores: BF16 operands, FP32 accumulation,
 // one v_mfma_f32_16x16x32_bf16 per 16 x 16 tile of channel pairs and per l
@@ -411,16 +384,20 @@ __device__ __forceinline__ double power_spectrum_mfma(const DevParams& P, const 
 }
 
 // the forward keeps the power spectrum in LDS when c and p of one atom together
-// stay within the row staging area or within 16 KB
+// stay within the row staging area or within 16 KB (not at n_max = 10)
 template <int NMAX, int LMAX>
 __host__ __device__ inline bool fwd_p_in_lds(const DevParams& P) {
   using S = Shape<NMAX, LMAX>;
   const int need = P.ns * NMAX * (P.LL + 1) + P.K;
-  return need <= S::CH * S::FRP || need * (int)sizeof(double) <= 16384;
+  // at n_max = 10, which runs 3 waves per SIMD, LDS beyond the staging area
+  // would cost a wave: p goes to the q row there
+  return need <= S::CH * S::FRP || (NMAX != 10 && need * (int)sizeof(double) <= 16384);
 }
 
+// Registers: 4 waves per SIMD up to n_max = 8, 3 at n_max = 10 (155 VGPRs; with
+// p out of LDS, 12 waves per CU fit), 2 at n_max = 12
 template <int NMAX, int LMAX, typename ST>
-__global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams P, const DevTables* __restrict__ T,
+__global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_descriptor(DevParams P, const DevTables* __restrict__ T,
                                                                      int n_atoms, const int* __restrict__ offsets,
                                                                      int bound, const int* __restrict__ nj,
                                                                      const int* __restrict__ species,
@@ -451,11 +428,6 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
   if constexpr (COLS) lane_columns<LMAX, EC, NC>(T, lane, P.l, LL, C);
   else lane_records<E2, NC>(T, lane, S::NREC, LL, R);
 
-  // one species: the pairs are taken in order, and each chunk's fields are
-  // loaded while the chunk before is processed
-  constexpr bool PF = NMAX > 8 && LMAX <= 10;  // the registers spill in the other buckets
-  double pf[(S::FR * CH + 63) / 64];
-  if (PF && P.ns == 1 && p0 < p1) prefetch_fields<S::FR, S::ROW, CH, ST>(rows, p0, min(CH, p1 - p0), pf, lane);
   for (int s = 0; s < P.ns; ++s) {
     double acc[NE][NP][NMAX];
 #pragma unroll
@@ -472,12 +444,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : 2) void k_descriptor(DevParams 
       if (take) idx[__popcll(mask & ((1ull << lane) - 1ull))] = pp;
       const int cnt = __popcll(mask);
       __syncthreads();
-      if (PF && P.ns == 1) {
-        stage_prefetched<S::FR, CH, FRP>(pf, cnt, dyn + S::LZ, lane);
-        if (w0 + CH < p1) prefetch_fields<S::FR, S::ROW, CH, ST>(rows, w0 + CH, min(CH, p1 - w0 - CH), pf, lane);
-      } else {
-        stage_fields<S::FR, S::ROW, CH, FRP, 6, ST>(rows, idx, cnt, dyn + S::LZ, lane);
-      }
+      stage_fields<S::FR, S::ROW, CH, FRP, 6, ST>(rows, idx, cnt, dyn + S::LZ, lane);
       __syncthreads();
       if (lane < cnt) {  // the azimuthal powers of staged pair `lane`
         double* __restrict__ zt = dyn + lane * FRP;
