@@ -322,6 +322,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
   __shared__ int s_pref[4][65];   // inclusive scan of candidate counts
   __shared__ int s_start[4][64];  // first cand slot of each offset
   __shared__ int s_shift[4][64];  // lattice shift of each offset (packed)
+  __shared__ int s_own[4][64];    // the offset whose first candidate is slot c - c0 of a chunk
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // centres are taken in cell-list order: wavefront mc takes the atom in slot mc,
   // so neighbouring wavefronts scan neighbouring bins (their candidate records and
@@ -355,15 +356,34 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
   const int m0 = FILL ? bin_start[bi] : 0;
   const int m1 = FILL ? mc : 0;
   int cnt = 0;
+  // offset o = x + n0 (y + n1 z): below 2^21 offsets the quotients come exactly
+  // from float reciprocals ((o + 0.5) / d lies at least 0.5 / d from an integer,
+  // far beyond the float rounding of o / d); beyond, integer division
+  const bool fdiv = n_off < (1 << 21);
+  const float i0f = 1.0f / (float)n0, i01f = 1.0f / (float)(n0 * n1);
+  // a bin shift of at most one cell count (R <= nbin) wraps at most once
+  const bool w0 = R0 <= nb0, w1 = R1 <= nb1, w2 = R2 <= nb2;
+  auto wrap = [](int u, int nb, bool once) { return once ? (u < 0 ? -1 : (u >= nb ? 1 : 0)) : floordiv(u, nb); };
   for (int g0 = 0; g0 < n_off; g0 += 64) {
     const int o = g0 + lane;
     int len = 0, start = 0, shift = 0;
     if (o < n_off) {
-      const int ox = o % n0 - R0, oy = (o / n0) % n1 - R1, oz = o / (n0 * n1) - R2;
+      int qx, qy, qz;
+      if (fdiv) {
+        qz = (int)(((float)o + 0.5f) * i01f);
+        const int r = o - qz * n0 * n1;
+        qy = (int)(((float)r + 0.5f) * i0f);
+        qx = r - qy * n0;
+      } else {
+        qx = o % n0;
+        qy = (o / n0) % n1;
+        qz = o / (n0 * n1);
+      }
+      const int ox = qx - R0, oy = qy - R1, oz = qz - R2;
       const int ux = b0 + ox, uy = b1 + oy, uz = b2 + oz;
-      const int gx = p0 ? floordiv(ux, nb0) : 0;
-      const int gy = p1 ? floordiv(uy, nb1) : 0;
-      const int gz = p2 ? floordiv(uz, nb2) : 0;
+      const int gx = p0 ? wrap(ux, nb0, w0) : 0;
+      const int gy = p1 ? wrap(uy, nb1, w1) : 0;
+      const int gz = p2 ? wrap(uz, nb2, w2) : 0;
       const int cx = ux - gx * nb0, cy = uy - gy * nb1, cz = uz - gz * nb2;
       const int bin = bin0 + (cz * nb1 + cy) * nb0 + cx;
       start = bin_start[bin];
@@ -385,8 +405,25 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS writes visible to the wave
     const int total = __shfl(incl, 63, 64);
     int my_hits = 0;  // count pass: hits of offset o (this lane's)
+    int carry = -1;   // the offset of candidate c0 - 1
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
+      // the offset of candidate c, the largest b with s_pref[b] <= c: each
+      // non-empty offset marks its first candidate, and a running maximum over
+      // the chunk (from the chunk before) fills the rest
+      s_own[wv][lane] = -1;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      if (len > 0 && excl >= c0 && excl < c0 + 64) s_own[wv][excl - c0] = lane;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      int own = s_own[wv][lane];
+      for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(own, d, 64);
+        if (lane >= d) own = max(own, v);
+      }
+      own = max(own, carry);
+      carry = __shfl(own, 63, 64);
       bool hit = false;
       int lo = 0, j = 0, mj = 0, T0 = 0, T1 = 0, T2 = 0;
       Cand a;
@@ -394,13 +431,7 @@ __global__ __launch_bounds__(256) void k_pairs(int n_atoms, const double* __rest
       a.j = a.wrap = 0;
       double ddx = 0.0, ddy = 0.0, ddz = 0.0;
       if (c < total) {
-        // offset b with s_pref[b] <= c < s_pref[b + 1]
-        int hi = 64;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_pref[wv][mid] <= c) lo = mid;
-          else hi = mid;
-        }
+        lo = own;                                      // s_pref[lo] <= c < s_pref[lo + 1]
         mj = s_start[wv][lo] + (c - s_pref[wv][lo]);  // j's slot
         a = cand[mj];
         j = a.j;
