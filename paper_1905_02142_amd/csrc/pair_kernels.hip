@@ -630,9 +630,9 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
 
 // cbar = M(l) c in place for every column lm < LL of one species' cb, one
 // column per lane: M_ab(l) = 2 vbar_aal (a = b), sqrt(2) vbar_abl (a != b),
-// vbar packed a <= b then l
-template <int NMAX, int LMAX, bool FULL>
-__device__ __forceinline__ void transform_columns_t(int n, int nch, int LL, int L1, double* cb, const double* vb,
+// vbar packed a <= b then l (stored as VT: double, or float in the mixed modes)
+template <int NMAX, int LMAX, bool FULL, typename VT>
+__device__ __forceinline__ void transform_columns_t(int n, int nch, int LL, int L1, double* cb, const VT* vb,
                                                     int lane) {
   // FULL: n_max and l_max fill the compiled bucket, so every vbar index is a
   // compile-time offset from the column's l (no index arithmetic per entry)
@@ -640,7 +640,7 @@ __device__ __forceinline__ void transform_columns_t(int n, int nch, int LL, int 
   for (int lm = lane; lm < LL; lm += 64) {
     const int l = isqrt_small(lm);
     double* col = cb + (size_t)lm * NMAX;
-    const double* __restrict__ vl = vb + l;
+    const VT* __restrict__ vl = vb + l;
     double cv[NMAX];
 #pragma unroll
     for (int kb = 0; kb < NMAX; kb += 2) {
@@ -658,7 +658,7 @@ __device__ __forceinline__ void transform_columns_t(int n, int nch, int LL, int 
 #pragma unroll
       for (int b = a; b < NMAX; ++b)
         if (b < n_) {
-          const double v = vl[(a * nch_ - a * (a - 1) / 2 + (b - a)) * L1_];
+          const double v = (double)vl[(a * nch_ - a * (a - 1) / 2 + (b - a)) * L1_];
           if (a == b) {
             acc[a] = fma(2.0 * v, cv[a], acc[a]);
           } else {
@@ -672,8 +672,8 @@ __device__ __forceinline__ void transform_columns_t(int n, int nch, int LL, int 
   }
 }
 
-template <int NMAX, int LMAX>
-__device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1, double* cb, const double* vb,
+template <int NMAX, int LMAX, typename VT>
+__device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1, double* cb, const VT* vb,
                                                   int lane) {
   if (n == NMAX && L1 == LMAX + 1) transform_columns_t<NMAX, LMAX, true>(n, nch, LL, L1, cb, vb, lane);
   else transform_columns_t<NMAX, LMAX, false>(n, nch, LL, L1, cb, vb, lane);
@@ -685,8 +685,8 @@ __device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1
 // read of a column precedes the writes to it (one wavefront: its LDS operations
 // complete in order).  abx[a][b] = (packed index of {a, b}) * (l_max + 1).  Each
 // output takes its terms in the order (sb, kb).
-template <int NMAX>
-__device__ __forceinline__ void transform_columns_species(int n, int ns, int nch, int LL, int L1, double* cb, const double* vb,
+template <int NMAX, typename VT>
+__device__ __forceinline__ void transform_columns_species(int n, int ns, int nch, int LL, int L1, double* cb, const VT* vb,
                                                  const int* abx, int lane) {
   const int LLP = LL + 1, cpp = 64 / ns;  // columns per pass
   const int lmo = lane / ns, sa = lane - lmo * ns;
@@ -714,7 +714,7 @@ __device__ __forceinline__ void transform_columns_species(int n, int ns, int nch
             const int* __restrict__ row = abx + a * nch + sb * n;
 #pragma unroll
             for (int kb = 0; kb < NMAX; ++kb)
-              if (kb < n) acc[ka] = fma((sb * n + kb == a ? 2.0 : kSqrt2) * vb[row[kb] + l], cv[kb], acc[ka]);
+              if (kb < n) acc[ka] = fma((sb * n + kb == a ? 2.0 : kSqrt2) * (double)vb[row[kb] + l], cv[kb], acc[ka]);
           }
         }
       }
@@ -735,8 +735,8 @@ __device__ __forceinline__ void transform_columns_species(int n, int ns, int nch
 // registers before any of them is written); the result goes to cb in the same
 // layout.  Entries outside the channels and columns (the sink column, channels
 // k >= n_max) are left as they are.  n_ch <= 48.
-template <int NMAX>
-__device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc, double* cb, const double* vb, int lane) {
+template <int NMAX, typename VT>
+__device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc, double* cb, const VT* vb, int lane) {
   const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
   const int r16 = lane & 15, kq = lane >> 4;
   const int TA = (nch + 15) / 16, TK = (nch + 31) / 32;
@@ -770,7 +770,7 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
           const int b = 32 * tk + 8 * kq + j;
           double v = 0.0;
           if (a < nch && b < nch)
-            v = (a == b ? 2.0 : kSqrt2) * vb[ab_index(a < b ? a : b, a < b ? b : a, nch) * L1 + l];
+            v = (a == b ? 2.0 : kSqrt2) * (double)vb[ab_index(a < b ? a : b, a < b ? b : a, nch) * L1 + l];
           A[j] = (__bf16)(float)v;
         }
 #pragma unroll
@@ -806,11 +806,11 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
 // NMAX <= 8 every global read (c, q, qbar, qbar2, |p|) is issued at once and q,
 // qbar stay in registers from the dot product to vbar; otherwise the reads go
 // eight per lane at a time.
-template <int NMAX, int LMAX, typename ST>
+template <int NMAX, int LMAX, typename ST, typename VT>
 __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
                                  const ST* __restrict__ qbar, const ST* __restrict__ qbar2, int qbar_pitch,
-                                 double* cb, double* vb, int* abx, int lane) {
+                                 double* cb, VT* vb, int* abx, int lane) {
   constexpr int B = 16;  // loads per lane in flight
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const ST* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
@@ -852,7 +852,7 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
       const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
 #pragma unroll
       for (int u = 0; u < KPL; ++u)
-        if (lane + 64 * u < K) vb[lane + 64 * u] = (g[u] - a[u] * dot) * inv;
+        if (lane + 64 * u < K) vb[lane + 64 * u] = (VT)((g[u] - a[u] * dot) * inv);
       __syncthreads();
       if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
       else transform_columns<NMAX, LMAX>(n, nch, LL, L1, cb, vb, lane);
@@ -889,7 +889,7 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
       if (qb2) g[u] += g2[u];
       if (k0 + lane + 64 * u < K) {
         dot = fma(a[u], g[u], dot);
-        vb[k0 + lane + 64 * u] = g[u];
+        vb[k0 + lane + 64 * u] = (VT)g[u];
       }
     }
   }
@@ -903,7 +903,7 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int k = k0 + lane + 64 * u;
-      if (k < K) vb[k] = (vb[k] - a[u] * dot) * inv;
+      if (k < K) vb[k] = (VT)(((double)vb[k] - a[u] * dot) * inv);
     }
   }
   // abx[a][b] = (packed index of the pair {a, b}) * (l_max + 1), the row of vbar
@@ -921,17 +921,19 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
 }
 
 // LDS of the adjoint: the atom's cbar for every species ([species][lm][k]), then
-// a region that first holds vbar (K doubles) and then the record coefficients
-// [r][NC] and (parity, cos column, sin column) [r][4], then the channel-pair
-// index table of form_cbar (n_ch^2 ints)
+// a region that first holds vbar (K values: FP64, or FP32 in the mixed modes
+// where that lets more wavefronts share a CU, see launch_pair_adjoint) and then
+// the record coefficients [r][NC] and (parity, cos column, sin column) [r][4],
+// then the channel-pair index table of form_cbar (n_ch^2 ints)
 template <int NMAX, int LMAX>
 struct AdjLds {
   static constexpr int NC = Shape<NMAX, LMAX>::NC;
   static size_t cb_doubles(const DevParams& P) { return (size_t)P.ns * (P.LL + 1) * NMAX; }
-  static size_t bytes(const DevParams& P) {
+  __host__ __device__ static int vbar_doubles(int K, int es) { return (K * es + 7) / 8; }
+  static size_t bytes(const DevParams& P, bool f32) {
     const size_t nrec = (size_t)(P.l + 1) * (P.l + 2) / 2, rec = nrec * NC + 2 * nrec;
-    return sizeof(double) * (cb_doubles(P) + (rec > (size_t)P.K ? rec : (size_t)P.K)) +
-           sizeof(int) * (size_t)P.nch * P.nch;
+    const size_t nv = (size_t)vbar_doubles(P.K, f32 ? 4 : 8);
+    return sizeof(double) * (cb_doubles(P) + (rec > nv ? rec : nv)) + sizeof(int) * (size_t)P.nch * P.nch;
   }
 };
 
@@ -1108,7 +1110,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
                                                                        const ST* __restrict__ qbar2,
                                                                        int qbar_pitch, double* __restrict__ gx,
                                                                        double* __restrict__ gy,
-                                                                       double* __restrict__ gz, int gstride) {
+                                                                       double* __restrict__ gz, int gstride, int vbar_f32) {
   using S = Shape<NMAX, LMAX>;
   constexpr int NC = S::NC;
   extern __shared__ __align__(16) double dyn[];
@@ -1141,9 +1143,16 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
       lc[k] = T->rec_lm[jj][slot][0];
       ls[k] = T->rec_lm[jj][slot][1];
     }
-    const int nrec_d = nrec * NC + 2 * nrec;
-    int* abx = reinterpret_cast<int*>(rc + (nrec_d > P.K ? nrec_d : P.K));
-    form_cbar<NMAX, LMAX, ST>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
+    const bool vf = sizeof(ST) == 4 && vbar_f32;  // vbar in FP32 (mixed modes only)
+    const int nrec_d = nrec * NC + 2 * nrec, nv_d = AdjLds<NMAX, LMAX>::vbar_doubles(P.K, vf ? 4 : 8);
+    int* abx = reinterpret_cast<int*>(rc + (nrec_d > nv_d ? nrec_d : nv_d));
+    if constexpr (sizeof(ST) == 4) {
+      if (vf) form_cbar<NMAX, LMAX, ST, float>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb,
+                                               reinterpret_cast<float*>(rc), abx, lane);
+      else form_cbar<NMAX, LMAX, ST, double>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
+    } else {
+      form_cbar<NMAX, LMAX, ST, double>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
+    }
 #pragma unroll
     for (int k = 0; k < RPL; ++k)
       if (lane + 64 * k < nrec * NC) rc[lane + 64 * k] = v[k];
@@ -1297,8 +1306,8 @@ size_t fwd_dyn_bytes(const DevParams& P) {
     return sizeof(double) * (rows > epi ? rows : epi);
   });
 }
-size_t adj_dyn_bytes(const DevParams& P) {
-  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return AdjLds<N, LM>::bytes(P); });
+size_t adj_dyn_bytes(const DevParams& P, bool f32) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return AdjLds<N, LM>::bytes(P, f32); });
 }
 
 }  // namespace
@@ -1317,7 +1326,7 @@ size_t pair_rows_bytes(const DevParams& P, long long n_pairs, bool f32) {
 size_t descriptor_lds_bytes(const DevParams& P) {
   return fwd_dyn_bytes(P) + 64 * sizeof(int);
 }
-size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P); }
+size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P, false); }  // the larger (FP64) layout
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, void* rows_v, bool rows_f32,
@@ -1390,18 +1399,24 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
                                int gstride, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   if (gstride != 1 && gstride != 4) return hipErrorInvalidValue;
-  const size_t dyn = adj_dyn_bytes(P);
+  // vbar in FP32 when the FP64 layout leaves a CU (160 KB of LDS) one wavefront
+  // per SIMD and the FP32 one fits more (three species at K = 2700: 39.6 -> 28.8
+  // KB, 4 -> 5 wavefronts per CU, adjoint 1.72 -> 1.49 ms); elsewhere the
+  // conversions cost more than the extra wavefronts gain
+  const size_t b64 = adj_dyn_bytes(P, false), b32 = adj_dyn_bytes(P, true), lds_cu = 160 * 1024;
+  const bool vbar_f32 = store_f32 && lds_cu / b64 <= 4 && lds_cu / b32 > lds_cu / b64;
+  const size_t dyn = vbar_f32 ? b32 : b64;
   auto f = [&]<int N, int LM>() {
     if (store_f32)
       hipLaunchKernelGGL((k_pair_adjoint<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
                          n_atoms, offsets, bound, nj, species, static_cast<const float*>(rows),
                          static_cast<const float*>(c), q, q_pitch, pnorm, static_cast<const float*>(qbar),
-                         static_cast<const float*>(qbar2), qbar_pitch, gx, gy, gz, gstride);
+                         static_cast<const float*>(qbar2), qbar_pitch, gx, gy, gz, gstride, vbar_f32 ? 1 : 0);
     else
       hipLaunchKernelGGL((k_pair_adjoint<N, LM, double>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
                          n_atoms, offsets, bound, nj, species, static_cast<const double*>(rows),
                          static_cast<const double*>(c), q, q_pitch, pnorm, static_cast<const double*>(qbar),
-                         static_cast<const double*>(qbar2), qbar_pitch, gx, gy, gz, gstride);
+                         static_cast<const double*>(qbar2), qbar_pitch, gx, gy, gz, gstride, 0);
     return hipGetLastError();
   };
   return dispatch(P.n, P.l, f);
