@@ -345,20 +345,21 @@ __device__ inline void stage_fields(const RT* __restrict__ rows, const int* idx,
 // [species][lm][k]; the packed entries a <= b (sqrt(2) off the diagonal) go to
 // pv[ab L1 + l].  Operand lane layout: lane j holds row j % 16 and contraction
 // positions 8 (j / 16) .. 8 (j / 16) + 7; result lane j holds rows
-// 4 (j / 16) .. + 3 of column j % 16.  Returns this lane's sum of squares.
-template <int NMAX>
-__device__ __forceinline__ double power_spectrum_mfma(const DevParams& P, const double* csh, double* pv, int lane) {
+// 4 (j / 16) .. + 3 of column j % 16.  Returns this lane's sum of squares.  CT:
+// the type c is staged in (double, or float where c was stored in FP32).
+template <int NMAX, typename CT>
+__device__ __forceinline__ double power_spectrum_mfma(const DevParams& P, const CT* csh, double* pv, int lane) {
   const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
   const int r16 = lane & 15, kq = lane >> 4, T = (nch + 15) / 16;
   // operand: channel row a, positions m' = 8 kq + j of degree l
   auto operand = [&](int a, int l) {
     bf16x8 v;
     const int sa = a / n, ka = a - sa * n;
-    const double* c = csh + ((size_t)sa * LLP + l * l) * NMAX + ka;
+    const CT* c = csh + ((size_t)sa * LLP + l * l) * NMAX + ka;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int m = 8 * kq + j;
-      v[j] = (__bf16)(float)((a < nch && m <= 2 * l) ? c[m * NMAX] : 0.0);
+      v[j] = (__bf16)(float)((a < nch && m <= 2 * l) ? (double)c[m * NMAX] : 0.0);
     }
     return v;
   };
@@ -392,6 +393,13 @@ __host__ __device__ inline bool fwd_p_in_lds(const DevParams& P) {
   // at n_max = 10, which runs 3 waves per SIMD, LDS beyond the staging area
   // would cost a wave: p goes to the q row there
   return need <= S::CH * S::FRP || (NMAX != 10 && need * (int)sizeof(double) <= 16384);
+}
+
+// the FP32 staging of c in the forward's epilogue (FP32 storage assumed): several
+// species, the matrix-core power spectrum, and p in the q row
+template <int NMAX, int LMAX>
+__host__ __device__ inline bool fwd_c32(const DevParams& P) {
+  return P.ps_mfma && P.ns > 1 && !fwd_p_in_lds<NMAX, LMAX>(P);
 }
 
 // Registers: 4 waves per SIMD up to n_max = 8, 3 at n_max = 10 (155 VGPRs; with
@@ -560,18 +568,33 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
   // (fwd_p_in_lds); otherwise it goes straight to the q row and is rescaled there
   // by the lane that wrote it, so that several species do not cut the number of
   // wavefronts per CU
+  // With several species, FP32 storage and the matrix-core power spectrum, c is
+  // staged in FP32, the precision it was stored in (its BF16 operands are the
+  // same), which halves the LDS the wave holds (fwd_c32)
   const int per_atom = P.ns * NMAX * LLP;
   double* csh = dyn;
   double* __restrict__ qi = q_out + (size_t)i * q_pitch;
   double* __restrict__ pv = fwd_p_in_lds<NMAX, LMAX>(P) ? dyn + per_atom : qi;
+  const bool c32 = sizeof(ST) == 4 && fwd_c32<NMAX, LMAX>(P);
   if (P.ns > 1) {
-    for (int t = lane; t < per_atom / 2; t += 64)
-      reinterpret_cast<double2*>(csh)[t] = load_pair(ci_out + 2 * t);
+    if (c32) {
+      for (int t = lane; t < per_atom / 2; t += 64)
+        reinterpret_cast<float2*>(dyn)[t] = reinterpret_cast<const float2*>(ci_out)[t];
+    } else {
+      for (int t = lane; t < per_atom / 2; t += 64)
+        reinterpret_cast<double2*>(csh)[t] = load_pair(ci_out + 2 * t);
+    }
     __syncthreads();
   }
   const int L1 = P.l + 1, nab = nch * (nch + 1) / 2;
   double ss = 0.0;
-  if (P.ps_mfma) ss = power_spectrum_mfma<NMAX>(P, csh, pv, lane);
+  if (P.ps_mfma) {
+    if constexpr (sizeof(ST) == 4)
+      ss = c32 ? power_spectrum_mfma<NMAX>(P, reinterpret_cast<const float*>(dyn), pv, lane)
+               : power_spectrum_mfma<NMAX>(P, csh, pv, lane);
+    else
+      ss = power_spectrum_mfma<NMAX>(P, csh, pv, lane);
+  }
   for (int ab = P.ps_mfma ? nab : lane; ab < nab; ab += 64) {
     int a, b;
     ab_decode(ab, nch, a, b);
@@ -686,9 +709,9 @@ __device__ __forceinline__ void transform_columns(int n, int nch, int LL, int L1
 // complete in order).  abx[a][b] = (packed index of {a, b}) * (l_max + 1).  Each
 // output takes its terms in the order (sb, kb).
 template <int NMAX, typename VT>
-__device__ __forceinline__ void transform_columns_species(int n, int ns, int nch, int LL, int L1, double* cb, const VT* vb,
-                                                 const int* abx, int lane) {
-  const int LLP = LL + 1, cpp = 64 / ns;  // columns per pass
+__device__ __forceinline__ void transform_columns_species(int n, int ns, int nch, int LL, int L1, int cbs, double* cb,
+                                                 const VT* vb, const int* abx, int lane) {
+  const int cpp = 64 / ns;  // columns per pass
   const int lmo = lane / ns, sa = lane - lmo * ns;
   for (int c0 = 0; c0 < LL; c0 += cpp) {
     const int lm = c0 + lmo;
@@ -699,7 +722,7 @@ __device__ __forceinline__ void transform_columns_species(int n, int ns, int nch
     if (live) {
       const int l = isqrt_small(lm);
       for (int sb = 0; sb < ns; ++sb) {
-        const double* col = cb + (size_t)(sb * LLP + lm) * NMAX;
+        const double* col = cb + (size_t)sb * cbs + lm * NMAX;
         double cv[NMAX];
 #pragma unroll
         for (int kb = 0; kb < NMAX; kb += 2) {
@@ -720,7 +743,7 @@ __device__ __forceinline__ void transform_columns_species(int n, int ns, int nch
       }
     }
     if (live) {
-      double* dst = cb + (size_t)(sa * LLP + lm) * NMAX;
+      double* dst = cb + (size_t)sa * cbs + lm * NMAX;
 #pragma unroll
       for (int k = 0; k < NMAX; k += 2) *reinterpret_cast<double2*>(dst + k) = double2{acc[k], acc[k + 1]};
     }
@@ -731,13 +754,16 @@ __device__ __forceinline__ void transform_columns_species(int n, int ns, int nch
 // vbar packed a <= b then l) on the matrix cores: BF16 operands, FP32
 // accumulation, v_mfma_f32_16x16x32_bf16 over 16 channel rows x 16 columns m'
 // of degree l, contracted over the channels b in steps of 32.  c comes from
-// csrc ([species][lm][k]; it may be cb itself: every tile of an l is formed in
-// registers before any of them is written); the result goes to cb in the same
-// layout.  Entries outside the channels and columns (the sink column, channels
-// k >= n_max) are left as they are.  n_ch <= 48.
-template <int NMAX, typename VT>
-__device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc, double* cb, const VT* vb, int lane) {
-  const int n = P.n, nch = P.nch, L1 = P.l + 1, LLP = P.LL + 1;
+// csrc ([species][lm][k], species cbs doubles apart; it may be cb itself: every
+// tile of an l is formed in registers before any of them is written); the result
+// goes to cb in the same layout.  Entries outside the channels and columns (the sink column, channels
+// k >= n_max) are left as they are.  n_ch <= 48.  vb: vbar as double or float, or
+// as the BF16 operand entries themselves (VT = __bf16: the factor 2 or sqrt(2)
+// already applied, see form_cbar).
+template <int NMAX, typename CT, typename VT>
+__device__ __forceinline__ void cbar_mfma(const DevParams& P, int cbs, const CT* csrc, CT* cb, const VT* vb,
+                                          int lane) {
+  const int n = P.n, nch = P.nch, L1 = P.l + 1;
   const int r16 = lane & 15, kq = lane >> 4;
   const int TA = (nch + 15) / 16, TK = (nch + 31) / 32;
   for (int l = 0; l < L1; ++l) {
@@ -756,7 +782,7 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
         for (int j = 0; j < 8; ++j) {
           const int b = 32 * tk + 8 * kq + j, sb = b / n;
           Bm[tm][j] = (__bf16)(float)((tm < TM && b < nch && m < w)
-                                          ? csrc[((size_t)sb * LLP + l * l + m) * NMAX + (b - sb * n)]
+                                          ? csrc[(size_t)sb * cbs + (l * l + m) * NMAX + (b - sb * n)]
                                           : 0.0);
         }
       }
@@ -768,10 +794,14 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int b = 32 * tk + 8 * kq + j;
-          double v = 0.0;
-          if (a < nch && b < nch)
-            v = (a == b ? 2.0 : kSqrt2) * (double)vb[ab_index(a < b ? a : b, a < b ? b : a, nch) * L1 + l];
-          A[j] = (__bf16)(float)v;
+          if constexpr (std::is_same_v<VT, __bf16>) {
+            A[j] = (a < nch && b < nch) ? vb[ab_index(a < b ? a : b, a < b ? b : a, nch) * L1 + l] : (__bf16)0.0f;
+          } else {
+            double v = 0.0;
+            if (a < nch && b < nch)
+              v = (a == b ? 2.0 : kSqrt2) * (double)vb[ab_index(a < b ? a : b, a < b ? b : a, nch) * L1 + l];
+            A[j] = (__bf16)(float)v;
+          }
         }
 #pragma unroll
         for (int tm = 0; tm < 2; ++tm)
@@ -789,7 +819,7 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
           const int a = 16 * ta + 4 * kq + r;
           if (a < nch) {
             const int sa = a / n;
-            cb[((size_t)sa * LLP + l * l + m) * NMAX + (a - sa * n)] = (double)D[ta][tm][r];
+            cb[(size_t)sa * cbs + (l * l + m) * NMAX + (a - sa * n)] = (CT)D[ta][tm][r];
           }
         }
       }
@@ -798,26 +828,32 @@ __device__ __forceinline__ void cbar_mfma(const DevParams& P, const double* csrc
 
 // vbar = (qbar - q (q . qbar)) / |p| and cbar_{a,lm} = sum_b M_ab(l) c_{b,lm} of atom
 // i (qbar = qbar + qbar2 when qbar2 is not null, in that order), written into cb
-// (LDS) in the padded layout of c ([species][lm < LL + 1][k < NMAX]) with zeros
-// in the sink column lm = LL and in the channels k >= n_max.  vb: K doubles of
-// LDS scratch; abx: n_ch^2 ints of LDS scratch.  Ends with a block barrier.  The
-// atom's c (every species) is first copied into cb and transformed there in
+// (LDS) in the padded layout of c ([species][lm < LL + 1][k < NMAX], species cbs
+// doubles apart) with zeros in the sink column lm = LL and in the channels
+// k >= n_max.  vb: K entries of LDS scratch (VT); abx: n_ch^2 ints of LDS
+// scratch (several species, VALU transform only).  Ends with a block barrier.
+// The atom's c (every species) is first copied into cb and transformed there in
 // place: a column of cbar needs only the same column of c.  With one species and
 // NMAX <= 8 every global read (c, q, qbar, qbar2, |p|) is issued at once and q,
 // qbar stay in registers from the dot product to vbar; otherwise the reads go
-// eight per lane at a time.
-template <int NMAX, int LMAX, typename ST, typename VT>
+// sixteen per lane at a time.  VT = __bf16 (matrix-core transform, several
+// species): vb holds the BF16 operands of cbar_mfma, vbar rounded to FP32 as in
+// the FP32 layout, times 2 (a = b) or sqrt(2), rounded to BF16; the same
+// operands as the FP32 layout gives, in half its LDS.
+template <int NMAX, int LMAX, typename ST, typename VT, typename CT>
 __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* __restrict__ c,
                                  const double* __restrict__ q, int q_pitch, const double* __restrict__ pnorm,
                                  const ST* __restrict__ qbar, const ST* __restrict__ qbar2, int qbar_pitch,
-                                 double* cb, VT* vb, int* abx, int lane) {
+                                 int cbs, CT* cb, VT* vb, int* abx, int lane) {
   constexpr int B = 16;  // loads per lane in flight
   const int n = P.n, ns = P.ns, nch = P.nch, LL = P.LL, LLP = LL + 1, K = P.K, L1 = P.l + 1;
   const ST* __restrict__ csh = c + (size_t)i * ns * NMAX * LLP;  // c of atom i, [species][lm][k]
   const double* qi = q + (size_t)i * q_pitch;
   const ST* qb = qbar + (size_t)i * qbar_pitch;
   const ST* qb2 = qbar2 ? qbar2 + (size_t)i * qbar_pitch : nullptr;  // a second part of qbar, added
-  if constexpr (NMAX <= 8) {
+  constexpr bool VB16 = std::is_same_v<VT, __bf16>;
+  static_assert(VB16 || std::is_same_v<CT, double>, "FP32 cbar comes from the matrix-core transform only");
+  if constexpr (NMAX <= 8 && !VB16) {
     constexpr int KPL = (NMAX * (NMAX + 1) / 2 * (LMAX + 1) + 63) / 64;   // K per lane, one species
     constexpr int CPL = (NMAX * ((LMAX + 1) * (LMAX + 1) + 1) + 63) / 64;  // c per lane
     const int nc = NMAX * LLP;
@@ -854,94 +890,166 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
       for (int u = 0; u < KPL; ++u)
         if (lane + 64 * u < K) vb[lane + 64 * u] = (VT)((g[u] - a[u] * dot) * inv);
       __syncthreads();
-      if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
+      if (P.ps_mfma) cbar_mfma<NMAX>(P, cbs, cb, cb, vb, lane);
       else transform_columns<NMAX, LMAX>(n, nch, LL, L1, cb, vb, lane);
       __syncthreads();
       return;
     }
   }
   {
-    // the atom's c, every species, into cb (transformed there in place below)
-    const int nc = ns * NMAX * LLP;
+    // the atom's c, every species, into cb (transformed there in place below),
+    // species s of c (nps values) at s cbs
+    const int nps = NMAX * LLP, nc = ns * nps;
     for (int t0 = 0; t0 < nc; t0 += 64 * B) {
       double v[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) v[u] = csh[min(t0 + lane + 64 * u, nc - 1)];
 #pragma unroll
-      for (int u = 0; u < B; ++u)
-        if (t0 + lane + 64 * u < nc) cb[t0 + lane + 64 * u] = v[u];
-    }
-  }
-  // dot = q . qbar, with qbar kept in vb; then vbar in place, q read again (now
-  // from the caches).  Each lane reads back only the entries it wrote.
-  double dot = 0.0;
-  for (int k0 = 0; k0 < K; k0 += 64 * B) {
-    double a[B], g[B], g2[B];
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int k = min(k0 + lane + 64 * u, K - 1);
-      a[u] = qi[k];
-      g[u] = qb[k];
-      if (qb2) g2[u] = qb2[k];
-    }
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      if (qb2) g[u] += g2[u];
-      if (k0 + lane + 64 * u < K) {
-        dot = fma(a[u], g[u], dot);
-        vb[k0 + lane + 64 * u] = (VT)g[u];
+      for (int u = 0; u < B; ++u) {
+        int t = t0 + lane + 64 * u;
+        if (t < nc) {
+          int o = 0;
+          while (t >= nps) {
+            t -= nps;
+            o += cbs;
+          }
+          cb[o + t] = (CT)v[u];
+        }
       }
     }
   }
-  dot = wave_sum(dot);
-  const double nrm = pnorm[i];
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int k0 = 0; k0 < K; k0 += 64 * B) {
-    double a[B];
+  if constexpr (VB16) {
+    // dot = q . qbar; then q and qbar read again (now from the caches) for vbar
+    double dot = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 64 * B) {
+      double a[B], g[B], g2[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) a[u] = qi[min(k0 + lane + 64 * u, K - 1)];
+      for (int u = 0; u < B; ++u) {
+        const int k = min(k0 + lane + 64 * u, K - 1);
+        a[u] = qi[k];
+        g[u] = qb[k];
+        if (qb2) g2[u] = qb2[k];
+      }
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int k = k0 + lane + 64 * u;
-      if (k < K) vb[k] = (VT)(((double)vb[k] - a[u] * dot) * inv);
+      for (int u = 0; u < B; ++u) {
+        if (qb2) g[u] += g2[u];
+        if (k0 + lane + 64 * u < K) dot = fma(a[u], g[u], dot);
+      }
     }
+    dot = wave_sum(dot);
+    const double nrm = pnorm[i];
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    // k = (packed pair {a, b}) (l_max + 1) + l, pairs a <= b in rows a: row a
+    // spans [rbeg, rend) and its first l_max + 1 entries are the diagonal a = b
+    int ra = 0, rbeg = 0, rend = nch * L1;
+    for (int k0 = 0; k0 < K; k0 += 64 * B) {
+      double a[B], g[B], g2[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int k = min(k0 + lane + 64 * u, K - 1);
+        a[u] = qi[k];
+        g[u] = qb[k];
+        if (qb2) g2[u] = qb2[k];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int k = k0 + lane + 64 * u;
+        if (qb2) g[u] += g2[u];
+        if (k < K) {
+          const float v = (float)(((double)(float)g[u] - a[u] * dot) * inv);
+          while (k >= rend) {
+            ++ra;
+            rbeg = rend;
+            rend += (nch - ra) * L1;
+          }
+          vb[k] = (__bf16)(float)((k < rbeg + L1 ? 2.0 : kSqrt2) * (double)v);
+        }
+      }
+    }
+    __syncthreads();
+    cbar_mfma<NMAX>(P, cbs, cb, cb, vb, lane);
+    __syncthreads();
+  } else {
+    // dot = q . qbar, with qbar kept in vb; then vbar in place, q read again (now
+    // from the caches).  Each lane reads back only the entries it wrote.
+    double dot = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 64 * B) {
+      double a[B], g[B], g2[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int k = min(k0 + lane + 64 * u, K - 1);
+        a[u] = qi[k];
+        g[u] = qb[k];
+        if (qb2) g2[u] = qb2[k];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (qb2) g[u] += g2[u];
+        if (k0 + lane + 64 * u < K) {
+          dot = fma(a[u], g[u], dot);
+          vb[k0 + lane + 64 * u] = (VT)g[u];
+        }
+      }
+    }
+    dot = wave_sum(dot);
+    const double nrm = pnorm[i];
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int k0 = 0; k0 < K; k0 += 64 * B) {
+      double a[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) a[u] = qi[min(k0 + lane + 64 * u, K - 1)];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int k = k0 + lane + 64 * u;
+        if (k < K) vb[k] = (VT)(((double)vb[k] - a[u] * dot) * inv);
+      }
+    }
+    // abx[a][b] = (packed index of the pair {a, b}) * (l_max + 1), the row of vbar
+    for (int r = lane; r < (ns > 1 && !P.ps_mfma ? nch * nch : 0); r += 64) {
+      const int a = r / nch, b = r - a * nch;
+      abx[r] = ab_index(a < b ? a : b, a < b ? b : a, nch) * L1;
+    }
+    __syncthreads();
+    // c of every species is in cb; the sink column and the channels k >= n_max are
+    // zero there and stay so
+    if (P.ps_mfma) cbar_mfma<NMAX>(P, cbs, cb, cb, vb, lane);
+    else if (ns == 1) transform_columns<NMAX, LMAX>(n, nch, LL, L1, cb, vb, lane);
+    else transform_columns_species<NMAX>(n, ns, nch, LL, L1, cbs, cb, vb, abx, lane);
+    __syncthreads();
   }
-  // abx[a][b] = (packed index of the pair {a, b}) * (l_max + 1), the row of vbar
-  for (int r = lane; r < (ns > 1 ? nch * nch : 0); r += 64) {
-    const int a = r / nch, b = r - a * nch;
-    abx[r] = ab_index(a < b ? a : b, a < b ? b : a, nch) * L1;
-  }
-  __syncthreads();
-  // c of every species is in cb; the sink column and the channels k >= n_max are
-  // zero there and stay so
-  if (P.ps_mfma) cbar_mfma<NMAX>(P, cb, cb, vb, lane);
-  else if (ns == 1) transform_columns<NMAX, LMAX>(n, nch, LL, L1, cb, vb, lane);
-  else transform_columns_species<NMAX>(n, ns, nch, LL, L1, cb, vb, abx, lane);
-  __syncthreads();
 }
 
-// LDS of the adjoint: the atom's cbar for every species ([species][lm][k]), then
+// LDS of the adjoint: the atom's cbar for every species ([species][lm][k], in
+// FP64, or in FP32 where the matrix-core transform forms it: C32), then
 // a region that first holds vbar (K values: FP64, or FP32 in the mixed modes
 // where that lets more wavefronts share a CU, see launch_pair_adjoint) and then
 // the record coefficients [r][NC] and (parity, cos column, sin column) [r][4],
-// then the channel-pair index table of form_cbar (n_ch^2 ints)
+// then the channel-pair index table of form_cbar (n_ch^2 ints, where the VALU
+// transform of several species needs it)
 template <int NMAX, int LMAX>
 struct AdjLds {
   static constexpr int NC = Shape<NMAX, LMAX>::NC;
-  static size_t cb_doubles(const DevParams& P) { return (size_t)P.ns * (P.LL + 1) * NMAX; }
+  __host__ __device__ static int cb_stride(int LL) { return (LL + 1) * NMAX; }
+  // the cbar region in doubles (c32: FP32 entries)
+  __host__ __device__ static int cb_doubles(int ns, int LL, bool c32) {
+    const int e = ns * cb_stride(LL);
+    return c32 ? (e + 1) / 2 : e;
+  }
   __host__ __device__ static int vbar_doubles(int K, int es) { return (K * es + 7) / 8; }
-  static size_t bytes(const DevParams& P, bool f32) {
+  // es: bytes per vbar entry (8, 4 or 2); c32: cbar in FP32
+  static size_t bytes(const DevParams& P, int es, bool c32) {
     const size_t nrec = (size_t)(P.l + 1) * (P.l + 2) / 2, rec = nrec * NC + 2 * nrec;
-    const size_t nv = (size_t)vbar_doubles(P.K, f32 ? 4 : 8);
-    return sizeof(double) * (cb_doubles(P) + (rec > nv ? rec : nv)) + sizeof(int) * (size_t)P.nch * P.nch;
+    const size_t nv = (size_t)vbar_doubles(P.K, es);
+    const size_t nabx = P.ns > 1 && !P.ps_mfma ? (size_t)P.nch * P.nch : 0;
+    return sizeof(double) * (cb_doubles(P.ns, P.LL, c32) + (rec > nv ? rec : nv)) + sizeof(int) * nabx;
   }
 };
 
 // the pair's contraction with the cbar of one species over the records (l, m) of
 // the degrees l set in deg (l outer, ascending, m inner): S_r, S_x, S_y, S_z of
 // the gradient (partial sums when deg holds only some degrees)
-template <int NMAX, int LMAX, typename FieldFn>
-__device__ __forceinline__ void adjoint_records(int L, unsigned deg, const double* __restrict__ cb,
+template <int NMAX, int LMAX, typename CT, typename FieldFn>
+__device__ __forceinline__ void adjoint_records(int L, unsigned deg, const CT* __restrict__ cb,
                                        const double* __restrict__ rc,
                                        const int* __restrict__ ri, FieldFn F, const double (&b)[NMAX],
                                        const double (&db)[NMAX], double uz, double ux, double uy, double& sr,
@@ -972,12 +1080,12 @@ __device__ __forceinline__ void adjoint_records(int L, unsigned deg, const doubl
       // zeros), no azimuthal factor and no contribution to S_x, S_y
       double Q, Qd;
       qbar(l, Q, Qd);
-      const double* __restrict__ c0 = cb + ri[4 * l + 1] * NMAX;
+      const CT* __restrict__ c0 = cb + ri[4 * l + 1] * NMAX;
       double U0 = 0.0, V0 = 0.0;
 #pragma unroll
       for (int k = 0; k < NMAX; ++k) {
-        U0 = fma(c0[k], db[k], U0);
-        V0 = fma(c0[k], b[k], V0);
+        U0 = fma((double)c0[k], db[k], U0);
+        V0 = fma((double)c0[k], b[k], V0);
       }
       sr = fma(Q, fma(U0, we, V0 * wd), sr);
       sz = fma(Qd, V0 * we, sz);
@@ -994,15 +1102,15 @@ __device__ __forceinline__ void adjoint_records(int L, unsigned deg, const doubl
       zr1 = zr;
       zi1 = zi;
       azimuthal_step(zr, zi, ux, uy);
-      const double* __restrict__ c0 = cb + lc * NMAX;
-      const double* __restrict__ c1 = cb + ls * NMAX;
+      const CT* __restrict__ c0 = cb + lc * NMAX;
+      const CT* __restrict__ c1 = cb + ls * NMAX;
       double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
 #pragma unroll
       for (int k = 0; k < NMAX; ++k) {
-        U0 = fma(c0[k], db[k], U0);
-        V0 = fma(c0[k], b[k], V0);
-        U1 = fma(c1[k], db[k], U1);
-        V1 = fma(c1[k], b[k], V1);
+        U0 = fma((double)c0[k], db[k], U0);
+        V0 = fma((double)c0[k], b[k], V0);
+        U1 = fma((double)c1[k], db[k], U1);
+        V1 = fma((double)c1[k], b[k], V1);
       }
       const double fm = (double)m;
       sr = fma(Q, fma(fma(U0, we, V0 * wd), zr, fma(U1, we, V1 * wd) * zi), sr);
@@ -1026,8 +1134,8 @@ constexpr bool kFullRecords = LMAX <= 10;
 // l - m, c columns l^2 + l + m and l^2 + l - m, parity (l - m) mod 2), so the
 // Horner steps, the table and cbar reads and the parity selects need no runtime
 // index arithmetic, loop control or branches
-template <int NMAX, int LMAX, typename FieldFn>
-__device__ __forceinline__ void adjoint_records_full(const double* __restrict__ cb, const double* __restrict__ rc,
+template <int NMAX, int LMAX, typename CT, typename FieldFn>
+__device__ __forceinline__ void adjoint_records_full(const CT* __restrict__ cb, const double* __restrict__ rc,
                                                      FieldFn F, const double (&b)[NMAX], const double (&db)[NMAX],
                                                      double uz, double ux, double uy, double& sr, double& sx,
                                                      double& sy, double& sz) {
@@ -1051,13 +1159,13 @@ __device__ __forceinline__ void adjoint_records_full(const double* __restrict__ 
       }
       const double Q = par ? uz * Rv : Rv;
       const double Qd = par ? fma(2.0 * x2, Rd, Rv) : 2.0 * uz * Rd;
-      const double* __restrict__ c0 = cb + (l * l + l + m) * NMAX;
+      const CT* __restrict__ c0 = cb + (l * l + l + m) * NMAX;
       if (m == 0) {
         double U0 = 0.0, V0 = 0.0;
 #pragma unroll
         for (int k = 0; k < NMAX; ++k) {
-          U0 = fma(c0[k], db[k], U0);
-          V0 = fma(c0[k], b[k], V0);
+          U0 = fma((double)c0[k], db[k], U0);
+          V0 = fma((double)c0[k], b[k], V0);
         }
         sr = fma(Q, fma(U0, we, V0 * wd), sr);
         sz = fma(Qd, V0 * we, sz);
@@ -1066,14 +1174,14 @@ __device__ __forceinline__ void adjoint_records_full(const double* __restrict__ 
       zr1 = zr;
       zi1 = zi;
       azimuthal_step(zr, zi, ux, uy);
-      const double* __restrict__ c1 = cb + (l * l + l - m) * NMAX;
+      const CT* __restrict__ c1 = cb + (l * l + l - m) * NMAX;
       double U0 = 0.0, V0 = 0.0, U1 = 0.0, V1 = 0.0;
 #pragma unroll
       for (int k = 0; k < NMAX; ++k) {
-        U0 = fma(c0[k], db[k], U0);
-        V0 = fma(c0[k], b[k], V0);
-        U1 = fma(c1[k], db[k], U1);
-        V1 = fma(c1[k], b[k], V1);
+        U0 = fma((double)c0[k], db[k], U0);
+        V0 = fma((double)c0[k], b[k], V0);
+        U1 = fma((double)c1[k], db[k], U1);
+        V1 = fma((double)c1[k], b[k], V1);
       }
       const double fm = (double)m;
       sr = fma(Q, fma(fma(U0, we, V0 * wd), zr, fma(U1, we, V1 * wd) * zi), sr);
@@ -1097,7 +1205,7 @@ __device__ __forceinline__ void adjoint_records_full(const double* __restrict__ 
 // as broadcasts.  Registers: up to 168 per lane (3 waves per SIMD) in the buckets
 // up to n_max = 8, where the compile-time record loop spills at 128; the larger
 // buckets need up to 256 (2 waves per SIMD).
-template <int NMAX, int LMAX, typename ST>
+template <int NMAX, int LMAX, typename ST, bool C32>
 __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParams P, const DevTables* __restrict__ T,
                                                                        int n_atoms, const int* __restrict__ offsets,
                                                                        int bound, const int* __restrict__ nj,
@@ -1120,9 +1228,12 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
   const int LLP = P.LL + 1, L = P.l, nrec = (L + 1) * (L + 2) / 2;
   const int p0 = min(offsets[i], bound), p1 = min(offsets[i + 1], bound);  // pairs below the bound only
   if (p0 >= p1) return;
-  const int ncb = P.ns * LLP * NMAX;
-  double* cb = dyn;
-  double* rc = dyn + ncb;
+  // cbar in FP32 (C32: the mixed modes' matrix-core transform, several species,
+  // whose FP32 results it holds exactly) or FP64
+  using CT = std::conditional_t<C32, float, double>;
+  const int cbs = AdjLds<NMAX, LMAX>::cb_stride(P.LL);
+  CT* cb = reinterpret_cast<CT*>(dyn);
+  double* rc = dyn + AdjLds<NMAX, LMAX>::cb_doubles(P.ns, P.LL, C32);
   int* ri = reinterpret_cast<int*>(rc + nrec * NC);
   {
     // the record table; its global reads are issued before form_cbar, its
@@ -1143,15 +1254,20 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
       lc[k] = T->rec_lm[jj][slot][0];
       ls[k] = T->rec_lm[jj][slot][1];
     }
-    const bool vf = sizeof(ST) == 4 && vbar_f32;  // vbar in FP32 (mixed modes only)
-    const int nrec_d = nrec * NC + 2 * nrec, nv_d = AdjLds<NMAX, LMAX>::vbar_doubles(P.K, vf ? 4 : 8);
+    // bytes per vbar entry: BF16 operands with C32, FP32 with vbar_f32 (the mixed
+    // modes only), FP64 otherwise
+    const int es = C32 ? 2 : (sizeof(ST) == 4 && vbar_f32 ? 4 : 8);
+    const int nrec_d = nrec * NC + 2 * nrec, nv_d = AdjLds<NMAX, LMAX>::vbar_doubles(P.K, es);
     int* abx = reinterpret_cast<int*>(rc + (nrec_d > nv_d ? nrec_d : nv_d));
-    if constexpr (sizeof(ST) == 4) {
-      if (vf) form_cbar<NMAX, LMAX, ST, float>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb,
+    if constexpr (C32) {
+      form_cbar<NMAX, LMAX, ST, __bf16, float>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cbs, cb,
+                                               reinterpret_cast<__bf16*>(rc), abx, lane);
+    } else if (es == 4) {
+      form_cbar<NMAX, LMAX, ST, float, double>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cbs, cb,
                                                reinterpret_cast<float*>(rc), abx, lane);
-      else form_cbar<NMAX, LMAX, ST, double>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
     } else {
-      form_cbar<NMAX, LMAX, ST, double>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cb, rc, abx, lane);
+      form_cbar<NMAX, LMAX, ST, double, double>(P, i, c, q, q_pitch, pnorm, qbar, qbar2, qbar_pitch, cbs, cb, rc,
+                                                abx, lane);
     }
 #pragma unroll
     for (int k = 0; k < RPL; ++k)
@@ -1192,7 +1308,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 3 : 2) void k_pair_adjoint(DevParam
       on = on && sj >= 0 && sj < P.ns;
       sj = on ? sj : 0;
     }
-    const double* __restrict__ cbj = cb + (size_t)sj * LLP * NMAX;
+    const CT* __restrict__ cbj = cb + (size_t)sj * cbs;
     if (kFullRecords<NMAX, LMAX> && R == 1 && L == LMAX)
       adjoint_records_full<NMAX, LMAX>(cbj, rc, F, b, db, uz, ux, uy, sr, sx, sy, sz);
     else
@@ -1298,16 +1414,19 @@ size_t dispatch_size(int n, int l, F&& f) {
   return f.template operator()<12, 12>();
 }
 
-size_t fwd_dyn_bytes(const DevParams& P) {
+// store_f32: c stored (and, with fwd_c32, staged) in FP32
+size_t fwd_dyn_bytes(const DevParams& P, bool store_f32) {
   return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t {
     using S = Shape<N, LM>;
+    const size_t nc = (size_t)P.ns * N * (P.LL + 1);
     const size_t rows = (size_t)S::CH * S::FRP,
-                 epi = (size_t)P.ns * N * (P.LL + 1) + (fwd_p_in_lds<N, LM>(P) ? (size_t)P.K : 0);
+                 epi = store_f32 && fwd_c32<N, LM>(P) ? (nc + 1) / 2
+                                                      : nc + (fwd_p_in_lds<N, LM>(P) ? (size_t)P.K : 0);
     return sizeof(double) * (rows > epi ? rows : epi);
   });
 }
-size_t adj_dyn_bytes(const DevParams& P, bool f32) {
-  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return AdjLds<N, LM>::bytes(P, f32); });
+size_t adj_dyn_bytes(const DevParams& P, int es, bool c32) {
+  return dispatch_size(P.n, P.l, [&]<int N, int LM>() -> size_t { return AdjLds<N, LM>::bytes(P, es, c32); });
 }
 
 }  // namespace
@@ -1324,9 +1443,9 @@ size_t pair_rows_bytes(const DevParams& P, long long n_pairs, bool f32) {
 }
 
 size_t descriptor_lds_bytes(const DevParams& P) {
-  return fwd_dyn_bytes(P) + 64 * sizeof(int);
+  return fwd_dyn_bytes(P, false) + 64 * sizeof(int);  // the larger (FP64) layout
 }
-size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P, false); }  // the larger (FP64) layout
+size_t adjoint_lds_bytes(const DevParams& P) { return adj_dyn_bytes(P, 8, false); }  // the largest (FP64) layout
 
 hipError_t launch_pair_prep(const DevParams& P, const DevTables* T, long long n_pairs, const int* count,
                             const double* dx, const double* dy, const double* dz, void* rows_v, bool rows_f32,
@@ -1377,7 +1496,7 @@ hipError_t launch_descriptor(const DevParams& P, const DevTables* T, int n_atoms
                              double* q, int q_pitch, double* pnorm, void* qc, int qc_pitch, hipStream_t st) {
   if (n_atoms == 0) return hipSuccess;
   if (qc && qc_pitch < P.K) return hipErrorInvalidValue;
-  const size_t dyn = fwd_dyn_bytes(P);
+  const size_t dyn = fwd_dyn_bytes(P, store_f32);
   auto f = [&]<int N, int LM>() {
     if (store_f32)
       hipLaunchKernelGGL((k_descriptor<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T, n_atoms,
@@ -1402,18 +1521,27 @@ hipError_t launch_pair_adjoint(const DevParams& P, const DevTables* T, int n_ato
   // vbar in FP32 when the FP64 layout leaves a CU (160 KB of LDS) one wavefront
   // per SIMD and the FP32 one fits more (three species at K = 2700: 39.6 -> 28.8
   // KB, 4 -> 5 wavefronts per CU, adjoint 1.72 -> 1.49 ms); elsewhere the
-  // conversions cost more than the extra wavefronts gain
-  const size_t b64 = adj_dyn_bytes(P, false), b32 = adj_dyn_bytes(P, true), lds_cu = 160 * 1024;
-  const bool vbar_f32 = store_f32 && lds_cu / b64 <= 4 && lds_cu / b32 > lds_cu / b64;
-  const size_t dyn = vbar_f32 ? b32 : b64;
+  // conversions cost more than the extra wavefronts gain.  The matrix-core
+  // transform of several species (C32) keeps cbar in FP32 and its BF16 operands
+  // instead of vbar, with no channel-pair table (three species at K = 2700:
+  // 28.8 -> 13.3 KB)
+  const size_t b64 = adj_dyn_bytes(P, 8, false), b32 = adj_dyn_bytes(P, 4, false), lds_cu = 160 * 1024;
+  const bool c32 = store_f32 && P.ps_mfma && P.ns > 1;
+  const bool vbar_f32 = !c32 && store_f32 && lds_cu / b64 <= 4 && lds_cu / b32 > lds_cu / b64;
+  const size_t dyn = c32 ? adj_dyn_bytes(P, 2, true) : (vbar_f32 ? b32 : b64);
   auto f = [&]<int N, int LM>() {
-    if (store_f32)
-      hipLaunchKernelGGL((k_pair_adjoint<N, LM, float>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
+    if (c32)
+      hipLaunchKernelGGL((k_pair_adjoint<N, LM, float, true>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
+                         n_atoms, offsets, bound, nj, species, static_cast<const float*>(rows),
+                         static_cast<const float*>(c), q, q_pitch, pnorm, static_cast<const float*>(qbar),
+                         static_cast<const float*>(qbar2), qbar_pitch, gx, gy, gz, gstride, 0);
+    else if (store_f32)
+      hipLaunchKernelGGL((k_pair_adjoint<N, LM, float, false>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
                          n_atoms, offsets, bound, nj, species, static_cast<const float*>(rows),
                          static_cast<const float*>(c), q, q_pitch, pnorm, static_cast<const float*>(qbar),
                          static_cast<const float*>(qbar2), qbar_pitch, gx, gy, gz, gstride, vbar_f32 ? 1 : 0);
     else
-      hipLaunchKernelGGL((k_pair_adjoint<N, LM, double>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
+      hipLaunchKernelGGL((k_pair_adjoint<N, LM, double, false>), dim3(8 * xcd_per(n_atoms)), dim3(64), dyn, st, P, T,
                          n_atoms, offsets, bound, nj, species, static_cast<const double*>(rows),
                          static_cast<const double*>(c), q, q_pitch, pnorm, static_cast<const double*>(qbar),
                          static_cast<const double*>(qbar2), qbar_pitch, gx, gy, gz, gstride, 0);
