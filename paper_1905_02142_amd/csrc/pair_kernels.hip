@@ -565,10 +565,9 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
   __syncthreads();
   // power spectrum from c staged in LDS in its HBM layout [species][lm][k]: lane per
   // channel pair (a, b), a <= b, all l.  p is kept in LDS when it fits
-  // (fwd_p_in_lds); otherwise it goes straight to the q row and is rescaled there
-  // by the lane that wrote it, so that several species do not cut the number of
-  // wavefronts per CU
-  // With several species, FP32 storage and the matrix-core power spectrum, c is
+  // (fwd_p_in_lds); otherwise it stays in registers (one channel pair per lane) or
+  // goes straight to the q row and is rescaled there, so that several species do
+  // not cut the number of wavefronts per CU.  With several species, FP32 storage and the matrix-core power spectrum, c is
   // staged in FP32, the precision it was stored in (its BF16 operands are the
   // same), which halves the LDS the wave holds (fwd_c32)
   const int per_atom = P.ns * NMAX * LLP;
@@ -587,6 +586,10 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
     __syncthreads();
   }
   const int L1 = P.l + 1, nab = nch * (nch + 1) / 2;
+  // p in the q row with at most one channel pair per lane (VALU power spectrum):
+  // the lane keeps its entries in registers and writes q once, already scaled
+  const bool hold = !P.ps_mfma && pv == qi && nab <= 64;
+  double pr[LMAX + 1];
   double ss = 0.0;
   if (P.ps_mfma) {
     if constexpr (sizeof(ST) == 4)
@@ -610,7 +613,8 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
 #pragma unroll
         for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) v = fma(ca[lm * NMAX], cb[lm * NMAX], v);
         v *= scale;
-        pv[ab * L1 + l] = v;
+        if (hold) pr[l] = v;
+        else pv[ab * L1 + l] = v;
         ss = fma(v, v, ss);
       }
     }
@@ -626,24 +630,43 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
     for (int k = lane; k < q_pitch; k += 64) qi[k] = k < P.K ? pv[k] * inv : 0.0;
     if (qci)
       for (int k = lane; k < qc_pitch; k += 64) qci[k] = (__bf16)(float)(k < P.K ? pv[k] * inv : 0.0);
-  } else if (P.ps_mfma) {
-    // p in the q row, written by the lanes that hold the matrix-core results: every
-    // lane rescales a contiguous part once those stores are visible to the wave
-    __threadfence_block();
-    __syncthreads();
-    for (int k = lane; k < P.K; k += 64) {
-      qi[k] *= inv;
-      if (qci) qci[k] = (__bf16)(float)qi[k];
-    }
-    for (int k = P.K + lane; k < q_pitch; k += 64) qi[k] = 0.0;
-    if (qci)
-      for (int k = P.K + lane; k < qc_pitch; k += 64) qci[k] = (__bf16)0.0f;
   } else {
-    for (int ab = lane; ab < nab; ab += 64)
-      for (int l = 0; l < L1; ++l) {
-        qi[ab * L1 + l] *= inv;
-        if (qci) qci[ab * L1 + l] = (__bf16)(float)qi[ab * L1 + l];
+    if (hold) {
+      if (lane < nab) {
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l)
+          if (l < L1) {
+            const double x = pr[l] * inv;
+            qi[lane * L1 + l] = x;
+            if (qci) qci[lane * L1 + l] = (__bf16)(float)x;
+          }
       }
+    } else {
+      // p in the q row, written by other lanes (the matrix-core layout) or several
+      // channel pairs per lane: once those stores are visible to the wave, every
+      // lane rescales a strided part, sixteen loads in flight at a time (a loop
+      // with one load per entry waits one memory round trip per entry)
+      constexpr int B = 16;
+      __threadfence_block();
+      __syncthreads();
+      for (int k0 = 0; k0 < P.K; k0 += 64 * B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int k = k0 + lane + 64 * u;
+          v[u] = k < P.K ? qi[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int k = k0 + lane + 64 * u;
+          if (k < P.K) {
+            const double x = v[u] * inv;
+            qi[k] = x;
+            if (qci) qci[k] = (__bf16)(float)x;
+          }
+        }
+      }
+    }
     for (int k = P.K + lane; k < q_pitch; k += 64) qi[k] = 0.0;
     if (qci)
       for (int k = P.K + lane; k < qc_pitch; k += 64) qci[k] = (__bf16)0.0f;
