@@ -58,6 +58,16 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Keeps a batch of loads in flight together: the empty statement takes every
+// value in a register, so the compiler cannot move a load down into the
+// conditional code that consumes it, where each load would wait for its own
+// memory round trip.  It reads and writes nothing.
+template <int B, typename T>
+__device__ __forceinline__ void hold_batch(T (&v)[B]) {
+#pragma unroll
+  for (int u = 0; u < B; ++u) asm volatile("" : "+v"(v[u]));
+}
+
 // packed index of the unordered channel pair a <= b ("for a, for b >= a")
 __device__ inline int ab_index(int a, int b, int nch) { return a * nch - a * (a - 1) / 2 + (b - a); }
 
@@ -656,6 +666,7 @@ __global__ __launch_bounds__(64, NMAX <= 8 ? 4 : (NMAX == 10 ? 3 : 2)) void k_de
           const int k = k0 + lane + 64 * u;
           v[u] = k < P.K ? qi[k] : 0.0;
         }
+        hold_batch(v);
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           const int k = k0 + lane + 64 * u;
@@ -920,25 +931,16 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
     }
   }
   {
-    // the atom's c, every species, into cb (transformed there in place below),
-    // species s of c (nps values) at s cbs
-    const int nps = NMAX * LLP, nc = ns * nps;
+    // the atom's c, every species, into cb (transformed there in place below)
+    const int nc = ns * cbs;
     for (int t0 = 0; t0 < nc; t0 += 64 * B) {
       double v[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) v[u] = csh[min(t0 + lane + 64 * u, nc - 1)];
+      hold_batch(v);
 #pragma unroll
-      for (int u = 0; u < B; ++u) {
-        int t = t0 + lane + 64 * u;
-        if (t < nc) {
-          int o = 0;
-          while (t >= nps) {
-            t -= nps;
-            o += cbs;
-          }
-          cb[o + t] = (CT)v[u];
-        }
-      }
+      for (int u = 0; u < B; ++u)
+        if (t0 + lane + 64 * u < nc) cb[t0 + lane + 64 * u] = (CT)v[u];
     }
   }
   if constexpr (VB16) {
@@ -951,11 +953,18 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
         const int k = min(k0 + lane + 64 * u, K - 1);
         a[u] = qi[k];
         g[u] = qb[k];
-        if (qb2) g2[u] = qb2[k];
       }
+      if (qb2) {  // a branch of its own, not one per entry: the loads stay together
+#pragma unroll
+        for (int u = 0; u < B; ++u) g2[u] = qb2[min(k0 + lane + 64 * u, K - 1)];
+        hold_batch(g2);
+#pragma unroll
+        for (int u = 0; u < B; ++u) g[u] += g2[u];
+      }
+      hold_batch(a);
+      hold_batch(g);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
-        if (qb2) g[u] += g2[u];
         if (k0 + lane + 64 * u < K) dot = fma(a[u], g[u], dot);
       }
     }
@@ -972,12 +981,19 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
         const int k = min(k0 + lane + 64 * u, K - 1);
         a[u] = qi[k];
         g[u] = qb[k];
-        if (qb2) g2[u] = qb2[k];
       }
+      if (qb2) {  // a branch of its own, not one per entry: the loads stay together
+#pragma unroll
+        for (int u = 0; u < B; ++u) g2[u] = qb2[min(k0 + lane + 64 * u, K - 1)];
+        hold_batch(g2);
+#pragma unroll
+        for (int u = 0; u < B; ++u) g[u] += g2[u];
+      }
+      hold_batch(a);
+      hold_batch(g);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int k = k0 + lane + 64 * u;
-        if (qb2) g[u] += g2[u];
         if (k < K) {
           const float v = (float)(((double)(float)g[u] - a[u] * dot) * inv);
           while (k >= rend) {
@@ -1003,11 +1019,18 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
         const int k = min(k0 + lane + 64 * u, K - 1);
         a[u] = qi[k];
         g[u] = qb[k];
-        if (qb2) g2[u] = qb2[k];
       }
+      if (qb2) {  // a branch of its own, not one per entry: the loads stay together
+#pragma unroll
+        for (int u = 0; u < B; ++u) g2[u] = qb2[min(k0 + lane + 64 * u, K - 1)];
+        hold_batch(g2);
+#pragma unroll
+        for (int u = 0; u < B; ++u) g[u] += g2[u];
+      }
+      hold_batch(a);
+      hold_batch(g);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
-        if (qb2) g[u] += g2[u];
         if (k0 + lane + 64 * u < K) {
           dot = fma(a[u], g[u], dot);
           vb[k0 + lane + 64 * u] = (VT)g[u];
@@ -1021,6 +1044,7 @@ __device__ __forceinline__ void form_cbar(const DevParams& P, int i, const ST* _
       double a[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) a[u] = qi[min(k0 + lane + 64 * u, K - 1)];
+      hold_batch(a);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int k = k0 + lane + 64 * u;
